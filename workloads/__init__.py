@@ -1,0 +1,109 @@
+"""Seeded synthetic workloads shared by the oracle, the tests and the benchmark.
+
+This module only draws random physical parameters (numpy PCG64 via
+``default_rng(seed)``) and states the fixed constants of each workload.  It
+holds none of the method's arithmetic: no eigenvalues, no coupling tensors, no
+scheme coefficients and no geometry solves.  Whatever a workload leaves to be
+derived (for example a plate area chosen so that the highest simulated mode
+sits at a given frequency) is named here as a target and derived separately by
+each consumer.
+
+The workloads follow the paper's own experiments (Sec. 3.2 benchmarks: von
+Karman and tension-modulated models at 10/50/100 modes, 1 s at 44.1 kHz;
+Sec. 3.3 inverse modelling) at the sizes of the five benchmark configurations.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+FS = 44100.0
+
+# steel, the material of the single-plate workload
+STEEL = dict(E=2e11, nu=0.3, rho=7860.0)
+
+
+def string_kc(seed: int = 1, n_modes: int = 30, n_steps: int = 22050) -> dict:
+    """Tension-modulated (Kirchhoff-Carrier) string, 0.65 m, 30 sine modes.
+
+    Raised-cosine pluck of 1 mm amplitude and total width 0.1 L, centred at a
+    seeded position in [0.1 L, 0.4 L]; output at a seeded point in
+    [0.1 L, 0.9 L].  Damping law sigma_k = 1 + 0.002 omega_k (rate, 1/s).
+    """
+    rng = np.random.default_rng(seed)
+    L = 0.65
+    x_pluck = rng.uniform(0.1 * L, 0.4 * L)
+    x_out = rng.uniform(0.1 * L, 0.9 * L)
+    return dict(
+        family="string", model="kc", L=L, T0=60.0, rhoA=6e-4, EA=3e5, EI=0.0,
+        n_modes=n_modes, fs=FS, n_steps=n_steps,
+        damping=("affine_omega", 1.0, 0.002),
+        pluck=dict(x0=x_pluck, amplitude=1e-3, width=0.1 * L),
+        x_out=x_out, proj_cells=4096,
+    )
+
+
+def plate_vk(seed: int = 2, n_t: int = 40, n_in: int | None = None,
+             n_steps: int = 44100, family: str = "clamped",
+             grid=(200, 150)) -> dict:
+    """Single von Karman plate, 0.4 x 0.3 m steel, 1 mm, simply supported.
+
+    Strike: raised-cosine initial displacement of seeded height in
+    [0.5 h, 3 h] and radius 0.1 min(Lx, Ly); strike centre and output point
+    drawn independently in [0.1, 0.9] x (Lx, Ly).  No pre-tension.
+    """
+    rng = np.random.default_rng(seed)
+    h = 1e-3
+    Lx, Ly = 0.4, 0.3
+    amp = rng.uniform(0.5, 3.0) * h
+    cx, cy = rng.uniform(0.1, 0.9, size=2)
+    ox, oy = rng.uniform(0.1, 0.9, size=2)
+    return dict(
+        family="plate", model="vk", inplane=family, Lx=Lx, Ly=Ly, h=h,
+        T0=0.0, **STEEL, n_t=n_t, n_in=n_t if n_in is None else n_in,
+        fs=FS, n_steps=n_steps, grid=tuple(grid),
+        damping=("affine_omega", 1.0, 0.002),
+        strike=dict(xc=cx * Lx, yc=cy * Ly, amplitude=amp,
+                    radius=0.1 * min(Lx, Ly)),
+        out=(ox * Lx, oy * Ly), proj_grid=tuple(grid),
+    )
+
+
+def plate_batch(seed: int = 3, batch: int = 256, n_lo: int = 50,
+                n_hi: int = 400, n_steps: int = 44100,
+                top_mode_hz: float = 5000.0) -> list[dict]:
+    """Batch of uneven von Karman plates for one persistent launch.
+
+    Transverse mode count N_b ~ U{n_lo..n_hi}, in-plane count equal to it;
+    aspect Ly/Lx ~ U[0.5, 1]; thickness ~ U[0.5, 2] mm; Young's modulus and
+    pre-tension log-uniform over one decade (centred on steel's 2e11 Pa;
+    10..100 N/m).  The plate area is left to the consumer: it is the one that
+    puts transverse mode N_b at ``top_mode_hz``.  Coupling tensors use the
+    sine in-plane family with exact integrals.  Strike height ~ U[0.5, 3] h,
+    radius 0.1 min(Lx, Ly); centre and output point ~ U[0.1, 0.9]^2 of the
+    plate.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(batch):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        aspect = float(rng.uniform(0.5, 1.0))
+        h = float(rng.uniform(0.5e-3, 2e-3))
+        E = float(2e11 * 10.0 ** rng.uniform(-0.5, 0.5))
+        T0 = float(10.0 ** rng.uniform(1.0, 2.0))
+        amp = float(rng.uniform(0.5, 3.0)) * h
+        cx, cy, ox, oy = (float(v) for v in rng.uniform(0.1, 0.9, size=4))
+        out.append(dict(
+            family="plate", model="vk", inplane="sine", grid=None,
+            aspect=aspect, top_mode_hz=top_mode_hz, h=h, E=E, nu=0.3,
+            rho=7860.0, T0=T0, n_t=n, n_in=n, fs=FS, n_steps=n_steps,
+            damping=("affine_omega", 1.0, 0.002),
+            strike_rel=dict(xc=cx, yc=cy, amplitude=amp, radius_rel=0.1),
+            out_rel=(ox, oy), proj_grid=(256, 256), index=b,
+        ))
+    return out
+
+
+def plate_sweep(n_t: int, seed: int = 2, n_steps: int = 44100) -> dict:
+    """The paper's benchmark shapes: the single-plate geometry at 10/50/100
+    modes (Sec. 3.2, Fig. 2), sine in-plane family, 1 s at 44.1 kHz."""
+    return plate_vk(seed=seed, n_t=n_t, n_steps=n_steps, family="sine")
