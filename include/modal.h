@@ -1,0 +1,162 @@
+/*
+ * modal.h -- C ABI of the MI355X modal time-stepping library (libmodal.so).
+ *
+ * The library steps batches of independent modal systems, one audio sample
+ * per step, each mode a damped oscillator driven by an external force and a
+ * nonlinear modal force (paper: Sec. 2.2, modal oscillator equation
+ *   q'' + 2 gamma q' + omega^2 q = f_ext - f_nl ).
+ * Nonlinear forces (paper: Sec. 2.1):
+ *   MODAL_KIND_TENSION  tension-modulated string / membrane (modal
+ *                       string-membrane equation with normalised modes):
+ *                       f_k = kappa lambda_k q_k sum_j lambda_j q_j^2
+ *   MODAL_KIND_VK       von Karman plate (nonlinear plate equation with the
+ *                       scaled coupling tensor Ht[n][k][j], symmetric in k, j):
+ *                       eta_n = sum_kj Ht[n][k][j] q_k q_j,
+ *                       f_k   = sum_{n,j} Ht[n][k][j] q_j eta_n
+ *   MODAL_KIND_LINEAR   f_nl = 0.
+ * Schemes (paper: Sec. 2.2): Stormer-Verlet (modal oscillator update) and the
+ * impulse-invariant transfer-function recursion (df update), both written as
+ *   q^{n+1} = g q^n + p q^{n-1} + r (f_ext^n - f_nl^n).
+ *
+ * Conventions for every entry point:
+ *  - Return value: MODAL_OK (0) or a negative modal_status.  Nothing throws
+ *    across the ABI.  modal_last_error() gives a message for the last failure
+ *    of the calling thread.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory of the current device.  Streams are hipStream_t passed as void*
+ *    (NULL = the default stream).
+ *  - modal_init deep-copies every input; the caller may free its arrays as
+ *    soon as it returns.  A context owns all device memory it allocates and
+ *    frees it in modal_destroy.  A context is not thread safe: use one
+ *    context per stream.
+ */
+#ifndef MODAL_H
+#define MODAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct modal_ctx modal_ctx;
+
+typedef enum {
+  MODAL_OK = 0,
+  MODAL_EINVAL = -1,     /* invalid argument or inconsistent sizes            */
+  MODAL_EUNSTABLE = -2,  /* a mode's recursion has a root outside |z| <= 1    */
+  MODAL_ENOMEM = -3,     /* device or host allocation failed                  */
+  MODAL_EHIP = -4,       /* a HIP runtime call failed                         */
+  MODAL_ENONFINITE = -5, /* a state became Inf/NaN during the run (sticky
+                            until modal_reset)                                */
+  MODAL_ESTATE = -6,     /* call not valid in the context's current state     */
+  MODAL_EHANG = -7       /* a per-instance step barrier timed out; the run
+                            was abandoned and the state is undefined          */
+} modal_status;
+
+enum { MODAL_KIND_LINEAR = 0, MODAL_KIND_TENSION = 1, MODAL_KIND_VK = 2 };
+enum { MODAL_SCHEME_SV = 0, MODAL_SCHEME_TF = 1 };
+
+/* modal_desc.flags */
+enum {
+  MODAL_FLAG_ASYNC = 1, /* modal_run does not wait for completion nor read
+                           the status flags; call modal_check afterwards     */
+  MODAL_FLAG_GRAPH = 2  /* modal_run records its launches into a hipGraph
+                           on first use for a given (n_steps, y, y_stride)
+                           and replays it afterwards                          */
+};
+
+/* One modal system.  All arrays are host memory. */
+typedef struct {
+  int32_t kind;          /* MODAL_KIND_*                                      */
+  int32_t n_t;           /* number of time-stepped modes, 1..1024             */
+  int32_t n_in;          /* VK: number of in-plane modes (>= 1); else 0       */
+  int32_t reserved;      /* must be 0                                         */
+  const double *omega;   /* [n_t] angular frequencies omega_k (rad/s)         */
+  const double *gamma;   /* [n_t] decay rates gamma_k >= 0 (1/s)              */
+  const double *lambda;  /* TENSION: [n_t] Laplacian eigenvalues; else NULL   */
+  double kappa;          /* TENSION: tau / rho_s; else ignored                */
+  const float *H;        /* VK: [n_in][n_t][n_t] scaled coupling tensor Ht,
+                            row-major, symmetric in the last two indices to
+                            1e-6 of its largest entry; host or device memory */
+  const double *x0;      /* [n_t] initial state q^0                           */
+  const double *xm1;     /* [n_t] initial state q^-1                          */
+  const double *b_ext;   /* [n_t] modal force weights, or NULL (no forcing)   */
+  const float *e_ext;    /* [n_exc] force signal: f_ext^n = b_ext e_ext[n]
+                            for n < n_exc (absolute step index), else 0       */
+  int64_t n_exc;
+  const double *c_out;   /* [n_t] output weights: y^n = sum_k c_k q_k^n       */
+} modal_instance;
+
+typedef struct {
+  int32_t batch;                /* number of instances, >= 1                  */
+  int32_t scheme;               /* MODAL_SCHEME_*                             */
+  const modal_instance *inst;   /* [batch]                                    */
+  double fs;                    /* sampling rate (Hz), T = 1/fs               */
+  int32_t flags;                /* MODAL_FLAG_*                               */
+  int32_t max_workgroups;       /* 0 = as many as fit co-resident on the GPU;
+                                   else an upper bound (tuning / tests)       */
+  int32_t chunk_steps;          /* steps per kernel launch; 0 = whole run     */
+  int32_t reserved;             /* must be 0                                  */
+} modal_desc;
+
+/* Validates the description (before any device work), computes the per-mode
+ * recursion coefficients in FP64 and stores them as float-float pairs,
+ * partitions the batch into per-workgroup work, allocates device memory and
+ * uploads the coupling tensors and initial states on `stream`.
+ * Errors: EINVAL (NULL/size/kind/finite/symmetry), EUNSTABLE (a mode's
+ * characteristic roots outside the unit circle; also gamma < 0 or, for TF,
+ * omega <= gamma), ENOMEM, EHIP.  On error *out is NULL. */
+int modal_init(modal_ctx **out, const modal_desc *d, void *stream);
+
+/* Advances every instance by n_steps samples from its current state and
+ * writes y[b * y_stride + i] = output of instance b at step (current + i),
+ * i < n_steps.  y is device memory of at least batch * y_stride floats,
+ * y_stride >= n_steps.  Launches on `stream`.  Unless MODAL_FLAG_ASYNC, waits
+ * for completion and returns ENONFINITE / EHANG if raised.  Steps already
+ * taken persist: two calls of a and b steps equal one call of a + b. */
+int modal_run(modal_ctx *c, int64_t n_steps, float *y, int64_t y_stride,
+              void *stream);
+
+/* Waits for `stream` and reports ENONFINITE / EHANG raised since init/reset. */
+int modal_check(modal_ctx *c, void *stream);
+
+/* Restores q^0, q^-1 and the step counter to their values at init. */
+int modal_reset(modal_ctx *c, void *stream);
+
+/* Copies the current state of every instance to host FP64 arrays laid out as
+ * the concatenation of the instances' modes: x = q^n, xm1 = q^{n-1}
+ * (each [sum n_t]).  Waits for `stream`. */
+int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
+
+/* Partition and sizes, for tests and measurement:
+ * info[0] workgroups launched, [1] work units, [2] split instances,
+ * [3] coupling bytes read per step (sum over VK instances of
+ * 4 n_in n_t n_t), [4] bytes of the padded device layout streamed per step,
+ * [5] steps taken so far, [6] dynamic LDS bytes per workgroup,
+ * [7] co-resident workgroups per CU used for the plan. */
+int modal_info(const modal_ctx *c, int64_t info[8]);
+
+void modal_destroy(modal_ctx *c);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char *modal_last_error(void);
+
+/* Host FP64 builder of the scaled coupling tensor for the sine in-plane
+ * family (paper: Sec. 2.1, coupling-coefficient equations; modes
+ * Phi_i = 2/sqrt(Lx Ly) sin(m_i pi x/Lx) sin(q_i pi y/Ly), Psi_n likewise
+ * with (a_n, b_n)):
+ *   out[n][i][j] = scale_n * int Psi_n L(Phi_i, Phi_j) dS
+ * with the integral exact when nx = ny = 0, else the midpoint rule on an
+ * nx x ny grid.  scale_n is given per in-plane mode (sqrt(E/2rho)/zeta_n^2
+ * for the scaled tensor).  out is host memory [n_in][n_t][n_t] (FP32),
+ * exactly symmetric in i, j.  Runs on `threads` host threads (0 = all). */
+int modal_vk_coupling_sine(double Lx, double Ly, int32_t n_t, const int32_t *m,
+                           const int32_t *q, int32_t n_in, const int32_t *a,
+                           const int32_t *b, int32_t nx, int32_t ny,
+                           const double *scale_n, float *out, int32_t threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MODAL_H */

@@ -60,13 +60,10 @@ def coupling_midpoint(Lx, Ly, n_t, n_in, nx, ny, family="clamped", K=None,
 
 
 def _sin_int(k, L):
-    """Exact integral over [0, L] of sin(k pi x / L), integer k (any sign)."""
+    """Exact integral over [0, L] of sin(k pi x / L) for integer k of any
+    sign: L (1 - cos k pi) / (k pi), i.e. 2 L / (k pi) for odd k, else 0."""
     k = np.asarray(k)
-    out = np.zeros(k.shape)
-    nz = k != 0
-    kk = k[nz].astype(float)
-    out[nz] = L * (1.0 - np.cos(kk * np.pi)) / (kk * np.pi)
-    return out
+    return 2.0 * L * (k % 2) / (np.pi * np.where(k == 0, 1, k))
 
 
 def _int_sss(a, i, j, L):
@@ -98,15 +95,15 @@ def coupling_sine_exact(Lx, Ly, n_t, n_in):
     be = q * np.pi / Ly
     A = al[:, None] ** 2 * be[None, :] ** 2 + be[:, None] ** 2 * al[None, :] ** 2
     B = 2.0 * (al * be)[:, None] * (al * be)[None, :]
-    ak = a_k[:, None, None]
-    bk = b_k[:, None, None]
-    mi, mj = m[None, :, None], m[None, None, :]
-    qi, qj = q[None, :, None], q[None, None, :]
-    Sx = _int_sss(ak, mi, mj, Lx)
-    Sy = _int_sss(bk, qi, qj, Ly)
-    Cx = _int_scc(ak, mi, mj, Lx)
-    Cy = _int_scc(bk, qi, qj, Ly)
-    H = c ** 3 * (A[None] * Sx * Sy - B[None] * Cx * Cy)
+    mi, mj = m[:, None], m[None, :]
+    qi, qj = q[:, None], q[None, :]
+    H = np.empty((n_in, n_t, n_t))
+    for k in range(n_in):
+        Sx = _int_sss(a_k[k], mi, mj, Lx)
+        Sy = _int_sss(b_k[k], qi, qj, Ly)
+        Cx = _int_scc(a_k[k], mi, mj, Lx)
+        Cy = _int_scc(b_k[k], qi, qj, Ly)
+        H[k] = c ** 3 * (A * Sx * Sy - B * Cx * Cy)
     return dict(H=H, zeta4=zeta4, m=m, q=q, lam=lam)
 
 

@@ -1,0 +1,58 @@
+// Device-side data layout shared by the step kernel and the host planner.
+#pragma once
+#include <stdint.h>
+
+namespace modal {
+
+constexpr int kWave = 64;        // CDNA wavefront width; one wave per workgroup
+constexpr int kMaxModes = 1024;  // per instance
+constexpr int kMaxGroups = kMaxModes / 4 / kWave;  // float4 groups per lane
+
+enum : int { KIND_LINEAR = 0, KIND_TENSION = 1, KIND_VK = 2 };
+
+// One instance (modal system).  Per-mode arrays are padded to ntp = round-up
+// of nt to a multiple of 4 with zeros, so every lane works on float4 groups.
+struct InstDev {
+  int kind, nt, nin, ntp;
+  long long h_off;     // float offset of Ht[nin][nt][ntp] in the tensor pool
+  int mode_off;        // offset into the per-mode arrays (multiple of 4)
+  int nslab;           // number of work units (workgroups) sharing it
+  long long part_off;  // float offset of its partial forces [2][nslab][ntp]
+  float kappa;         // TENSION
+  int out_row;         // row of y
+  long long e_off;     // offset into the excitation pool
+  long long n_exc;     // excitation length (0 = none)
+};
+
+// A slice of in-plane rows [row0, row1) of one instance, owned by one
+// workgroup.  Each owner keeps a private copy of the instance state.
+struct UnitDev {
+  int inst, row0, row1, slab;
+  int state_off;  // offset into the per-unit state arrays (multiple of 4)
+  int qs;         // stored rows of Ht[n] per sweep of the wave
+  int J;          // float4 loads per lane per sweep
+  int pad;
+};
+
+struct StepParams {
+  const InstDev* inst;
+  const UnitDev* unit;
+  const int* wg_begin;  // [n_wg + 1] unit ranges per workgroup
+  const float* H;       // tensor pool
+  // per-mode float-float coefficients of d+ = m X - p d + r (f_ext - f)
+  const float *m_hi, *m_lo, *p_hi, *p_lo, *r_hi, *r_lo;
+  const float *c_out, *lam, *b_ext;
+  const float* e_ext;
+  // per-unit state (float-float X = q^n and d = q^n - q^{n-1})
+  float *x_hi, *x_lo, *d_hi, *d_lo;
+  float* part;              // partial forces of split instances
+  unsigned int* ctr;        // arrival counters of split instances
+  int* flags;               // [0] barrier timeout, [1] non-finite state
+  long long* step_base;     // absolute index of the next step (device)
+  float* y;                 // output, y[row * y_stride + s]
+  long long y_stride;
+  int n_steps;              // steps of this launch
+  int red_floats;           // LDS floats reserved for the reduction buffer
+};
+
+}  // namespace modal

@@ -1,0 +1,644 @@
+// Host side of libmodal: validation, FP64 scheme coefficients, the work
+// partition, device memory, launches and graph capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "../../include/modal.h"
+#include "kernels.h"
+
+namespace modal {
+hipError_t launch_step(const StepParams& P, int n_wg, size_t lds_bytes, hipStream_t s);
+hipError_t launch_advance(long long* step_base, int n, hipStream_t s);
+hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s);
+hipError_t step_occupancy(int* blocks_per_cu, size_t lds_bytes);
+}  // namespace modal
+
+using namespace modal;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(MODAL_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+bool finite_all(const double* v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+int round4(int n) { return (n + 3) & ~3; }
+
+// float-float split of an FP64 value
+void split(double v, float& hi, float& lo) {
+  hi = (float)v;
+  lo = (float)(v - (double)hi);
+}
+
+struct Coef {
+  double m, p, r;
+};
+
+// Per-mode recursion q+ = g q + p q- + r f, returned as (m = g + p - 1, p, r).
+// Stormer-Verlet (paper: Sec. 2.2): r = 2T^2/(2 + 2 gamma T),
+// g = r (2/T^2 - omega^2), p = r (-1/T^2 + gamma/T); hence
+// p = -(1 - gamma T)/(1 + gamma T) and m = -r omega^2 exactly.
+// Transfer function (impulse invariance, Sec. 2.2, denominator
+// z^2 + a1 z + a2): g = -a1 = 2 e^{-gamma T} cos(w T), p = -a2 = -e^{-2 gamma T},
+// r = T e^{-gamma T} sin(w T)/w with w = sqrt(omega^2 - gamma^2) (force per
+// unit mass), and m = -(1 - e^{-gamma T})^2 - 4 e^{-gamma T} sin^2(w T/2).
+Coef coefficients(int scheme, double omega, double gamma, double T) {
+  Coef c;
+  if (scheme == MODAL_SCHEME_SV) {
+    c.r = T * T / (1.0 + gamma * T);
+    c.p = -(1.0 - gamma * T) / (1.0 + gamma * T);
+    c.m = -c.r * omega * omega;
+  } else {
+    const double w = std::sqrt(omega * omega - gamma * gamma);
+    const double e = std::exp(-gamma * T);
+    const double em1 = std::expm1(-gamma * T);
+    const double sh = std::sin(0.5 * w * T);
+    c.p = -e * e;
+    c.r = T * e * std::sin(w * T) / w;
+    c.m = -em1 * em1 - 4.0 * e * sh * sh;
+  }
+  return c;
+}
+
+// Schur-Cohn (Jury) test for z^2 - g z - p: both roots in |z| <= 1.
+bool stable(const Coef& c) {
+  const double g = c.m - c.p + 1.0;
+  const double tol = 1e-12;
+  return std::fabs(c.p) <= 1.0 + tol && std::fabs(g) <= 1.0 - c.p + tol;
+}
+
+struct Unit {
+  int inst, row0, row1, slab;
+  double cost;
+};
+
+}  // namespace
+
+struct modal_ctx {
+  int batch = 0, scheme = 0, flags = 0, chunk = 0;
+  double fs = 0;
+  int n_wg = 0, n_units = 0, n_split = 0, occ = 0;
+  size_t lds_bytes = 0;
+  long long coupling_bytes = 0, padded_bytes = 0, steps = 0;
+  int state_floats = 0, mode_floats = 0;
+  std::vector<int> nt, unit_state_of_inst, inst_mode_off;
+  std::vector<float> state0;  // x_hi, x_lo, d_hi, d_lo concatenated
+  // device
+  float* dH = nullptr;
+  void* dMeta = nullptr;     // InstDev, UnitDev, wg_begin
+  float* dCoef = nullptr;    // 9 per-mode arrays
+  float* dState = nullptr;   // 4 per-unit arrays
+  float* dPart = nullptr;
+  unsigned int* dCtr = nullptr;
+  int* dFlags = nullptr;
+  long long* dStep = nullptr;
+  float* dE = nullptr;
+  StepParams P{};
+  hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
+  struct Graph {
+    int64_t n, stride;
+    float* y;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+};
+
+namespace {
+
+void free_ctx(modal_ctx* c) {
+  if (!c) return;
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  void* ptrs[] = {c->dH, c->dMeta, c->dCoef, c->dState, c->dPart, c->dCtr, c->dFlags, c->dStep, c->dE};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+}
+
+template <class T>
+int dalloc(T** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MODAL_ENOMEM : MODAL_EHIP,
+                                   std::string("hipMalloc: ") + hipGetErrorString(e));
+  return MODAL_OK;
+}
+
+// Stored rows per sweep (qs) and float4 loads per lane (J) for a row of nc
+// float4 columns: the pair that keeps the most lanes busy.
+void choose_sweep(int nt, int nc, int& qs, int& J) {
+  double best = -1;
+  qs = 1;
+  J = 4;
+  for (int j = 1; j <= 4; ++j) {
+    int q = (kWave * j) / nc;
+    if (q < 1) continue;
+    q = std::min(q, nt);
+    const double eff = (double)q * nc / (kWave * j);
+    if (eff > best + 1e-9) {
+      best = eff;
+      qs = q;
+      J = j;
+    }
+  }
+}
+
+int validate(const modal_desc* d) {
+  if (!d) return fail(MODAL_EINVAL, "desc is NULL");
+  if (d->batch < 1 || !d->inst) return fail(MODAL_EINVAL, "batch < 1 or inst NULL");
+  if (!(d->fs > 0) || !std::isfinite(d->fs)) return fail(MODAL_EINVAL, "fs must be > 0");
+  if (d->scheme != MODAL_SCHEME_SV && d->scheme != MODAL_SCHEME_TF)
+    return fail(MODAL_EINVAL, "unknown scheme");
+  if (d->reserved != 0 || d->max_workgroups < 0 || d->chunk_steps < 0)
+    return fail(MODAL_EINVAL, "reserved/max_workgroups/chunk_steps");
+  const double T = 1.0 / d->fs;
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    const std::string at = " (instance " + std::to_string(b) + ")";
+    if (I.kind < MODAL_KIND_LINEAR || I.kind > MODAL_KIND_VK) return fail(MODAL_EINVAL, "kind" + at);
+    if (I.n_t < 1 || I.n_t > kMaxModes) return fail(MODAL_EINVAL, "n_t outside 1..1024" + at);
+    if (I.reserved != 0) return fail(MODAL_EINVAL, "reserved must be 0" + at);
+    if (!I.omega || !I.gamma || !I.x0 || !I.xm1 || !I.c_out)
+      return fail(MODAL_EINVAL, "NULL per-mode array" + at);
+    if (!finite_all(I.omega, I.n_t) || !finite_all(I.gamma, I.n_t) || !finite_all(I.x0, I.n_t) ||
+        !finite_all(I.xm1, I.n_t) || !finite_all(I.c_out, I.n_t))
+      return fail(MODAL_EINVAL, "non-finite per-mode input" + at);
+    if (I.kind == MODAL_KIND_VK) {
+      if (I.n_in < 1 || !I.H) return fail(MODAL_EINVAL, "VK needs n_in >= 1 and H" + at);
+    } else if (I.n_in != 0) {
+      return fail(MODAL_EINVAL, "n_in must be 0 unless VK" + at);
+    }
+    if (I.kind == MODAL_KIND_TENSION) {
+      if (!I.lambda || !finite_all(I.lambda, I.n_t) || !std::isfinite(I.kappa))
+        return fail(MODAL_EINVAL, "TENSION needs finite lambda and kappa" + at);
+    }
+    if (I.n_exc < 0 || (I.n_exc > 0 && (!I.e_ext || !I.b_ext)))
+      return fail(MODAL_EINVAL, "forcing needs b_ext and e_ext" + at);
+    if (I.b_ext && !finite_all(I.b_ext, I.n_t)) return fail(MODAL_EINVAL, "non-finite b_ext" + at);
+    for (int64_t i = 0; i < I.n_exc; ++i)
+      if (!std::isfinite(I.e_ext[i])) return fail(MODAL_EINVAL, "non-finite e_ext" + at);
+    for (int k = 0; k < I.n_t; ++k) {
+      if (I.gamma[k] < 0) return fail(MODAL_EUNSTABLE, "gamma < 0" + at);
+      if (I.omega[k] < 0) return fail(MODAL_EINVAL, "omega < 0" + at);
+      if (d->scheme == MODAL_SCHEME_TF && !(I.omega[k] > I.gamma[k]))
+        return fail(MODAL_EUNSTABLE, "TF needs omega > gamma" + at);
+      if (!stable(coefficients(d->scheme, I.omega[k], I.gamma[k], T)))
+        return fail(MODAL_EUNSTABLE, "mode " + std::to_string(k) + " unstable" + at);
+    }
+  }
+  return MODAL_OK;
+}
+
+// LPT over `n_bins` workgroups: instances costlier than `thresh` are cut
+// into slabs of in-plane rows, every item goes to the least loaded bin.
+// Returns the makespan; fills units and their bins.
+double plan(const modal_desc* d, const std::vector<double>& row_cost,
+            const std::vector<double>& fixed_cost, double thresh, int n_bins,
+            std::vector<Unit>& units, std::vector<int>& bin_of, int& nslab_max) {
+  units.clear();
+  nslab_max = 1;
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    const int rows = I.kind == MODAL_KIND_VK ? I.n_in : 1;
+    const double total = fixed_cost[b] + rows * row_cost[b];
+    int S = 1;
+    if (I.kind == MODAL_KIND_VK && total > thresh) S = std::min(rows, (int)std::ceil(total / thresh));
+    S = std::min(S, n_bins);
+    nslab_max = std::max(nslab_max, S);
+    for (int s = 0; s < S; ++s) {
+      const int r0 = (int)((long long)rows * s / S), r1 = (int)((long long)rows * (s + 1) / S);
+      units.push_back({b, r0, r1, s, fixed_cost[b] + (r1 - r0) * row_cost[b]});
+    }
+  }
+  std::vector<int> order(units.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return units[a].cost > units[b].cost; });
+  using E = std::pair<double, int>;
+  std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
+  for (int i = 0; i < n_bins; ++i) heap.push({0.0, i});
+  bin_of.assign(units.size(), 0);
+  double makespan = 0;
+  for (int i : order) {
+    E e = heap.top();
+    heap.pop();
+    bin_of[i] = e.second;
+    e.first += units[i].cost;
+    makespan = std::max(makespan, e.first);
+    heap.push(e);
+  }
+  return makespan;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* modal_last_error(void) { return g_err.c_str(); }
+
+int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
+  if (!out) return fail(MODAL_EINVAL, "out is NULL");
+  *out = nullptr;
+  g_err.clear();
+  int rc = validate(d);
+  if (rc) return rc;
+  hipStream_t stream = (hipStream_t)stream_;
+  const double T = 1.0 / d->fs;
+  modal_ctx* c = new modal_ctx();
+  c->batch = d->batch;
+  c->scheme = d->scheme;
+  c->flags = d->flags;
+  c->fs = d->fs;
+  c->chunk = d->chunk_steps;
+
+  // ---------------- instance layout
+  std::vector<InstDev> inst(d->batch);
+  long long h_floats = 0, e_floats = 0;
+  int mode_floats = 0;
+  std::vector<double> row_cost(d->batch), fixed_cost(d->batch);
+  int red_floats = 0;
+  std::vector<int> qs_of(d->batch, 1), J_of(d->batch, 1);
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    InstDev& D = inst[b];
+    D.kind = I.kind;
+    D.nt = I.n_t;
+    D.nin = I.kind == MODAL_KIND_VK ? I.n_in : 0;
+    D.ntp = round4(I.n_t);
+    D.mode_off = mode_floats;
+    mode_floats += D.ntp;
+    D.kappa = (float)I.kappa;
+    D.out_row = b;
+    D.e_off = e_floats;
+    D.n_exc = I.n_exc;
+    e_floats += I.n_exc;
+    D.h_off = 0;
+    if (I.kind == MODAL_KIND_VK) {
+      D.h_off = h_floats;
+      const long long f = (long long)D.nin * D.nt * D.ntp;
+      h_floats += (f + 63) & ~63LL;  // 256-byte aligned instances
+      c->coupling_bytes += 4LL * D.nin * D.nt * D.nt;
+      c->padded_bytes += 4 * f;
+      choose_sweep(D.nt, D.ntp / 4, qs_of[b], J_of[b]);
+      red_floats = std::max(red_floats, 2 * qs_of[b] * D.ntp);
+      // bytes streamed per row plus the per-row reduction, in byte units
+      row_cost[b] = 4.0 * D.nt * D.ntp + 4096.0;
+      fixed_cost[b] = 8192.0;
+    } else {
+      row_cost[b] = 0;
+      fixed_cost[b] = 8192.0 + 64.0 * D.ntp;
+    }
+  }
+  c->mode_floats = mode_floats;
+  c->lds_bytes = sizeof(float) * (size_t)(kMaxModes + red_floats);
+
+  // ---------------- partition over co-resident workgroups
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  int occ = 0;
+  HIP_TRY(step_occupancy(&occ, c->lds_bytes));
+  if (occ < 1) {
+    free_ctx(c);
+    return fail(MODAL_EHIP, "step kernel does not fit on a CU");
+  }
+  c->occ = occ;
+  int n_bins = occ * prop.multiProcessorCount;
+  if (d->max_workgroups > 0) n_bins = std::min(n_bins, d->max_workgroups);
+  n_bins = std::max(1, std::min(n_bins, 1 << 20));
+  double total = 0;
+  for (int b = 0; b < d->batch; ++b)
+    total += fixed_cost[b] + (inst[b].kind == KIND_VK ? inst[b].nin : 1) * row_cost[b];
+  std::vector<Unit> units, best_units;
+  std::vector<int> bin_of, best_bin;
+  double best = 1e300;
+  int nslab_max = 1;
+  const double fr[] = {0.5, 0.75, 1.0, 1.25, 1.5, 2.0, 3.0, 1e30};
+  for (double f : fr) {
+    int ns = 1;
+    const double ms = plan(d, row_cost, fixed_cost, f * total / n_bins, n_bins, units, bin_of, ns);
+    if (ms < best * (1 - 1e-9)) {
+      best = ms;
+      best_units = units;
+      best_bin = bin_of;
+      nslab_max = ns;
+    }
+  }
+  units.swap(best_units);
+  bin_of.swap(best_bin);
+  // workgroups actually used, renumbered densely; within a workgroup split
+  // units come first so their partial forces are published early
+  std::vector<int> used(n_bins, -1);
+  int n_wg = 0;
+  for (size_t i = 0; i < units.size(); ++i)
+    if (used[bin_of[i]] < 0) used[bin_of[i]] = n_wg++;
+  std::vector<int> nslab(d->batch, 0);
+  for (auto& u : units) nslab[u.inst]++;
+  std::vector<int> order(units.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int wa = used[bin_of[a]], wb = used[bin_of[b]];
+    if (wa != wb) return wa < wb;
+    const bool sa = nslab[units[a].inst] > 1, sb = nslab[units[b].inst] > 1;
+    if (sa != sb) return sa;
+    return units[a].inst < units[b].inst;
+  });
+  std::vector<UnitDev> udev(units.size());
+  std::vector<int> wg_begin(n_wg + 1, 0);
+  int state_floats = 0;
+  c->unit_state_of_inst.assign(d->batch, -1);
+  for (size_t k = 0; k < order.size(); ++k) {
+    const Unit& u = units[order[k]];
+    UnitDev& U = udev[k];
+    U.inst = u.inst;
+    U.row0 = u.row0;
+    U.row1 = u.row1;
+    U.slab = u.slab;
+    U.state_off = state_floats;
+    if (c->unit_state_of_inst[u.inst] < 0) c->unit_state_of_inst[u.inst] = state_floats;
+    state_floats += inst[u.inst].ntp;
+    U.qs = qs_of[u.inst];
+    U.J = J_of[u.inst];
+    U.pad = 0;
+    wg_begin[used[bin_of[order[k]]] + 1] = (int)k + 1;
+  }
+  for (int w = 1; w <= n_wg; ++w) wg_begin[w] = std::max(wg_begin[w], wg_begin[w - 1]);
+  long long part_floats = 0;
+  for (int b = 0; b < d->batch; ++b) {
+    inst[b].nslab = nslab[b];
+    inst[b].part_off = part_floats;
+    if (nslab[b] > 1) {
+      part_floats += 2LL * nslab[b] * inst[b].ntp;
+      c->n_split++;
+    }
+  }
+  c->n_wg = n_wg;
+  c->n_units = (int)udev.size();
+  c->state_floats = state_floats;
+
+  // ---------------- coefficients, initial state
+  std::vector<float> coef(9 * (size_t)mode_floats, 0.f);
+  float *m_hi = &coef[0], *m_lo = m_hi + mode_floats, *p_hi = m_lo + mode_floats,
+        *p_lo = p_hi + mode_floats, *r_hi = p_lo + mode_floats, *r_lo = r_hi + mode_floats,
+        *cw = r_lo + mode_floats, *lam = cw + mode_floats, *bx = lam + mode_floats;
+  c->nt.resize(d->batch);
+  c->inst_mode_off.resize(d->batch);
+  std::vector<float> xinit(4 * (size_t)mode_floats, 0.f);
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    const int o = inst[b].mode_off;
+    c->nt[b] = I.n_t;
+    c->inst_mode_off[b] = o;
+    for (int k = 0; k < I.n_t; ++k) {
+      const Coef q = coefficients(d->scheme, I.omega[k], I.gamma[k], T);
+      split(q.m, m_hi[o + k], m_lo[o + k]);
+      split(q.p, p_hi[o + k], p_lo[o + k]);
+      split(q.r, r_hi[o + k], r_lo[o + k]);
+      cw[o + k] = (float)I.c_out[k];
+      lam[o + k] = I.lambda ? (float)I.lambda[k] : 0.f;
+      bx[o + k] = I.b_ext ? (float)I.b_ext[k] : 0.f;
+      split(I.x0[k], xinit[o + k], xinit[mode_floats + o + k]);
+      split(I.x0[k] - I.xm1[k], xinit[2 * mode_floats + o + k], xinit[3 * mode_floats + o + k]);
+    }
+  }
+  c->state0.assign(4 * (size_t)state_floats, 0.f);
+  for (const UnitDev& U : udev) {
+    const int o = inst[U.inst].mode_off, n = inst[U.inst].ntp;
+    for (int a = 0; a < 4; ++a)
+      std::memcpy(&c->state0[(size_t)a * state_floats + U.state_off], &xinit[(size_t)a * mode_floats + o],
+                  sizeof(float) * n);
+  }
+
+  // ---------------- device memory
+  const size_t meta_bytes = sizeof(InstDev) * d->batch + sizeof(UnitDev) * udev.size() +
+                            sizeof(int) * (n_wg + 1);
+#define ALLOC(p, bytes)                 \
+  do {                                  \
+    int r_ = dalloc(&(p), (bytes));     \
+    if (r_) {                           \
+      free_ctx(c);                      \
+      return r_;                        \
+    }                                   \
+  } while (0)
+  ALLOC(c->dH, sizeof(float) * (size_t)(h_floats + 64));
+  ALLOC(c->dMeta, meta_bytes);
+  ALLOC(c->dCoef, sizeof(float) * coef.size());
+  ALLOC(c->dState, sizeof(float) * c->state0.size());
+  ALLOC(c->dPart, sizeof(float) * (size_t)(part_floats + 64));
+  ALLOC(c->dCtr, sizeof(unsigned int) * d->batch);
+  ALLOC(c->dFlags, sizeof(int) * (2 + 2 * d->batch));
+  ALLOC(c->dStep, sizeof(long long));
+  ALLOC(c->dE, sizeof(float) * (size_t)(e_floats + 1));
+#undef ALLOC
+  auto bail = [&](int r) {
+    free_ctx(c);
+    return r;
+  };
+#define HIP_TRY_C(expr)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return bail(fail(MODAL_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)));   \
+  } while (0)
+  HIP_TRY_C(hipMemsetAsync(c->dH, 0, sizeof(float) * (size_t)(h_floats + 64), stream));
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    if (I.kind != MODAL_KIND_VK) continue;
+    HIP_TRY_C(hipMemcpy2DAsync(c->dH + inst[b].h_off, sizeof(float) * inst[b].ntp, I.H,
+                               sizeof(float) * I.n_t, sizeof(float) * I.n_t,
+                               (size_t)I.n_in * I.n_t, hipMemcpyDefault, stream));
+  }
+  char* meta = (char*)c->dMeta;
+  InstDev* dInst = (InstDev*)meta;
+  UnitDev* dUnit = (UnitDev*)(meta + sizeof(InstDev) * d->batch);
+  int* dWg = (int*)(meta + sizeof(InstDev) * d->batch + sizeof(UnitDev) * udev.size());
+  HIP_TRY_C(hipMemcpyAsync(dInst, inst.data(), sizeof(InstDev) * d->batch, hipMemcpyHostToDevice, stream));
+  HIP_TRY_C(hipMemcpyAsync(dUnit, udev.data(), sizeof(UnitDev) * udev.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY_C(hipMemcpyAsync(dWg, wg_begin.data(), sizeof(int) * (n_wg + 1), hipMemcpyHostToDevice, stream));
+  HIP_TRY_C(hipMemcpyAsync(c->dCoef, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice, stream));
+  {
+    std::vector<float> epool((size_t)e_floats + 1, 0.f);
+    for (int b = 0; b < d->batch; ++b)
+      if (d->inst[b].n_exc > 0)
+        std::memcpy(&epool[inst[b].e_off], d->inst[b].e_ext, sizeof(float) * d->inst[b].n_exc);
+    HIP_TRY_C(hipMemcpyAsync(c->dE, epool.data(), sizeof(float) * epool.size(), hipMemcpyHostToDevice, stream));
+    // symmetry / finiteness of the tensors
+    HIP_TRY_C(hipMemsetAsync(c->dFlags, 0, sizeof(int) * (2 + 2 * d->batch), stream));
+    HIP_TRY_C(launch_check(c->dH, dInst, d->batch, c->dFlags + 2, stream));
+    std::vector<int> chk(2 * d->batch);
+    HIP_TRY_C(hipMemcpyAsync(chk.data(), c->dFlags + 2, sizeof(int) * chk.size(), hipMemcpyDeviceToHost, stream));
+    HIP_TRY_C(hipStreamSynchronize(stream));
+    for (int b = 0; b < d->batch; ++b) {
+      if (inst[b].kind != KIND_VK) continue;
+      float dmax, hmax;
+      std::memcpy(&dmax, &chk[2 * b], 4);
+      std::memcpy(&hmax, &chk[2 * b + 1], 4);
+      if (!std::isfinite(dmax) || !std::isfinite(hmax))
+        return bail(fail(MODAL_EINVAL, "non-finite H (instance " + std::to_string(b) + ")"));
+      if (dmax > 1e-6f * hmax)
+        return bail(fail(MODAL_EINVAL, "H not symmetric in its last two indices (instance " +
+                                           std::to_string(b) + ")"));
+    }
+  }
+  StepParams& P = c->P;
+  P.inst = dInst;
+  P.unit = dUnit;
+  P.wg_begin = dWg;
+  P.H = c->dH;
+  P.m_hi = c->dCoef;
+  P.m_lo = P.m_hi + mode_floats;
+  P.p_hi = P.m_lo + mode_floats;
+  P.p_lo = P.p_hi + mode_floats;
+  P.r_hi = P.p_lo + mode_floats;
+  P.r_lo = P.r_hi + mode_floats;
+  P.c_out = P.r_lo + mode_floats;
+  P.lam = P.c_out + mode_floats;
+  P.b_ext = P.lam + mode_floats;
+  P.e_ext = c->dE;
+  P.x_hi = c->dState;
+  P.x_lo = P.x_hi + state_floats;
+  P.d_hi = P.x_lo + state_floats;
+  P.d_lo = P.d_hi + state_floats;
+  P.part = c->dPart;
+  P.ctr = c->dCtr;
+  P.flags = c->dFlags;
+  P.step_base = c->dStep;
+  P.red_floats = red_floats;
+#undef HIP_TRY_C
+  int r = modal_reset(c, stream_);
+  if (r) return bail(r);
+  HIP_TRY(hipStreamSynchronize(stream));
+  *out = c;
+  return MODAL_OK;
+}
+
+int modal_reset(modal_ctx* c, void* stream_) {
+  if (!c) return fail(MODAL_EINVAL, "ctx is NULL");
+  hipStream_t s = (hipStream_t)stream_;
+  HIP_TRY(hipMemcpyAsync(c->dState, c->state0.data(), sizeof(float) * c->state0.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(c->dCtr, 0, sizeof(unsigned int) * c->batch, s));
+  HIP_TRY(hipMemsetAsync(c->dFlags, 0, sizeof(int) * 2, s));
+  HIP_TRY(hipMemsetAsync(c->dStep, 0, sizeof(long long), s));
+  c->steps = 0;
+  return MODAL_OK;
+}
+
+static int enqueue_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, hipStream_t s) {
+  const int64_t chunk = c->chunk > 0 ? c->chunk : n_steps;
+  for (int64_t done = 0; done < n_steps; done += chunk) {
+    const int64_t k = std::min<int64_t>(chunk, n_steps - done);
+    StepParams P = c->P;
+    P.y = y + done;
+    P.y_stride = y_stride;
+    P.n_steps = (int)k;
+    HIP_TRY(launch_step(P, c->n_wg, c->lds_bytes, s));
+    HIP_TRY(launch_advance(c->dStep, (int)k, s));
+  }
+  return MODAL_OK;
+}
+
+int modal_check(modal_ctx* c, void* stream_) {
+  if (!c) return fail(MODAL_EINVAL, "ctx is NULL");
+  hipStream_t s = (hipStream_t)stream_;
+  int fl[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(fl, c->dFlags, sizeof(fl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (fl[0]) return fail(MODAL_EHANG, "a per-instance step barrier timed out");
+  if (fl[1]) return fail(MODAL_ENONFINITE, "a modal state became non-finite");
+  return MODAL_OK;
+}
+
+int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* stream_) {
+  if (!c) return fail(MODAL_EINVAL, "ctx is NULL");
+  if (n_steps < 0 || n_steps > (1LL << 31) - 1) return fail(MODAL_EINVAL, "n_steps out of range");
+  if (n_steps == 0) return MODAL_OK;
+  if (!y || y_stride < n_steps) return fail(MODAL_EINVAL, "y NULL or y_stride < n_steps");
+  hipStream_t s = (hipStream_t)stream_;
+  if (c->flags & MODAL_FLAG_GRAPH) {
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : c->graphs)
+      if (g.n == n_steps && g.y == y && g.stride == y_stride) exec = g.exec;
+    if (!exec) {
+      // The caller's stream may be the legacy default stream, which cannot
+      // be captured; record on a private stream and launch on the caller's.
+      if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      hipGraph_t graph;
+      HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      int r = enqueue_run(c, n_steps, y, y_stride, c->cap_stream);
+      hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+      if (r) return r;
+      if (e != hipSuccess) return fail(MODAL_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return fail(MODAL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      c->graphs.push_back({n_steps, y_stride, y, exec});
+    }
+    HIP_TRY(hipGraphLaunch(exec, s));
+  } else {
+    int r = enqueue_run(c, n_steps, y, y_stride, s);
+    if (r) return r;
+  }
+  c->steps += n_steps;
+  if (c->flags & MODAL_FLAG_ASYNC) return MODAL_OK;
+  return modal_check(c, stream_);
+}
+
+int modal_get_state(modal_ctx* c, double* x, double* xm1, void* stream_) {
+  if (!c || !x || !xm1) return fail(MODAL_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream_;
+  std::vector<float> st(c->state0.size());
+  HIP_TRY(hipMemcpyAsync(st.data(), c->dState, sizeof(float) * st.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const size_t S = c->state_floats;
+  size_t o = 0;
+  for (int b = 0; b < c->batch; ++b) {
+    const int so = c->unit_state_of_inst[b];
+    for (int k = 0; k < c->nt[b]; ++k, ++o) {
+      const double xv = (double)st[so + k] + (double)st[S + so + k];
+      const double dv = (double)st[2 * S + so + k] + (double)st[3 * S + so + k];
+      x[o] = xv;
+      xm1[o] = xv - dv;
+    }
+  }
+  return MODAL_OK;
+}
+
+int modal_info(const modal_ctx* c, int64_t info[8]) {
+  if (!c || !info) return fail(MODAL_EINVAL, "NULL argument");
+  info[0] = c->n_wg;
+  info[1] = c->n_units;
+  info[2] = c->n_split;
+  info[3] = c->coupling_bytes;
+  info[4] = c->padded_bytes;
+  info[5] = c->steps;
+  info[6] = (int64_t)c->lds_bytes;
+  info[7] = c->occ;
+  return MODAL_OK;
+}
+
+void modal_destroy(modal_ctx* c) { free_ctx(c); }
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+"""ctypes binding of libmodal.so (argument marshalling only).
+
+Every step of the time loop runs in the library's HIP kernels; this module
+converts numpy / torch arguments to the C structures of ``include/modal.h``.
+Importing it without the built library raises immediately: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmodal.so")
+
+KIND = {"linear": 0, "tension": 1, "vk": 2}
+SCHEME = {"sv": 0, "tf": 1}
+FLAG_ASYNC = 1
+FLAG_GRAPH = 2
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSTABLE", -3: "ENOMEM", -4: "EHIP",
+          -5: "ENONFINITE", -6: "ESTATE", -7: "EHANG"}
+
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+_ip = C.POINTER(C.c_int32)
+
+
+class modal_instance(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_t", C.c_int32), ("n_in", C.c_int32),
+                ("reserved", C.c_int32), ("omega", _dp), ("gamma", _dp), ("lam", _dp),
+                ("kappa", C.c_double), ("H", _fp), ("x0", _dp), ("xm1", _dp),
+                ("b_ext", _dp), ("e_ext", _fp), ("n_exc", C.c_int64), ("c_out", _dp)]
+
+
+class modal_desc(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("scheme", C.c_int32),
+                ("inst", C.POINTER(modal_instance)), ("fs", C.c_double),
+                ("flags", C.c_int32), ("max_workgroups", C.c_int32),
+                ("chunk_steps", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ModalError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2505_05940_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.modal_init.argtypes = [C.POINTER(vp), C.POINTER(modal_desc), vp]
+    lib.modal_run.argtypes = [vp, C.c_int64, _fp, C.c_int64, vp]
+    lib.modal_check.argtypes = [vp, vp]
+    lib.modal_reset.argtypes = [vp, vp]
+    lib.modal_get_state.argtypes = [vp, _dp, _dp, vp]
+    lib.modal_info.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.modal_destroy.argtypes = [vp]
+    lib.modal_destroy.restype = None
+    lib.modal_last_error.restype = C.c_char_p
+    lib.modal_vk_coupling_sine.argtypes = [C.c_double, C.c_double, C.c_int32, _ip, _ip,
+                                           C.c_int32, _ip, _ip, C.c_int32, C.c_int32,
+                                           _dp, _fp, C.c_int32]
+    for f in ("modal_init", "modal_run", "modal_check", "modal_reset", "modal_get_state",
+              "modal_info", "modal_vk_coupling_sine"):
+        getattr(lib, f).restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _check(code):
+    if code != 0:
+        raise ModalError(code, lib.modal_last_error().decode())
+
+
+def _d(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None:
+        assert a.shape == (n,), (a.shape, n)
+    return a
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def vk_coupling_sine(Lx, Ly, m, q, a, b, scale_n, grid=None, threads=0):
+    """Scaled sine-family coupling tensor [n_in, n_t, n_t] (float32) from the
+    library's host builder; grid None = exact integrals."""
+    m = np.ascontiguousarray(m, np.int32)
+    q = np.ascontiguousarray(q, np.int32)
+    a = np.ascontiguousarray(a, np.int32)
+    b = np.ascontiguousarray(b, np.int32)
+    sc = _d(scale_n, len(a))
+    out = np.empty((len(a), len(m), len(m)), np.float32)
+    nx, ny = (0, 0) if grid is None else grid
+    _check(lib.modal_vk_coupling_sine(
+        Lx, Ly, len(m), m.ctypes.data_as(_ip), q.ctypes.data_as(_ip), len(a),
+        a.ctypes.data_as(_ip), b.ctypes.data_as(_ip), nx, ny,
+        sc.ctypes.data_as(_dp), out.ctypes.data_as(_fp), threads))
+    return out
+
+
+class Sim:
+    """A batch of modal systems resident on the GPU (``modal_init``).
+
+    ``instances``: list of dicts with keys kind ('linear' | 'tension' | 'vk'),
+    omega, gamma, x0, xm1, c [n_t]; lam, kappa (tension); Ht float32
+    [n_in, n_t, n_t] (vk, host numpy or a CUDA tensor); optional b_ext [n_t]
+    and e_ext [n_exc] (float32).
+    """
+
+    def __init__(self, instances, fs, scheme="sv", flags=0, max_workgroups=0,
+                 chunk_steps=0, stream=None):
+        self._ctx = C.c_void_p()
+        self.batch = len(instances)
+        keep = []
+        arr = (modal_instance * self.batch)()
+        self.n_t = []
+        for i, inst in enumerate(instances):
+            n = len(inst["omega"])
+            self.n_t.append(n)
+            s = arr[i]
+            s.kind = KIND[inst["kind"]]
+            s.n_t = n
+            s.reserved = 0
+            for field, key in (("omega", "omega"), ("gamma", "gamma"), ("x0", "x0"),
+                               ("xm1", "xm1"), ("c_out", "c")):
+                a = _d(inst[key], n)
+                keep.append(a)
+                setattr(s, field, a.ctypes.data_as(_dp))
+            if inst["kind"] == "tension":
+                if inst.get("lam") is not None:
+                    a = _d(inst["lam"], n)
+                    keep.append(a)
+                    s.lam = a.ctypes.data_as(_dp)
+                s.kappa = float(inst["kappa"])
+            if inst["kind"] == "vk":
+                H = inst["Ht"]
+                if hasattr(H, "data_ptr"):
+                    assert H.dtype.itemsize == 4 and H.is_contiguous() and tuple(H.shape) == (H.shape[0], n, n)
+                    s.H = C.cast(C.c_void_p(H.data_ptr()), _fp)
+                    s.n_in = H.shape[0]
+                else:
+                    H = np.ascontiguousarray(H, dtype=np.float32)
+                    assert H.ndim == 3 and H.shape[1:] == (n, n)
+                    s.H = H.ctypes.data_as(_fp)
+                    s.n_in = H.shape[0]
+                keep.append(H)
+            else:
+                s.n_in = 0
+            if inst.get("e_ext") is not None:
+                b = _d(inst["b_ext"], n)
+                e = np.ascontiguousarray(inst["e_ext"], dtype=np.float32)
+                keep += [b, e]
+                s.b_ext = b.ctypes.data_as(_dp)
+                s.e_ext = e.ctypes.data_as(_fp)
+                s.n_exc = len(e)
+        desc = modal_desc(batch=self.batch, scheme=SCHEME[scheme], inst=arr, fs=float(fs),
+                          flags=flags, max_workgroups=max_workgroups,
+                          chunk_steps=chunk_steps, reserved=0)
+        self._stream = stream
+        _check(lib.modal_init(C.byref(self._ctx), C.byref(desc), _stream_handle(stream)))
+        self.modes_total = sum(self.n_t)
+
+    def run(self, n_steps, out=None):
+        """Advance by n_steps; returns y [batch, n_steps] float32 on the GPU."""
+        import torch
+        if out is None:
+            out = torch.empty((self.batch, n_steps), dtype=torch.float32, device="cuda")
+        assert out.dtype == torch.float32 and out.is_cuda and out.shape[0] == self.batch
+        assert out.stride(1) == 1 and out.shape[1] >= n_steps
+        _check(lib.modal_run(self._ctx, n_steps, C.cast(C.c_void_p(out.data_ptr()), _fp),
+                             out.stride(0), _stream_handle(self._stream)))
+        return out
+
+    def check(self):
+        _check(lib.modal_check(self._ctx, _stream_handle(self._stream)))
+
+    def reset(self):
+        _check(lib.modal_reset(self._ctx, _stream_handle(self._stream)))
+
+    def state(self):
+        x = np.empty(self.modes_total)
+        xm = np.empty(self.modes_total)
+        _check(lib.modal_get_state(self._ctx, x.ctypes.data_as(_dp), xm.ctypes.data_as(_dp),
+                                   _stream_handle(self._stream)))
+        return x, xm
+
+    def info(self):
+        v = (C.c_int64 * 8)()
+        _check(lib.modal_info(self._ctx, v))
+        keys = ("workgroups", "units", "split_instances", "coupling_bytes_per_step",
+                "padded_bytes_per_step", "steps", "lds_bytes", "workgroups_per_cu")
+        return dict(zip(keys, list(v)))
+
+    def close(self):
+        if self._ctx:
+            lib.modal_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -44,12 +44,15 @@ def string_kc(seed: int = 1, n_modes: int = 30, n_steps: int = 22050) -> dict:
 
 def plate_vk(seed: int = 2, n_t: int = 40, n_in: int | None = None,
              n_steps: int = 44100, family: str = "clamped",
-             grid=(200, 150)) -> dict:
+             grid=(200, 150), proj_grid=None) -> dict:
     """Single von Karman plate, 0.4 x 0.3 m steel, 1 mm, simply supported.
 
     Strike: raised-cosine initial displacement of seeded height in
     [0.5 h, 3 h] and radius 0.1 min(Lx, Ly); strike centre and output point
     drawn independently in [0.1, 0.9] x (Lx, Ly).  No pre-tension.
+    ``grid``: midpoint grid of the coupling integrals (None = exact, sine
+    family only); ``proj_grid``: grid of the strike projection (default: the
+    coupling grid, else 200 x 150).
     """
     rng = np.random.default_rng(seed)
     h = 1e-3
@@ -60,11 +63,12 @@ def plate_vk(seed: int = 2, n_t: int = 40, n_in: int | None = None,
     return dict(
         family="plate", model="vk", inplane=family, Lx=Lx, Ly=Ly, h=h,
         T0=0.0, **STEEL, n_t=n_t, n_in=n_t if n_in is None else n_in,
-        fs=FS, n_steps=n_steps, grid=tuple(grid),
+        fs=FS, n_steps=n_steps, grid=None if grid is None else tuple(grid),
         damping=("affine_omega", 1.0, 0.002),
         strike=dict(xc=cx * Lx, yc=cy * Ly, amplitude=amp,
                     radius=0.1 * min(Lx, Ly)),
-        out=(ox * Lx, oy * Ly), proj_grid=tuple(grid),
+        out=(ox * Lx, oy * Ly),
+        proj_grid=tuple(proj_grid or grid or (200, 150)),
     )
 
 
