@@ -44,10 +44,12 @@ def measured_traffic(samples_per_step):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(wls, n_inst, n_steps, seed):
+def cpu_baseline(wls, n_inst, seconds, seed):
     """The FP64 oracle's time loop on a seeded sample of the batch (its
-    coupling tensors built beforehand, untimed).  Rate = sum N x steps / time
-    over the sample (a ratio estimator of the whole batch's rate)."""
+    coupling tensors built beforehand, untimed).  Each sampled instance runs
+    for about ``seconds / n_inst`` seconds from its initial state (the step
+    count set from a 5-step probe).  Rate = sum N x steps / time over the
+    sample, a ratio estimator of the whole batch's rate."""
     from oracle import instances as OI
     from oracle import simulate as OS
     try:
@@ -57,17 +59,22 @@ def cpu_baseline(wls, n_inst, n_steps, seed):
         cores = os.cpu_count()
     rng = np.random.default_rng(seed)
     pick = sorted(rng.choice(len(wls), size=n_inst, replace=False).tolist())
-    work, secs = 0, 0.0
+    work, secs, steps_used = 0, 0.0, []
     for i in pick:
         inst = OI.plate_instance(wls[i])
+        t0 = time.perf_counter()
+        OS.run(inst, 5, wls[i]["fs"])
+        per = (time.perf_counter() - t0) / 5
+        n_steps = int(max(20, min(44100, seconds / n_inst / per)))
         t0 = time.perf_counter()
         OS.run(inst, n_steps, wls[i]["fs"])
         secs += time.perf_counter() - t0
         work += wls[i]["n_t"] * n_steps
+        steps_used.append(n_steps)
     return dict(value=work / secs, unit="instance*mode*samples/s", cores=int(cores),
                 kind="oracle",
                 sample=f"instances {pick} (N={[wls[i]['n_t'] for i in pick]}) of the batch, "
-                       f"{n_steps} steps each, FP64 numpy time loop, {secs:.1f} s")
+                       f"{steps_used} steps each from rest, FP64 numpy time loop, {secs:.1f} s")
 
 
 def main():
@@ -81,7 +88,7 @@ def main():
     ap.add_argument("--max-workgroups", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-instances", type=int, default=3)
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -171,7 +178,7 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wls, args.cpu_instances, args.cpu_steps, args.seed)
+        out["cpu_baseline"] = cpu_baseline(wls, args.cpu_instances, args.cpu_seconds, args.seed)
     print(json.dumps(out))
 
 

@@ -134,8 +134,10 @@ int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
  * [3] coupling bytes read per step (sum over VK instances of
  * 4 n_in n_t n_t), [4] bytes of the padded device layout streamed per step,
  * [5] steps taken so far, [6] dynamic LDS bytes per workgroup,
- * [7] co-resident workgroups per CU used for the plan. */
-int modal_info(const modal_ctx *c, int64_t info[8]);
+ * [7] co-resident workgroups per CU used for the plan, [8] planned cost of
+ * the most loaded workgroup and [9] the mean planned cost per co-resident
+ * workgroup (both in streamed-byte units). */
+int modal_info(const modal_ctx *c, int64_t info[10]);
 
 void modal_destroy(modal_ctx *c);
 

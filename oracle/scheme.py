@@ -13,13 +13,13 @@ import numpy as np
 
 def omega_from(lam, D, T0, rho_s):
     """Angular frequency omega = sqrt((D lambda^2 + T0 lambda) / rho_s)."""
-    lam = np.asarray(lam, dtype=float)
+    lam = np.asarray(lam) * 1.0
     return np.sqrt((D * lam ** 2 + T0 * lam) / rho_s)
 
 
 def gamma_from_d(lam, d1, d3, rho_s):
     """Decay rate gamma = (d1 + d3 lambda) / (2 rho_s)."""
-    return (d1 + d3 * np.asarray(lam, dtype=float)) / (2.0 * rho_s)
+    return (d1 + d3 * np.asarray(lam)) / (2.0 * rho_s)
 
 
 def gamma_affine_omega(omega, g0, g1):
@@ -34,8 +34,8 @@ def sv_coefficients(omega, gamma, T):
         g = r (2 / T^2 - omega^2)
         p = r (-1 / T^2 + 2 gamma / (2 T)).
     """
-    omega = np.asarray(omega, dtype=float)
-    gamma = np.asarray(gamma, dtype=float)
+    omega = np.asarray(omega) * 1.0  # real or complex (complex-step checks)
+    gamma = np.asarray(gamma) * 1.0
     r = 2.0 * T * T / (2.0 + 2.0 * gamma * T)
     g = r * (2.0 / (T * T) - omega ** 2)
     p = r * (-1.0 / (T * T) + 2.0 * gamma / (2.0 * T))

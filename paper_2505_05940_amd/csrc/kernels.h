@@ -7,6 +7,7 @@ namespace modal {
 constexpr int kWave = 64;        // CDNA wavefront width; one wave per workgroup
 constexpr int kMaxModes = 1024;  // per instance
 constexpr int kMaxGroups = kMaxModes / 4 / kWave;  // float4 groups per lane
+constexpr int kSweepLoads = 4;  // float4 loads per lane per sweep of Ht rows
 
 enum : int { KIND_LINEAR = 0, KIND_TENSION = 1, KIND_VK = 2 };
 
@@ -30,7 +31,7 @@ struct UnitDev {
   int inst, row0, row1, slab;
   int state_off;  // offset into the per-unit state arrays (multiple of 4)
   int qs;         // stored rows of Ht[n] per sweep of the wave
-  int J;          // float4 loads per lane per sweep
+  int J;          // float4 loads per lane per sweep (kSweepLoads)
   int pad;
 };
 

@@ -13,10 +13,10 @@
 #include "kernels.h"
 
 namespace modal {
-hipError_t launch_step(const StepParams& P, int n_wg, size_t lds_bytes, hipStream_t s);
+hipError_t launch_step(const StepParams& P, int gm, int n_wg, size_t lds_bytes, hipStream_t s);
 hipError_t launch_advance(long long* step_base, int n, hipStream_t s);
 hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s);
-hipError_t step_occupancy(int* blocks_per_cu, size_t lds_bytes);
+hipError_t step_occupancy(int* blocks_per_cu, int gm, size_t lds_bytes);
 }  // namespace modal
 
 using namespace modal;
@@ -98,7 +98,8 @@ struct Unit {
 struct modal_ctx {
   int batch = 0, scheme = 0, flags = 0, chunk = 0;
   double fs = 0;
-  int n_wg = 0, n_units = 0, n_split = 0, occ = 0;
+  int n_wg = 0, n_units = 0, n_split = 0, occ = 0, gm = 1;
+  double makespan = 0, mean_load = 0;
   size_t lds_bytes = 0;
   long long coupling_bytes = 0, padded_bytes = 0, steps = 0;
   int state_floats = 0, mode_floats = 0;
@@ -145,23 +146,11 @@ int dalloc(T** p, size_t bytes) {
   return MODAL_OK;
 }
 
-// Stored rows per sweep (qs) and float4 loads per lane (J) for a row of nc
-// float4 columns: the pair that keeps the most lanes busy.
+// Stored rows of a tensor row swept at once: as many as kSweepLoads float4
+// loads per lane cover (nc float4 columns each), at most nt.
 void choose_sweep(int nt, int nc, int& qs, int& J) {
-  double best = -1;
-  qs = 1;
-  J = 4;
-  for (int j = 1; j <= 4; ++j) {
-    int q = (kWave * j) / nc;
-    if (q < 1) continue;
-    q = std::min(q, nt);
-    const double eff = (double)q * nc / (kWave * j);
-    if (eff > best + 1e-9) {
-      best = eff;
-      qs = q;
-      J = j;
-    }
-  }
+  J = kSweepLoads;
+  qs = std::max(1, std::min(nt, (kWave * J) / nc));
 }
 
 int validate(const modal_desc* d) {
@@ -251,6 +240,79 @@ double plan(const modal_desc* d, const std::vector<double>& row_cost,
   return makespan;
 }
 
+// Copies every instance's Ht into the padded device layout (rows of ntp
+// floats).  Device sources are copied directly; host sources are padded into
+// two pinned staging buffers that alternate with the asynchronous copies.
+int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>& inst,
+                   hipStream_t stream) {
+  const size_t kStage = 64u << 20;
+  float* stage[2] = {nullptr, nullptr};
+  hipEvent_t done[2] = {nullptr, nullptr};
+  int rc = MODAL_OK;
+  auto cleanup = [&]() {
+    for (int i = 0; i < 2; ++i) {
+      if (done[i]) (void)hipEventDestroy(done[i]);
+      if (stage[i]) (void)hipHostFree(stage[i]);
+    }
+  };
+#define UP_TRY(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      rc = fail(MODAL_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+      cleanup();                                                                       \
+      return rc;                                                                       \
+    }                                                                                  \
+  } while (0)
+  int slot = 0;
+  bool used[2] = {false, false};
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    if (I.kind != MODAL_KIND_VK) continue;
+    const InstDev& D = inst[b];
+    hipPointerAttribute_t attr;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&attr, I.H) == hipSuccess)
+      on_device = attr.type == hipMemoryTypeDevice;
+    else
+      (void)hipGetLastError();
+    if (on_device) {
+      UP_TRY(hipMemcpy2DAsync(c->dH + D.h_off, sizeof(float) * D.ntp, I.H, sizeof(float) * D.nt,
+                              sizeof(float) * D.nt, (size_t)D.nin * D.nt, hipMemcpyDeviceToDevice,
+                              stream));
+      continue;
+    }
+    if (!stage[0]) {
+      for (int i = 0; i < 2; ++i) {
+        UP_TRY(hipHostMalloc((void**)&stage[i], kStage, hipHostMallocDefault));
+        UP_TRY(hipEventCreateWithFlags(&done[i], hipEventDisableTiming));
+      }
+    }
+    const size_t rows = (size_t)D.nin * D.nt;
+    const size_t rows_per = std::max<size_t>(1, kStage / (sizeof(float) * D.ntp));
+    for (size_t r0 = 0; r0 < rows; r0 += rows_per) {
+      const size_t nr = std::min(rows_per, rows - r0);
+      if (used[slot]) UP_TRY(hipEventSynchronize(done[slot]));
+      float* dst = stage[slot];
+      for (size_t r = 0; r < nr; ++r) {
+        std::memcpy(dst + r * D.ntp, I.H + (r0 + r) * D.nt, sizeof(float) * D.nt);
+        for (int k = D.nt; k < D.ntp; ++k) dst[r * D.ntp + k] = 0.f;
+      }
+      UP_TRY(hipMemcpyAsync(c->dH + D.h_off + r0 * D.ntp, dst, sizeof(float) * nr * D.ntp,
+                            hipMemcpyHostToDevice, stream));
+      UP_TRY(hipEventRecord(done[slot], stream));
+      used[slot] = true;
+      slot ^= 1;
+    }
+  }
+  if (stage[0]) {
+    UP_TRY(hipStreamSynchronize(stream));
+  }
+#undef UP_TRY
+  cleanup();
+  return MODAL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -312,6 +374,10 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   }
   c->mode_floats = mode_floats;
   c->lds_bytes = sizeof(float) * (size_t)(kMaxModes + red_floats);
+  for (int b = 0; b < d->batch; ++b) {
+    const int g = (inst[b].ntp / 4 + kWave - 1) / kWave;
+    c->gm = std::max(c->gm, g <= 1 ? 1 : (g <= 2 ? 2 : 4));
+  }
 
   // ---------------- partition over co-resident workgroups
   int dev = 0;
@@ -319,7 +385,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, dev));
   int occ = 0;
-  HIP_TRY(step_occupancy(&occ, c->lds_bytes));
+  HIP_TRY(step_occupancy(&occ, c->gm, c->lds_bytes));
   if (occ < 1) {
     free_ctx(c);
     return fail(MODAL_EHIP, "step kernel does not fit on a CU");
@@ -348,6 +414,8 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   }
   units.swap(best_units);
   bin_of.swap(best_bin);
+  c->makespan = best;
+  c->mean_load = total / n_bins;
   // workgroups actually used, renumbered densely; within a workgroup split
   // units come first so their partial forces are published early
   std::vector<int> used(n_bins, -1);
@@ -463,12 +531,9 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
       return bail(fail(MODAL_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)));   \
   } while (0)
   HIP_TRY_C(hipMemsetAsync(c->dH, 0, sizeof(float) * (size_t)(h_floats + 64), stream));
-  for (int b = 0; b < d->batch; ++b) {
-    const modal_instance& I = d->inst[b];
-    if (I.kind != MODAL_KIND_VK) continue;
-    HIP_TRY_C(hipMemcpy2DAsync(c->dH + inst[b].h_off, sizeof(float) * inst[b].ntp, I.H,
-                               sizeof(float) * I.n_t, sizeof(float) * I.n_t,
-                               (size_t)I.n_in * I.n_t, hipMemcpyDefault, stream));
+  {
+    int r = upload_tensors(c, d, inst, stream);
+    if (r) return bail(r);
   }
   char* meta = (char*)c->dMeta;
   InstDev* dInst = (InstDev*)meta;
@@ -554,7 +619,7 @@ static int enqueue_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride
     P.y = y + done;
     P.y_stride = y_stride;
     P.n_steps = (int)k;
-    HIP_TRY(launch_step(P, c->n_wg, c->lds_bytes, s));
+    HIP_TRY(launch_step(P, c->gm, c->n_wg, c->lds_bytes, s));
     HIP_TRY(launch_advance(c->dStep, (int)k, s));
   }
   return MODAL_OK;
@@ -626,7 +691,7 @@ int modal_get_state(modal_ctx* c, double* x, double* xm1, void* stream_) {
   return MODAL_OK;
 }
 
-int modal_info(const modal_ctx* c, int64_t info[8]) {
+int modal_info(const modal_ctx* c, int64_t info[10]) {
   if (!c || !info) return fail(MODAL_EINVAL, "NULL argument");
   info[0] = c->n_wg;
   info[1] = c->n_units;
@@ -636,6 +701,8 @@ int modal_info(const modal_ctx* c, int64_t info[8]) {
   info[5] = c->steps;
   info[6] = (int64_t)c->lds_bytes;
   info[7] = c->occ;
+  info[8] = (int64_t)c->makespan;
+  info[9] = (int64_t)c->mean_load;
   return MODAL_OK;
 }
 

@@ -128,73 +128,66 @@ __device__ bool wait_counter(unsigned int* ctr, unsigned int target, int* flags)
 
 // -------------------------------------------------------- von Karman rows
 // Rows [row0, row1) of one instance's Ht.  Row n is an nt x ntp matrix
-// (nc = ntp/4 float4 per stored row).  The wave sweeps it qs stored rows at
-// a time: lane slot v = lane + 64 j (j < J) reads float4 number v of the
-// contiguous block of qs rows, i.e. stored row q0 + v / nc, columns
-// 4 (v % nc) .. +3, so each sweep is one contiguous, fully coalesced read.
-// Slot accumulators are reduced over the qs sub-rows through LDS (double
-// buffered by row parity, one wave barrier per row), giving V[n, :] on the
-// lanes that own each float4 column group (k4 = lane + 64 g).
-template <int J>
+// (nc = ntp/4 float4 per stored row), read as consecutive blocks of qs
+// stored rows.  A block is contiguous, so lane slot v = lane + 64 j
+// (j < kSweepLoads) simply reads float4 number v of the block: stored row
+// q0 + v / nc, columns 4 (v % nc) .. +3.  Each sweep is one fully coalesced
+// 4 KB read per wave.  Slot accumulators are reduced over the qs sub-rows
+// through LDS (double buffered by row parity, one wave barrier per row),
+// giving V[n, :] on the lanes that own each float4 column group
+// (k4 = lane + 64 g); then eta_n and the force update follow.
+template <int GM>
 __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, int row0,
-                        int row1, const float* Xs, float* red, float4 (&Fa)[kMaxGroups],
-                        int G, int lane) {
+                        int row1, const float* Xs, float* red, float4 (&Fa)[GM], int G,
+                        int lane) {
+  constexpr int J = kSweepLoads;
   const int nc = ntp >> 2;
   const int qsnc = qs * nc;
-  int vsub[J], voff[J];
-  bool vok[J];
+  int xsub[J];  // sub-row of slot j within a block, -1 if the slot is idle
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int v = lane + kWave * j;
-    vok[j] = v < qsnc;
-    vsub[j] = vok[j] ? v / nc : 0;
-    voff[j] = vok[j] ? vsub[j] * ntp + 4 * (v % nc) : 0;  // offset in the block
+    xsub[j] = v < qsnc ? v / nc : -1;
   }
   const int nfull = nt / qs;
   const int tail = nt - nfull * qs;
+  const long long blk_floats = (long long)qs * ntp;
   const long long row_floats = (long long)nt * ntp;
-  for (int n = row0; n < row1; ++n) {
-    const float* Hn = Hb + (long long)n * row_floats;
+  const float* rowp = Hb + (long long)row0 * row_floats + 4 * lane;
+  for (int n = row0; n < row1; ++n, rowp += row_floats) {
     float4 acc[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
-    const float* blk = Hn;
+    const float* p = rowp;
     int q0 = 0;
 #pragma unroll 2
-    for (int b = 0; b < nfull; ++b) {
-      float4 h[J];
-      float x[J];
+    for (int b = 0; b < nfull; ++b, p += blk_floats, q0 += qs) {
 #pragma unroll
       for (int j = 0; j < J; ++j) {
-        if (vok[j]) {
-          h[j] = ldnt4(blk + voff[j]);
-          x[j] = Xs[q0 + vsub[j]];
+        if (xsub[j] >= 0) {
+          const float4 h = ldnt4(p + 4 * kWave * j);
+          acc[j] = fma4(h, Xs[q0 + xsub[j]], acc[j]);
         }
       }
-#pragma unroll
-      for (int j = 0; j < J; ++j)
-        if (vok[j]) acc[j] = fma4(h[j], x[j], acc[j]);
-      blk += (long long)qs * ntp;
-      q0 += qs;
     }
     if (tail) {
 #pragma unroll
       for (int j = 0; j < J; ++j) {
-        if (vok[j] && vsub[j] < tail) {
-          float4 h = ldnt4(blk + voff[j]);
-          acc[j] = fma4(h, Xs[q0 + vsub[j]], acc[j]);
+        if (xsub[j] >= 0 && xsub[j] < tail) {
+          const float4 h = ldnt4(p + 4 * kWave * j);
+          acc[j] = fma4(h, Xs[q0 + xsub[j]], acc[j]);
         }
       }
     }
     float* rb = red + (n & 1) * qs * ntp;
 #pragma unroll
     for (int j = 0; j < J; ++j)
-      if (vok[j]) st4(rb + voff[j], acc[j]);
+      if (xsub[j] >= 0) st4(rb + 4 * (lane + kWave * j), acc[j]);
     __syncthreads();
     float eta = 0.f;
-    float4 V[kMaxGroups];
+    float4 V[GM];
 #pragma unroll
-    for (int g = 0; g < kMaxGroups; ++g) {
+    for (int g = 0; g < GM; ++g) {
       V[g] = f4(0.f);
       const int k4 = lane + kWave * g;
       if (g < G && k4 < nc) {
@@ -206,20 +199,21 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
     }
     eta = wave_sum(eta);
 #pragma unroll
-    for (int g = 0; g < kMaxGroups; ++g) Fa[g] = fma4(V[g], eta, Fa[g]);
+    for (int g = 0; g < GM; ++g) Fa[g] = fma4(V[g], eta, Fa[g]);
   }
 }
 
 // Per-mode state update of the float4 groups owned by this lane.
+template <int GM>
 __device__ __forceinline__ void update_groups(const StepParams& P, const InstDev& I, int soff,
-                                              const float4 (&F)[kMaxGroups], long long n,
+                                              const float4 (&F)[GM], long long n,
                                               int G, int lane) {
   const int nc = I.ntp >> 2;
   float e = 0.f;
   if (n < I.n_exc) e = P.e_ext[I.e_off + n];
   bool bad = false;
 #pragma unroll
-  for (int g = 0; g < kMaxGroups; ++g) {
+  for (int g = 0; g < GM; ++g) {
     const int k4 = lane + kWave * g;
     if (g < G && k4 < nc) {
       const int so = soff + 4 * k4;
@@ -245,13 +239,8 @@ __device__ __forceinline__ void update_groups(const StepParams& P, const InstDev
   if (__any(bad) && lane == 0) atomicOr(&P.flags[1], 1);
 }
 
-template <int J>
-__device__ __forceinline__ void vk_dispatch_rows(const StepParams& P, const InstDev& I,
-                                                 const UnitDev& U, const float* Xs, float* red,
-                                                 float4 (&Fa)[kMaxGroups], int G, int lane) {
-  vk_rows<J>(P.H + I.h_off, I.nt, I.ntp, U.qs, U.row0, U.row1, Xs, red, Fa, G, lane);
-}
-
+// GM: float4 column groups per lane the launch supports (modes <= 256 GM).
+template <int GM>
 __global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
   extern __shared__ float4 lds4[];
   float* Xs = reinterpret_cast<float*>(lds4);
@@ -271,7 +260,7 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
       const int G = (nc + kWave - 1) / kWave;
       float ypart = 0.f, spart = 0.f;
 #pragma unroll
-      for (int g = 0; g < kMaxGroups; ++g) {
+      for (int g = 0; g < GM; ++g) {
         const int k4 = lane + kWave * g;
         if (g < G && k4 < nc) {
           const float4 xh = ld4(P.x_hi + U.state_off + 4 * k4);
@@ -290,21 +279,16 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
         const float yv = wave_sum(ypart);
         if (lane == 0) P.y[(long long)I.out_row * P.y_stride + s] = yv;
       }
-      float4 Fa[kMaxGroups];
+      float4 Fa[GM];
 #pragma unroll
-      for (int g = 0; g < kMaxGroups; ++g) Fa[g] = f4(0.f);
+      for (int g = 0; g < GM; ++g) Fa[g] = f4(0.f);
       if (I.kind == KIND_VK) {
         __syncthreads();
-        switch (U.J) {
-          case 1: vk_dispatch_rows<1>(P, I, U, Xs, red, Fa, G, lane); break;
-          case 2: vk_dispatch_rows<2>(P, I, U, Xs, red, Fa, G, lane); break;
-          case 3: vk_dispatch_rows<3>(P, I, U, Xs, red, Fa, G, lane); break;
-          default: vk_dispatch_rows<4>(P, I, U, Xs, red, Fa, G, lane); break;
-        }
+        vk_rows<GM>(P.H + I.h_off, I.nt, I.ntp, U.qs, U.row0, U.row1, Xs, red, Fa, G, lane);
       } else if (I.kind == KIND_TENSION) {
         const float S = wave_sum(spart) * I.kappa;
 #pragma unroll
-        for (int g = 0; g < kMaxGroups; ++g) {
+        for (int g = 0; g < GM; ++g) {
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc) {
             const float4 xh = ld4(P.x_hi + U.state_off + 4 * k4);
@@ -314,11 +298,11 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
         }
       }
       if (I.nslab == 1) {
-        update_groups(P, I, U.state_off, Fa, n, G, lane);
+        update_groups<GM>(P, I, U.state_off, Fa, n, G, lane);
       } else {
         float* dst = P.part + I.part_off + ((long long)(n & 1) * I.nslab + U.slab) * I.ntp;
 #pragma unroll
-        for (int g = 0; g < kMaxGroups; ++g) {
+        for (int g = 0; g < GM; ++g) {
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc) st4(dst + 4 * k4, Fa[g]);
         }
@@ -340,15 +324,15 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
       const int nc = I.ntp >> 2;
       const int G = (nc + kWave - 1) / kWave;
       const float* src = P.part + I.part_off + (long long)(n & 1) * I.nslab * I.ntp;
-      float4 F[kMaxGroups];
+      float4 F[GM];
 #pragma unroll
-      for (int g = 0; g < kMaxGroups; ++g) {
+      for (int g = 0; g < GM; ++g) {
         F[g] = f4(0.f);
         const int k4 = lane + kWave * g;
         if (g < G && k4 < nc)
           for (int t = 0; t < I.nslab; ++t) F[g] = add4(F[g], ld4(src + (long long)t * I.ntp + 4 * k4));
       }
-      update_groups(P, I, U.state_off, F, n, G, lane);
+      update_groups<GM>(P, I, U.state_off, F, n, G, lane);
     }
   }
 }
@@ -398,8 +382,14 @@ __global__ void check_kernel(const float* H, const InstDev* inst, int* out) {
 // Launch wrappers used by the host code (same translation unit keeps the
 // kernels' symbols local to this file).
 namespace modal {
-hipError_t launch_step(const StepParams& P, int n_wg, size_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(step_kernel, dim3(n_wg), dim3(kWave), lds_bytes, s, P);
+// gm: float4 column groups per lane needed by the widest instance (1, 2 or 4)
+hipError_t launch_step(const StepParams& P, int gm, int n_wg, size_t lds_bytes, hipStream_t s) {
+  if (gm <= 1)
+    hipLaunchKernelGGL(step_kernel<1>, dim3(n_wg), dim3(kWave), lds_bytes, s, P);
+  else if (gm <= 2)
+    hipLaunchKernelGGL(step_kernel<2>, dim3(n_wg), dim3(kWave), lds_bytes, s, P);
+  else
+    hipLaunchKernelGGL(step_kernel<4>, dim3(n_wg), dim3(kWave), lds_bytes, s, P);
   return hipGetLastError();
 }
 hipError_t launch_advance(long long* step_base, int n, hipStream_t s) {
@@ -410,7 +400,11 @@ hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out
   hipLaunchKernelGGL(check_kernel, dim3(64, batch), dim3(256), 0, s, H, inst, out);
   return hipGetLastError();
 }
-hipError_t step_occupancy(int* blocks_per_cu, size_t lds_bytes) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel, kWave, lds_bytes);
+hipError_t step_occupancy(int* blocks_per_cu, int gm, size_t lds_bytes) {
+  if (gm <= 1)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<1>, kWave, lds_bytes);
+  if (gm <= 2)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<2>, kWave, lds_bytes);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<4>, kWave, lds_bytes);
 }
 }  // namespace modal

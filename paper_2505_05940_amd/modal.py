@@ -198,10 +198,11 @@ class Sim:
         return x, xm
 
     def info(self):
-        v = (C.c_int64 * 8)()
+        v = (C.c_int64 * 10)()
         _check(lib.modal_info(self._ctx, v))
         keys = ("workgroups", "units", "split_instances", "coupling_bytes_per_step",
-                "padded_bytes_per_step", "steps", "lds_bytes", "workgroups_per_cu")
+                "padded_bytes_per_step", "steps", "lds_bytes", "workgroups_per_cu",
+                "plan_makespan", "plan_mean")
         return dict(zip(keys, list(v)))
 
     def close(self):
