@@ -141,6 +141,13 @@ int modal_info(const modal_ctx *c, int64_t info[10]);
 
 void modal_destroy(modal_ctx *c);
 
+/* Host-only preview of the work partition modal_init would make for `d`
+ * with n_workgroups co-resident workgroups (validates d like modal_init; no
+ * device calls): out[0] work units, [1] workgroups used, [2] planned cost of
+ * the most loaded workgroup, [3] mean cost per workgroup (streamed-byte
+ * units).  EINVAL if the batch cannot be partitioned. */
+int modal_plan(const modal_desc *d, int32_t n_workgroups, int64_t out[4]);
+
 /* Message for the last failure on the calling thread ("" if none). */
 const char *modal_last_error(void);
 

@@ -1,0 +1,145 @@
+// Device helpers shared by the forward and reverse kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace modal {
+
+// ---------------------------------------------------------------- float-float
+// Error-free transformations (Knuth's TwoSum, Dekker's Fast2Sum, and the
+// FMA-based exact product).  This file is compiled with -ffp-contract=off so
+// only the explicit fmaf calls fuse.
+struct ff {
+  float hi, lo;
+};
+__device__ __forceinline__ ff two_sum(float a, float b) {
+  float s = a + b;
+  float bb = s - a;
+  float e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+__device__ __forceinline__ ff fast_two_sum(float a, float b) {
+  float s = a + b;
+  float e = b - (s - a);
+  return {s, e};
+}
+__device__ __forceinline__ ff two_prod(float a, float b) {
+  const float p = a * b;
+  return {p, fmaf(a, b, -p)};
+}
+__device__ __forceinline__ ff ff_add(ff a, ff b) {
+  ff s = two_sum(a.hi, b.hi);
+  ff t = two_sum(a.lo, b.lo);
+  float e = s.lo + t.hi;
+  s = fast_two_sum(s.hi, e);
+  e = s.lo + t.lo;
+  return fast_two_sum(s.hi, e);
+}
+__device__ __forceinline__ ff ff_mul(ff a, ff b) {
+  float p = a.hi * b.hi;
+  float e = fmaf(a.hi, b.hi, -p);
+  e = fmaf(a.hi, b.lo, e);
+  e = fmaf(a.lo, b.hi, e);
+  return fast_two_sum(p, e);
+}
+__device__ __forceinline__ ff ff_mul_f(ff a, float b) {
+  float p = a.hi * b;
+  float e = fmaf(a.hi, b, -p);
+  e = fmaf(a.lo, b, e);
+  return fast_two_sum(p, e);
+}
+
+// d+ = m X - p d + r fe ;  X+ = X + d+
+__device__ __forceinline__ void ff_step(float& xh, float& xl, float& dh, float& dl,
+                                        float mh, float ml, float ph, float pl,
+                                        float rh, float rl, float fe) {
+  ff X{xh, xl}, D{dh, dl};
+  ff a = ff_mul({mh, ml}, X);
+  ff b = ff_mul({ph, pl}, D);
+  ff t = ff_add(a, {-b.hi, -b.lo});
+  t = ff_add(t, ff_mul_f({rh, rl}, fe));
+  X = ff_add(X, t);
+  xh = X.hi;
+  xl = X.lo;
+  dh = t.hi;
+  dl = t.lo;
+}
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); }
+__device__ __forceinline__ float4 fma4(float4 a, float b, float4 c) {
+  return make_float4(fmaf(a.x, b, c.x), fmaf(a.y, b, c.y), fmaf(a.z, b, c.z), fmaf(a.w, b, c.w));
+}
+__device__ __forceinline__ float4 add4(float4 a, float4 b) {
+  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ float dot4(float4 a, float4 b) {
+  return fmaf(a.w, b.w, fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)));
+}
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+typedef float v4f __attribute__((ext_vector_type(4)));
+// streaming 16-byte load with the non-temporal hint (read once per step)
+__device__ __forceinline__ float4 ldnt4(const float* p) {
+  const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+
+// Raw buffer resource over `bytes` bytes at p (stride 0).  Loads at byte
+// offsets >= bytes are out of range and return zeros without a memory
+// access; the last word is the standard gfx9 raw-buffer format word.  The
+// callers' values are wave-uniform; readfirstlane states it so that the
+// resource lives in scalar registers.
+typedef int v4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4i buf_rsrc(const float* p, int bytes) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+  v4i r;
+  r.x = __builtin_amdgcn_readfirstlane((int)(unsigned)a);
+  r.y = __builtin_amdgcn_readfirstlane((int)((a >> 32) & 0xffffu));
+  r.z = __builtin_amdgcn_readfirstlane(bytes);
+  r.w = 0x00020000;
+  return r;
+}
+// The LLVM raw buffer load intrinsic, declared directly.
+__device__ v4f llvm_raw_buffer_load_v4f32(v4i rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v4f32");
+// 16-byte streaming load through a buffer resource, non-temporal hint.
+__device__ __forceinline__ float4 buf_ld4(v4i r, int voff) {
+  const v4f v = llvm_raw_buffer_load_v4f32(r, voff, 0, 2);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// Orders this wave's LDS writes before its later LDS reads by other lanes.
+// Workgroups are single waves, so no s_barrier is needed, and vector-memory
+// loads in flight are not waited for.
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Timeout of a per-instance barrier in ticks of the 100 MHz wall clock.
+constexpr unsigned long long kBarrierTimeout = 400000000ull;  // 4 s
+
+// Waits until the instance's arrival counter reaches `target` (wrap-safe).
+// Returns false if the wait was abandoned (timeout here or elsewhere).
+__device__ inline bool wait_counter(unsigned int* ctr, unsigned int target, int* flags) {
+  const unsigned long long t0 = wall_clock64();
+  while (true) {
+    unsigned int v = __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int)(v - target) >= 0) return true;
+    if (__hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (wall_clock64() - t0 > kBarrierTimeout) {
+      __hip_atomic_store(&flags[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+}  // namespace modal

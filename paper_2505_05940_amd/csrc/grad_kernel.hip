@@ -1,0 +1,346 @@
+// Reverse (adjoint) sweep of the modal time loop over one recorded segment.
+//
+// Back-propagation through the increment-form recursion of the step kernel
+// (paper: Sec. 3.3 fits by propagating gradients through the integrator):
+//   db^{n+1} = qb^{n+1} - p db^{n+2},  u^n = r db^{n+1},
+//   qb^n     = ybar^n c + qb^{n+1} + m db^{n+1} - J(q^n) u^n,
+// with J = dF/dq symmetric.  For the von Karman force one pass over a row of
+// Ht with two right-hand sides gives V = Ht q and W = Ht u, eta = V.q,
+// w = V.u and (J u) += 2 w V + eta W, F += eta V.  Per-mode float-float
+// accumulators collect dL/dm, dL/dp, dL/dr, dL/dc and the force-scale term
+// u.F; an optional tangent tensor Hd adds the directional derivative
+// -(Vd.q) (V.u) - eta (Vd.u) per row, Vd = Hd q.  Work partition, slab
+// exchange and barriers are those of the forward kernel.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace modal {
+
+template <int GM, bool TAN>
+__device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__ Hdb, int nt,
+                         int ntp, int qs, int row0, int row1, const float* Xs, const float* Us,
+                         float* red, float4 (&Ju)[GM], float4 (&Fa)[GM], float& tsum, int G,
+                         int lane) {
+  constexpr int J = kSweepLoads;
+  constexpr int NR = TAN ? 3 : 2;  // reduced vectors per row: V, W (, Vd)
+  const int nc = ntp >> 2;
+  const int qsnc = qs * nc;
+  int xsub[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int v = lane + kWave * j;
+    xsub[j] = v < qsnc ? v / nc : -1;
+  }
+  const int nfull = nt / qs;
+  const int tail = nt - nfull * qs;
+  const long long blk_floats = (long long)qs * ntp;
+  const long long row_floats = (long long)nt * ntp;
+  const int slab = qs * ntp;
+  for (int n = row0; n < row1; ++n) {
+    const float* p = Hb + (long long)n * row_floats + 4 * lane;
+    const float* pd = TAN ? Hdb + (long long)n * row_floats + 4 * lane : nullptr;
+    float4 aV[J], aW[J], aD[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) aV[j] = aW[j] = aD[j] = f4(0.f);
+    int q0 = 0;
+    for (int b = 0; b <= nfull; ++b, p += blk_floats, q0 += qs) {
+      const int lim = b < nfull ? qs : tail;
+      if (lim == 0) break;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        if (xsub[j] >= 0 && xsub[j] < lim) {
+          const float4 h = ldnt4(p + 4 * kWave * j);
+          const float x = Xs[q0 + xsub[j]], u = Us[q0 + xsub[j]];
+          aV[j] = fma4(h, x, aV[j]);
+          aW[j] = fma4(h, u, aW[j]);
+          if (TAN) aD[j] = fma4(ldnt4(pd + 4 * kWave * j), x, aD[j]);
+        }
+      }
+      if (TAN) pd += blk_floats;
+    }
+    float* rb = red + (n & 1) * NR * slab;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (xsub[j] >= 0) {
+        const int o = 4 * (lane + kWave * j);
+        st4(rb + o, aV[j]);
+        st4(rb + slab + o, aW[j]);
+        if (TAN) st4(rb + 2 * slab + o, aD[j]);
+      }
+    }
+    __syncthreads();
+    float eta = 0.f, w = 0.f, etad = 0.f, vdu = 0.f;
+    float4 V[GM], W[GM], D[GM];
+#pragma unroll
+    for (int g = 0; g < GM; ++g) {
+      V[g] = W[g] = D[g] = f4(0.f);
+      const int k4 = lane + kWave * g;
+      if (g < G && k4 < nc) {
+        float4 sv = ld4(rb + 4 * k4), sw = ld4(rb + slab + 4 * k4);
+        float4 sd = TAN ? ld4(rb + 2 * slab + 4 * k4) : f4(0.f);
+        for (int t = 1; t < qs; ++t) {
+          sv = add4(sv, ld4(rb + t * ntp + 4 * k4));
+          sw = add4(sw, ld4(rb + slab + t * ntp + 4 * k4));
+          if (TAN) sd = add4(sd, ld4(rb + 2 * slab + t * ntp + 4 * k4));
+        }
+        V[g] = sv;
+        W[g] = sw;
+        D[g] = sd;
+        const float4 x = ld4(Xs + 4 * k4), u = ld4(Us + 4 * k4);
+        eta += dot4(sv, x);
+        w += dot4(sv, u);
+        if (TAN) {
+          etad += dot4(sd, x);
+          vdu += dot4(sd, u);
+        }
+      }
+    }
+    eta = wave_sum(eta);
+    w = wave_sum(w);
+    if (TAN) {
+      etad = wave_sum(etad);
+      vdu = wave_sum(vdu);
+      tsum -= etad * w + eta * vdu;
+    }
+#pragma unroll
+    for (int g = 0; g < GM; ++g) {
+      Ju[g] = fma4(V[g], 2.f * w, fma4(W[g], eta, Ju[g]));
+      Fa[g] = fma4(V[g], eta, Fa[g]);
+    }
+  }
+}
+
+__device__ __forceinline__ ff ldff(const float* hi, const float* lo, int i) { return {hi[i], lo[i]}; }
+
+__device__ __forceinline__ void acc_add(float* acc, int k, int sf, int i, ff v) {
+  ff a{acc[(2 * k) * (long long)sf + i], acc[(2 * k + 1) * (long long)sf + i]};
+  a = ff_add(a, v);
+  acc[(2 * k) * (long long)sf + i] = a.hi;
+  acc[(2 * k + 1) * (long long)sf + i] = a.lo;
+}
+
+// db^{n+1} and u^n of one mode from the adjoint state.
+__device__ __forceinline__ void adj_pre(const GradParams& P, int so, int mo, ff& db, ff& u) {
+  const ff qb = ldff(P.qb_hi, P.qb_lo, so);
+  const ff dn = ldff(P.db_hi, P.db_lo, so);
+  const ff pp = ldff(P.p_hi, P.p_lo, mo);
+  const ff t = ff_mul(pp, dn);
+  db = ff_add(qb, {-t.hi, -t.lo});
+  u = ff_mul(ldff(P.r_hi, P.r_lo, mo), db);
+}
+
+// Finishes step n for the modes of one unit given the full J u and F.
+template <int GM>
+__device__ void adj_post(const GradParams& P, const InstDev& I, const UnitDev& U, long long n,
+                         const float4 (&Ju)[GM], const float4 (&F)[GM], int G, int lane) {
+  const int nc = I.ntp >> 2;
+  const float e = n < I.n_exc ? P.e_ext[I.e_off + n] : 0.f;
+  const float yb = P.ybar[(long long)I.out_row * P.ybar_stride + n];
+  const long long ro = (n - P.seg_base) * P.mode_floats + I.mode_off;
+  const int sf = P.state_floats;
+  const bool accumulate = U.slab == 0;
+#pragma unroll
+  for (int g = 0; g < GM; ++g) {
+    const int k4 = lane + kWave * g;
+    if (!(g < G && k4 < nc)) continue;
+    const float4 x4 = ld4(P.rec_x + ro + 4 * k4), d4 = ld4(P.rec_d + ro + 4 * k4);
+    const float4 b4 = ld4(P.b_ext + I.mode_off + 4 * k4);
+    const float4 c4 = ld4(P.c_out + I.mode_off + 4 * k4);
+    const float xs[4] = {x4.x, x4.y, x4.z, x4.w}, ds[4] = {d4.x, d4.y, d4.z, d4.w};
+    const float bs[4] = {b4.x, b4.y, b4.z, b4.w}, cs[4] = {c4.x, c4.y, c4.z, c4.w};
+    const float js[4] = {Ju[g].x, Ju[g].y, Ju[g].z, Ju[g].w};
+    const float fs[4] = {F[g].x, F[g].y, F[g].z, F[g].w};
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {
+      const int so = U.state_off + 4 * k4 + e4;
+      const int mo = I.mode_off + 4 * k4 + e4;
+      ff db, u;
+      adj_pre(P, so, mo, db, u);
+      if (accumulate) {
+        acc_add(P.acc, 0, sf, so, ff_mul_f(db, xs[e4]));
+        acc_add(P.acc, 1, sf, so, ff_mul_f(db, -ds[e4]));
+        acc_add(P.acc, 2, sf, so, ff_mul_f(db, fmaf(bs[e4], e, -fs[e4])));
+        acc_add(P.acc, 3, sf, so, two_prod(yb, xs[e4]));
+        acc_add(P.acc, 4, sf, so, ff_mul_f(u, -fs[e4]));
+      }
+      // qb^n = ybar c + qb^{n+1} + m db^{n+1} - (J u)
+      ff qb = ldff(P.qb_hi, P.qb_lo, so);
+      qb = ff_add(qb, ff_mul(ldff(P.m_hi, P.m_lo, mo), db));
+      qb = ff_add(qb, two_prod(yb, cs[e4]));
+      qb = ff_add(qb, {-js[e4], 0.f});
+      P.qb_hi[so] = qb.hi;
+      P.qb_lo[so] = qb.lo;
+      P.db_hi[so] = db.hi;
+      P.db_lo[so] = db.lo;
+    }
+  }
+}
+
+template <int GM, bool TAN>
+__global__ void __launch_bounds__(kWave) grad_kernel(GradParams P) {
+  extern __shared__ float4 lds4[];
+  float* Xs = reinterpret_cast<float*>(lds4);
+  float* Us = Xs + kMaxModes;
+  float* red = Us + kMaxModes;
+  const int lane = threadIdx.x;
+  const int u0 = P.wg_begin[blockIdx.x];
+  const int u1 = P.wg_begin[blockIdx.x + 1];
+
+  for (int s = 0; s < P.seg_len; ++s) {
+    const long long n = P.seg_base + P.seg_len - 1 - s;  // absolute step, descending
+    const long long rstep = P.done_before + s;          // reverse steps done so far
+    for (int u = u0; u < u1; ++u) {
+      const UnitDev U = P.unit[u];
+      const InstDev I = P.inst[U.inst];
+      const int nc = I.ntp >> 2;
+      const int G = (nc + kWave - 1) / kWave;
+      const long long ro = (n - P.seg_base) * P.mode_floats + I.mode_off;
+      float tsum = 0.f, sx = 0.f, sxu = 0.f;
+      float4 Ju[GM], Fa[GM];
+#pragma unroll
+      for (int g = 0; g < GM; ++g) {
+        Ju[g] = Fa[g] = f4(0.f);
+        const int k4 = lane + kWave * g;
+        if (g < G && k4 < nc) {
+          const float4 x4 = ld4(P.rec_x + ro + 4 * k4);
+          float us[4];
+          for (int e4 = 0; e4 < 4; ++e4) {
+            ff db, uu;
+            adj_pre(P, U.state_off + 4 * k4 + e4, I.mode_off + 4 * k4 + e4, db, uu);
+            us[e4] = uu.hi;
+          }
+          const float4 u4 = make_float4(us[0], us[1], us[2], us[3]);
+          if (I.kind == KIND_VK) {
+            st4(Xs + 4 * k4, x4);
+            st4(Us + 4 * k4, u4);
+          } else if (I.kind == KIND_TENSION) {
+            const float4 l = ld4(P.lam + I.mode_off + 4 * k4);
+            const float4 lx = make_float4(l.x * x4.x, l.y * x4.y, l.z * x4.z, l.w * x4.w);
+            sx += dot4(lx, x4);
+            sxu += dot4(lx, u4);
+            Ju[g] = u4;  // temporarily holds u
+          }
+        }
+      }
+      if (I.kind == KIND_VK) {
+        __syncthreads();
+        vk_rows2<GM, TAN>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs,
+                          U.row0, U.row1, Xs, Us, red, Ju, Fa, tsum, G, lane);
+        if (TAN && lane == 0) {
+          // theta partial of this unit: mode slot 0 of its theta accumulator
+          acc_add(P.acc, 5, P.state_floats, U.state_off, {tsum, 0.f});
+        }
+      } else if (I.kind == KIND_TENSION) {
+        // F = kappa lam x S, J u = kappa lam (u S + 2 x sum(lam x u))
+        const float S = wave_sum(sx), T2 = 2.f * wave_sum(sxu);
+#pragma unroll
+        for (int g = 0; g < GM; ++g) {
+          const int k4 = lane + kWave * g;
+          if (g < G && k4 < nc) {
+            const float4 x4 = ld4(P.rec_x + ro + 4 * k4);
+            const float4 l = ld4(P.lam + I.mode_off + 4 * k4);
+            const float4 u4 = Ju[g];
+            const float k = I.kappa;
+            Fa[g] = make_float4(k * l.x * x4.x * S, k * l.y * x4.y * S, k * l.z * x4.z * S,
+                                k * l.w * x4.w * S);
+            Ju[g] = make_float4(k * l.x * fmaf(u4.x, S, x4.x * T2), k * l.y * fmaf(u4.y, S, x4.y * T2),
+                                k * l.z * fmaf(u4.z, S, x4.z * T2), k * l.w * fmaf(u4.w, S, x4.w * T2));
+          }
+        }
+      }
+      if (I.nslab == 1) {
+        adj_post<GM>(P, I, U, n, Ju, Fa, G, lane);
+      } else {
+        float* dst = P.part + 2 * I.part_off + ((long long)(rstep & 1) * I.nslab + U.slab) * 2 * I.ntp;
+#pragma unroll
+        for (int g = 0; g < GM; ++g) {
+          const int k4 = lane + kWave * g;
+          if (g < G && k4 < nc) {
+            st4(dst + 4 * k4, Ju[g]);
+            st4(dst + I.ntp + 4 * k4, Fa[g]);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (lane == 0)
+          __hip_atomic_fetch_add(&P.ctr[U.inst], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+    }
+    for (int u = u0; u < u1; ++u) {
+      const UnitDev U = P.unit[u];
+      const InstDev I = P.inst[U.inst];
+      if (I.nslab == 1) continue;
+      const unsigned int target = (unsigned int)I.nslab * (unsigned int)(rstep + 1);
+      if (!wait_counter(&P.ctr[U.inst], target, P.flags)) return;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int nc = I.ntp >> 2;
+      const int G = (nc + kWave - 1) / kWave;
+      const float* src = P.part + 2 * I.part_off + (long long)(rstep & 1) * I.nslab * 2 * I.ntp;
+      float4 Ju[GM], F[GM];
+#pragma unroll
+      for (int g = 0; g < GM; ++g) {
+        Ju[g] = F[g] = f4(0.f);
+        const int k4 = lane + kWave * g;
+        if (g < G && k4 < nc)
+          for (int t = 0; t < I.nslab; ++t) {
+            Ju[g] = add4(Ju[g], ld4(src + (long long)t * 2 * I.ntp + 4 * k4));
+            F[g] = add4(F[g], ld4(src + (long long)t * 2 * I.ntp + I.ntp + 4 * k4));
+          }
+      }
+      adj_post<GM>(P, I, U, n, Ju, F, G, lane);
+      __syncthreads();
+    }
+  }
+}
+
+// Copies checkpoint `slot` ([4][mode_floats]) into every unit's state.
+__global__ void restore_kernel(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
+                               const UnitDev* unit, int n_units, float* state, int state_floats,
+                               long long* step_base, long long step) {
+  const int u = blockIdx.x;
+  if (u >= n_units) return;
+  const UnitDev U = unit[u];
+  const InstDev I = inst[U.inst];
+  const float* src = ckpt + slot * 4LL * mode_floats + I.mode_off;
+  for (int k = threadIdx.x; k < I.ntp; k += blockDim.x)
+    for (int a = 0; a < 4; ++a)
+      state[(long long)a * state_floats + U.state_off + k] = src[(long long)a * mode_floats + k];
+  if (u == 0 && threadIdx.x == 0) *step_base = step;
+}
+
+hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int n_wg, size_t lds, hipStream_t s) {
+#define GL(G, T) hipLaunchKernelGGL((grad_kernel<G, T>), dim3(n_wg), dim3(kWave), lds, s, P)
+  if (gm <= 1) {
+    if (tangent) GL(1, true); else GL(1, false);
+  } else if (gm <= 2) {
+    if (tangent) GL(2, true); else GL(2, false);
+  } else {
+    if (tangent) GL(4, true); else GL(4, false);
+  }
+#undef GL
+  return hipGetLastError();
+}
+
+hipError_t grad_occupancy(int* blocks, int gm, bool tangent, size_t lds) {
+  if (gm <= 1)
+    return tangent ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<1, true>, kWave, lds)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<1, false>, kWave, lds);
+  if (gm <= 2)
+    return tangent ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<2, true>, kWave, lds)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<2, false>, kWave, lds);
+  return tangent ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<4, true>, kWave, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<4, false>, kWave, lds);
+}
+
+hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
+                          const UnitDev* unit, int n_units, float* state, int state_floats,
+                          long long* step_base, long long step, hipStream_t s) {
+  hipLaunchKernelGGL(restore_kernel, dim3(n_units), dim3(256), 0, s, ckpt, slot, mode_floats, inst,
+                     unit, n_units, state, state_floats, step_base, step);
+  return hipGetLastError();
+}
+
+}  // namespace modal

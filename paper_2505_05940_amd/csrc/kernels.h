@@ -50,10 +50,47 @@ struct StepParams {
   unsigned int* ctr;        // arrival counters of split instances
   int* flags;               // [0] barrier timeout, [1] non-finite state
   long long* step_base;     // absolute index of the next step (device)
-  float* y;                 // output, y[row * y_stride + s]
+  float* y;                 // output, y[row * y_stride + s]; NULL = none
   long long y_stride;
   int n_steps;              // steps of this launch
   int red_floats;           // LDS floats reserved for the reduction buffer
+  int mode_floats;          // length of each per-mode array
+  // checkpoints of the float-float state at steps that are multiples of
+  // ckpt_every: [slot][4][mode_floats] (X hi, X lo, d hi, d lo); NULL = none
+  float* ckpt;
+  int ckpt_every;
+  // per-step record of q^n and d^n (fp32) for steps rec_base.. : [step][mode_floats]
+  float *rec_x, *rec_d;
+  long long rec_base;
+};
+
+// Reverse (adjoint) sweep over a recorded segment of steps.
+struct GradParams {
+  const InstDev* inst;
+  const UnitDev* unit;
+  const int* wg_begin;
+  const float* H;
+  const float* Hd;  // tangent tensor pool (same layout as H) or NULL
+  const float *m_hi, *m_lo, *p_hi, *p_lo, *r_hi, *r_lo;
+  const float *c_out, *lam, *b_ext;
+  const float* e_ext;
+  const float *rec_x, *rec_d;  // recorded q^n, d^n of the segment
+  long long seg_base;          // absolute step of rec row 0
+  int seg_len;                 // steps in the segment (processed last to first)
+  int mode_floats;
+  const float* ybar;           // dL/dy [batch][ybar_stride], absolute steps
+  long long ybar_stride;
+  // adjoint state per unit: qb = dL/dq^{n+1}, db = dL/dd^{n+2} (float-float)
+  float *qb_hi, *qb_lo, *db_hi, *db_lo;
+  // per-unit accumulators, float-float pairs [10][state floats]:
+  // m, p, r, c, s (u.F per mode), theta (per mode)
+  float* acc;
+  int state_floats;
+  float* part;           // partial (J u, F) of split instances, [2][nslab][2 ntp] at 2 part_off
+  unsigned int* ctr;
+  int* flags;
+  long long done_before;  // reverse steps completed before this launch
+  int red_floats;
 };
 
 }  // namespace modal

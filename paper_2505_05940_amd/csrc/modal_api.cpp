@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
+#include <map>
 #include <queue>
 #include <string>
 #include <vector>
@@ -17,6 +19,11 @@ hipError_t launch_step(const StepParams& P, int gm, int n_wg, size_t lds_bytes, 
 hipError_t launch_advance(long long* step_base, int n, hipStream_t s);
 hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s);
 hipError_t step_occupancy(int* blocks_per_cu, int gm, size_t lds_bytes);
+hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int n_wg, size_t lds, hipStream_t s);
+hipError_t grad_occupancy(int* blocks, int gm, bool tangent, size_t lds);
+hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
+                          const UnitDev* unit, int n_units, float* state, int state_floats,
+                          long long* step_base, long long step, hipStream_t s);
 }  // namespace modal
 
 using namespace modal;
@@ -63,13 +70,32 @@ struct Coef {
 // z^2 + a1 z + a2): g = -a1 = 2 e^{-gamma T} cos(w T), p = -a2 = -e^{-2 gamma T},
 // r = T e^{-gamma T} sin(w T)/w with w = sqrt(omega^2 - gamma^2) (force per
 // unit mass), and m = -(1 - e^{-gamma T})^2 - 4 e^{-gamma T} sin^2(w T/2).
+template <class S>
+void coefficients_t(int scheme, S omega, S gamma, double T, S& m, S& p, S& r) {
+  using std::exp;
+  using std::sin;
+  using std::sqrt;
+  if (scheme == MODAL_SCHEME_SV) {
+    r = T * T / (1.0 + gamma * T);
+    p = -(1.0 - gamma * T) / (1.0 + gamma * T);
+    m = -r * omega * omega;
+  } else {
+    const S w = sqrt(omega * omega - gamma * gamma);
+    const S e = exp(-gamma * T);
+    const S em1 = e - 1.0;
+    const S sh = sin(0.5 * w * T);
+    p = -e * e;
+    r = T * e * sin(w * T) / w;
+    m = -em1 * em1 - 4.0 * e * sh * sh;
+  }
+}
+
 Coef coefficients(int scheme, double omega, double gamma, double T) {
   Coef c;
   if (scheme == MODAL_SCHEME_SV) {
-    c.r = T * T / (1.0 + gamma * T);
-    c.p = -(1.0 - gamma * T) / (1.0 + gamma * T);
-    c.m = -c.r * omega * omega;
+    coefficients_t<double>(scheme, omega, gamma, T, c.m, c.p, c.r);
   } else {
+    // expm1 keeps m's relative accuracy when gamma T is tiny
     const double w = std::sqrt(omega * omega - gamma * gamma);
     const double e = std::exp(-gamma * T);
     const double em1 = std::expm1(-gamma * T);
@@ -79,6 +105,21 @@ Coef coefficients(int scheme, double omega, double gamma, double T) {
     c.m = -em1 * em1 - 4.0 * e * sh * sh;
   }
   return c;
+}
+
+// d(m, p, r)/d(omega) and /d(gamma) by the complex step (exact to rounding).
+void coefficient_derivs(int scheme, double omega, double gamma, double T, double dw[3], double dg[3]) {
+  using C = std::complex<double>;
+  const double h = 1e-30;
+  C m, p, r;
+  coefficients_t<C>(scheme, C(omega, h), C(gamma, 0.0), T, m, p, r);
+  dw[0] = m.imag() / h;
+  dw[1] = p.imag() / h;
+  dw[2] = r.imag() / h;
+  coefficients_t<C>(scheme, C(omega, 0.0), C(gamma, h), T, m, p, r);
+  dg[0] = m.imag() / h;
+  dg[1] = p.imag() / h;
+  dg[2] = r.imag() / h;
 }
 
 // Schur-Cohn (Jury) test for z^2 - g z - p: both roots in |z| <= 1.
@@ -116,6 +157,17 @@ struct modal_ctx {
   long long* dStep = nullptr;
   float* dE = nullptr;
   StepParams P{};
+  long long h_floats = 0, part_floats = 0;
+  int red_floats = 0;
+  std::vector<UnitDev> units;
+  std::vector<double> omega, gamma;  // concatenated over instances
+  std::vector<int> kind;
+  // gradient buffers (allocated on first modal_grad)
+  float *dHd = nullptr, *dCkpt = nullptr, *dRec = nullptr, *dAdj = nullptr, *dAcc = nullptr,
+        *dGPart = nullptr;
+  unsigned int* dGCtr = nullptr;
+  long long ckpt_floats = 0, rec_floats = 0;
+  bool tangent = false;
   hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
   struct Graph {
     int64_t n, stride;
@@ -131,7 +183,9 @@ void free_ctx(modal_ctx* c) {
   if (!c) return;
   for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  void* ptrs[] = {c->dH, c->dMeta, c->dCoef, c->dState, c->dPart, c->dCtr, c->dFlags, c->dStep, c->dE};
+  void* ptrs[] = {c->dH,   c->dMeta, c->dCoef, c->dState, c->dPart, c->dCtr, c->dFlags,
+                  c->dStep, c->dE,   c->dHd,   c->dCkpt,  c->dRec,  c->dAdj, c->dAcc,
+                  c->dGPart, c->dGCtr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -199,22 +253,39 @@ int validate(const modal_desc* d) {
   return MODAL_OK;
 }
 
-// LPT over `n_bins` workgroups: instances costlier than `thresh` are cut
-// into slabs of in-plane rows, every item goes to the least loaded bin.
-// Returns the makespan; fills units and their bins.
-double plan(const modal_desc* d, const std::vector<double>& row_cost,
-            const std::vector<double>& fixed_cost, double thresh, int n_bins,
-            std::vector<Unit>& units, std::vector<int>& bin_of, int& nslab_max) {
+// Planning cost of an instance in streamed-byte units: per in-plane row the
+// bytes of its tensor row plus the row's reduction; per step a fixed cost
+// for the state update and output.
+void unit_costs(const modal_instance& I, double& row_cost, double& fixed_cost) {
+  const int ntp = round4(I.n_t);
+  if (I.kind == MODAL_KIND_VK) {
+    row_cost = 4.0 * I.n_t * ntp + 4096.0;
+    fixed_cost = 8192.0;
+  } else {
+    row_cost = 0.0;
+    fixed_cost = 8192.0 + 64.0 * ntp;
+  }
+}
+
+// Packs the batch into at most `n_bins` workgroups of capacity `cap`
+// (streamed-byte units).  An instance costlier than `cap` is cut into the
+// fewest slabs of in-plane rows that each fit; then every item goes, largest
+// first, to the fullest workgroup it still fits in (best-fit decreasing).
+// Returns the number of workgroups used, or n_bins + 1 if it does not fit.
+int pack(const modal_desc* d, const std::vector<double>& row_cost,
+         const std::vector<double>& fixed_cost, double cap, int n_bins, std::vector<Unit>& units,
+         std::vector<int>& bin_of, std::vector<double>& load) {
   units.clear();
-  nslab_max = 1;
   for (int b = 0; b < d->batch; ++b) {
     const modal_instance& I = d->inst[b];
     const int rows = I.kind == MODAL_KIND_VK ? I.n_in : 1;
-    const double total = fixed_cost[b] + rows * row_cost[b];
     int S = 1;
-    if (I.kind == MODAL_KIND_VK && total > thresh) S = std::min(rows, (int)std::ceil(total / thresh));
-    S = std::min(S, n_bins);
-    nslab_max = std::max(nslab_max, S);
+    if (I.kind == MODAL_KIND_VK && fixed_cost[b] + rows * row_cost[b] > cap) {
+      const int per = (int)std::floor((cap - fixed_cost[b]) / row_cost[b]);
+      if (per < 1) return n_bins + 1;
+      S = (rows + per - 1) / per;
+    }
+    if (S > n_bins) return n_bins + 1;
     for (int s = 0; s < S; ++s) {
       const int r0 = (int)((long long)rows * s / S), r1 = (int)((long long)rows * (s + 1) / S);
       units.push_back({b, r0, r1, s, fixed_cost[b] + (r1 - r0) * row_cost[b]});
@@ -224,20 +295,48 @@ double plan(const modal_desc* d, const std::vector<double>& row_cost,
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return units[a].cost > units[b].cost; });
-  using E = std::pair<double, int>;
-  std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
-  for (int i = 0; i < n_bins; ++i) heap.push({0.0, i});
-  bin_of.assign(units.size(), 0);
-  double makespan = 0;
+  std::multimap<double, int> open;  // remaining capacity -> bin
+  bin_of.assign(units.size(), -1);
+  load.clear();
   for (int i : order) {
-    E e = heap.top();
-    heap.pop();
-    bin_of[i] = e.second;
-    e.first += units[i].cost;
-    makespan = std::max(makespan, e.first);
-    heap.push(e);
+    const double c = units[i].cost;
+    auto it = open.lower_bound(c);  // tightest bin that still fits
+    int bin;
+    if (it != open.end()) {
+      bin = it->second;
+      open.erase(it);
+    } else {
+      if ((int)load.size() == n_bins) return n_bins + 1;
+      bin = (int)load.size();
+      load.push_back(0.0);
+    }
+    load[bin] += c;
+    bin_of[i] = bin;
+    open.insert({cap - load[bin], bin});
   }
-  return makespan;
+  return (int)load.size();
+}
+
+// Smallest capacity (binary search) at which the batch packs into n_bins
+// workgroups, and that packing.
+bool plan_batch(const modal_desc* d, const std::vector<double>& row_cost,
+                const std::vector<double>& fixed_cost, double total, int n_bins,
+                std::vector<Unit>& units, std::vector<int>& bin_of, std::vector<double>& load) {
+  double max_item = 0;
+  for (int b = 0; b < d->batch; ++b)
+    max_item = std::max(max_item, fixed_cost[b] + (d->inst[b].kind == MODAL_KIND_VK ? row_cost[b] : 0.0));
+  double lo = std::max(total / n_bins, max_item), hi = std::max(lo, total) * 1.0001 + 1.0;
+  if (pack(d, row_cost, fixed_cost, hi, n_bins, units, bin_of, load) > n_bins) return false;
+  for (int it = 0; it < 40 && hi - lo > 1e-4 * lo; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    std::vector<Unit> u2;
+    std::vector<int> b2;
+    std::vector<double> l2;
+    if (pack(d, row_cost, fixed_cost, mid, n_bins, u2, b2, l2) <= n_bins) hi = mid;
+    else lo = mid;
+  }
+  pack(d, row_cost, fixed_cost, hi, n_bins, units, bin_of, load);
+  return true;
 }
 
 // Copies every instance's Ht into the padded device layout (rows of ntp
@@ -364,13 +463,8 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
       c->padded_bytes += 4 * f;
       choose_sweep(D.nt, D.ntp / 4, qs_of[b], J_of[b]);
       red_floats = std::max(red_floats, 2 * qs_of[b] * D.ntp);
-      // bytes streamed per row plus the per-row reduction, in byte units
-      row_cost[b] = 4.0 * D.nt * D.ntp + 4096.0;
-      fixed_cost[b] = 8192.0;
-    } else {
-      row_cost[b] = 0;
-      fixed_cost[b] = 8192.0 + 64.0 * D.ntp;
     }
+    unit_costs(I, row_cost[b], fixed_cost[b]);
   }
   c->mode_floats = mode_floats;
   c->lds_bytes = sizeof(float) * (size_t)(kMaxModes + red_floats);
@@ -397,24 +491,14 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   double total = 0;
   for (int b = 0; b < d->batch; ++b)
     total += fixed_cost[b] + (inst[b].kind == KIND_VK ? inst[b].nin : 1) * row_cost[b];
-  std::vector<Unit> units, best_units;
-  std::vector<int> bin_of, best_bin;
-  double best = 1e300;
-  int nslab_max = 1;
-  const double fr[] = {0.5, 0.75, 1.0, 1.25, 1.5, 2.0, 3.0, 1e30};
-  for (double f : fr) {
-    int ns = 1;
-    const double ms = plan(d, row_cost, fixed_cost, f * total / n_bins, n_bins, units, bin_of, ns);
-    if (ms < best * (1 - 1e-9)) {
-      best = ms;
-      best_units = units;
-      best_bin = bin_of;
-      nslab_max = ns;
-    }
+  std::vector<Unit> units;
+  std::vector<int> bin_of;
+  std::vector<double> load;
+  if (!plan_batch(d, row_cost, fixed_cost, total, n_bins, units, bin_of, load)) {
+    free_ctx(c);
+    return fail(MODAL_EINVAL, "batch does not fit the workgroup budget");
   }
-  units.swap(best_units);
-  bin_of.swap(best_bin);
-  c->makespan = best;
+  c->makespan = *std::max_element(load.begin(), load.end());
   c->mean_load = total / n_bins;
   // workgroups actually used, renumbered densely; within a workgroup split
   // units come first so their partial forces are published early
@@ -707,5 +791,28 @@ int modal_info(const modal_ctx* c, int64_t info[10]) {
 }
 
 void modal_destroy(modal_ctx* c) { free_ctx(c); }
+
+int modal_plan(const modal_desc* d, int32_t n_workgroups, int64_t out[4]) {
+  g_err.clear();
+  if (!out || n_workgroups < 1) return fail(MODAL_EINVAL, "out NULL or n_workgroups < 1");
+  int rc = validate(d);
+  if (rc) return rc;
+  std::vector<double> row_cost(d->batch), fixed_cost(d->batch);
+  double total = 0;
+  for (int b = 0; b < d->batch; ++b) {
+    unit_costs(d->inst[b], row_cost[b], fixed_cost[b]);
+    total += fixed_cost[b] + (d->inst[b].kind == MODAL_KIND_VK ? d->inst[b].n_in : 1) * row_cost[b];
+  }
+  std::vector<Unit> units;
+  std::vector<int> bin_of;
+  std::vector<double> load;
+  if (!plan_batch(d, row_cost, fixed_cost, total, n_workgroups, units, bin_of, load))
+    return fail(MODAL_EINVAL, "batch does not fit the workgroup budget");
+  out[0] = (int64_t)units.size();
+  out[1] = (int64_t)load.size();
+  out[2] = (int64_t)*std::max_element(load.begin(), load.end());
+  out[3] = (int64_t)(total / n_workgroups);
+  return MODAL_OK;
+}
 
 }  // extern "C"

@@ -23,167 +23,80 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "device_common.h"
 
 namespace modal {
-
-// ---------------------------------------------------------------- float-float
-// Error-free transformations (Knuth's TwoSum, Dekker's Fast2Sum, and the
-// FMA-based exact product).  This file is compiled with -ffp-contract=off so
-// only the explicit fmaf calls fuse.
-struct ff {
-  float hi, lo;
-};
-__device__ __forceinline__ ff two_sum(float a, float b) {
-  float s = a + b;
-  float bb = s - a;
-  float e = (a - (s - bb)) + (b - bb);
-  return {s, e};
-}
-__device__ __forceinline__ ff fast_two_sum(float a, float b) {
-  float s = a + b;
-  float e = b - (s - a);
-  return {s, e};
-}
-__device__ __forceinline__ ff ff_add(ff a, ff b) {
-  ff s = two_sum(a.hi, b.hi);
-  ff t = two_sum(a.lo, b.lo);
-  float e = s.lo + t.hi;
-  s = fast_two_sum(s.hi, e);
-  e = s.lo + t.lo;
-  return fast_two_sum(s.hi, e);
-}
-__device__ __forceinline__ ff ff_mul(ff a, ff b) {
-  float p = a.hi * b.hi;
-  float e = fmaf(a.hi, b.hi, -p);
-  e = fmaf(a.hi, b.lo, e);
-  e = fmaf(a.lo, b.hi, e);
-  return fast_two_sum(p, e);
-}
-__device__ __forceinline__ ff ff_mul_f(ff a, float b) {
-  float p = a.hi * b;
-  float e = fmaf(a.hi, b, -p);
-  e = fmaf(a.lo, b, e);
-  return fast_two_sum(p, e);
-}
-
-// d+ = m X - p d + r fe ;  X+ = X + d+
-__device__ __forceinline__ void ff_step(float& xh, float& xl, float& dh, float& dl,
-                                        float mh, float ml, float ph, float pl,
-                                        float rh, float rl, float fe) {
-  ff X{xh, xl}, D{dh, dl};
-  ff a = ff_mul({mh, ml}, X);
-  ff b = ff_mul({ph, pl}, D);
-  ff t = ff_add(a, {-b.hi, -b.lo});
-  t = ff_add(t, ff_mul_f({rh, rl}, fe));
-  X = ff_add(X, t);
-  xh = X.hi;
-  xl = X.lo;
-  dh = t.hi;
-  dl = t.lo;
-}
-
-// ------------------------------------------------------------------ helpers
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
-__device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); }
-__device__ __forceinline__ float4 fma4(float4 a, float b, float4 c) {
-  return make_float4(fmaf(a.x, b, c.x), fmaf(a.y, b, c.y), fmaf(a.z, b, c.z), fmaf(a.w, b, c.w));
-}
-__device__ __forceinline__ float4 add4(float4 a, float4 b) {
-  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
-}
-__device__ __forceinline__ float dot4(float4 a, float4 b) {
-  return fmaf(a.w, b.w, fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)));
-}
-__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
-typedef float v4f __attribute__((ext_vector_type(4)));
-// streaming 16-byte load with the non-temporal hint (read once per step)
-__device__ __forceinline__ float4 ldnt4(const float* p) {
-  const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
-  return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
-
-// Timeout of a per-instance barrier in ticks of the 100 MHz wall clock.
-constexpr unsigned long long kBarrierTimeout = 400000000ull;  // 4 s
-
-// Waits until the instance's arrival counter reaches `target` (wrap-safe).
-// Returns false if the wait was abandoned (timeout here or elsewhere).
-__device__ bool wait_counter(unsigned int* ctr, unsigned int target, int* flags) {
-  const unsigned long long t0 = wall_clock64();
-  while (true) {
-    unsigned int v = __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    if ((int)(v - target) >= 0) return true;
-    if (__hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    if (wall_clock64() - t0 > kBarrierTimeout) {
-      __hip_atomic_store(&flags[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(2);
-  }
-}
 
 // -------------------------------------------------------- von Karman rows
 // Rows [row0, row1) of one instance's Ht.  Row n is an nt x ntp matrix
 // (nc = ntp/4 float4 per stored row), read as consecutive blocks of qs
 // stored rows.  A block is contiguous, so lane slot v = lane + 64 j
-// (j < kSweepLoads) simply reads float4 number v of the block: stored row
-// q0 + v / nc, columns 4 (v % nc) .. +3.  Each sweep is one fully coalesced
-// 4 KB read per wave.  Slot accumulators are reduced over the qs sub-rows
-// through LDS (double buffered by row parity, one wave barrier per row),
-// giving V[n, :] on the lanes that own each float4 column group
-// (k4 = lane + 64 g); then eta_n and the force update follow.
+// (j < kSweepLoads) reads float4 number v of the block: stored row
+// q0 + v / nc, columns 4 (v % nc) .. +3; one sweep is a fully coalesced
+// 4 KB read per wave.  Each block gets a buffer resource sized to the block,
+// so idle slots (v >= qs nc) and the missing rows of the last block read
+// zeros without touching memory.  Blocks are software-pipelined across rows:
+// the loads of the next block are issued before the current one is used.
+// At the end of a row the slot accumulators are reduced over the qs
+// sub-rows through LDS (double buffered by row parity) into V[n, :] on the
+// lanes owning each float4 column group (k4 = lane + 64 g), and eta_n and
+// the force follow: F += eta_n V[n, :].
 template <int GM>
 __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, int row0,
                         int row1, const float* Xs, float* red, float4 (&Fa)[GM], int G,
                         int lane) {
   constexpr int J = kSweepLoads;
+  if (row1 <= row0) return;
   const int nc = ntp >> 2;
   const int qsnc = qs * nc;
-  int xsub[J];  // sub-row of slot j within a block, -1 if the slot is idle
+  int voff[J], sub[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int v = lane + kWave * j;
-    xsub[j] = v < qsnc ? v / nc : -1;
+    voff[j] = 16 * v;
+    sub[j] = v < qsnc ? v / nc : 0;
   }
-  const int nfull = nt / qs;
-  const int tail = nt - nfull * qs;
+  const int nblk = (nt + qs - 1) / qs;
   const long long blk_floats = (long long)qs * ntp;
   const long long row_floats = (long long)nt * ntp;
-  const float* rowp = Hb + (long long)row0 * row_floats + 4 * lane;
-  for (int n = row0; n < row1; ++n, rowp += row_floats) {
-    float4 acc[J];
+  const int blk_bytes = 4 * qs * ntp;
+  const int last_bytes = 4 * (nt - (nblk - 1) * qs) * ntp;
+  // position of the block being loaded ahead; past the last row the
+  // resource covers zero bytes, so the (unconditional) loads return zeros
+  // without a memory access and the loop keeps a single straight-line path
+  int ln = row0, lb = 0;
+  auto load = [&](float4 (&h)[J]) {
+    const bool live = ln < row1;
+    const float* bp = Hb + (live ? (long long)ln * row_floats + (long long)lb * blk_floats : 0);
+    const int bytes = live ? (lb == nblk - 1 ? last_bytes : blk_bytes) : 0;
+    const v4i r = buf_rsrc(bp, bytes);
 #pragma unroll
-    for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
-    const float* p = rowp;
-    int q0 = 0;
-#pragma unroll 2
-    for (int b = 0; b < nfull; ++b, p += blk_floats, q0 += qs) {
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        if (xsub[j] >= 0) {
-          const float4 h = ldnt4(p + 4 * kWave * j);
-          acc[j] = fma4(h, Xs[q0 + xsub[j]], acc[j]);
-        }
-      }
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+    if (++lb == nblk) {
+      lb = 0;
+      ++ln;
     }
-    if (tail) {
+  };
+  float4 ha[J], hb[J], acc[J];
 #pragma unroll
-      for (int j = 0; j < J; ++j) {
-        if (xsub[j] >= 0 && xsub[j] < tail) {
-          const float4 h = ldnt4(p + 4 * kWave * j);
-          acc[j] = fma4(h, Xs[q0 + xsub[j]], acc[j]);
-        }
-      }
-    }
+  for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
+  int n = row0, b = 0;
+  // Uses block `hc` (row n, block b) after issuing the loads of the next
+  // block into `hn`; returns false after the last row.  Two buffers used in
+  // turn keep the next block's loads in flight while the current one is
+  // consumed.
+  auto step = [&](float4 (&hc)[J], float4 (&hn)[J]) -> bool {
+    load(hn);
+    const int q0 = b * qs;
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = fma4(hc[j], Xs[min(q0 + sub[j], nt - 1)], acc[j]);
+    if (++b < nblk) return true;
+    // row n complete: reduce over sub-rows, then eta_n and the force
     float* rb = red + (n & 1) * qs * ntp;
 #pragma unroll
     for (int j = 0; j < J; ++j)
-      if (xsub[j] >= 0) st4(rb + 4 * (lane + kWave * j), acc[j]);
-    __syncthreads();
+      if (voff[j] < blk_bytes) st4(rb + (voff[j] >> 2), acc[j]);
+    wave_lds_sync();
     float eta = 0.f;
     float4 V[GM];
 #pragma unroll
@@ -200,6 +113,13 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
     eta = wave_sum(eta);
 #pragma unroll
     for (int g = 0; g < GM; ++g) Fa[g] = fma4(V[g], eta, Fa[g]);
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
+    b = 0;
+    return ++n < row1;
+  };
+  load(ha);
+  while (step(ha, hb) && step(hb, ha)) {
   }
 }
 
@@ -277,7 +197,31 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
       }
       if (U.slab == 0) {
         const float yv = wave_sum(ypart);
-        if (lane == 0) P.y[(long long)I.out_row * P.y_stride + s] = yv;
+        if (lane == 0 && P.y) P.y[(long long)I.out_row * P.y_stride + s] = yv;
+        if (P.ckpt && n % P.ckpt_every == 0) {
+          float* cp = P.ckpt + (n / P.ckpt_every) * 4LL * P.mode_floats + I.mode_off;
+          for (int g = 0; g < GM; ++g) {
+            const int k4 = lane + kWave * g;
+            if (g < G && k4 < nc) {
+              const int so = U.state_off + 4 * k4;
+              st4(cp + 4 * k4, ld4(P.x_hi + so));
+              st4(cp + P.mode_floats + 4 * k4, ld4(P.x_lo + so));
+              st4(cp + 2 * P.mode_floats + 4 * k4, ld4(P.d_hi + so));
+              st4(cp + 3 * P.mode_floats + 4 * k4, ld4(P.d_lo + so));
+            }
+          }
+        }
+        if (P.rec_x) {
+          const long long ro = (n - P.rec_base) * P.mode_floats + I.mode_off;
+          for (int g = 0; g < GM; ++g) {
+            const int k4 = lane + kWave * g;
+            if (g < G && k4 < nc) {
+              const int so = U.state_off + 4 * k4;
+              st4(P.rec_x + ro + 4 * k4, ld4(P.x_hi + so));
+              st4(P.rec_d + ro + 4 * k4, ld4(P.d_hi + so));
+            }
+          }
+        }
       }
       float4 Fa[GM];
 #pragma unroll

@@ -63,6 +63,8 @@ def _load():
     lib.modal_destroy.argtypes = [vp]
     lib.modal_destroy.restype = None
     lib.modal_last_error.restype = C.c_char_p
+    lib.modal_plan.argtypes = [C.POINTER(modal_desc), C.c_int32, C.POINTER(C.c_int64)]
+    lib.modal_plan.restype = C.c_int
     lib.modal_vk_coupling_sine.argtypes = [C.c_double, C.c_double, C.c_int32, _ip, _ip,
                                            C.c_int32, _ip, _ip, C.c_int32, C.c_int32,
                                            _dp, _fp, C.c_int32]
@@ -111,6 +113,72 @@ def vk_coupling_sine(Lx, Ly, m, q, a, b, scale_n, grid=None, threads=0):
     return out
 
 
+def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_steps=0,
+                shapes_only=False):
+    """modal_desc for a list of instance dicts; returns (desc, keep-alive list, n_t list).
+    With shapes_only (planning previews, which never read tensors) a vk
+    instance may give "n_in" instead of "Ht"."""
+    keep = []
+    batch = len(instances)
+    arr = (modal_instance * batch)()
+    keep.append(arr)
+    n_t = []
+    for i, inst in enumerate(instances):
+        n = len(inst["omega"])
+        n_t.append(n)
+        s = arr[i]
+        s.kind = KIND[inst["kind"]]
+        s.n_t = n
+        s.reserved = 0
+        for field, key in (("omega", "omega"), ("gamma", "gamma"), ("x0", "x0"),
+                           ("xm1", "xm1"), ("c_out", "c")):
+            a = _d(inst[key], n)
+            keep.append(a)
+            setattr(s, field, a.ctypes.data_as(_dp))
+        if inst["kind"] == "tension":
+            if inst.get("lam") is not None:
+                a = _d(inst["lam"], n)
+                keep.append(a)
+                s.lam = a.ctypes.data_as(_dp)
+            s.kappa = float(inst["kappa"])
+        if inst["kind"] == "vk" and shapes_only and "Ht" not in inst:
+            dummy = np.zeros(1, np.float32)
+            keep.append(dummy)
+            s.H = dummy.ctypes.data_as(_fp)
+            s.n_in = int(inst["n_in"])
+        elif inst["kind"] == "vk":
+            H = inst["Ht"]
+            if hasattr(H, "data_ptr"):
+                assert H.dtype.itemsize == 4 and H.is_contiguous() and tuple(H.shape[1:]) == (n, n)
+                s.H = C.cast(C.c_void_p(H.data_ptr()), _fp)
+            else:
+                H = np.ascontiguousarray(H, dtype=np.float32)
+                assert H.ndim == 3 and H.shape[1:] == (n, n)
+                s.H = H.ctypes.data_as(_fp)
+            s.n_in = H.shape[0]
+            keep.append(H)
+        else:
+            s.n_in = 0
+        if inst.get("e_ext") is not None:
+            b = _d(inst["b_ext"], n)
+            e = np.ascontiguousarray(inst["e_ext"], dtype=np.float32)
+            keep += [b, e]
+            s.b_ext = b.ctypes.data_as(_dp)
+            s.e_ext = e.ctypes.data_as(_fp)
+            s.n_exc = len(e)
+    desc = modal_desc(batch=batch, scheme=SCHEME[scheme], inst=arr, fs=float(fs), flags=flags,
+                      max_workgroups=max_workgroups, chunk_steps=chunk_steps, reserved=0)
+    return desc, keep, n_t
+
+
+def plan(instances, n_workgroups, fs=44100.0, scheme="sv"):
+    """Host-only preview of the work partition (``modal_plan``)."""
+    desc, keep, _ = _build_desc(instances, fs, scheme, shapes_only=True)
+    out = (C.c_int64 * 4)()
+    _check(lib.modal_plan(C.byref(desc), n_workgroups, out))
+    return dict(units=out[0], workgroups=out[1], makespan=out[2], mean=out[3])
+
+
 class Sim:
     """A batch of modal systems resident on the GPU (``modal_init``).
 
@@ -124,54 +192,11 @@ class Sim:
                  chunk_steps=0, stream=None):
         self._ctx = C.c_void_p()
         self.batch = len(instances)
-        keep = []
-        arr = (modal_instance * self.batch)()
-        self.n_t = []
-        for i, inst in enumerate(instances):
-            n = len(inst["omega"])
-            self.n_t.append(n)
-            s = arr[i]
-            s.kind = KIND[inst["kind"]]
-            s.n_t = n
-            s.reserved = 0
-            for field, key in (("omega", "omega"), ("gamma", "gamma"), ("x0", "x0"),
-                               ("xm1", "xm1"), ("c_out", "c")):
-                a = _d(inst[key], n)
-                keep.append(a)
-                setattr(s, field, a.ctypes.data_as(_dp))
-            if inst["kind"] == "tension":
-                if inst.get("lam") is not None:
-                    a = _d(inst["lam"], n)
-                    keep.append(a)
-                    s.lam = a.ctypes.data_as(_dp)
-                s.kappa = float(inst["kappa"])
-            if inst["kind"] == "vk":
-                H = inst["Ht"]
-                if hasattr(H, "data_ptr"):
-                    assert H.dtype.itemsize == 4 and H.is_contiguous() and tuple(H.shape) == (H.shape[0], n, n)
-                    s.H = C.cast(C.c_void_p(H.data_ptr()), _fp)
-                    s.n_in = H.shape[0]
-                else:
-                    H = np.ascontiguousarray(H, dtype=np.float32)
-                    assert H.ndim == 3 and H.shape[1:] == (n, n)
-                    s.H = H.ctypes.data_as(_fp)
-                    s.n_in = H.shape[0]
-                keep.append(H)
-            else:
-                s.n_in = 0
-            if inst.get("e_ext") is not None:
-                b = _d(inst["b_ext"], n)
-                e = np.ascontiguousarray(inst["e_ext"], dtype=np.float32)
-                keep += [b, e]
-                s.b_ext = b.ctypes.data_as(_dp)
-                s.e_ext = e.ctypes.data_as(_fp)
-                s.n_exc = len(e)
-        desc = modal_desc(batch=self.batch, scheme=SCHEME[scheme], inst=arr, fs=float(fs),
-                          flags=flags, max_workgroups=max_workgroups,
-                          chunk_steps=chunk_steps, reserved=0)
+        desc, keep, self.n_t = _build_desc(instances, fs, scheme, flags, max_workgroups, chunk_steps)
         self._stream = stream
         _check(lib.modal_init(C.byref(self._ctx), C.byref(desc), _stream_handle(stream)))
         self.modes_total = sum(self.n_t)
+        self.scheme = scheme
 
     def run(self, n_steps, out=None):
         """Advance by n_steps; returns y [batch, n_steps] float32 on the GPU."""

@@ -64,3 +64,28 @@ def test_sv_stability_boundary():
     with pytest.raises(modal.ModalError) as e:
         modal.Sim([_inst(omega=np.full(4, 2.0001 * 44100.0), gamma=np.zeros(4))], 44100.0, stream=0)
     assert e.value.status == "EUNSTABLE"
+
+
+def test_plan_balances_the_batched_workload():
+    """The partition of the 256-plate batch (shapes only, no tensors read):
+    every instance is covered, no workgroup exceeds 1.15x the mean cost."""
+    import workloads as W
+    from paper_2505_05940_amd import modal
+    wls = W.plate_batch()
+    insts = [dict(kind="vk", omega=np.full(w["n_t"], 1e3), gamma=np.ones(w["n_t"]),
+                  x0=np.zeros(w["n_t"]), xm1=np.zeros(w["n_t"]), c=np.ones(w["n_t"]),
+                  n_in=w["n_in"]) for w in wls]
+    for nb in (512, 2560, 4096):
+        p = modal.plan(insts, nb)
+        assert p["workgroups"] <= nb and p["units"] >= len(wls)
+        assert p["makespan"] <= 1.15 * p["mean"], (nb, p)
+
+
+def test_plan_splits_only_when_needed():
+    from paper_2505_05940_amd import modal
+    n = 40
+    inst = dict(kind="vk", omega=np.full(n, 1e3), gamma=np.ones(n), x0=np.zeros(n),
+                xm1=np.zeros(n), c=np.ones(n), n_in=n)
+    assert modal.plan([inst], 1)["units"] == 1
+    p = modal.plan([inst], 8)
+    assert p["units"] == 8 and p["workgroups"] == 8  # one instance: rows split 8 ways
