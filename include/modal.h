@@ -61,9 +61,11 @@ enum { MODAL_SCHEME_SV = 0, MODAL_SCHEME_TF = 1 };
 enum {
   MODAL_FLAG_ASYNC = 1, /* modal_run does not wait for completion nor read
                            the status flags; call modal_check afterwards     */
-  MODAL_FLAG_GRAPH = 2  /* modal_run records its launches into a hipGraph
+  MODAL_FLAG_GRAPH = 2, /* modal_run records its launches into a hipGraph
                            on first use for a given (n_steps, y, y_stride)
                            and replays it afterwards                          */
+  MODAL_FLAG_GRAD = 4   /* plan the work so that modal_grad can run (its
+                           reverse kernel needs more LDS per workgroup)       */
 };
 
 /* One modal system.  All arrays are host memory. */
@@ -140,6 +142,32 @@ int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
 int modal_info(const modal_ctx *c, int64_t info[10]);
 
 void modal_destroy(modal_ctx *c);
+
+/* Tangent tensor of instance `inst` (VK only): Hd = dHt/dtheta for one
+ * scalar parameter theta, [n_in][n_t][n_t] like H, host or device memory,
+ * copied.  modal_grad then also returns dL/dtheta through the tensor. */
+int modal_set_tangent(modal_ctx *c, int32_t inst, const float *Hd, void *stream);
+
+/* Reverse-mode gradient of a loss L(y) over the first n_steps outputs of
+ * every instance, run from the initial state (paper: Sec. 3.3, fitting by
+ * propagating gradients through the time integrator).  dL_dy is device
+ * memory [batch][y_stride] (FP32).  The forward pass is recomputed from
+ * float-float checkpoints taken every ckpt_every steps (0 = 512); each
+ * segment is re-run, recorded, and swept backwards by the adjoint kernel.
+ * Outputs (host, FP64, modes concatenated over instances; NULL to skip):
+ *   g_omega, g_gamma  dL/d omega_k, dL/d gamma_k (through the scheme's
+ *                     coefficients, differentiated exactly on the host)
+ *   g_c               dL/d c_k
+ *   g_x0, g_xm1       dL/d q^0_k, dL/d q^-1_k
+ *   g_scale [batch]   dL/d log s for a factor s on the nonlinear force
+ *   g_theta [batch]   dL/d theta through the tangent tensor (0 without one)
+ * Needs a context created with MODAL_FLAG_GRAD (else ESTATE).  Leaves the
+ * context reset to its initial state.  Errors: EINVAL, ENOMEM, EHIP,
+ * ENONFINITE, EHANG. */
+int modal_grad(modal_ctx *c, int64_t n_steps, const float *dL_dy, int64_t y_stride,
+               int32_t ckpt_every, double *g_omega, double *g_gamma, double *g_c,
+               double *g_x0, double *g_xm1, double *g_scale, double *g_theta,
+               void *stream);
 
 /* Host-only preview of the work partition modal_init would make for `d`
  * with n_workgroups co-resident workgroups (validates d like modal_init; no

@@ -1,0 +1,52 @@
+"""Oracle-side plate built from the five fitted parameters
+theta = (T0/rho_s, D/rho_s, aspect a = Ly/Lx, d1/(2 rho_s), d3/(2 rho_s))
+(paper, Sec. 3.3: density-normalised parameters; Sec. 2.2: omega^2 =
+(D lambda^2 + T0 lambda)/rho_s and gamma = (d1 + d3 lambda)/(2 rho_s)).
+
+Fixed: area S (Lx = sqrt(S/a), Ly = sqrt(S a)), thickness, Poisson ratio,
+strike and pickup at relative positions, and the mode index sets, taken at
+the base aspect.  The von Karman prefactor E/(2 rho) = 6 (1 - nu^2) D^/h^2
+follows the bending stiffness.  Sine in-plane family, exact integrals.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import coupling, excitation, modes
+
+
+def _mode_sets(fit):
+    a0, S = fit["base_aspect"], fit["area"]
+    Lx, Ly = np.sqrt(S / a0), np.sqrt(S * a0)
+    m, q, _ = modes.plate_modes(Lx, Ly, fit["n_t"])
+    a, b, _ = modes.plate_modes(Lx, Ly, fit["n_in"])
+    return m, q, a, b
+
+
+def plate_from_theta(fit, theta):
+    T0h, Dh, asp, d1, d3 = theta
+    S = fit["area"]
+    Lx, Ly = np.sqrt(S / asp), np.sqrt(S * asp)
+    m, q, ai, bi = _mode_sets(fit)
+    lam = (m * np.pi / Lx) ** 2 + (q * np.pi / Ly) ** 2
+    lam_in = (ai * np.pi / Lx) ** 2 + (bi * np.pi / Ly) ** 2
+    omega = np.sqrt(Dh * lam ** 2 + T0h * lam)
+    gamma = d1 + d3 * lam
+    # exact sine-family integrals for the fixed index sets
+    c = 2.0 / np.sqrt(Lx * Ly)
+    al, be = m * np.pi / Lx, q * np.pi / Ly
+    A = al[:, None] ** 2 * be[None, :] ** 2 + be[:, None] ** 2 * al[None, :] ** 2
+    B = 2.0 * (al * be)[:, None] * (al * be)[None, :]
+    H = np.empty((len(ai), len(m), len(m)))
+    for k in range(len(ai)):
+        H[k] = c ** 3 * (A * coupling._int_sss(ai[k], m[:, None], m[None, :], Lx)
+                         * coupling._int_sss(bi[k], q[:, None], q[None, :], Ly)
+                         - B * coupling._int_scc(ai[k], m[:, None], m[None, :], Lx)
+                         * coupling._int_scc(bi[k], q[:, None], q[None, :], Ly))
+    E_over_2rho = 6.0 * (1.0 - fit["nu"] ** 2) * Dh / fit["h"] ** 2
+    Ht = np.sqrt(E_over_2rho) * H / lam_in[:, None, None]
+    xc, yc, amp, rr = fit["strike"]
+    x0 = excitation.plate_strike_modal(m, q, Lx, Ly, *fit["proj_grid"], xc * Lx, yc * Ly, amp,
+                                       rr * min(Lx, Ly))
+    cw = excitation.plate_output(m, q, Lx, Ly, fit["out"][0] * Lx, fit["out"][1] * Ly)
+    return dict(kind="vk", omega=omega, gamma=gamma, lam=lam, Ht=Ht, x0=x0, xm1=x0.copy(), c=cw)

@@ -296,14 +296,16 @@ __global__ void __launch_bounds__(kWave) grad_kernel(GradParams P) {
   }
 }
 
-// Copies checkpoint `slot` ([4][mode_floats]) into every unit's state.
+// Copies checkpoint `slot` ([4][mode_floats]) into every unit's state and
+// rewinds the step counter and the forward arrival counters to `step`.
 __global__ void restore_kernel(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
                                const UnitDev* unit, int n_units, float* state, int state_floats,
-                               long long* step_base, long long step) {
+                               long long* step_base, long long step, unsigned int* ctr) {
   const int u = blockIdx.x;
   if (u >= n_units) return;
   const UnitDev U = unit[u];
   const InstDev I = inst[U.inst];
+  if (U.slab == 0 && threadIdx.x == 0) ctr[U.inst] = (unsigned int)I.nslab * (unsigned int)step;
   const float* src = ckpt + slot * 4LL * mode_floats + I.mode_off;
   for (int k = threadIdx.x; k < I.ntp; k += blockDim.x)
     for (int a = 0; a < 4; ++a)
@@ -337,9 +339,9 @@ hipError_t grad_occupancy(int* blocks, int gm, bool tangent, size_t lds) {
 
 hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
                           const UnitDev* unit, int n_units, float* state, int state_floats,
-                          long long* step_base, long long step, hipStream_t s) {
+                          long long* step_base, long long step, unsigned int* ctr, hipStream_t s) {
   hipLaunchKernelGGL(restore_kernel, dim3(n_units), dim3(256), 0, s, ckpt, slot, mode_floats, inst,
-                     unit, n_units, state, state_floats, step_base, step);
+                     unit, n_units, state, state_floats, step_base, step, ctr);
   return hipGetLastError();
 }
 

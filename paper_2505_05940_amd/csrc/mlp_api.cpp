@@ -1,0 +1,174 @@
+// Host side of the proposal network: layer bookkeeping, forward, backward
+// and Adam around the kernels of mlp_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mlp.h"
+#include "../../include/modal.h"
+
+namespace modal {
+hipError_t launch_gemm(const float* A, long long sam, long long sak, const float* B, long long sbk,
+                       long long sbn, float* C, long long scm, int M, int N, int K, int epi,
+                       const float* bias, const float* mask, hipStream_t s);
+hipError_t launch_colsum(const float* G, int M, int N, float* db, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
+                       float b2, float eps, int t, hipStream_t s);
+}  // namespace modal
+
+using namespace modal;
+
+namespace {
+thread_local std::string g_mlp_err;
+int mfail(int code, const std::string& m) {
+  g_mlp_err = m;
+  return code;
+}
+#define MHIP(expr)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return mfail(MODAL_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_MASK = 3 };
+}  // namespace
+
+struct mlp_ctx {
+  int L = 0, max_batch = 0, max_d = 0, last_batch = 0;
+  std::vector<int> dims;
+  std::vector<long long> w_off, b_off, act_off;
+  long long n_params = 0, act_floats = 0;
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *act = nullptr, *d0 = nullptr,
+        *d1 = nullptr;
+};
+
+extern "C" {
+
+const char* mlp_last_error(void) { return g_mlp_err.c_str(); }
+
+void mlp_destroy(mlp_ctx* c) {
+  if (!c) return;
+  for (float* q : {c->p, c->g, c->m, c->v, c->act, c->d0, c->d1})
+    if (q) (void)hipFree(q);
+  delete c;
+}
+
+int mlp_init(mlp_ctx** out, int32_t n_layers, const int32_t* dims, int32_t max_batch, void* stream) {
+  if (!out || n_layers < 1 || !dims || max_batch < 1) return mfail(MODAL_EINVAL, "bad arguments");
+  *out = nullptr;
+  for (int l = 0; l <= n_layers; ++l)
+    if (dims[l] < 1 || dims[l] > (1 << 16)) return mfail(MODAL_EINVAL, "layer width out of range");
+  mlp_ctx* c = new mlp_ctx();
+  c->L = n_layers;
+  c->max_batch = max_batch;
+  c->dims.assign(dims, dims + n_layers + 1);
+  for (int l = 0; l < n_layers; ++l) {
+    c->w_off.push_back(c->n_params);
+    c->n_params += (long long)dims[l] * dims[l + 1];
+    c->b_off.push_back(c->n_params);
+    c->n_params += dims[l + 1];
+  }
+  for (int l = 0; l <= n_layers; ++l) {
+    c->act_off.push_back(c->act_floats);
+    c->act_floats += (long long)max_batch * dims[l];
+    c->max_d = std::max(c->max_d, dims[l]);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const size_t pb = sizeof(float) * (size_t)c->n_params;
+  float** bufs[] = {&c->p, &c->g, &c->m, &c->v};
+  for (float** b : bufs) {
+    if (hipMalloc((void**)b, pb) != hipSuccess) {
+      mlp_destroy(c);
+      return mfail(MODAL_ENOMEM, "hipMalloc params");
+    }
+    if (hipMemsetAsync(*b, 0, pb, s) != hipSuccess) {
+      mlp_destroy(c);
+      return mfail(MODAL_EHIP, "memset");
+    }
+  }
+  if (hipMalloc((void**)&c->act, sizeof(float) * (size_t)c->act_floats) != hipSuccess ||
+      hipMalloc((void**)&c->d0, sizeof(float) * (size_t)max_batch * c->max_d) != hipSuccess ||
+      hipMalloc((void**)&c->d1, sizeof(float) * (size_t)max_batch * c->max_d) != hipSuccess) {
+    mlp_destroy(c);
+    return mfail(MODAL_ENOMEM, "hipMalloc activations");
+  }
+  *out = c;
+  return MODAL_OK;
+}
+
+int mlp_n_params(const mlp_ctx* c, int64_t* n) {
+  if (!c || !n) return mfail(MODAL_EINVAL, "NULL");
+  *n = c->n_params;
+  return MODAL_OK;
+}
+
+int mlp_set_params(mlp_ctx* c, const float* host, void* stream) {
+  if (!c || !host) return mfail(MODAL_EINVAL, "NULL");
+  hipStream_t s = (hipStream_t)stream;
+  MHIP(hipMemcpyAsync(c->p, host, sizeof(float) * (size_t)c->n_params, hipMemcpyHostToDevice, s));
+  MHIP(hipMemsetAsync(c->m, 0, sizeof(float) * (size_t)c->n_params, s));
+  MHIP(hipMemsetAsync(c->v, 0, sizeof(float) * (size_t)c->n_params, s));
+  MHIP(hipStreamSynchronize(s));
+  return MODAL_OK;
+}
+
+int mlp_get(mlp_ctx* c, int32_t which, float* host, void* stream) {
+  if (!c || !host || which < 0 || which > 1) return mfail(MODAL_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  MHIP(hipMemcpyAsync(host, which == 0 ? c->p : c->g, sizeof(float) * (size_t)c->n_params,
+                      hipMemcpyDeviceToHost, s));
+  MHIP(hipStreamSynchronize(s));
+  return MODAL_OK;
+}
+
+int mlp_forward(mlp_ctx* c, const float* x, int32_t B, float* y, void* stream) {
+  if (!c || !x || !y || B < 1 || B > c->max_batch) return mfail(MODAL_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  MHIP(hipMemcpyAsync(c->act, x, sizeof(float) * (size_t)B * c->dims[0], hipMemcpyDeviceToDevice, s));
+  for (int l = 0; l < c->L; ++l) {
+    const int in = c->dims[l], out = c->dims[l + 1];
+    const float* a = c->act + c->act_off[l];
+    float* z = c->act + c->act_off[l + 1];
+    MHIP(launch_gemm(a, in, 1, c->p + c->w_off[l], 1, in, z, out, B, out, in,
+                     l + 1 < c->L ? EPI_BIAS_RELU : EPI_BIAS, c->p + c->b_off[l], nullptr, s));
+  }
+  MHIP(hipMemcpyAsync(y, c->act + c->act_off[c->L], sizeof(float) * (size_t)B * c->dims[c->L],
+                      hipMemcpyDeviceToDevice, s));
+  c->last_batch = B;
+  return MODAL_OK;
+}
+
+int mlp_backward(mlp_ctx* c, const float* dy, void* stream) {
+  if (!c || !dy || c->last_batch < 1) return mfail(MODAL_ESTATE, "backward needs a forward first");
+  hipStream_t s = (hipStream_t)stream;
+  const int B = c->last_batch;
+  float* gcur = c->d0;
+  float* gnext = c->d1;
+  MHIP(hipMemcpyAsync(gcur, dy, sizeof(float) * (size_t)B * c->dims[c->L], hipMemcpyDeviceToDevice, s));
+  for (int l = c->L - 1; l >= 0; --l) {
+    const int in = c->dims[l], out = c->dims[l + 1];
+    const float* a = c->act + c->act_off[l];
+    // dW[o, i] = sum_b g[b, o] a[b, i]
+    MHIP(launch_gemm(gcur, 1, out, a, in, 1, c->g + c->w_off[l], in, out, in, B, EPI_STORE, nullptr,
+                     nullptr, s));
+    MHIP(launch_colsum(gcur, B, out, c->g + c->b_off[l], s));
+    if (l > 0) {
+      // g_prev[b, i] = (sum_o g[b, o] W[o, i]) * [a[b, i] > 0]
+      MHIP(launch_gemm(gcur, out, 1, c->p + c->w_off[l], in, 1, gnext, in, B, in, out, EPI_MASK,
+                       nullptr, a, s));
+      std::swap(gcur, gnext);
+    }
+  }
+  return MODAL_OK;
+}
+
+int mlp_adam_step(mlp_ctx* c, float lr, float b1, float b2, float eps, int32_t t, void* stream) {
+  if (!c || t < 1) return mfail(MODAL_EINVAL, "bad arguments");
+  MHIP(launch_adam(c->p, c->g, c->m, c->v, c->n_params, lr, b1, b2, eps, t, (hipStream_t)stream));
+  return MODAL_OK;
+}
+
+}  // extern "C"

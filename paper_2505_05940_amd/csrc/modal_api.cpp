@@ -23,7 +23,7 @@ hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int n_wg, size
 hipError_t grad_occupancy(int* blocks, int gm, bool tangent, size_t lds);
 hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
                           const UnitDev* unit, int n_units, float* state, int state_floats,
-                          long long* step_base, long long step, hipStream_t s);
+                          long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
 }  // namespace modal
 
 using namespace modal;
@@ -141,7 +141,7 @@ struct modal_ctx {
   double fs = 0;
   int n_wg = 0, n_units = 0, n_split = 0, occ = 0, gm = 1;
   double makespan = 0, mean_load = 0;
-  size_t lds_bytes = 0;
+  size_t lds_bytes = 0, grad_lds = 0;
   long long coupling_bytes = 0, padded_bytes = 0, steps = 0;
   int state_floats = 0, mode_floats = 0;
   std::vector<int> nt, unit_state_of_inst, inst_mode_off;
@@ -480,6 +480,16 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   HIP_TRY(hipGetDeviceProperties(&prop, dev));
   int occ = 0;
   HIP_TRY(step_occupancy(&occ, c->gm, c->lds_bytes));
+  c->red_floats = red_floats;
+  c->grad_lds = sizeof(float) * (size_t)(2 * kMaxModes + 3 * red_floats);
+  if (d->flags & MODAL_FLAG_GRAD) {
+    // the reverse kernel (with or without a tangent) must fit as many
+    // co-resident workgroups as the plan uses
+    int og = 0, ot = 0;
+    HIP_TRY(grad_occupancy(&og, c->gm, false, c->grad_lds));
+    HIP_TRY(grad_occupancy(&ot, c->gm, true, c->grad_lds));
+    occ = std::min(occ, std::min(og, ot));
+  }
   if (occ < 1) {
     free_ctx(c);
     return fail(MODAL_EHIP, "step kernel does not fit on a CU");
@@ -549,6 +559,16 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   c->n_wg = n_wg;
   c->n_units = (int)udev.size();
   c->state_floats = state_floats;
+  c->units = udev;
+  c->h_floats = h_floats;
+  c->part_floats = part_floats;
+  for (int b = 0; b < d->batch; ++b) {
+    c->kind.push_back(d->inst[b].kind);
+    for (int k = 0; k < d->inst[b].n_t; ++k) {
+      c->omega.push_back(d->inst[b].omega[k]);
+      c->gamma.push_back(d->inst[b].gamma[k]);
+    }
+  }
 
   // ---------------- coefficients, initial state
   std::vector<float> coef(9 * (size_t)mode_floats, 0.f);
@@ -675,6 +695,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   P.flags = c->dFlags;
   P.step_base = c->dStep;
   P.red_floats = red_floats;
+  P.mode_floats = mode_floats;
 #undef HIP_TRY_C
   int r = modal_reset(c, stream_);
   if (r) return bail(r);
@@ -753,6 +774,157 @@ int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* s
   c->steps += n_steps;
   if (c->flags & MODAL_FLAG_ASYNC) return MODAL_OK;
   return modal_check(c, stream_);
+}
+
+
+int modal_set_tangent(modal_ctx* c, int32_t b, const float* Hd, void* stream_) {
+  if (!c || !Hd) return fail(MODAL_EINVAL, "NULL argument");
+  if (b < 0 || b >= c->batch || c->kind[b] != MODAL_KIND_VK)
+    return fail(MODAL_EINVAL, "tangent needs a VK instance index");
+  hipStream_t s = (hipStream_t)stream_;
+  if (!c->dHd) {
+    int r = dalloc(&c->dHd, sizeof(float) * (size_t)(c->h_floats + 64));
+    if (r) return r;
+    HIP_TRY(hipMemsetAsync(c->dHd, 0, sizeof(float) * (size_t)(c->h_floats + 64), s));
+  }
+  std::vector<InstDev> inst(c->batch);
+  HIP_TRY(hipMemcpyAsync(inst.data(), c->P.inst, sizeof(InstDev) * c->batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const InstDev& D = inst[b];
+  HIP_TRY(hipMemcpy2DAsync(c->dHd + D.h_off, sizeof(float) * D.ntp, Hd, sizeof(float) * D.nt,
+                           sizeof(float) * D.nt, (size_t)D.nin * D.nt, hipMemcpyDefault, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  c->tangent = true;
+  return MODAL_OK;
+}
+
+int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_stride, int32_t ckpt_every,
+               double* g_omega, double* g_gamma, double* g_c, double* g_x0, double* g_xm1,
+               double* g_scale, double* g_theta, void* stream_) {
+  if (!c) return fail(MODAL_EINVAL, "ctx is NULL");
+  if (!(c->flags & MODAL_FLAG_GRAD)) return fail(MODAL_ESTATE, "context not created with MODAL_FLAG_GRAD");
+  if (n_steps < 1 || n_steps > (1LL << 31) - 1 || !ybar || y_stride < n_steps)
+    return fail(MODAL_EINVAL, "n_steps, dL_dy or y_stride");
+  if (ckpt_every < 0) return fail(MODAL_EINVAL, "ckpt_every < 0");
+  const int K = ckpt_every > 0 ? ckpt_every : 512;
+  const long long nseg = (n_steps + K - 1) / K;
+  hipStream_t s = (hipStream_t)stream_;
+  const int mf = c->mode_floats, sf = c->state_floats;
+  // buffers (grown on demand)
+  if (c->ckpt_floats < nseg * 4LL * mf) {
+    if (c->dCkpt) HIP_TRY(hipFree(c->dCkpt));
+    c->dCkpt = nullptr;
+    c->ckpt_floats = 0;
+    int r = dalloc(&c->dCkpt, sizeof(float) * (size_t)(nseg * 4LL * mf));
+    if (r) return r;
+    c->ckpt_floats = nseg * 4LL * mf;
+  }
+  if (c->rec_floats < 2LL * K * mf) {
+    if (c->dRec) HIP_TRY(hipFree(c->dRec));
+    c->dRec = nullptr;
+    c->rec_floats = 0;
+    int r = dalloc(&c->dRec, sizeof(float) * (size_t)(2LL * K * mf));
+    if (r) return r;
+    c->rec_floats = 2LL * K * mf;
+  }
+  if (!c->dAdj) {
+    int r = dalloc(&c->dAdj, sizeof(float) * 4 * (size_t)sf);
+    if (!r) r = dalloc(&c->dAcc, sizeof(float) * 12 * (size_t)sf);
+    if (!r) r = dalloc(&c->dGPart, sizeof(float) * (size_t)(2 * c->part_floats + 64));
+    if (!r) r = dalloc(&c->dGCtr, sizeof(unsigned int) * c->batch);
+    if (r) return r;
+  }
+  // forward from the initial state with checkpoints
+  int r = modal_reset(c, stream_);
+  if (r) return r;
+  {
+    StepParams P = c->P;
+    P.y = nullptr;
+    P.ckpt = c->dCkpt;
+    P.ckpt_every = K;
+    P.n_steps = (int)n_steps;
+    HIP_TRY(launch_step(P, c->gm, c->n_wg, c->lds_bytes, s));
+  }
+  HIP_TRY(hipMemsetAsync(c->dAdj, 0, sizeof(float) * 4 * (size_t)sf, s));
+  HIP_TRY(hipMemsetAsync(c->dAcc, 0, sizeof(float) * 12 * (size_t)sf, s));
+  HIP_TRY(hipMemsetAsync(c->dGCtr, 0, sizeof(unsigned int) * c->batch, s));
+  GradParams G{};
+  const StepParams& F = c->P;
+  G.inst = F.inst;
+  G.unit = F.unit;
+  G.wg_begin = F.wg_begin;
+  G.H = F.H;
+  G.Hd = c->tangent ? c->dHd : nullptr;
+  G.m_hi = F.m_hi; G.m_lo = F.m_lo; G.p_hi = F.p_hi; G.p_lo = F.p_lo;
+  G.r_hi = F.r_hi; G.r_lo = F.r_lo;
+  G.c_out = F.c_out; G.lam = F.lam; G.b_ext = F.b_ext; G.e_ext = F.e_ext;
+  G.rec_x = c->dRec;
+  G.rec_d = c->dRec + (size_t)K * mf;
+  G.mode_floats = mf;
+  G.ybar = ybar;
+  G.ybar_stride = y_stride;
+  G.qb_hi = c->dAdj; G.qb_lo = c->dAdj + sf; G.db_hi = c->dAdj + 2 * (size_t)sf; G.db_lo = c->dAdj + 3 * (size_t)sf;
+  G.acc = c->dAcc;
+  G.state_floats = sf;
+  G.part = c->dGPart;
+  G.ctr = c->dGCtr;
+  G.flags = F.flags;
+  G.red_floats = 3 * c->red_floats;
+  for (long long seg = nseg - 1; seg >= 0; --seg) {
+    const long long s0 = seg * K;
+    const int len = (int)std::min<long long>(K, n_steps - s0);
+    HIP_TRY(launch_restore(c->dCkpt, seg, mf, F.inst, F.unit, c->n_units, c->dState, sf, c->dStep, s0,
+                           c->dCtr, s));
+    StepParams P = c->P;
+    P.y = nullptr;
+    P.rec_x = c->dRec;
+    P.rec_d = c->dRec + (size_t)K * mf;
+    P.rec_base = s0;
+    P.n_steps = len;
+    HIP_TRY(launch_step(P, c->gm, c->n_wg, c->lds_bytes, s));
+    G.seg_base = s0;
+    G.seg_len = len;
+    G.done_before = n_steps - s0 - len;
+    HIP_TRY(launch_grad(G, c->gm, c->tangent, c->n_wg, c->grad_lds, s));
+  }
+  r = modal_check(c, stream_);
+  if (r) return r;
+  std::vector<float> acc(12 * (size_t)sf), adj(4 * (size_t)sf);
+  HIP_TRY(hipMemcpyAsync(acc.data(), c->dAcc, sizeof(float) * acc.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(adj.data(), c->dAdj, sizeof(float) * adj.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  auto A = [&](int k, int i) { return (double)acc[(size_t)(2 * k) * sf + i] + (double)acc[(size_t)(2 * k + 1) * sf + i]; };
+  // per instance: its slab-0 unit holds the accumulators; every unit its theta partial
+  std::vector<int> slab0(c->batch, -1);
+  std::vector<double> theta(c->batch, 0.0);
+  for (const UnitDev& U : c->units) {
+    if (U.slab == 0) slab0[U.inst] = U.state_off;
+    theta[U.inst] += A(5, U.state_off);
+  }
+  const double T = 1.0 / c->fs;
+  size_t o = 0;
+  for (int b = 0; b < c->batch; ++b) {
+    const int so = slab0[b];
+    double gs = 0.0;
+    for (int k = 0; k < c->nt[b]; ++k, ++o) {
+      const double gm = A(0, so + k), gp = A(1, so + k), gr = A(2, so + k);
+      double dw[3], dg[3];
+      coefficient_derivs(c->scheme, c->omega[o], c->gamma[o], T, dw, dg);
+      if (g_omega) g_omega[o] = gm * dw[0] + gp * dw[1] + gr * dw[2];
+      if (g_gamma) g_gamma[o] = gm * dg[0] + gp * dg[1] + gr * dg[2];
+      if (g_c) g_c[o] = A(3, so + k);
+      gs += A(4, so + k);
+      const Coef q = coefficients(c->scheme, c->omega[o], c->gamma[o], T);
+      const double qb0 = (double)adj[so + k] + (double)adj[(size_t)sf + so + k];
+      const double db1 = (double)adj[2 * (size_t)sf + so + k] + (double)adj[3 * (size_t)sf + so + k];
+      const double d0b = -q.p * db1;  // d^0 = q^0 - q^-1 only feeds d^1
+      if (g_x0) g_x0[o] = qb0 + d0b;
+      if (g_xm1) g_xm1[o] = -d0b;
+    }
+    if (g_scale) g_scale[b] = gs;
+    if (g_theta) g_theta[b] = theta[b];
+  }
+  return modal_reset(c, stream_);
 }
 
 int modal_get_state(modal_ctx* c, double* x, double* xm1, void* stream_) {

@@ -1,0 +1,201 @@
+"""Physical-parameter fitting through the GPU time loop.
+
+Paper, Sec. 3.3: parameters are fitted by propagating gradients through the
+time integrator (BPTT), in density-normalised form (D^ = D/rho_s,
+T0^ = T0/rho_s), with the damping kept in the stable half plane, using Adam
+with a one-cycle cosine learning-rate schedule and a spectral loss.
+
+A plate here has five parameters theta = (T0^, D^, a, d1^, d3^):
+    omega_k^2 = D^ lambda_k^2 + T0^ lambda_k,   gamma_k = d1^ + d3^ lambda_k,
+    lambda_k  = pi^2 (m_k^2 a / S + q_k^2 / (a S))   (Lx = sqrt(S/a), Ly = sqrt(S a)),
+with the area S, thickness, Poisson ratio, strike and pickup (relative
+positions) fixed, and the mode index sets fixed at the base aspect so that
+derivatives do not cross mode reorderings.  The von Karman prefactor follows
+the bending stiffness: E/(2 rho) = 6 (1 - nu^2) D^ / h^2.  For the sine
+in-plane family the unscaled coupling integrals at fixed area do not depend
+on a (the Lx, Ly factors cancel), so the coupling tensor's aspect tangent is
+a per-row rescaling through zeta_n^2 = lambda_n(a).
+
+``ModalFn`` is a torch.autograd.Function whose forward runs modal_run and
+whose backward runs modal_grad, followed by the FP64 chain rule to theta.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import modal, physics
+from .losses import mrstft_loss
+
+PARAM_NAMES = ("T0hat", "Dhat", "aspect", "d1hat", "d3hat")
+
+
+@dataclass
+class PlateSetup:
+    """Fixed part of a fitted plate."""
+    n_t: int = 200
+    n_in: int = 200
+    area: float = 0.12
+    h: float = 1e-3
+    nu: float = 0.3
+    base_aspect: float = 0.75
+    strike: tuple = (0.37, 0.61, 1e-3, 0.1)   # xc/Lx, yc/Ly, amplitude, radius/min(Lx,Ly)
+    out: tuple = (0.71, 0.29)                   # xo/Lx, yo/Ly
+    proj_grid: tuple = (200, 150)
+    fs: float = 44100.0
+    modes: tuple = field(default=None, repr=False)  # (m, q, a_in, b_in) at base aspect
+
+    def __post_init__(self):
+        if self.modes is None:
+            Lx, Ly = math.sqrt(self.area / self.base_aspect), math.sqrt(self.area * self.base_aspect)
+            m, q, _ = physics.plate_eigs(Lx, Ly, self.n_t)
+            a, b, _ = physics.plate_eigs(Lx, Ly, self.n_in)
+            self.modes = (m, q, a, b)
+
+
+def _lam(m, q, aspect, area):
+    return np.pi ** 2 * (m ** 2 * aspect / area + q ** 2 / (aspect * area))
+
+
+def _dlam_da(m, q, aspect, area):
+    return np.pi ** 2 * (m ** 2 / area - q ** 2 / (aspect ** 2 * area))
+
+
+def _excitation(setup, aspect):
+    m, q, _, _ = setup.modes
+    Lx, Ly = math.sqrt(setup.area / aspect), math.sqrt(setup.area * aspect)
+    xc, yc, amp, rr = setup.strike
+    x0 = physics.plate_initial(m, q, Lx, Ly, setup.proj_grid, xc * Lx, yc * Ly, amp,
+                               rr * min(Lx, Ly))
+    c = physics.plate_pickup(m, q, Lx, Ly, setup.out[0] * Lx, setup.out[1] * Ly)
+    return x0, c
+
+
+def plate_instance(setup: PlateSetup, theta, threads=0):
+    """Instance dict for theta = (T0^, D^, a, d1^, d3^), plus the pieces the
+    chain rule needs."""
+    T0h, Dh, a, d1, d3 = (float(v) for v in theta)
+    m, q, ai, bi = setup.modes
+    Lx, Ly = math.sqrt(setup.area / a), math.sqrt(setup.area * a)
+    lam = _lam(m, q, a, setup.area)
+    omega = np.sqrt(Dh * lam ** 2 + T0h * lam)
+    gamma = d1 + d3 * lam
+    zeta2 = _lam(ai, bi, a, setup.area)
+    pref = math.sqrt(6.0 * (1.0 - setup.nu ** 2) * Dh / setup.h ** 2)
+    Ht = modal.vk_coupling_sine(Lx, Ly, m, q, ai, bi, pref / zeta2, grid=None, threads=threads)
+    x0, c = _excitation(setup, a)
+    return dict(kind="vk", omega=omega, gamma=gamma, lam=lam, Ht=Ht, x0=x0, xm1=x0.copy(), c=c,
+                zeta2=zeta2)
+
+
+def aspect_tangent(setup, inst, a):
+    """dHt/da: row n of Ht scales as 1/zeta_n^2(a)."""
+    _, _, ai, bi = setup.modes
+    kappa = -_dlam_da(ai, bi, a, setup.area) / inst["zeta2"]
+    return (inst["Ht"] * kappa[:, None, None].astype(np.float32)).astype(np.float32)
+
+
+def chain_rule(setup, theta, inst, g, h_rel=1e-6):
+    """dL/dtheta from the per-mode gradients of modal_grad (one instance)."""
+    T0h, Dh, a, d1, d3 = (float(v) for v in theta)
+    m, q, _, _ = setup.modes
+    lam, om = inst["lam"], inst["omega"]
+    gw, gg = g["omega"], g["gamma"]
+    dlam = _dlam_da(m, q, a, setup.area)
+    dT0 = np.sum(gw * lam / (2 * om))
+    dD = np.sum(gw * lam ** 2 / (2 * om)) + g["scale"] / Dh
+    dd1 = np.sum(gg)
+    dd3 = np.sum(gg * lam)
+    # aspect: frequencies, damping, coupling rows, excitation and pickup
+    da = np.sum(gw * (2 * Dh * lam + T0h) * dlam / (2 * om)) + np.sum(gg * d3 * dlam) + g["theta"]
+    eps = h_rel * a
+    xp, cp = _excitation(setup, a + eps)
+    xm, cm = _excitation(setup, a - eps)
+    da += np.sum((g["x0"] + g["xm1"]) * (xp - xm) / (2 * eps)) + np.sum(g["c"] * (cp - cm) / (2 * eps))
+    return np.array([dT0, dD, da, dd1, dd3])
+
+
+class ModalFn(torch.autograd.Function):
+    """y = simulate(theta) for a batch of parameter vectors (one plate each).
+    forward: modal_init + modal_run; backward: modal_grad + chain rule."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, setup: PlateSetup, n_steps: int, ckpt: int = 512):
+        th = theta.detach().double().cpu().numpy().reshape(-1, 5)
+        insts = [plate_instance(setup, t) for t in th]
+        sim = modal.Sim(insts, setup.fs, flags=modal.FLAG_GRAD)
+        y = sim.run(n_steps).clone()
+        ctx.save = (sim, insts, th, setup, n_steps, ckpt)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        sim, insts, th, setup, n_steps, ckpt = ctx.save
+        for b, inst in enumerate(insts):
+            sim.set_tangent(b, aspect_tangent(setup, inst, th[b][2]))
+        g = sim.grad(n_steps, gy.contiguous().float(), ckpt_every=ckpt)
+        out = np.stack([chain_rule(setup, th[b], insts[b],
+                                   {k: (v[b] if isinstance(v, list) else v[b]) for k, v in g.items()})
+                        for b in range(len(insts))])
+        sim.close()
+        return torch.tensor(out, dtype=torch.float64).reshape(-1, 5), None, None, None
+
+
+def one_cycle_cosine(step, total, peak, warm_frac=0.3, div=25.0, final_div=1e4):
+    """One-cycle schedule: cosine rise from peak/div to peak over the first
+    warm_frac of the steps, then cosine decay to peak/final_div."""
+    w = max(1, int(warm_frac * total))
+    if step < w:
+        t = step / w
+        lo = peak / div
+        return lo + (peak - lo) * 0.5 * (1 - math.cos(math.pi * t))
+    t = (step - w) / max(1, total - w)
+    lo = peak / final_div
+    return lo + (peak - lo) * 0.5 * (1 + math.cos(math.pi * t))
+
+
+def to_unconstrained(theta):
+    """theta -> z: logs of the positive parameters, logit of a in (0.3, 1.5)
+    (keeps gamma > 0 and the plate non-degenerate)."""
+    t = np.asarray(theta, float)
+    z = np.log(t.copy())
+    z[2] = math.log((t[2] - 0.3) / (1.5 - t[2]))
+    return z
+
+
+def from_unconstrained(z):
+    z = torch.as_tensor(z)
+    t = torch.exp(z)
+    a = 0.3 + 1.2 * torch.sigmoid(z[..., 2])
+    return torch.cat([t[..., :2], a[..., None], t[..., 3:]], dim=-1)
+
+
+def fit(target: torch.Tensor, theta0, setup: PlateSetup, n_steps: int, iters: int = 100,
+        lr: float = 0.05, tol: float = 0.1, loss_fn=mrstft_loss, callback=None):
+    """Adam with a one-cycle cosine schedule on unconstrained parameters,
+    batched over rows of theta0.  Stops early when every loss is below tol.
+    Returns (theta [B,5], losses [B], iterations, history)."""
+    z = torch.tensor(np.stack([to_unconstrained(t) for t in np.atleast_2d(theta0)]),
+                     dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([z], lr=lr)
+    hist = []
+    tgt = target.reshape(-1, target.shape[-1])
+    for it in range(iters):
+        for gparam in opt.param_groups:
+            gparam["lr"] = one_cycle_cosine(it, iters, lr)
+        opt.zero_grad()
+        theta = from_unconstrained(z)
+        y = ModalFn.apply(theta, setup, n_steps)
+        L = loss_fn(y, tgt.expand_as(y), reduce=False)
+        hist.append(L.detach().cpu().numpy())
+        if callback:
+            callback(it, theta.detach(), L.detach())
+        if bool((L < tol).all()):
+            return theta.detach().numpy(), L.detach().cpu().numpy(), it, hist
+        L.sum().backward()
+        opt.step()
+    theta = from_unconstrained(z).detach()
+    return theta.numpy(), hist[-1], iters, hist

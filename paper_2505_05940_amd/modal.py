@@ -19,6 +19,7 @@ KIND = {"linear": 0, "tension": 1, "vk": 2}
 SCHEME = {"sv": 0, "tf": 1}
 FLAG_ASYNC = 1
 FLAG_GRAPH = 2
+FLAG_GRAD = 4
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSTABLE", -3: "ENOMEM", -4: "EHIP",
           -5: "ENONFINITE", -6: "ESTATE", -7: "EHANG"}
@@ -63,6 +64,11 @@ def _load():
     lib.modal_destroy.argtypes = [vp]
     lib.modal_destroy.restype = None
     lib.modal_last_error.restype = C.c_char_p
+    lib.modal_grad.argtypes = [vp, C.c_int64, _fp, C.c_int64, C.c_int32, _dp, _dp, _dp, _dp, _dp,
+                               _dp, _dp, vp]
+    lib.modal_grad.restype = C.c_int
+    lib.modal_set_tangent.argtypes = [vp, C.c_int32, _fp, vp]
+    lib.modal_set_tangent.restype = C.c_int
     lib.modal_plan.argtypes = [C.POINTER(modal_desc), C.c_int32, C.POINTER(C.c_int64)]
     lib.modal_plan.restype = C.c_int
     lib.modal_vk_coupling_sine.argtypes = [C.c_double, C.c_double, C.c_int32, _ip, _ip,
@@ -211,6 +217,38 @@ class Sim:
 
     def check(self):
         _check(lib.modal_check(self._ctx, _stream_handle(self._stream)))
+
+    def set_tangent(self, b, Hd):
+        """Tangent tensor dHt/dtheta of instance b (float32 [n_in, n_t, n_t])."""
+        if hasattr(Hd, "data_ptr"):
+            ptr = C.cast(C.c_void_p(Hd.data_ptr()), _fp)
+            keep = Hd
+        else:
+            keep = np.ascontiguousarray(Hd, dtype=np.float32)
+            ptr = keep.ctypes.data_as(_fp)
+        _check(lib.modal_set_tangent(self._ctx, b, ptr, _stream_handle(self._stream)))
+        del keep
+
+    def grad(self, n_steps, dL_dy, ckpt_every=0):
+        """Reverse-mode gradient of L over the first n_steps outputs from the
+        initial state; dL_dy is a CUDA float32 tensor [batch, >= n_steps].
+        Returns per-instance lists of numpy arrays (omega, gamma, c, x0, xm1)
+        and [batch] arrays (scale = dL/dlog s, theta)."""
+        assert dL_dy.is_cuda and dL_dy.dtype.itemsize == 4 and dL_dy.stride(1) == 1
+        M = self.modes_total
+        out = {k: np.zeros(M) for k in ("omega", "gamma", "c", "x0", "xm1")}
+        scale = np.zeros(self.batch)
+        theta = np.zeros(self.batch)
+        _check(lib.modal_grad(self._ctx, n_steps, C.cast(C.c_void_p(dL_dy.data_ptr()), _fp),
+                              dL_dy.stride(0), ckpt_every,
+                              *(out[k].ctypes.data_as(_dp) for k in ("omega", "gamma", "c", "x0", "xm1")),
+                              scale.ctypes.data_as(_dp), theta.ctypes.data_as(_dp),
+                              _stream_handle(self._stream)))
+        splits = np.cumsum(self.n_t)[:-1]
+        res = {k: np.split(v, splits) for k, v in out.items()}
+        res["scale"] = scale
+        res["theta"] = theta
+        return res
 
     def reset(self):
         _check(lib.modal_reset(self._ctx, _stream_handle(self._stream)))

@@ -1,0 +1,116 @@
+"""The reverse-mode gradient kernel (modal_grad, through the C ABI) against the
+FP64 oracle's reverse recursion, and against central differences of the GPU
+forward pass.
+
+The loss is a seeded linear functional L = sum_n g_n y_n (dL/dy = g), so both
+sides differentiate exactly the same scalar.  Bar: relative L2 error of each
+gradient vector <= 1e-4 against the oracle; 1e-3 against central
+differences (step 1e-4 relative)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint as OA
+from oracle import instances as OI
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2505_05940_amd import modal, physics
+    return modal, physics, torch
+
+
+def _oracle_grads(oinst, steps, g, Hdot=None):
+    r = OA.reverse(oinst, steps, 44100.0, g, Hdot=Hdot)
+    om, ga = OA.sv_omega_gamma_grads(r, oinst["omega"], oinst["gamma"], 1 / 44100.0)
+    return dict(omega=om, gamma=ga, c=r["c"], x0=r["x0"], xm1=r["xm1"], scale=r["scale"],
+                theta=r["theta"])
+
+
+def _cases():
+    wl_vk = W.plate_vk(n_t=14, n_in=11, family="sine", grid=None, n_steps=600)
+    wl_vk["strike"]["amplitude"] = 3e-3
+    wl_kc = W.string_kc(n_modes=12)
+    return wl_vk, wl_kc
+
+
+@pytest.mark.parametrize("max_wg,ckpt", [(0, 0), (3, 128)])
+def test_grad_matches_oracle(gpu, max_wg, ckpt):
+    modal, physics, torch = gpu
+    wl_vk, wl_kc = _cases()
+    steps = 600
+    pinsts = [physics.plate_instance(wl_vk), physics.string_instance(wl_kc)]
+    oinsts = [OI.plate_instance(wl_vk), OI.string_instance(wl_kc)]
+    rng = np.random.default_rng(5)
+    g = rng.normal(size=(2, steps))
+    g[0] /= np.abs(oinsts[0]["x0"]).max()
+    g[1] /= np.abs(oinsts[1]["x0"]).max()
+    print(f"case: grad vK 14/11 + KC 12, {steps} steps, max_wg={max_wg}, ckpt={ckpt}", flush=True)
+    sim = modal.Sim(pinsts, 44100.0, flags=modal.FLAG_GRAD, max_workgroups=max_wg)
+    if max_wg:
+        assert sim.info()["split_instances"] >= 1
+    res = sim.grad(steps, torch.tensor(g, dtype=torch.float32, device="cuda"), ckpt_every=ckpt)
+    for b in range(2):
+        ref = _oracle_grads(oinsts[b], steps, g[b].astype(np.float32).astype(float))
+        for k in ("omega", "gamma", "c", "x0", "xm1"):
+            assert rel(res[k][b], ref[k]) < TOL, (b, k, rel(res[k][b], ref[k]))
+        assert rel([res["scale"][b]], [ref["scale"]]) < TOL, (b, res["scale"][b], ref["scale"])
+    # the context is left at its initial state
+    y1 = sim.run(50).cpu().numpy()
+    sim.reset()
+    assert np.array_equal(sim.run(50).cpu().numpy(), y1)
+
+
+def test_tangent_direction(gpu):
+    modal, physics, torch = gpu
+    wl_vk, _ = _cases()
+    steps = 400
+    p = physics.plate_instance(wl_vk)
+    o = OI.plate_instance(wl_vk)
+    rng = np.random.default_rng(6)
+    Hd = rng.normal(size=p["Ht"].shape)
+    Hd = (0.5 * (Hd + Hd.transpose(0, 2, 1)) * np.abs(o["Ht"]).max()).astype(np.float32)
+    g = rng.normal(size=(1, steps)) / np.abs(o["x0"]).max()
+    sim = modal.Sim([p], 44100.0, flags=modal.FLAG_GRAD, max_workgroups=2)
+    sim.set_tangent(0, Hd)
+    res = sim.grad(steps, torch.tensor(g, dtype=torch.float32, device="cuda"), ckpt_every=150)
+    ref = _oracle_grads(o, steps, g[0].astype(np.float32).astype(float), Hdot=Hd.astype(float))
+    assert rel([res["theta"][0]], [ref["theta"]]) < TOL, (res["theta"][0], ref["theta"])
+    assert rel(res["omega"][0], ref["omega"]) < TOL
+
+
+def test_grad_matches_central_differences_on_gpu(gpu):
+    """dL/domega_k of the GPU adjoint against central differences of the GPU
+    forward (step 1e-4 relative): the float-float forward keeps the
+    difference quotient well above rounding."""
+    modal, physics, torch = gpu
+    wl_vk, _ = _cases()
+    steps = 600
+    p = physics.plate_instance(wl_vk)
+    rng = np.random.default_rng(7)
+    g = rng.normal(size=(1, steps)) / np.abs(p["x0"]).max()
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda")
+    sim = modal.Sim([p], 44100.0, flags=modal.FLAG_GRAD)
+    res = sim.grad(steps, gt)
+    for k in (0, 6, 13):
+        h = 1e-4 * p["omega"][k]
+        Ls = []
+        for sgn in (1, -1):
+            q = dict(p)
+            q["omega"] = p["omega"].copy()
+            q["omega"][k] += sgn * h
+            y = modal.Sim([q], 44100.0).run(steps).double().cpu().numpy()[0]
+            Ls.append(float(np.sum(g[0].astype(np.float32).astype(float) * y)))
+        fd = (Ls[0] - Ls[1]) / (2 * h)
+        assert abs(fd - res["omega"][0][k]) < 1e-3 * abs(res["omega"][0][k]), (k, fd, res["omega"][0][k])

@@ -111,3 +111,29 @@ def plate_sweep(n_t: int, seed: int = 2, n_steps: int = 44100) -> dict:
     """The paper's benchmark shapes: the single-plate geometry at 10/50/100
     modes (Sec. 3.2, Fig. 2), sine in-plane family, 1 s at 44.1 kHz."""
     return plate_vk(seed=seed, n_t=n_t, n_steps=n_steps, family="sine")
+
+
+def plate_fit(seed: int = 4, n_t: int = 200, n_in: int | None = None, n_steps: int = 44100,
+              perturb: float = 0.1) -> dict:
+    """Parameter fitting of one von Karman plate (steel, 1 mm, area 0.12 m^2,
+    base aspect 0.75, i.e. 0.4 x 0.3 m) by gradients through the time loop.
+
+    theta = (T0/rho_s, D/rho_s, aspect Ly/Lx, d1/(2 rho_s), d3/(2 rho_s)).
+    The base point has T0 = 50 N/m, steel's bending stiffness, d1^ = 1 /s and
+    d3^ such that the damping of a 5 kHz mode is about 50 /s; the target
+    parameters are the base ones times exp(U[-perturb, perturb]) each
+    (seeded).  Strike 1 h at a fixed relative position; pickup fixed.
+    """
+    rng = np.random.default_rng(seed)
+    h, rho, E, nu = 1e-3, 7860.0, 2e11, 0.3
+    rho_s = rho * h
+    D = E * h ** 3 / (12 * (1 - nu ** 2))
+    base = np.array([50.0 / rho_s, D / rho_s, 0.75, 1.0, 0.0])
+    # d3^ lambda at 5 kHz ~ 49 /s: lambda from omega^2 = D^ lambda^2 + T0^ lambda
+    w = 2 * np.pi * 5000.0
+    lam5 = (-base[0] + np.sqrt(base[0] ** 2 + 4 * base[1] * w * w)) / (2 * base[1])
+    base[4] = 49.0 / lam5
+    target = base * np.exp(rng.uniform(-perturb, perturb, size=5))
+    return dict(n_t=n_t, n_in=n_t if n_in is None else n_in, area=0.12, h=h, nu=nu, rho=rho,
+                base_aspect=0.75, strike=(0.37, 0.61, 1.0 * h, 0.1), out=(0.71, 0.29),
+                proj_grid=(200, 150), fs=FS, n_steps=n_steps, theta0=base, theta_target=target)
