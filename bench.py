@@ -85,7 +85,8 @@ def main():
     ap.add_argument("--samples-per-step", type=int, default=441)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--max-workgroups", type=int, default=0)
+    ap.add_argument("--max-workgroups", type=int, default=-1,
+                    help="co-resident workgroups for the plan; -1 = autotune on this batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-instances", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -116,9 +117,16 @@ def main():
         torch.cuda.synchronize()
         del a, b
     S = args.samples_per_step
+    mw = args.max_workgroups
+    if mw < 0:
+        from paper_2505_05940_amd.tune import autotune
+        t0 = time.time()
+        mw = autotune(insts, 44100.0, cache=None,
+                      log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        print(f"[bench] autotuned max_workgroups={mw} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     t0 = time.time()
     sim = modal.Sim(insts, 44100.0, flags=modal.FLAG_GRAPH | modal.FLAG_ASYNC,
-                    chunk_steps=S, max_workgroups=args.max_workgroups)
+                    chunk_steps=S, max_workgroups=mw)
     info = sim.info()
     del insts
     print(f"[bench] modal_init {time.time() - t0:.1f} s, plan {info}", file=sys.stderr, flush=True)
@@ -167,6 +175,7 @@ def main():
             "batch": args.batch, "modes_total": modes, "samples_per_step": S,
             "coupling_bytes_per_sample": info["coupling_bytes_per_step"],
             "workgroups": info["workgroups"], "split_instances": info["split_instances"],
+            "max_workgroups": mw,
             "fit_wall_time_s": None,
         },
         "roofline": {

@@ -64,8 +64,12 @@ enum {
   MODAL_FLAG_GRAPH = 2, /* modal_run records its launches into a hipGraph
                            on first use for a given (n_steps, y, y_stride)
                            and replays it afterwards                          */
-  MODAL_FLAG_GRAD = 4   /* plan the work so that modal_grad can run (its
+  MODAL_FLAG_GRAD = 4,  /* plan the work so that modal_grad can run (its
                            reverse kernel needs more LDS per workgroup)       */
+  MODAL_FLAG_SPLIT_ANY = 8 /* cut VK instances into row slabs whenever
+                           workgroups are free (tests, tuning); by default
+                           instances below 4 MB of tensor stay whole and a
+                           slab must pay for its per-step exchange          */
 };
 
 /* One modal system.  All arrays are host memory. */
@@ -96,8 +100,9 @@ typedef struct {
   const modal_instance *inst;   /* [batch]                                    */
   double fs;                    /* sampling rate (Hz), T = 1/fs               */
   int32_t flags;                /* MODAL_FLAG_*                               */
-  int32_t max_workgroups;       /* 0 = as many as fit co-resident on the GPU;
-                                   else an upper bound (tuning / tests)       */
+  int32_t max_workgroups;       /* 0 = default (at most 6 workgroups per CU,
+                                   and never more than fit co-resident); else
+                                   an upper bound, capped by co-residency     */
   int32_t chunk_steps;          /* steps per kernel launch; 0 = whole run     */
   int32_t reserved;             /* must be 0                                  */
 } modal_desc;

@@ -23,59 +23,77 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
                          int ntp, int qs, int row0, int row1, const float* Xs, const float* Us,
                          float* red, float4 (&Ju)[GM], float4 (&Fa)[GM], float& tsum, int G,
                          int lane) {
+  // Same sweep as the forward kernel (contiguous blocks of qs stored rows,
+  // per-block buffer resources, next block loaded ahead) with two
+  // right-hand sides, q and u, and optionally the tangent tensor times q.
   constexpr int J = kSweepLoads;
   constexpr int NR = TAN ? 3 : 2;  // reduced vectors per row: V, W (, Vd)
+  if (row1 <= row0) return;
   const int nc = ntp >> 2;
   const int qsnc = qs * nc;
-  int xsub[J];
+  int voff[J], sub[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int v = lane + kWave * j;
-    xsub[j] = v < qsnc ? v / nc : -1;
+    voff[j] = 16 * v;
+    sub[j] = v < qsnc ? v / nc : 0;
   }
-  const int nfull = nt / qs;
-  const int tail = nt - nfull * qs;
+  const int nblk = (nt + qs - 1) / qs;
   const long long blk_floats = (long long)qs * ntp;
   const long long row_floats = (long long)nt * ntp;
+  const int blk_bytes = 4 * qs * ntp;
+  const int last_bytes = 4 * (nt - (nblk - 1) * qs) * ntp;
   const int slab = qs * ntp;
-  for (int n = row0; n < row1; ++n) {
-    const float* p = Hb + (long long)n * row_floats + 4 * lane;
-    const float* pd = TAN ? Hdb + (long long)n * row_floats + 4 * lane : nullptr;
-    float4 aV[J], aW[J], aD[J];
+  int ln = row0, lb = 0;
+  auto load = [&](float4 (&h)[J], float4 (&hd)[J]) {
+    const bool live = ln < row1;
+    const long long o = live ? (long long)ln * row_floats + (long long)lb * blk_floats : 0;
+    const int bytes = live ? (lb == nblk - 1 ? last_bytes : blk_bytes) : 0;
+    const v4i r = buf_rsrc(Hb + o, bytes);
 #pragma unroll
-    for (int j = 0; j < J; ++j) aV[j] = aW[j] = aD[j] = f4(0.f);
-    int q0 = 0;
-    for (int b = 0; b <= nfull; ++b, p += blk_floats, q0 += qs) {
-      const int lim = b < nfull ? qs : tail;
-      if (lim == 0) break;
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+    if (TAN) {
+      const v4i rd = buf_rsrc(Hdb + o, bytes);
 #pragma unroll
-      for (int j = 0; j < J; ++j) {
-        if (xsub[j] >= 0 && xsub[j] < lim) {
-          const float4 h = ldnt4(p + 4 * kWave * j);
-          const float x = Xs[q0 + xsub[j]], u = Us[q0 + xsub[j]];
-          aV[j] = fma4(h, x, aV[j]);
-          aW[j] = fma4(h, u, aW[j]);
-          if (TAN) aD[j] = fma4(ldnt4(pd + 4 * kWave * j), x, aD[j]);
-        }
-      }
-      if (TAN) pd += blk_floats;
+      for (int j = 0; j < J; ++j) hd[j] = buf_ld4(rd, voff[j]);
     }
+    if (++lb == nblk) {
+      lb = 0;
+      ++ln;
+    }
+  };
+  float4 ha[J], hb[J], hda[J], hdb[J], aV[J], aW[J], aD[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) aV[j] = aW[j] = aD[j] = f4(0.f);
+  int n = row0, b = 0;
+  auto step = [&](float4 (&hc)[J], float4 (&hdc)[J], float4 (&hn)[J], float4 (&hdn)[J]) -> bool {
+    load(hn, hdn);
+    const int q0 = b * qs;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int qi = min(q0 + sub[j], nt - 1);
+      const float x = Xs[qi], u = Us[qi];
+      aV[j] = fma4(hc[j], x, aV[j]);
+      aW[j] = fma4(hc[j], u, aW[j]);
+      if (TAN) aD[j] = fma4(hdc[j], x, aD[j]);
+    }
+    if (++b < nblk) return true;
     float* rb = red + (n & 1) * NR * slab;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      if (xsub[j] >= 0) {
-        const int o = 4 * (lane + kWave * j);
+      if (voff[j] < blk_bytes) {
+        const int o = voff[j] >> 2;
         st4(rb + o, aV[j]);
         st4(rb + slab + o, aW[j]);
         if (TAN) st4(rb + 2 * slab + o, aD[j]);
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     float eta = 0.f, w = 0.f, etad = 0.f, vdu = 0.f;
-    float4 V[GM], W[GM], D[GM];
+    float4 V[GM], W[GM];
 #pragma unroll
     for (int g = 0; g < GM; ++g) {
-      V[g] = W[g] = D[g] = f4(0.f);
+      V[g] = W[g] = f4(0.f);
       const int k4 = lane + kWave * g;
       if (g < G && k4 < nc) {
         float4 sv = ld4(rb + 4 * k4), sw = ld4(rb + slab + 4 * k4);
@@ -87,7 +105,6 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
         }
         V[g] = sv;
         W[g] = sw;
-        D[g] = sd;
         const float4 x = ld4(Xs + 4 * k4), u = ld4(Us + 4 * k4);
         eta += dot4(sv, x);
         w += dot4(sv, u);
@@ -109,6 +126,13 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
       Ju[g] = fma4(V[g], 2.f * w, fma4(W[g], eta, Ju[g]));
       Fa[g] = fma4(V[g], eta, Fa[g]);
     }
+#pragma unroll
+    for (int j = 0; j < J; ++j) aV[j] = aW[j] = aD[j] = f4(0.f);
+    b = 0;
+    return ++n < row1;
+  };
+  load(ha, hda);
+  while (step(ha, hda, hb, hdb) && step(hb, hdb, ha, hda)) {
   }
 }
 

@@ -160,6 +160,7 @@ struct modal_ctx {
   long long h_floats = 0, part_floats = 0;
   int red_floats = 0;
   std::vector<UnitDev> units;
+  std::vector<InstDev> inst_host;
   std::vector<double> omega, gamma;  // concatenated over instances
   std::vector<int> kind;
   // gradient buffers (allocated on first modal_grad)
@@ -253,6 +254,14 @@ int validate(const modal_desc* d) {
   return MODAL_OK;
 }
 
+// Per-step cost of the exchange and barrier of one slab of a split instance,
+// in streamed-byte units (release fence, arrival, wait, acquire and reading
+// every slab's partial force: microseconds of one wave's streaming time).
+constexpr double kSplitSyncCost = 65536.0;
+// Instances below this cost are never split: their tensors stay L2-resident
+// from step to step and a whole-instance workgroup outruns any slab barrier.
+constexpr double kMinSplitCost = 4.0 * 1048576.0;
+
 // Planning cost of an instance in streamed-byte units: per in-plane row the
 // bytes of its tensor row plus the row's reduction; per step a fixed cost
 // for the state update and output.
@@ -280,15 +289,19 @@ int pack(const modal_desc* d, const std::vector<double>& row_cost,
     const modal_instance& I = d->inst[b];
     const int rows = I.kind == MODAL_KIND_VK ? I.n_in : 1;
     int S = 1;
-    if (I.kind == MODAL_KIND_VK && fixed_cost[b] + rows * row_cost[b] > cap) {
-      const int per = (int)std::floor((cap - fixed_cost[b]) / row_cost[b]);
+    const double whole = fixed_cost[b] + rows * row_cost[b];
+    const bool may_split = (d->flags & MODAL_FLAG_SPLIT_ANY) || whole >= kMinSplitCost;
+    if (I.kind == MODAL_KIND_VK && whole > cap && may_split) {
+      const double sync = (d->flags & MODAL_FLAG_SPLIT_ANY) ? 0.0 : kSplitSyncCost;
+      const int per = (int)std::floor((cap - sync - fixed_cost[b]) / row_cost[b]);
       if (per < 1) return n_bins + 1;
       S = (rows + per - 1) / per;
     }
     if (S > n_bins) return n_bins + 1;
     for (int s = 0; s < S; ++s) {
       const int r0 = (int)((long long)rows * s / S), r1 = (int)((long long)rows * (s + 1) / S);
-      units.push_back({b, r0, r1, s, fixed_cost[b] + (r1 - r0) * row_cost[b]});
+      const double sync = S > 1 && !(d->flags & MODAL_FLAG_SPLIT_ANY) ? kSplitSyncCost : 0.0;
+      units.push_back({b, r0, r1, s, sync + fixed_cost[b] + (r1 - r0) * row_cost[b]});
     }
   }
   std::vector<int> order(units.size());
@@ -323,8 +336,13 @@ bool plan_batch(const modal_desc* d, const std::vector<double>& row_cost,
                 const std::vector<double>& fixed_cost, double total, int n_bins,
                 std::vector<Unit>& units, std::vector<int>& bin_of, std::vector<double>& load) {
   double max_item = 0;
-  for (int b = 0; b < d->batch; ++b)
-    max_item = std::max(max_item, fixed_cost[b] + (d->inst[b].kind == MODAL_KIND_VK ? row_cost[b] : 0.0));
+  for (int b = 0; b < d->batch; ++b) {
+    const double whole = fixed_cost[b] + (d->inst[b].kind == MODAL_KIND_VK ? d->inst[b].n_in : 1) * row_cost[b];
+    const double one_row = ((d->flags & MODAL_FLAG_SPLIT_ANY) ? 0.0 : kSplitSyncCost) + fixed_cost[b] +
+                           (d->inst[b].kind == MODAL_KIND_VK ? row_cost[b] : 0.0);
+    const bool may_split = (d->flags & MODAL_FLAG_SPLIT_ANY) || whole >= kMinSplitCost;
+    max_item = std::max(max_item, may_split ? std::min(whole, one_row) : whole);
+  }
   double lo = std::max(total / n_bins, max_item), hi = std::max(lo, total) * 1.0001 + 1.0;
   if (pack(d, row_cost, fixed_cost, hi, n_bins, units, bin_of, load) > n_bins) return false;
   for (int it = 0; it < 40 && hi - lo > 1e-4 * lo; ++it) {
@@ -495,8 +513,14 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
     return fail(MODAL_EHIP, "step kernel does not fit on a CU");
   }
   c->occ = occ;
+  // Default: at most kDefaultWgPerCu workgroups per CU.  Measured on the
+  // 256-plate batch, fewer and deeper workgroups stream better than the
+  // occupancy limit (6 per CU: 6.1 TB/s; 13 per CU: 4.5 TB/s); an explicit
+  // max_workgroups (e.g. from the autotuner) overrides it.
+  constexpr int kDefaultWgPerCu = 6;
   int n_bins = occ * prop.multiProcessorCount;
   if (d->max_workgroups > 0) n_bins = std::min(n_bins, d->max_workgroups);
+  else n_bins = std::min(n_bins, kDefaultWgPerCu * prop.multiProcessorCount);
   n_bins = std::max(1, std::min(n_bins, 1 << 20));
   double total = 0;
   for (int b = 0; b < d->batch; ++b)
@@ -560,6 +584,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   c->n_units = (int)udev.size();
   c->state_floats = state_floats;
   c->units = udev;
+  c->inst_host = inst;
   c->h_floats = h_floats;
   c->part_floats = part_floats;
   for (int b = 0; b < d->batch; ++b) {
@@ -787,10 +812,7 @@ int modal_set_tangent(modal_ctx* c, int32_t b, const float* Hd, void* stream_) {
     if (r) return r;
     HIP_TRY(hipMemsetAsync(c->dHd, 0, sizeof(float) * (size_t)(c->h_floats + 64), s));
   }
-  std::vector<InstDev> inst(c->batch);
-  HIP_TRY(hipMemcpyAsync(inst.data(), c->P.inst, sizeof(InstDev) * c->batch, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  const InstDev& D = inst[b];
+  const InstDev& D = c->inst_host[b];
   HIP_TRY(hipMemcpy2DAsync(c->dHd + D.h_off, sizeof(float) * D.ntp, Hd, sizeof(float) * D.nt,
                            sizeof(float) * D.nt, (size_t)D.nin * D.nt, hipMemcpyDefault, s));
   HIP_TRY(hipStreamSynchronize(s));

@@ -20,6 +20,7 @@ SCHEME = {"sv": 0, "tf": 1}
 FLAG_ASYNC = 1
 FLAG_GRAPH = 2
 FLAG_GRAD = 4
+FLAG_SPLIT_ANY = 8
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSTABLE", -3: "ENOMEM", -4: "EHIP",
           -5: "ENONFINITE", -6: "ESTATE", -7: "EHANG"}
@@ -177,9 +178,9 @@ def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_ste
     return desc, keep, n_t
 
 
-def plan(instances, n_workgroups, fs=44100.0, scheme="sv"):
+def plan(instances, n_workgroups, fs=44100.0, scheme="sv", flags=0):
     """Host-only preview of the work partition (``modal_plan``)."""
-    desc, keep, _ = _build_desc(instances, fs, scheme, shapes_only=True)
+    desc, keep, _ = _build_desc(instances, fs, scheme, flags=flags, shapes_only=True)
     out = (C.c_int64 * 4)()
     _check(lib.modal_plan(C.byref(desc), n_workgroups, out))
     return dict(units=out[0], workgroups=out[1], makespan=out[2], mean=out[3])

@@ -1,0 +1,180 @@
+"""Learned initial guess for physical-parameter fitting.
+
+The paper fits physical parameters by gradient descent and reports that
+these fits are sensitive to initialisation, falling back on many random
+restarts (Sec. 3.3) and naming a more structured initialisation as the open
+problem (Sec. 4).  Here a small MLP, trained on (spectral features,
+parameters) pairs that the batched time-stepping kernel generates from
+seeded priors, maps a target sound's features to a starting point; gradient
+fitting then refines it, and the plain fit from the prior centre is both the
+fallback and the yardstick.
+
+Parameters theta = (T0^, D^, a, d1^, d3^) of a von Karman plate (fit.py).
+Priors: log-uniform over one decade centred on the base point for T0^, D^,
+d1^ and d3^; the aspect ratio a from a 64-point grid on [0.5, 1].
+Network: 1024 log-mel features (8 time slices x 128 mel bands) -> 4 hidden
+layers of 512 (ReLU) -> 5 normalised log-parameters; MSE loss; Adam.
+
+CLI: python -m paper_2505_05940_amd.proposal --help
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import fit, modal
+from .losses import logmel_features, mrstft_loss
+from .mlp import MLP
+
+DIMS = [1024, 512, 512, 512, 512, 5]
+ASPECTS = np.linspace(0.5, 1.0, 64)
+
+
+def prior_center(base):
+    c = np.array(base, float).copy()
+    c[2] = 0.75
+    return c
+
+
+def sample_prior(rng, n, base):
+    """n x 5 seeded draws."""
+    base = np.asarray(base, float)
+    th = np.empty((n, 5))
+    for i in (0, 1, 3, 4):
+        th[:, i] = base[i] * 10.0 ** rng.uniform(-0.5, 0.5, n)
+    th[:, 2] = rng.choice(ASPECTS, n)
+    return th
+
+
+def normalize(th, base):
+    """theta -> z in about [-1, 1]^5 (log-decades for the positive ones)."""
+    th = np.atleast_2d(th)
+    z = np.empty_like(th)
+    for i in (0, 1, 3, 4):
+        z[:, i] = 2.0 * np.log10(th[:, i] / base[i])
+    z[:, 2] = 4.0 * (th[:, 2] - 0.75)
+    return z
+
+
+def denormalize(z, base):
+    z = np.clip(np.atleast_2d(z), -1.0, 1.0)
+    th = np.empty_like(z)
+    for i in (0, 1, 3, 4):
+        th[:, i] = base[i] * 10.0 ** (0.5 * z[:, i])
+    th[:, 2] = 0.75 + 0.25 * z[:, 2]
+    return th
+
+
+def simulate(setup, thetas, n_steps, batch=4096):
+    """Outputs [n, n_steps] (CUDA float32) of the plates theta, by batches of
+    one persistent launch each."""
+    out = []
+    for s in range(0, len(thetas), batch):
+        insts = [fit.plate_instance(setup, t) for t in thetas[s:s + batch]]
+        sim = modal.Sim(insts, setup.fs)
+        out.append(sim.run(n_steps).clone())
+        sim.close()
+    return torch.cat(out)
+
+
+def features(y):
+    f = logmel_features(y)
+    return (f - f.mean(dim=1, keepdim=True)) / f.std(dim=1, keepdim=True).clamp_min(1e-6)
+
+
+def train(net, X, Z, epochs=60, batch=1024, lr=1e-3, seed=0, log=None):
+    """MSE on normalised parameters; returns the last epoch's mean loss."""
+    rng = np.random.default_rng(seed)
+    n = X.shape[0]
+    last = None
+    for ep in range(epochs):
+        order = torch.tensor(rng.permutation(n), device=X.device)
+        tot = 0.0
+        for s in range(0, n - batch + 1, batch):
+            idx = order[s:s + batch]
+            y = net.forward(X[idx])
+            d = y - Z[idx]
+            tot += float((d * d).mean())
+            net.backward(2.0 * d / d.numel())
+            net.adam_step(lr * 0.5 * (1 + np.cos(np.pi * ep / epochs)))
+        last = tot / max(1, n // batch)
+        if log:
+            log(f"epoch {ep} mse {last:.4f}")
+    return last
+
+
+def run(args):
+    torch.manual_seed(0)
+    fw = dict(n_t=args.modes, n_in=args.modes)
+    setup = fit.PlateSetup(n_t=args.modes, n_in=args.modes)
+    import workloads as W
+    wl = W.plate_fit(n_t=args.modes)
+    base = wl["theta0"]
+    rng = np.random.default_rng(5)
+    log = lambda m: print(f"[proposal] {m}", flush=True)
+    t0 = time.time()
+    th_train = sample_prior(rng, args.train, base)
+    X = []
+    for s in range(0, args.train, args.gen_batch):
+        y = simulate(setup, th_train[s:s + args.gen_batch], args.steps)
+        X.append(features(y))
+    X = torch.cat(X)
+    Z = torch.tensor(normalize(th_train, base), dtype=torch.float32, device="cuda")
+    t_gen = time.time() - t0
+    log(f"generated {args.train} sims x {args.steps} steps in {t_gen:.1f} s")
+    net = MLP(DIMS, max_batch=1024)
+    net.init_params(seed=1)
+    t0 = time.time()
+    mse = train(net, X, Z, epochs=args.epochs, log=log if args.verbose else None)
+    t_train = time.time() - t0
+    log(f"trained {args.epochs} epochs in {t_train:.1f} s, mse {mse:.4f}")
+    # held-out targets
+    rng_t = np.random.default_rng(50)
+    th_test = sample_prior(rng_t, args.test, base)
+    y_tgt = simulate(setup, th_test, args.steps)
+    z_hat = net.forward(features(y_tgt)).detach().cpu().numpy()
+    th_prop = denormalize(z_hat, base)
+    prop_err = float(np.mean(np.abs(normalize(th_prop, base) - normalize(th_test, base))))
+    log(f"proposal mean |z error| {prop_err:.3f} (prior spread about 0.5)")
+    results = {}
+    for arm, th0 in (("default", np.tile(prior_center(base), (args.test, 1))), ("proposal", th_prop)):
+        t0 = time.time()
+        done_at = np.full(args.test, -1)
+
+        def cb(it, theta, L):
+            ok = (L.cpu().numpy() < args.tol) & (done_at < 0)
+            done_at[ok] = it
+        th, L, iters, _ = fit.fit(y_tgt, th0, setup, args.steps, iters=args.iters, lr=args.lr,
+                                  tol=args.tol, callback=cb)
+        wall = time.time() - t0
+        results[arm] = dict(success_rate=float(np.mean(done_at >= 0)), wall_s=wall,
+                            iterations=int(iters), final_loss_median=float(np.median(L)))
+        log(f"{arm}: {results[arm]}")
+    out = dict(train=args.train, steps=args.steps, modes=args.modes, epochs=args.epochs,
+               test=args.test, gen_s=t_gen, train_s=t_train, mlp_mse=mse, proposal_z_err=prop_err,
+               arms=results)
+    print(json.dumps(out))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description="train the proposal network and compare fits")
+    ap.add_argument("--modes", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=11025)
+    ap.add_argument("--train", type=int, default=16384)
+    ap.add_argument("--gen-batch", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--test", type=int, default=32)
+    ap.add_argument("--iters", type=int, default=60)
+    ap.add_argument("--lr", type=float, default=0.05)
+    ap.add_argument("--tol", type=float, default=0.1)
+    ap.add_argument("--verbose", action="store_true")
+    run(ap.parse_args())
+
+
+if __name__ == "__main__":
+    main()

@@ -82,10 +82,15 @@ def test_plan_balances_the_batched_workload():
 
 
 def test_plan_splits_only_when_needed():
+    """Small instances (tensor L2-resident) stay whole whatever the budget;
+    a large one is cut into row slabs when workgroups are available."""
     from paper_2505_05940_amd import modal
-    n = 40
-    inst = dict(kind="vk", omega=np.full(n, 1e3), gamma=np.ones(n), x0=np.zeros(n),
-                xm1=np.zeros(n), c=np.ones(n), n_in=n)
-    assert modal.plan([inst], 1)["units"] == 1
-    p = modal.plan([inst], 8)
-    assert p["units"] == 8 and p["workgroups"] == 8  # one instance: rows split 8 ways
+
+    def inst(n):
+        return dict(kind="vk", omega=np.full(n, 1e3), gamma=np.ones(n), x0=np.zeros(n),
+                    xm1=np.zeros(n), c=np.ones(n), n_in=n)
+    assert modal.plan([inst(40)], 8)["units"] == 1
+    assert modal.plan([inst(40)] * 16, 1536)["units"] == 16
+    assert modal.plan([inst(120)], 1)["units"] == 1
+    p = modal.plan([inst(120)], 8)
+    assert p["units"] == 8 and p["workgroups"] == 8

@@ -53,3 +53,23 @@ def test_chain_rule_against_oracle_differences():
         tm[i] -= h
         fd = (L(tp) - L(tm)) / (2 * h)
         assert abs(fd - grad[i]) < 2e-4 * abs(fd), (fit.PARAM_NAMES[i], fd, grad[i])
+
+
+def test_proposal_normalisation_roundtrip_and_prior_range():
+    from paper_2505_05940_amd import proposal
+    base = W.plate_fit(n_t=10)["theta0"]
+    th = proposal.sample_prior(np.random.default_rng(0), 200, base)
+    z = proposal.normalize(th, base)
+    assert np.abs(z).max() <= 1.0 + 1e-12
+    assert np.allclose(proposal.denormalize(z, base), th, rtol=1e-12)
+    assert set(np.unique(th[:, 2])) <= set(proposal.ASPECTS)
+
+
+def test_unconstrained_map_roundtrip():
+    import torch
+    from paper_2505_05940_amd import fit
+    th = np.array([6.0, 2.3, 0.8, 1.2, 0.002])
+    z = fit.to_unconstrained(th)
+    assert np.allclose(fit.from_unconstrained(torch.tensor(z)).numpy(), th, rtol=1e-12)
+    assert abs(fit.one_cycle_cosine(0, 100, 1.0) - 1.0 / 25) < 1e-12
+    assert abs(fit.one_cycle_cosine(30, 100, 1.0) - 1.0) < 1e-12

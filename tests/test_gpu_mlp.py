@@ -1,7 +1,9 @@
 """The proposal network's HIP kernels (through the C ABI) against the FP64
-reference.  Operands are rounded to BF16 inside the GEMMs (FP32 accumulate),
-so the bar is a relative error of 2e-2 on outputs and gradients computed from
-BF16-representable inputs and weights (the reference sees the same values)."""
+reference.  Operands are rounded to BF16 inside the GEMMs (FP32 accumulate).
+Against the same arithmetic in FP64 (operands rounded to BF16 per GEMM) the
+bar is 1e-3 on outputs and 5e-3 on gradients; against the exact FP64 network, 2e-2 on outputs and, for the
+five-layer network, 8e-2 on gradients, where the per-GEMM BF16 rounding of
+the back-propagated signal compounds."""
 import numpy as np
 import pytest
 
@@ -15,6 +17,55 @@ def _bf16(a):
     u = a.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
     return u.astype(np.uint32).view(np.float32)
+
+
+def _bf16_forward(theta, dims, x):
+    """The kernel's arithmetic in FP64: GEMM operands rounded to BF16,
+    products accumulated exactly, bias and ReLU in full precision."""
+    acts = [x]
+    layers = OM.unflatten(theta, dims)
+    for l, (W, b) in enumerate(layers):
+        z = _bf16(acts[-1]).astype(float) @ _bf16(W).astype(float).T + b
+        acts.append(np.maximum(z, 0.0) if l + 1 < len(layers) else z)
+    return acts
+
+
+def _bf16_backward(theta, dims, acts, dy):
+    layers = OM.unflatten(theta, dims)
+    g = dy
+    out = [None] * len(layers)
+    for l in range(len(layers) - 1, -1, -1):
+        W, _ = layers[l]
+        gb = _bf16(g).astype(float)
+        out[l] = np.concatenate([(gb.T @ _bf16(acts[l]).astype(float)).ravel(), g.sum(axis=0)])
+        if l > 0:
+            g = (gb @ _bf16(W).astype(float)) * (acts[l] > 0)
+    return np.concatenate(out)
+
+
+def test_matches_bf16_operand_reference_at_full_size():
+    """1024 -> 4 x 512 -> 5 at batch 256 against the same arithmetic in FP64
+    (operands rounded to BF16 per GEMM): only FP32 accumulation order and
+    rare ReLU decisions at zero differ."""
+    import torch
+    from paper_2505_05940_amd.mlp import MLP
+    dims, B = [1024, 512, 512, 512, 512, 5], 256
+    rng = np.random.default_rng(4)
+    net = MLP(dims, max_batch=B)
+    net.init_params(seed=5)
+    theta = net.params().astype(float)
+    x = rng.normal(size=(B, dims[0]))
+    y = net.forward(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    acts = _bf16_forward(theta, dims, x.astype(np.float32).astype(float))
+    assert np.linalg.norm(y - acts[-1]) / np.linalg.norm(acts[-1]) < 1e-3
+    dy = rng.normal(size=(B, dims[-1]))
+    net.backward(torch.tensor(dy, dtype=torch.float32, device="cuda"))
+    g = net.grads()
+    g_ref = _bf16_backward(theta, dims, acts, dy.astype(np.float32).astype(float))
+    # a handful of ReLU decisions at z ~ 0 differ between the FP32 and FP64
+    # activations and re-round the back-propagated signal differently
+    assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) < 5e-3
+    net.close()
 
 
 @pytest.mark.parametrize("dims,B", [([1024, 512, 512, 512, 512, 5], 256), ([37, 70, 3], 45)])
@@ -34,7 +85,8 @@ def test_forward_backward_adam_match_reference(dims, B):
     net.backward(torch.tensor(dy, device="cuda"))
     g = net.grads()
     g_ref = OM.backward(theta.astype(float), dims, x.astype(float), dy.astype(float))
-    assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) < 2e-2
+    # BF16 operands in every GEMM compound over the layers (2^-8 each)
+    assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) < (8e-2 if len(dims) > 3 else 2e-2)
     net.adam_step(1e-3)
     p1 = net.params()
     p_ref, _, _ = OM.adam(theta.astype(float), g.astype(float), 0 * g_ref, 0 * g_ref, 1, lr=1e-3)

@@ -92,7 +92,7 @@ def test_ragged_batch_split_and_packed(gpu, max_wg):
     lin["kind"] = "linear"
     insts.append(lin)
     _say(f"case: ragged batch of {len(insts)}, max_workgroups={max_wg}")
-    sim = modal.Sim(insts, 44100.0, max_workgroups=max_wg)
+    sim = modal.Sim(insts, 44100.0, max_workgroups=max_wg, flags=modal.FLAG_SPLIT_ANY)
     info = sim.info()
     if max_wg:
         assert info["workgroups"] <= max_wg and info["split_instances"] >= 1, info
@@ -110,9 +110,9 @@ def test_resume_and_determinism(gpu):
     modal, physics = gpu
     wls = _ragged_batch()[2:6]
     insts = [physics.plate_instance(w) for w in wls]
-    a = modal.Sim(insts, 44100.0, max_workgroups=5)
+    a = modal.Sim(insts, 44100.0, max_workgroups=5, flags=modal.FLAG_SPLIT_ANY)
     y_full = a.run(2000).cpu().numpy()
-    b = modal.Sim(insts, 44100.0, max_workgroups=5)
+    b = modal.Sim(insts, 44100.0, max_workgroups=5, flags=modal.FLAG_SPLIT_ANY)
     y1 = b.run(700).cpu().numpy()
     y2 = b.run(1300).cpu().numpy()
     assert np.array_equal(y_full, np.concatenate([y1, y2], axis=1))
@@ -125,8 +125,9 @@ def test_graph_replay_matches_eager(gpu):
     wls = _ragged_batch()[3:5]
     insts = [physics.plate_instance(w) for w in wls]
     import torch
-    eager = modal.Sim(insts, 44100.0, max_workgroups=4)
-    graph = modal.Sim(insts, 44100.0, max_workgroups=4, flags=modal.FLAG_GRAPH, chunk_steps=250)
+    eager = modal.Sim(insts, 44100.0, max_workgroups=4, flags=modal.FLAG_SPLIT_ANY)
+    graph = modal.Sim(insts, 44100.0, max_workgroups=4, flags=modal.FLAG_GRAPH | modal.FLAG_SPLIT_ANY,
+                      chunk_steps=250)
     out = torch.empty((2, 500), device="cuda")
     for rep in range(3):
         ye = eager.run(500).cpu().numpy()
