@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--max-workgroups", type=int, default=-1,
                     help="co-resident workgroups for the plan; -1 = autotune on this batch")
+    ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (with --max-workgroups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-instances", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -117,16 +118,17 @@ def main():
         torch.cuda.synchronize()
         del a, b
     S = args.samples_per_step
-    mw = args.max_workgroups
+    mw, waves = args.max_workgroups, args.waves
     if mw < 0:
         from paper_2505_05940_amd.tune import autotune
         t0 = time.time()
-        mw = autotune(insts, 44100.0, cache=None,
-                      log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
-        print(f"[bench] autotuned max_workgroups={mw} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+        waves, mw = autotune(insts, 44100.0, cache=None,
+                             log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        print(f"[bench] autotuned waves={waves} max_workgroups={mw} in {time.time() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     t0 = time.time()
     sim = modal.Sim(insts, 44100.0, flags=modal.FLAG_GRAPH | modal.FLAG_ASYNC,
-                    chunk_steps=S, max_workgroups=mw)
+                    chunk_steps=S, max_workgroups=mw, waves=waves)
     info = sim.info()
     del insts
     print(f"[bench] modal_init {time.time() - t0:.1f} s, plan {info}", file=sys.stderr, flush=True)
@@ -175,7 +177,7 @@ def main():
             "batch": args.batch, "modes_total": modes, "samples_per_step": S,
             "coupling_bytes_per_sample": info["coupling_bytes_per_step"],
             "workgroups": info["workgroups"], "split_instances": info["split_instances"],
-            "max_workgroups": mw,
+            "max_workgroups": mw, "waves_per_workgroup": waves or 4,
             "fit_wall_time_s": None,
         },
         "roofline": {

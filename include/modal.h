@@ -104,7 +104,8 @@ typedef struct {
                                    and never more than fit co-resident); else
                                    an upper bound, capped by co-residency     */
   int32_t chunk_steps;          /* steps per kernel launch; 0 = whole run     */
-  int32_t reserved;             /* must be 0                                  */
+  int32_t waves;                /* waves (64 lanes) per workgroup sharing a
+                                   work unit's rows: 0 = default (4), 1 or 4  */
 } modal_desc;
 
 /* Validates the description (before any device work), computes the per-mode

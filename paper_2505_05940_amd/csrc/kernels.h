@@ -1,5 +1,7 @@
 // Device-side data layout shared by the step kernel and the host planner.
 #pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace modal {
@@ -34,6 +36,26 @@ struct UnitDev {
   int J;          // float4 loads per lane per sweep (kSweepLoads)
   int pad;
 };
+
+// Dynamic LDS of the step kernel: q^n [kMaxModes], per-wave partial forces
+// [NW][kMaxModes] (NW > 1), a flag word (16 bytes), per-wave reduction
+// buffers [NW][red_floats].
+struct StepLds {
+  float *xs, *fred, *red;
+  int* flag;
+};
+__host__ __device__ inline size_t step_lds_bytes(int nw, int red_floats) {
+  return sizeof(float) * ((size_t)kMaxModes + (nw > 1 ? (size_t)nw * kMaxModes : 0) + 4 +
+                          (size_t)nw * red_floats);
+}
+__host__ __device__ inline StepLds step_lds(float* base, int nw, int red_floats) {
+  StepLds L;
+  L.xs = base;
+  L.fred = base + kMaxModes;
+  L.flag = reinterpret_cast<int*>(L.fred + (nw > 1 ? nw * kMaxModes : 0));
+  L.red = reinterpret_cast<float*>(L.flag + 4);
+  return L;
+}
 
 struct StepParams {
   const InstDev* inst;

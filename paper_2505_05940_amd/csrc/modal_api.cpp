@@ -15,10 +15,10 @@
 #include "kernels.h"
 
 namespace modal {
-hipError_t launch_step(const StepParams& P, int gm, int n_wg, size_t lds_bytes, hipStream_t s);
+hipError_t launch_step(const StepParams& P, int gm, int nw, int n_wg, size_t lds_bytes, hipStream_t s);
 hipError_t launch_advance(long long* step_base, int n, hipStream_t s);
 hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s);
-hipError_t step_occupancy(int* blocks_per_cu, int gm, size_t lds_bytes);
+hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes);
 hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int n_wg, size_t lds, hipStream_t s);
 hipError_t grad_occupancy(int* blocks, int gm, bool tangent, size_t lds);
 hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
@@ -139,7 +139,7 @@ struct Unit {
 struct modal_ctx {
   int batch = 0, scheme = 0, flags = 0, chunk = 0;
   double fs = 0;
-  int n_wg = 0, n_units = 0, n_split = 0, occ = 0, gm = 1;
+  int n_wg = 0, n_units = 0, n_split = 0, occ = 0, gm = 1, nw = 4;
   double makespan = 0, mean_load = 0;
   size_t lds_bytes = 0, grad_lds = 0;
   long long coupling_bytes = 0, padded_bytes = 0, steps = 0;
@@ -214,8 +214,8 @@ int validate(const modal_desc* d) {
   if (!(d->fs > 0) || !std::isfinite(d->fs)) return fail(MODAL_EINVAL, "fs must be > 0");
   if (d->scheme != MODAL_SCHEME_SV && d->scheme != MODAL_SCHEME_TF)
     return fail(MODAL_EINVAL, "unknown scheme");
-  if (d->reserved != 0 || d->max_workgroups < 0 || d->chunk_steps < 0)
-    return fail(MODAL_EINVAL, "reserved/max_workgroups/chunk_steps");
+  if ((d->waves != 0 && d->waves != 1 && d->waves != 4) || d->max_workgroups < 0 || d->chunk_steps < 0)
+    return fail(MODAL_EINVAL, "waves (0, 1 or 4), max_workgroups or chunk_steps");
   const double T = 1.0 / d->fs;
   for (int b = 0; b < d->batch; ++b) {
     const modal_instance& I = d->inst[b];
@@ -485,7 +485,8 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
     unit_costs(I, row_cost[b], fixed_cost[b]);
   }
   c->mode_floats = mode_floats;
-  c->lds_bytes = sizeof(float) * (size_t)(kMaxModes + red_floats);
+  c->nw = d->waves == 0 ? 4 : d->waves;
+  c->lds_bytes = step_lds_bytes(c->nw, red_floats);
   for (int b = 0; b < d->batch; ++b) {
     const int g = (inst[b].ntp / 4 + kWave - 1) / kWave;
     c->gm = std::max(c->gm, g <= 1 ? 1 : (g <= 2 ? 2 : 4));
@@ -497,7 +498,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, dev));
   int occ = 0;
-  HIP_TRY(step_occupancy(&occ, c->gm, c->lds_bytes));
+  HIP_TRY(step_occupancy(&occ, c->gm, c->nw, c->lds_bytes));
   c->red_floats = red_floats;
   c->grad_lds = sizeof(float) * (size_t)(2 * kMaxModes + 3 * red_floats);
   if (d->flags & MODAL_FLAG_GRAD) {
@@ -749,7 +750,7 @@ static int enqueue_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride
     P.y = y + done;
     P.y_stride = y_stride;
     P.n_steps = (int)k;
-    HIP_TRY(launch_step(P, c->gm, c->n_wg, c->lds_bytes, s));
+    HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
     HIP_TRY(launch_advance(c->dStep, (int)k, s));
   }
   return MODAL_OK;
@@ -865,7 +866,7 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     P.ckpt = c->dCkpt;
     P.ckpt_every = K;
     P.n_steps = (int)n_steps;
-    HIP_TRY(launch_step(P, c->gm, c->n_wg, c->lds_bytes, s));
+    HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
   }
   HIP_TRY(hipMemsetAsync(c->dAdj, 0, sizeof(float) * 4 * (size_t)sf, s));
   HIP_TRY(hipMemsetAsync(c->dAcc, 0, sizeof(float) * 12 * (size_t)sf, s));
@@ -903,7 +904,7 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     P.rec_d = c->dRec + (size_t)K * mf;
     P.rec_base = s0;
     P.n_steps = len;
-    HIP_TRY(launch_step(P, c->gm, c->n_wg, c->lds_bytes, s));
+    HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
     G.seg_base = s0;
     G.seg_len = len;
     G.done_before = n_steps - s0 - len;

@@ -160,12 +160,18 @@ __device__ __forceinline__ void update_groups(const StepParams& P, const InstDev
 }
 
 // GM: float4 column groups per lane the launch supports (modes <= 256 GM).
-template <int GM>
-__global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
+// NW: waves per workgroup.  A unit's rows are divided among the NW waves,
+// each sweeping its share with its own LDS reduction buffer; the per-wave
+// partial forces are summed through LDS by wave 0, which also owns the
+// output, the exchange with other workgroups and the state update.
+template <int GM, int NW>
+__global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
   extern __shared__ float4 lds4[];
-  float* Xs = reinterpret_cast<float*>(lds4);
-  float* red = Xs + kMaxModes;
-  const int lane = threadIdx.x;
+  StepLds L = step_lds(reinterpret_cast<float*>(lds4), NW, P.red_floats);
+  float* Xs = L.xs;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  float* red = L.red + wave * P.red_floats;
   const int u0 = P.wg_begin[blockIdx.x];
   const int u1 = P.wg_begin[blockIdx.x + 1];
   const long long base = *P.step_base;
@@ -178,47 +184,50 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
       const InstDev I = P.inst[U.inst];
       const int nc = I.ntp >> 2;
       const int G = (nc + kWave - 1) / kWave;
-      float ypart = 0.f, spart = 0.f;
+      float spart = 0.f;
+      if (wave == 0) {
+        float ypart = 0.f;
 #pragma unroll
-      for (int g = 0; g < GM; ++g) {
-        const int k4 = lane + kWave * g;
-        if (g < G && k4 < nc) {
-          const float4 xh = ld4(P.x_hi + U.state_off + 4 * k4);
-          const float4 c = ld4(P.c_out + I.mode_off + 4 * k4);
-          ypart += dot4(c, xh);
-          if (I.kind == KIND_VK) {
-            st4(Xs + 4 * k4, xh);
-          } else if (I.kind == KIND_TENSION) {
-            const float4 l = ld4(P.lam + I.mode_off + 4 * k4);
-            const float4 lx = make_float4(l.x * xh.x, l.y * xh.y, l.z * xh.z, l.w * xh.w);
-            spart += dot4(lx, xh);
-          }
-        }
-      }
-      if (U.slab == 0) {
-        const float yv = wave_sum(ypart);
-        if (lane == 0 && P.y) P.y[(long long)I.out_row * P.y_stride + s] = yv;
-        if (P.ckpt && n % P.ckpt_every == 0) {
-          float* cp = P.ckpt + (n / P.ckpt_every) * 4LL * P.mode_floats + I.mode_off;
-          for (int g = 0; g < GM; ++g) {
-            const int k4 = lane + kWave * g;
-            if (g < G && k4 < nc) {
-              const int so = U.state_off + 4 * k4;
-              st4(cp + 4 * k4, ld4(P.x_hi + so));
-              st4(cp + P.mode_floats + 4 * k4, ld4(P.x_lo + so));
-              st4(cp + 2 * P.mode_floats + 4 * k4, ld4(P.d_hi + so));
-              st4(cp + 3 * P.mode_floats + 4 * k4, ld4(P.d_lo + so));
+        for (int g = 0; g < GM; ++g) {
+          const int k4 = lane + kWave * g;
+          if (g < G && k4 < nc) {
+            const float4 xh = ld4(P.x_hi + U.state_off + 4 * k4);
+            const float4 c = ld4(P.c_out + I.mode_off + 4 * k4);
+            ypart += dot4(c, xh);
+            if (I.kind == KIND_VK) {
+              st4(Xs + 4 * k4, xh);
+            } else if (I.kind == KIND_TENSION) {
+              const float4 l = ld4(P.lam + I.mode_off + 4 * k4);
+              const float4 lx = make_float4(l.x * xh.x, l.y * xh.y, l.z * xh.z, l.w * xh.w);
+              spart += dot4(lx, xh);
             }
           }
         }
-        if (P.rec_x) {
-          const long long ro = (n - P.rec_base) * P.mode_floats + I.mode_off;
-          for (int g = 0; g < GM; ++g) {
-            const int k4 = lane + kWave * g;
-            if (g < G && k4 < nc) {
-              const int so = U.state_off + 4 * k4;
-              st4(P.rec_x + ro + 4 * k4, ld4(P.x_hi + so));
-              st4(P.rec_d + ro + 4 * k4, ld4(P.d_hi + so));
+        if (U.slab == 0) {
+          const float yv = wave_sum(ypart);
+          if (lane == 0 && P.y) P.y[(long long)I.out_row * P.y_stride + s] = yv;
+          if (P.ckpt && n % P.ckpt_every == 0) {
+            float* cp = P.ckpt + (n / P.ckpt_every) * 4LL * P.mode_floats + I.mode_off;
+            for (int g = 0; g < GM; ++g) {
+              const int k4 = lane + kWave * g;
+              if (g < G && k4 < nc) {
+                const int so = U.state_off + 4 * k4;
+                st4(cp + 4 * k4, ld4(P.x_hi + so));
+                st4(cp + P.mode_floats + 4 * k4, ld4(P.x_lo + so));
+                st4(cp + 2 * P.mode_floats + 4 * k4, ld4(P.d_hi + so));
+                st4(cp + 3 * P.mode_floats + 4 * k4, ld4(P.d_lo + so));
+              }
+            }
+          }
+          if (P.rec_x) {
+            const long long ro = (n - P.rec_base) * P.mode_floats + I.mode_off;
+            for (int g = 0; g < GM; ++g) {
+              const int k4 = lane + kWave * g;
+              if (g < G && k4 < nc) {
+                const int so = U.state_off + 4 * k4;
+                st4(P.rec_x + ro + 4 * k4, ld4(P.x_hi + so));
+                st4(P.rec_d + ro + 4 * k4, ld4(P.d_hi + so));
+              }
             }
           }
         }
@@ -227,9 +236,27 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
 #pragma unroll
       for (int g = 0; g < GM; ++g) Fa[g] = f4(0.f);
       if (I.kind == KIND_VK) {
-        __syncthreads();
-        vk_rows<GM>(P.H + I.h_off, I.nt, I.ntp, U.qs, U.row0, U.row1, Xs, red, Fa, G, lane);
-      } else if (I.kind == KIND_TENSION) {
+        __syncthreads();  // q^n in LDS
+        const int R = U.row1 - U.row0;
+        const int r0 = U.row0 + (R * wave) / NW, r1 = U.row0 + (R * (wave + 1)) / NW;
+        vk_rows<GM>(P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa, G, lane);
+        if (NW > 1) {
+#pragma unroll
+          for (int g = 0; g < GM; ++g) {
+            const int k4 = lane + kWave * g;
+            if (g < G && k4 < nc) st4(L.fred + wave * kMaxModes + 4 * k4, Fa[g]);
+          }
+          __syncthreads();
+          if (wave == 0) {
+#pragma unroll
+            for (int g = 0; g < GM; ++g) {
+              const int k4 = lane + kWave * g;
+              if (g < G && k4 < nc)
+                for (int w = 1; w < NW; ++w) Fa[g] = add4(Fa[g], ld4(L.fred + w * kMaxModes + 4 * k4));
+            }
+          }
+        }
+      } else if (I.kind == KIND_TENSION && wave == 0) {
         const float S = wave_sum(spart) * I.kappa;
 #pragma unroll
         for (int g = 0; g < GM; ++g) {
@@ -241,42 +268,53 @@ __global__ void __launch_bounds__(kWave) step_kernel(StepParams P) {
           }
         }
       }
-      if (I.nslab == 1) {
-        update_groups<GM>(P, I, U.state_off, Fa, n, G, lane);
-      } else {
-        float* dst = P.part + I.part_off + ((long long)(n & 1) * I.nslab + U.slab) * I.ntp;
+      if (wave == 0) {
+        if (I.nslab == 1) {
+          update_groups<GM>(P, I, U.state_off, Fa, n, G, lane);
+        } else {
+          float* dst = P.part + I.part_off + ((long long)(n & 1) * I.nslab + U.slab) * I.ntp;
 #pragma unroll
-        for (int g = 0; g < GM; ++g) {
-          const int k4 = lane + kWave * g;
-          if (g < G && k4 < nc) st4(dst + 4 * k4, Fa[g]);
+          for (int g = 0; g < GM; ++g) {
+            const int k4 = lane + kWave * g;
+            if (g < G && k4 < nc) st4(dst + 4 * k4, Fa[g]);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __builtin_amdgcn_wave_barrier();
+          if (lane == 0)
+            __hip_atomic_fetch_add(&P.ctr[U.inst], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (lane == 0)
-          __hip_atomic_fetch_add(&P.ctr[U.inst], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
-      __syncthreads();
+      __syncthreads();  // LDS reused by the next unit
     }
     // ---------------- phase 2: split instances wait, sum partials, update
     for (int u = u0; u < u1; ++u) {
       const UnitDev U = P.unit[u];
       const InstDev I = P.inst[U.inst];
       if (I.nslab == 1) continue;
-      const unsigned int target = (unsigned int)I.nslab * (unsigned int)(n + 1);
-      if (!wait_counter(&P.ctr[U.inst], target, P.flags)) return;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      const int nc = I.ntp >> 2;
-      const int G = (nc + kWave - 1) / kWave;
-      const float* src = P.part + I.part_off + (long long)(n & 1) * I.nslab * I.ntp;
-      float4 F[GM];
-#pragma unroll
-      for (int g = 0; g < GM; ++g) {
-        F[g] = f4(0.f);
-        const int k4 = lane + kWave * g;
-        if (g < G && k4 < nc)
-          for (int t = 0; t < I.nslab; ++t) F[g] = add4(F[g], ld4(src + (long long)t * I.ntp + 4 * k4));
+      if (wave == 0) {
+        const unsigned int target = (unsigned int)I.nslab * (unsigned int)(n + 1);
+        const bool ok = wait_counter(&P.ctr[U.inst], target, P.flags);
+        if (lane == 0) L.flag[0] = ok ? 1 : 0;
       }
-      update_groups<GM>(P, I, U.state_off, F, n, G, lane);
+      __syncthreads();
+      if (L.flag[0] == 0) return;  // every wave leaves together
+      if (wave == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int nc = I.ntp >> 2;
+        const int G = (nc + kWave - 1) / kWave;
+        const float* src = P.part + I.part_off + (long long)(n & 1) * I.nslab * I.ntp;
+        float4 F[GM];
+#pragma unroll
+        for (int g = 0; g < GM; ++g) {
+          F[g] = f4(0.f);
+          const int k4 = lane + kWave * g;
+          if (g < G && k4 < nc)
+            for (int t = 0; t < I.nslab; ++t)
+              F[g] = add4(F[g], ld4(src + (long long)t * I.ntp + 4 * k4));
+        }
+        update_groups<GM>(P, I, U.state_off, F, n, G, lane);
+      }
+      __syncthreads();  // flag reused
     }
   }
 }
@@ -326,14 +364,16 @@ __global__ void check_kernel(const float* H, const InstDev* inst, int* out) {
 // Launch wrappers used by the host code (same translation unit keeps the
 // kernels' symbols local to this file).
 namespace modal {
-// gm: float4 column groups per lane needed by the widest instance (1, 2 or 4)
-hipError_t launch_step(const StepParams& P, int gm, int n_wg, size_t lds_bytes, hipStream_t s) {
-  if (gm <= 1)
-    hipLaunchKernelGGL(step_kernel<1>, dim3(n_wg), dim3(kWave), lds_bytes, s, P);
-  else if (gm <= 2)
-    hipLaunchKernelGGL(step_kernel<2>, dim3(n_wg), dim3(kWave), lds_bytes, s, P);
-  else
-    hipLaunchKernelGGL(step_kernel<4>, dim3(n_wg), dim3(kWave), lds_bytes, s, P);
+// gm: float4 column groups per lane needed by the widest instance (1, 2 or
+// 4); nw: waves per workgroup (1 or 4).
+hipError_t launch_step(const StepParams& P, int gm, int nw, int n_wg, size_t lds_bytes, hipStream_t s) {
+#define SL(G, W) hipLaunchKernelGGL((step_kernel<G, W>), dim3(n_wg), dim3(kWave * W), lds_bytes, s, P)
+  if (nw == 1) {
+    if (gm <= 1) SL(1, 1); else if (gm <= 2) SL(2, 1); else SL(4, 1);
+  } else {
+    if (gm <= 1) SL(1, 4); else if (gm <= 2) SL(2, 4); else SL(4, 4);
+  }
+#undef SL
   return hipGetLastError();
 }
 hipError_t launch_advance(long long* step_base, int n, hipStream_t s) {
@@ -344,11 +384,17 @@ hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out
   hipLaunchKernelGGL(check_kernel, dim3(64, batch), dim3(256), 0, s, H, inst, out);
   return hipGetLastError();
 }
-hipError_t step_occupancy(int* blocks_per_cu, int gm, size_t lds_bytes) {
-  if (gm <= 1)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<1>, kWave, lds_bytes);
-  if (gm <= 2)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<2>, kWave, lds_bytes);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<4>, kWave, lds_bytes);
+hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes) {
+#define SO(G, W) \
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<G, W>, kWave * W, lds_bytes)
+  if (nw == 1) {
+    if (gm <= 1) SO(1, 1);
+    if (gm <= 2) SO(2, 1);
+    SO(4, 1);
+  }
+  if (gm <= 1) SO(1, 4);
+  if (gm <= 2) SO(2, 4);
+  SO(4, 4);
+#undef SO
 }
 }  // namespace modal

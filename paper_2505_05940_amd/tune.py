@@ -24,8 +24,10 @@ def _key(insts, device):
     return h
 
 
-def autotune(insts, fs, per_cu=(3, 4, 5, 6, 7, 8, 10, 12), samples=200, cache=CACHE, log=None):
-    """Returns the best max_workgroups for this batch (cached)."""
+def autotune(insts, fs, shapes=((4, 1), (4, 2), (4, 3), (1, 5), (1, 6), (1, 7), (1, 8)),
+             samples=200, cache=CACHE, log=None):
+    """Returns the best (waves per workgroup, max_workgroups) for this batch
+    among `shapes` = (waves, workgroups per CU) pairs (cached)."""
     import torch
     props = torch.cuda.get_device_properties(0)
     cus = props.multi_processor_count
@@ -35,11 +37,12 @@ def autotune(insts, fs, per_cu=(3, 4, 5, 6, 7, 8, 10, 12), samples=200, cache=CA
         with open(cache) as f:
             table = json.load(f)
         if key in table:
-            return table[key]["max_workgroups"]
+            return tuple(table[key]["best"])
     best, best_ms, trials = None, None, {}
-    for k in per_cu:
+    for waves, k in shapes:
         mw = k * cus
-        sim = modal.Sim(insts, fs, flags=modal.FLAG_ASYNC, chunk_steps=samples, max_workgroups=mw)
+        sim = modal.Sim(insts, fs, flags=modal.FLAG_ASYNC, chunk_steps=samples, max_workgroups=mw,
+                        waves=waves)
         y = torch.empty((len(insts), samples), device="cuda")
         sim.run(samples, out=y)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -49,13 +52,13 @@ def autotune(insts, fs, per_cu=(3, 4, 5, 6, 7, 8, 10, 12), samples=200, cache=CA
         torch.cuda.synchronize()
         sim.check()
         ms = a.elapsed_time(b) / samples
-        trials[mw] = ms
+        trials[f"{waves}x{mw}"] = ms
         if log:
-            log(f"autotune: {mw} workgroups -> {ms:.3f} ms/sample")
+            log(f"autotune: {waves} waves x {mw} workgroups -> {ms:.3f} ms/sample")
         sim.close()
         if best_ms is None or ms < best_ms:
-            best, best_ms = mw, ms
-    table[key] = dict(max_workgroups=best, ms_per_sample=best_ms, trials=trials)
+            best, best_ms = (waves, mw), ms
+    table[key] = dict(best=list(best), ms_per_sample=best_ms, trials=trials)
     if cache:
         with open(cache, "w") as f:
             json.dump(table, f, indent=1)

@@ -78,10 +78,11 @@ def _ragged_batch():
     return out
 
 
-@pytest.mark.parametrize("max_wg", [0, 7, 3])
-def test_ragged_batch_split_and_packed(gpu, max_wg):
+@pytest.mark.parametrize("max_wg,waves", [(0, 4), (0, 1), (7, 4), (7, 1), (3, 4)])
+def test_ragged_batch_split_and_packed(gpu, max_wg, waves):
     """max_workgroups 7 and 3 force instances to be cut into row slabs that
-    exchange partial forces every step, next to instances packed whole."""
+    exchange partial forces every step, next to instances packed whole; one
+    or four waves per workgroup share a unit's rows."""
     modal, physics = gpu
     wls = _ragged_batch()
     steps = 3000
@@ -91,8 +92,8 @@ def test_ragged_batch_split_and_packed(gpu, max_wg):
     lin = physics.string_instance(W.string_kc(seed=8, n_modes=9))
     lin["kind"] = "linear"
     insts.append(lin)
-    _say(f"case: ragged batch of {len(insts)}, max_workgroups={max_wg}")
-    sim = modal.Sim(insts, 44100.0, max_workgroups=max_wg, flags=modal.FLAG_SPLIT_ANY)
+    _say(f"case: ragged batch of {len(insts)}, max_workgroups={max_wg}, waves={waves}")
+    sim = modal.Sim(insts, 44100.0, max_workgroups=max_wg, flags=modal.FLAG_SPLIT_ANY, waves=waves)
     info = sim.info()
     if max_wg:
         assert info["workgroups"] <= max_wg and info["split_instances"] >= 1, info
