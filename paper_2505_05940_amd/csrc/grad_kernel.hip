@@ -202,13 +202,19 @@ __device__ void adj_post(const GradParams& P, const InstDev& I, const UnitDev& U
   }
 }
 
-template <int GM, bool TAN>
-__global__ void __launch_bounds__(kWave) grad_kernel(GradParams P) {
+// GM: float4 column groups per lane; TAN: tangent tensor present; NW: waves
+// per workgroup.  As in the forward kernel, the waves of a workgroup divide a
+// unit's rows among themselves and wave 0 sums their partial J u, F and
+// tangent sums, finishes the step or publishes the unit's share.
+template <int GM, bool TAN, int NW>
+__global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
   extern __shared__ float4 lds4[];
-  float* Xs = reinterpret_cast<float*>(lds4);
-  float* Us = Xs + kMaxModes;
-  float* red = Us + kMaxModes;
-  const int lane = threadIdx.x;
+  const GradLds L = grad_lds(reinterpret_cast<float*>(lds4));
+  float* Xs = L.xs;
+  float* Us = L.us;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  float* red = L.red + wave * P.red_floats;
   const int u0 = P.wg_begin[blockIdx.x];
   const int u1 = P.wg_begin[blockIdx.x + 1];
 
@@ -227,7 +233,7 @@ __global__ void __launch_bounds__(kWave) grad_kernel(GradParams P) {
       for (int g = 0; g < GM; ++g) {
         Ju[g] = Fa[g] = f4(0.f);
         const int k4 = lane + kWave * g;
-        if (g < G && k4 < nc) {
+        if (wave == 0 && g < G && k4 < nc) {
           const float4 x4 = ld4(P.rec_x + ro + 4 * k4);
           float us[4];
           for (int e4 = 0; e4 < 4; ++e4) {
@@ -249,14 +255,42 @@ __global__ void __launch_bounds__(kWave) grad_kernel(GradParams P) {
         }
       }
       if (I.kind == KIND_VK) {
-        __syncthreads();
-        vk_rows2<GM, TAN>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs,
-                          U.row0, U.row1, Xs, Us, red, Ju, Fa, tsum, G, lane);
-        if (TAN && lane == 0) {
+        __syncthreads();  // q^n, u^n in LDS
+        const int R = U.row1 - U.row0;
+        const int r0 = U.row0 + (R * wave) / NW, r1 = U.row0 + (R * (wave + 1)) / NW;
+        vk_rows2<GM, TAN>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs, r0, r1,
+                          Xs, Us, red, Ju, Fa, tsum, G, lane);
+        if (NW > 1) {
+#pragma unroll
+          for (int g = 0; g < GM; ++g) {
+            const int k4 = lane + kWave * g;
+            if (g < G && k4 < nc) {
+              st4(red + 4 * k4, Ju[g]);
+              st4(red + I.ntp + 4 * k4, Fa[g]);
+            }
+          }
+          if (lane == 0) red[2 * I.ntp] = tsum;
+          __syncthreads();
+          if (wave == 0) {
+#pragma unroll
+            for (int g = 0; g < GM; ++g) {
+              const int k4 = lane + kWave * g;
+              if (g < G && k4 < nc)
+                for (int w = 1; w < NW; ++w) {
+                  const float* o = L.red + w * P.red_floats;
+                  Ju[g] = add4(Ju[g], ld4(o + 4 * k4));
+                  Fa[g] = add4(Fa[g], ld4(o + I.ntp + 4 * k4));
+                }
+            }
+            if (TAN)
+              for (int w = 1; w < NW; ++w) tsum += L.red[w * P.red_floats + 2 * I.ntp];
+          }
+        }
+        if (TAN && wave == 0 && lane == 0) {
           // theta partial of this unit: mode slot 0 of its theta accumulator
           acc_add(P.acc, 5, P.state_floats, U.state_off, {tsum, 0.f});
         }
-      } else if (I.kind == KIND_TENSION) {
+      } else if (I.kind == KIND_TENSION && wave == 0) {
         // F = kappa lam x S, J u = kappa lam (u S + 2 x sum(lam x u))
         const float S = wave_sum(sx), T2 = 2.f * wave_sum(sxu);
 #pragma unroll
@@ -274,48 +308,57 @@ __global__ void __launch_bounds__(kWave) grad_kernel(GradParams P) {
           }
         }
       }
-      if (I.nslab == 1) {
-        adj_post<GM>(P, I, U, n, Ju, Fa, G, lane);
-      } else {
-        float* dst = P.part + 2 * I.part_off + ((long long)(rstep & 1) * I.nslab + U.slab) * 2 * I.ntp;
+      if (wave == 0) {
+        if (I.nslab == 1) {
+          adj_post<GM>(P, I, U, n, Ju, Fa, G, lane);
+        } else {
+          float* dst = P.part + 2 * I.part_off + ((long long)(rstep & 1) * I.nslab + U.slab) * 2 * I.ntp;
 #pragma unroll
-        for (int g = 0; g < GM; ++g) {
-          const int k4 = lane + kWave * g;
-          if (g < G && k4 < nc) {
-            st4(dst + 4 * k4, Ju[g]);
-            st4(dst + I.ntp + 4 * k4, Fa[g]);
+          for (int g = 0; g < GM; ++g) {
+            const int k4 = lane + kWave * g;
+            if (g < G && k4 < nc) {
+              st4(dst + 4 * k4, Ju[g]);
+              st4(dst + I.ntp + 4 * k4, Fa[g]);
+            }
           }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __builtin_amdgcn_wave_barrier();
+          if (lane == 0)
+            __hip_atomic_fetch_add(&P.ctr[U.inst], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (lane == 0)
-          __hip_atomic_fetch_add(&P.ctr[U.inst], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
-      __syncthreads();
+      __syncthreads();  // LDS reused by the next unit
     }
     for (int u = u0; u < u1; ++u) {
       const UnitDev U = P.unit[u];
       const InstDev I = P.inst[U.inst];
       if (I.nslab == 1) continue;
-      const unsigned int target = (unsigned int)I.nslab * (unsigned int)(rstep + 1);
-      if (!wait_counter(&P.ctr[U.inst], target, P.flags)) return;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      const int nc = I.ntp >> 2;
-      const int G = (nc + kWave - 1) / kWave;
-      const float* src = P.part + 2 * I.part_off + (long long)(rstep & 1) * I.nslab * 2 * I.ntp;
-      float4 Ju[GM], F[GM];
-#pragma unroll
-      for (int g = 0; g < GM; ++g) {
-        Ju[g] = F[g] = f4(0.f);
-        const int k4 = lane + kWave * g;
-        if (g < G && k4 < nc)
-          for (int t = 0; t < I.nslab; ++t) {
-            Ju[g] = add4(Ju[g], ld4(src + (long long)t * 2 * I.ntp + 4 * k4));
-            F[g] = add4(F[g], ld4(src + (long long)t * 2 * I.ntp + I.ntp + 4 * k4));
-          }
+      if (wave == 0) {
+        const unsigned int target = (unsigned int)I.nslab * (unsigned int)(rstep + 1);
+        const bool ok = wait_counter(&P.ctr[U.inst], target, P.flags);
+        if (lane == 0) L.flag[0] = ok ? 1 : 0;
       }
-      adj_post<GM>(P, I, U, n, Ju, F, G, lane);
       __syncthreads();
+      if (L.flag[0] == 0) return;  // every wave leaves together
+      if (wave == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int nc = I.ntp >> 2;
+        const int G = (nc + kWave - 1) / kWave;
+        const float* src = P.part + 2 * I.part_off + (long long)(rstep & 1) * I.nslab * 2 * I.ntp;
+        float4 Ju[GM], F[GM];
+#pragma unroll
+        for (int g = 0; g < GM; ++g) {
+          Ju[g] = F[g] = f4(0.f);
+          const int k4 = lane + kWave * g;
+          if (g < G && k4 < nc)
+            for (int t = 0; t < I.nslab; ++t) {
+              Ju[g] = add4(Ju[g], ld4(src + (long long)t * 2 * I.ntp + 4 * k4));
+              F[g] = add4(F[g], ld4(src + (long long)t * 2 * I.ntp + I.ntp + 4 * k4));
+            }
+        }
+        adj_post<GM>(P, I, U, n, Ju, F, G, lane);
+      }
+      __syncthreads();  // flag reused
     }
   }
 }
@@ -337,28 +380,40 @@ __global__ void restore_kernel(const float* ckpt, long long slot, int mode_float
   if (u == 0 && threadIdx.x == 0) *step_base = step;
 }
 
-hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int n_wg, size_t lds, hipStream_t s) {
-#define GL(G, T) hipLaunchKernelGGL((grad_kernel<G, T>), dim3(n_wg), dim3(kWave), lds, s, P)
+// gm: float4 column groups per lane (1, 2 or 4); nw: waves per workgroup (1 or 4).
+hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, int n_wg, size_t lds,
+                       hipStream_t s) {
+#define GL(G, T, W) hipLaunchKernelGGL((grad_kernel<G, T, W>), dim3(n_wg), dim3(kWave * W), lds, s, P)
+#define GL_NW(G, T) \
+  if (nw == 1) GL(G, T, 1); else GL(G, T, 4);
+#define GL_T(G) \
+  if (tangent) { GL_NW(G, true) } else { GL_NW(G, false) }
   if (gm <= 1) {
-    if (tangent) GL(1, true); else GL(1, false);
+    GL_T(1)
   } else if (gm <= 2) {
-    if (tangent) GL(2, true); else GL(2, false);
+    GL_T(2)
   } else {
-    if (tangent) GL(4, true); else GL(4, false);
+    GL_T(4)
   }
+#undef GL_T
+#undef GL_NW
 #undef GL
   return hipGetLastError();
 }
 
-hipError_t grad_occupancy(int* blocks, int gm, bool tangent, size_t lds) {
-  if (gm <= 1)
-    return tangent ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<1, true>, kWave, lds)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<1, false>, kWave, lds);
-  if (gm <= 2)
-    return tangent ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<2, true>, kWave, lds)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<2, false>, kWave, lds);
-  return tangent ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<4, true>, kWave, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<4, false>, kWave, lds);
+hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, size_t lds) {
+#define GO(G, T, W) \
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<G, T, W>, kWave * W, lds)
+#define GO_NW(G, T) \
+  if (nw == 1) GO(G, T, 1); else GO(G, T, 4);
+#define GO_T(G) \
+  if (tangent) { GO_NW(G, true) } else { GO_NW(G, false) }
+  if (gm <= 1) GO_T(1)
+  if (gm <= 2) GO_T(2)
+  GO_T(4)
+#undef GO_T
+#undef GO_NW
+#undef GO
 }
 
 hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,

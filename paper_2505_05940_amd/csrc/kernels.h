@@ -40,19 +40,43 @@ struct UnitDev {
 // Dynamic LDS of the step kernel: q^n [kMaxModes], per-wave partial forces
 // [NW][kMaxModes] (NW > 1), a flag word (16 bytes), per-wave reduction
 // buffers [NW][red_floats].
+// LDS of one step workgroup: q^n of the current unit, a flag word, and one
+// row-reduction region of red_floats per wave.  A wave that has finished its
+// row sweep parks its partial force in the first ntp floats of its own region
+// (red_floats >= 2 ntp for every instance), where wave 0 sums them.
 struct StepLds {
-  float *xs, *fred, *red;
+  float *xs, *red;
   int* flag;
 };
 __host__ __device__ inline size_t step_lds_bytes(int nw, int red_floats) {
-  return sizeof(float) * ((size_t)kMaxModes + (nw > 1 ? (size_t)nw * kMaxModes : 0) + 4 +
-                          (size_t)nw * red_floats);
+  return sizeof(float) * ((size_t)kMaxModes + 4 + (size_t)nw * red_floats);
 }
 __host__ __device__ inline StepLds step_lds(float* base, int nw, int red_floats) {
+  (void)nw;
+  (void)red_floats;
   StepLds L;
   L.xs = base;
-  L.fred = base + kMaxModes;
-  L.flag = reinterpret_cast<int*>(L.fred + (nw > 1 ? nw * kMaxModes : 0));
+  L.flag = reinterpret_cast<int*>(base + kMaxModes);
+  L.red = reinterpret_cast<float*>(L.flag + 4);
+  return L;
+}
+
+// LDS of one reverse-sweep workgroup: q^n and u^n of the current unit, a
+// flag word, and one reduction region of red_floats per wave (three vectors
+// per row, double-buffered); a finished wave parks J u, F and its tangent
+// sum in the first 2 ntp + 1 floats of its region.
+struct GradLds {
+  float *xs, *us, *red;
+  int* flag;
+};
+__host__ __device__ inline size_t grad_lds_bytes(int nw, int red_floats) {
+  return sizeof(float) * (2 * (size_t)kMaxModes + 4 + (size_t)nw * red_floats);
+}
+__host__ __device__ inline GradLds grad_lds(float* base) {
+  GradLds L;
+  L.xs = base;
+  L.us = base + kMaxModes;
+  L.flag = reinterpret_cast<int*>(base + 2 * kMaxModes);
   L.red = reinterpret_cast<float*>(L.flag + 4);
   return L;
 }

@@ -19,8 +19,9 @@ hipError_t launch_step(const StepParams& P, int gm, int nw, int n_wg, size_t lds
 hipError_t launch_advance(long long* step_base, int n, hipStream_t s);
 hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s);
 hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes);
-hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int n_wg, size_t lds, hipStream_t s);
-hipError_t grad_occupancy(int* blocks, int gm, bool tangent, size_t lds);
+hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, int n_wg, size_t lds,
+                       hipStream_t s);
+hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, size_t lds);
 hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
                           const UnitDev* unit, int n_units, float* state, int state_floats,
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
@@ -500,13 +501,13 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   int occ = 0;
   HIP_TRY(step_occupancy(&occ, c->gm, c->nw, c->lds_bytes));
   c->red_floats = red_floats;
-  c->grad_lds = sizeof(float) * (size_t)(2 * kMaxModes + 3 * red_floats);
+  c->grad_lds = grad_lds_bytes(c->nw, 3 * red_floats);
   if (d->flags & MODAL_FLAG_GRAD) {
     // the reverse kernel (with or without a tangent) must fit as many
     // co-resident workgroups as the plan uses
     int og = 0, ot = 0;
-    HIP_TRY(grad_occupancy(&og, c->gm, false, c->grad_lds));
-    HIP_TRY(grad_occupancy(&ot, c->gm, true, c->grad_lds));
+    HIP_TRY(grad_occupancy(&og, c->gm, false, c->nw, c->grad_lds));
+    HIP_TRY(grad_occupancy(&ot, c->gm, true, c->nw, c->grad_lds));
     occ = std::min(occ, std::min(og, ot));
   }
   if (occ < 1) {
@@ -908,7 +909,7 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     G.seg_base = s0;
     G.seg_len = len;
     G.done_before = n_steps - s0 - len;
-    HIP_TRY(launch_grad(G, c->gm, c->tangent, c->n_wg, c->grad_lds, s));
+    HIP_TRY(launch_grad(G, c->gm, c->tangent, c->nw, c->n_wg, c->grad_lds, s));
   }
   r = modal_check(c, stream_);
   if (r) return r;

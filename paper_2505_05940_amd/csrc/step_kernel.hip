@@ -161,9 +161,9 @@ __device__ __forceinline__ void update_groups(const StepParams& P, const InstDev
 
 // GM: float4 column groups per lane the launch supports (modes <= 256 GM).
 // NW: waves per workgroup.  A unit's rows are divided among the NW waves,
-// each sweeping its share with its own LDS reduction buffer; the per-wave
-// partial forces are summed through LDS by wave 0, which also owns the
-// output, the exchange with other workgroups and the state update.
+// each sweeping its share with its own LDS reduction region; the per-wave
+// partial forces are summed through those regions by wave 0, which also owns
+// the output, the exchange with other workgroups and the state update.
 template <int GM, int NW>
 __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
   extern __shared__ float4 lds4[];
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
             const int k4 = lane + kWave * g;
-            if (g < G && k4 < nc) st4(L.fred + wave * kMaxModes + 4 * k4, Fa[g]);
+            if (g < G && k4 < nc) st4(red + 4 * k4, Fa[g]);
           }
           __syncthreads();
           if (wave == 0) {
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
             for (int g = 0; g < GM; ++g) {
               const int k4 = lane + kWave * g;
               if (g < G && k4 < nc)
-                for (int w = 1; w < NW; ++w) Fa[g] = add4(Fa[g], ld4(L.fred + w * kMaxModes + 4 * k4));
+                for (int w = 1; w < NW; ++w) Fa[g] = add4(Fa[g], ld4(L.red + w * P.red_floats + 4 * k4));
             }
           }
         }

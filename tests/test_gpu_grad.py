@@ -44,8 +44,8 @@ def _cases():
     return wl_vk, wl_kc
 
 
-@pytest.mark.parametrize("max_wg,ckpt", [(0, 0), (3, 128)])
-def test_grad_matches_oracle(gpu, max_wg, ckpt):
+@pytest.mark.parametrize("max_wg,ckpt,waves", [(0, 0, 4), (3, 128, 4), (3, 128, 1), (0, 200, 1)])
+def test_grad_matches_oracle(gpu, max_wg, ckpt, waves):
     modal, physics, torch = gpu
     wl_vk, wl_kc = _cases()
     steps = 600
@@ -55,9 +55,10 @@ def test_grad_matches_oracle(gpu, max_wg, ckpt):
     g = rng.normal(size=(2, steps))
     g[0] /= np.abs(oinsts[0]["x0"]).max()
     g[1] /= np.abs(oinsts[1]["x0"]).max()
-    print(f"case: grad vK 14/11 + KC 12, {steps} steps, max_wg={max_wg}, ckpt={ckpt}", flush=True)
+    print(f"case: grad vK 14/11 + KC 12, {steps} steps, max_wg={max_wg}, ckpt={ckpt}, waves={waves}",
+          flush=True)
     sim = modal.Sim(pinsts, 44100.0, flags=modal.FLAG_GRAD | modal.FLAG_SPLIT_ANY,
-                    max_workgroups=max_wg)
+                    max_workgroups=max_wg, waves=waves)
     if max_wg:
         assert sim.info()["split_instances"] >= 1
     res = sim.grad(steps, torch.tensor(g, dtype=torch.float32, device="cuda"), ckpt_every=ckpt)
