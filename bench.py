@@ -33,15 +33,52 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(samples_per_step):
+def measured_traffic(samples_per_step, launch):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
     were taken on the current kernel source and launch shape."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE))
-    if t.get("kernel_sha") != kernel_hash() or t.get("samples_per_step") != samples_per_step:
+    if (t.get("kernel_sha") != kernel_hash() or t.get("samples_per_step") != samples_per_step
+            or t.get("launch") != launch):
         return None
     return t.get("bytes_per_launch")
+
+
+def _counter_rows(path, counter):
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def write_traffic(fetch_csv, write_csv, copy_mib, samples_per_step, launch):
+    """HBM bytes per step-kernel launch from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what the
+    same counter reads for the calibration kernel (torch's elementwise
+    negation) that reads and writes copy_mib MiB."""
+    out = {"kernel_sha": kernel_hash(), "samples_per_step": samples_per_step, "launch": launch,
+           "calibration_copy_mib": copy_mib}
+    total = 0.0
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _counter_rows(path, name)
+        cal = [v for k, v in rows if "neg_kernel" in k]
+        step = [v for k, v in rows if "step_kernel" in k]
+        if not cal or not step:
+            raise SystemExit(f"{path}: no calibration or step_kernel dispatch for {name}")
+        factor = copy_mib * 1024.0 / cal[0]  # true KiB per counted KiB
+        kib = float(np.mean(step)) * factor
+        out[name.lower()] = {"raw_kib_per_dispatch": float(np.mean(step)), "dispatches": len(step),
+                             "calibration_raw_kib": cal[0], "scale": factor,
+                             "bytes_per_launch": kib * 1024.0}
+        total += kib * 1024.0
+    out["bytes_per_launch"] = total
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline(wls, n_inst, seconds, seed):
@@ -85,15 +122,24 @@ def main():
     ap.add_argument("--samples-per-step", type=int, default=441)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--max-workgroups", type=int, default=-1,
-                    help="co-resident workgroups for the plan; -1 = autotune on this batch")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate launch shapes first and use the best")
+    ap.add_argument("--max-workgroups", type=int, default=0,
+                    help="co-resident workgroups for the plan (0: the library default)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (with --max-workgroups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-instances", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the measured-traffic record from two rocprofv3 --pmc "
+                         "counter_collection.csv files of this command, then exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from, args.calibrate_copy_mib, args.samples_per_step,
+                      {"max_workgroups": args.max_workgroups, "waves": args.waves})
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: the batched instances are independent and would "
               "shard across GPUs without communication; multi-GPU runs are not part of "
@@ -111,15 +157,16 @@ def main():
     t_pre = time.time() - t0
     print(f"[bench] host precompute of {len(insts)} instances: {t_pre:.1f} s", file=sys.stderr, flush=True)
     if args.calibrate_copy_mib:
+        # one elementwise kernel that reads and writes exactly this many bytes
         n = args.calibrate_copy_mib * (1 << 20) // 4
         a = torch.ones(n, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
     S = args.samples_per_step
     mw, waves = args.max_workgroups, args.waves
-    if mw < 0:
+    if args.autotune:
         from paper_2505_05940_amd.tune import autotune
         t0 = time.time()
         waves, mw = autotune(insts, 44100.0, cache=None,
@@ -156,7 +203,8 @@ def main():
     value = modes * S * args.steps / wall
     alg_bytes = info["coupling_bytes_per_step"] * S  # per launch
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(S)
+    traffic = measured_traffic(S, {"max_workgroups": args.max_workgroups, "waves": args.waves}
+                               if not args.autotune else None)
     out = {
         "metric": "simulated instance*mode*samples/s (batched vK plate)",
         "value": value,

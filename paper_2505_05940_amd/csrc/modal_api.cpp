@@ -515,14 +515,15 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
     return fail(MODAL_EHIP, "step kernel does not fit on a CU");
   }
   c->occ = occ;
-  // Default: at most kDefaultWgPerCu workgroups per CU.  Measured on the
-  // 256-plate batch, fewer and deeper workgroups stream better than the
-  // occupancy limit (6 per CU: 6.1 TB/s; 13 per CU: 4.5 TB/s); an explicit
-  // max_workgroups (e.g. from the autotuner) overrides it.
-  constexpr int kDefaultWgPerCu = 6;
+  // Default budget per CU.  Measured on the 256-plate batch, fewer and
+  // deeper workgroups stream better than the occupancy limit: with four
+  // waves, 2 workgroups per CU reach 6.4 TB/s (3: 6.1, 4: 5.6); with one
+  // wave, 6 per CU reach 6.1 TB/s (13: 4.5).  An explicit max_workgroups
+  // (e.g. from the autotuner) overrides it.
+  const int wg_per_cu = c->nw > 1 ? 2 : 6;
   int n_bins = occ * prop.multiProcessorCount;
   if (d->max_workgroups > 0) n_bins = std::min(n_bins, d->max_workgroups);
-  else n_bins = std::min(n_bins, kDefaultWgPerCu * prop.multiProcessorCount);
+  else n_bins = std::min(n_bins, wg_per_cu * prop.multiProcessorCount);
   n_bins = std::max(1, std::min(n_bins, 1 << 20));
   double total = 0;
   for (int b = 0; b < d->batch; ++b)
