@@ -66,10 +66,11 @@ enum {
                            and replays it afterwards                          */
   MODAL_FLAG_GRAD = 4,  /* plan the work so that modal_grad can run (its
                            reverse kernel needs more LDS per workgroup)       */
-  MODAL_FLAG_SPLIT_ANY = 8 /* cut VK instances into row slabs whenever
+  MODAL_FLAG_SPLIT_ANY = 8, /* cut VK instances into row slabs whenever
                            workgroups are free (tests, tuning); by default
                            instances below 4 MB of tensor stay whole and a
                            slab must pay for its per-step exchange          */
+  MODAL_FLAG_NO_SHARED = 16 /* never use the shared-tensor (MFMA) path      */
 };
 
 /* One modal system.  All arrays are host memory. */
@@ -92,6 +93,10 @@ typedef struct {
                             for n < n_exc (absolute step index), else 0       */
   int64_t n_exc;
   const double *c_out;   /* [n_t] output weights: y^n = sum_k c_k q_k^n       */
+  const double *h_row_scale; /* VK, optional [n_in]: the instance's tensor is
+                            h_row_scale[n] * H[n][k][j] (NULL = 1).  Instances
+                            that pass the same H pointer (and n_t, n_in) share
+                            one tensor up to these scales; see modal_init.   */
 } modal_instance;
 
 typedef struct {
@@ -112,6 +117,14 @@ typedef struct {
  * recursion coefficients in FP64 and stores them as float-float pairs,
  * partitions the batch into per-workgroup work, allocates device memory and
  * uploads the coupling tensors and initial states on `stream`.
+ * Shared-tensor path: when every instance is VK with n_t <= 64, the
+ * instances pass at most batch/16 distinct H pointers (so the tensors are
+ * shared by 16 instances on average) and neither MODAL_FLAG_GRAD nor
+ * MODAL_FLAG_NO_SHARED is set, each distinct tensor is stored once and the
+ * force is evaluated as a dense FP32 matrix product over the instances that
+ * share it (MFMA); otherwise every instance streams its own (scaled) copy.
+ * Both paths compute the same recursion; they differ only in the FP32
+ * rounding inside the force (order of sums, where the row scale is applied).
  * Errors: EINVAL (NULL/size/kind/finite/symmetry), EUNSTABLE (a mode's
  * characteristic roots outside the unit circle; also gamma < 0 or, for TF,
  * omega <= gamma), ENOMEM, EHIP.  On error *out is NULL. */
@@ -144,8 +157,11 @@ int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
  * [5] steps taken so far, [6] dynamic LDS bytes per workgroup,
  * [7] co-resident workgroups per CU used for the plan, [8] planned cost of
  * the most loaded workgroup and [9] the mean planned cost per co-resident
- * workgroup (both in streamed-byte units). */
-int modal_info(const modal_ctx *c, int64_t info[10]);
+ * workgroup (both in streamed-byte units), [10] 1 on the shared-tensor path
+ * (then [1] is the number of instance columns and [2], [8], [9] are 0),
+ * [11] FP32 operations of the force per step (sum over VK instances of
+ * 2 n_in n_t^2 + 4 n_in n_t). */
+int modal_info(const modal_ctx *c, int64_t info[12]);
 
 void modal_destroy(modal_ctx *c);
 

@@ -47,7 +47,8 @@ def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
-    srcs = [("step_kernel.hip", True), ("grad_kernel.hip", True), ("modal_api.cpp", True),
+    srcs = [("step_kernel.hip", True), ("grad_kernel.hip", True), ("shared_kernel.hip", True),
+            ("modal_api.cpp", True),
             ("mlp_kernels.hip", True), ("mlp_api.cpp", True), ("coupling_host.cpp", False)]
     for src, hip in srcs:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")

@@ -405,9 +405,9 @@ hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, size_t lds)
 #define GO(G, T, W) \
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<G, T, W>, kWave * W, lds)
 #define GO_NW(G, T) \
-  if (nw == 1) GO(G, T, 1); else GO(G, T, 4);
+  { if (nw == 1) { GO(G, T, 1); } else { GO(G, T, 4); } }
 #define GO_T(G) \
-  if (tangent) { GO_NW(G, true) } else { GO_NW(G, false) }
+  { if (tangent) { GO_NW(G, true) } else { GO_NW(G, false) } }
   if (gm <= 1) GO_T(1)
   if (gm <= 2) GO_T(2)
   GO_T(4)

@@ -139,4 +139,46 @@ struct GradParams {
   int red_floats;
 };
 
+// ------------------------------------------------------------ shared tensor
+// Batches whose instances share one coupling tensor up to a per-row scale
+// (Ht_b[n] = s_b[n] H0[n]) run on the MFMA kernel: V0 = H0[n] X is a dense
+// product with the instances as columns.  A workgroup of kSharedWaves waves
+// owns 16 JT columns per wave (one group, one tensor) and runs every step
+// without talking to other workgroups.
+constexpr int kSharedWaves = 4;
+constexpr int kSharedMaxKT = 4;  // modes per instance <= 16 kSharedMaxKT
+
+struct SharedWg {
+  long long a_off;  // packed tensor of the group (floats)
+  int nin, nt;      // in-plane rows, modes
+  int kt, kc;       // 16-row tiles and 4-wide K steps of the group
+};
+
+struct SharedSlot {
+  int out_row;      // output row, or -1 for an empty column
+  int pad;
+  long long e_off;  // excitation offset
+  long long n_exc;
+};
+
+struct SharedParams {
+  const SharedWg* wg;
+  const SharedSlot* slot;    // [n_wg * cols]
+  const float* A;            // packed tensors: [n][t][c][64] per group
+  const float* s2;           // [n_wg][nin_max][cols] squared row scales
+  int nin_max, cols, ktot;   // cols = 64 JT, ktot = 16 KT
+  // per (column, mode), layout [n_wg * cols][ktot]
+  float *x_hi, *x_lo, *d_hi, *d_lo;
+  const float *m_hi, *m_lo, *p_hi, *p_lo, *r_hi, *r_lo, *c_out, *b_ext;
+  const float* e_ext;
+  float* y;
+  long long y_stride;
+  int n_steps;
+  const long long* step_base;
+  int* flags;
+};
+__host__ __device__ inline size_t shared_lds_bytes(int kt, int jt) {
+  return sizeof(float) * (2 * (size_t)kt * 4 * kt * 64 + (size_t)kSharedWaves * 16 * kt * 16 * jt);
+}
+
 }  // namespace modal

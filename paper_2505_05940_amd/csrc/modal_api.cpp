@@ -9,6 +9,7 @@
 #include <map>
 #include <queue>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/modal.h"
@@ -25,6 +26,7 @@ hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, size_t lds)
 hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
                           const UnitDev* unit, int n_units, float* state, int state_floats,
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
+hipError_t launch_shared(const SharedParams& P, int kt, int jt, int n_wg, hipStream_t s);
 }  // namespace modal
 
 using namespace modal;
@@ -170,6 +172,12 @@ struct modal_ctx {
   unsigned int* dGCtr = nullptr;
   long long ckpt_floats = 0, rec_floats = 0;
   bool tangent = false;
+  // shared-tensor path
+  bool shared = false;
+  int sh_kt = 0, sh_jt = 0;
+  long long flops = 0;
+  float *dShA = nullptr, *dShS2 = nullptr;
+  SharedParams SP{};
   hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
   struct Graph {
     int64_t n, stride;
@@ -187,7 +195,7 @@ void free_ctx(modal_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   void* ptrs[] = {c->dH,   c->dMeta, c->dCoef, c->dState, c->dPart, c->dCtr, c->dFlags,
                   c->dStep, c->dE,   c->dHd,   c->dCkpt,  c->dRec,  c->dAdj, c->dAcc,
-                  c->dGPart, c->dGCtr};
+                  c->dGPart, c->dGCtr, c->dShA, c->dShS2};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -231,8 +239,10 @@ int validate(const modal_desc* d) {
       return fail(MODAL_EINVAL, "non-finite per-mode input" + at);
     if (I.kind == MODAL_KIND_VK) {
       if (I.n_in < 1 || !I.H) return fail(MODAL_EINVAL, "VK needs n_in >= 1 and H" + at);
-    } else if (I.n_in != 0) {
-      return fail(MODAL_EINVAL, "n_in must be 0 unless VK" + at);
+      if (I.h_row_scale && !finite_all(I.h_row_scale, I.n_in))
+        return fail(MODAL_EINVAL, "non-finite h_row_scale" + at);
+    } else if (I.n_in != 0 || I.h_row_scale) {
+      return fail(MODAL_EINVAL, "n_in must be 0 and h_row_scale NULL unless VK" + at);
     }
     if (I.kind == MODAL_KIND_TENSION) {
       if (!I.lambda || !finite_all(I.lambda, I.n_t) || !std::isfinite(I.kappa))
@@ -394,11 +404,19 @@ int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>
       on_device = attr.type == hipMemoryTypeDevice;
     else
       (void)hipGetLastError();
-    if (on_device) {
+    if (on_device && !I.h_row_scale) {
       UP_TRY(hipMemcpy2DAsync(c->dH + D.h_off, sizeof(float) * D.ntp, I.H, sizeof(float) * D.nt,
                               sizeof(float) * D.nt, (size_t)D.nin * D.nt, hipMemcpyDeviceToDevice,
                               stream));
       continue;
+    }
+    // host rows (a device tensor with row scales is read back first)
+    std::vector<float> host_copy;
+    const float* src = I.H;
+    if (on_device) {
+      host_copy.resize((size_t)D.nin * D.nt * D.nt);
+      UP_TRY(hipMemcpy(host_copy.data(), I.H, sizeof(float) * host_copy.size(), hipMemcpyDeviceToHost));
+      src = host_copy.data();
     }
     if (!stage[0]) {
       for (int i = 0; i < 2; ++i) {
@@ -413,7 +431,13 @@ int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>
       if (used[slot]) UP_TRY(hipEventSynchronize(done[slot]));
       float* dst = stage[slot];
       for (size_t r = 0; r < nr; ++r) {
-        std::memcpy(dst + r * D.ntp, I.H + (r0 + r) * D.nt, sizeof(float) * D.nt);
+        const float* row = src + (r0 + r) * D.nt;
+        if (I.h_row_scale) {
+          const double sc = I.h_row_scale[(r0 + r) / D.nt];
+          for (int k = 0; k < D.nt; ++k) dst[r * D.ntp + k] = (float)(sc * (double)row[k]);
+        } else {
+          std::memcpy(dst + r * D.ntp, row, sizeof(float) * D.nt);
+        }
         for (int k = D.nt; k < D.ntp; ++k) dst[r * D.ntp + k] = 0.f;
       }
       UP_TRY(hipMemcpyAsync(c->dH + D.h_off + r0 * D.ntp, dst, sizeof(float) * nr * D.ntp,
@@ -428,6 +452,196 @@ int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>
   }
 #undef UP_TRY
   cleanup();
+  return MODAL_OK;
+}
+
+// ------------------------------------------------------------ shared tensor
+struct SharedGroup {
+  const float* H;
+  int nt, nin;
+  std::vector<int> members;
+};
+
+// Instances grouped by (H pointer, n_t, n_in); empty unless the batch takes
+// the shared-tensor path (every instance VK with n_t <= 16 kSharedMaxKT and
+// at least 16 instances per distinct tensor on average).
+std::vector<SharedGroup> shared_groups(const modal_desc* d) {
+  std::vector<SharedGroup> g;
+  if (d->flags & (MODAL_FLAG_GRAD | MODAL_FLAG_NO_SHARED)) return g;
+  std::map<std::tuple<const float*, int, int>, int> index;
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    if (I.kind != MODAL_KIND_VK || I.n_t > 16 * kSharedMaxKT) return {};
+    auto key = std::make_tuple(I.H, I.n_t, I.n_in);
+    auto it = index.find(key);
+    if (it == index.end()) {
+      it = index.emplace(key, (int)g.size()).first;
+      g.push_back({I.H, I.n_t, I.n_in, {}});
+    }
+    g[it->second].members.push_back(b);
+  }
+  if ((long long)d->batch < 16LL * (long long)g.size()) return {};
+  return g;
+}
+
+// Builds a context on the shared-tensor path: packs each group's tensor
+// once in the MFMA operand order, lays every instance out as one column of
+// its group's workgroups and uploads coefficients, scales and state.
+int init_shared(modal_ctx* c, const modal_desc* d, std::vector<SharedGroup>& groups,
+                hipStream_t stream) {
+  const double T = 1.0 / d->fs;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  int kt = 1, nin_max = 1;
+  long long wg2 = 0;
+  for (auto& g : groups) {
+    kt = std::max(kt, (g.nt + 15) / 16);
+    nin_max = std::max(nin_max, g.nin);
+    wg2 += ((long long)g.members.size() + 127) / 128;
+  }
+  // two column tiles per wave once that still gives every CU a workgroup
+  const int jt = wg2 >= prop.multiProcessorCount ? 2 : 1;
+  const int cols = 64 * jt, ktot = 16 * kt;
+  long long n_wg = 0;
+  for (auto& g : groups) n_wg += ((long long)g.members.size() + cols - 1) / cols;
+  if (n_wg > (1 << 30) / cols) return fail(MODAL_EINVAL, "batch too large");
+  const long long ncol = n_wg * cols, ncolk = ncol * ktot;
+
+  // packed tensors: A[n][t][c][l] = H[n][16 t + l%16][4 c + l/16]
+  std::vector<SharedWg> wgs;
+  std::vector<SharedSlot> slots(ncol, SharedSlot{-1, 0, 0, 0});
+  std::vector<float> apool, s2((size_t)n_wg * nin_max * cols, 0.f);
+  std::vector<float> coef(8 * (size_t)ncolk, 0.f);
+  c->state0.assign(4 * (size_t)ncolk, 0.f);
+  c->unit_state_of_inst.assign(d->batch, 0);
+  std::vector<float> epool(1, 0.f);
+  for (auto& g : groups) {
+    const size_t hn = (size_t)g.nin * g.nt * g.nt;
+    std::vector<float> H(hn);
+    hipPointerAttribute_t attr;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&attr, g.H) == hipSuccess)
+      on_device = attr.type == hipMemoryTypeDevice;
+    else
+      (void)hipGetLastError();
+    if (on_device) HIP_TRY(hipMemcpy(H.data(), g.H, sizeof(float) * hn, hipMemcpyDeviceToHost));
+    else std::memcpy(H.data(), g.H, sizeof(float) * hn);
+    float hmax = 0.f, dmax = 0.f;
+    for (int n = 0; n < g.nin; ++n)
+      for (int k = 0; k < g.nt; ++k)
+        for (int j = 0; j < g.nt; ++j) {
+          const float a = H[((size_t)n * g.nt + k) * g.nt + j], b = H[((size_t)n * g.nt + j) * g.nt + k];
+          if (!std::isfinite(a)) return fail(MODAL_EINVAL, "non-finite H (instance " + std::to_string(g.members[0]) + ")");
+          hmax = std::max(hmax, std::fabs(a));
+          dmax = std::max(dmax, std::fabs(a - b));
+        }
+    if (dmax > 1e-6f * hmax)
+      return fail(MODAL_EINVAL, "H not symmetric in its last two indices (instance " +
+                                    std::to_string(g.members[0]) + ")");
+    const int gkt = (g.nt + 15) / 16, gkc = (g.nt + 3) / 4;
+    const long long a_off = (long long)apool.size();
+    apool.resize(apool.size() + (((size_t)g.nin * gkt * gkc * 64 + 63) & ~(size_t)63), 0.f);
+    for (int n = 0; n < g.nin; ++n)
+      for (int t = 0; t < gkt; ++t)
+        for (int cc = 0; cc < gkc; ++cc)
+          for (int l = 0; l < 64; ++l) {
+            const int k = 16 * t + l % 16, q = 4 * cc + l / 16;
+            apool[a_off + (((size_t)n * gkt + t) * gkc + cc) * 64 + l] =
+                k < g.nt && q < g.nt ? H[((size_t)n * g.nt + k) * g.nt + q] : 0.f;
+          }
+    c->coupling_bytes += 4LL * g.nin * g.nt * g.nt * (long long)g.members.size();
+    for (size_t i0 = 0; i0 < g.members.size(); i0 += cols) {
+      const long long w = (long long)wgs.size();
+      wgs.push_back(SharedWg{a_off, g.nin, g.nt, gkt, gkc});
+      c->padded_bytes += 4LL * g.nin * gkt * gkc * 64;
+      for (size_t i = i0; i < std::min(g.members.size(), i0 + cols); ++i) {
+        const int b = g.members[i];
+        const modal_instance& I = d->inst[b];
+        const long long col = w * cols + (long long)(i - i0);
+        SharedSlot& sl = slots[col];
+        sl.out_row = b;
+        sl.n_exc = I.n_exc;
+        sl.e_off = (long long)epool.size();
+        if (I.n_exc > 0) epool.insert(epool.end(), I.e_ext, I.e_ext + I.n_exc);
+        for (int n = 0; n < g.nin; ++n) {
+          const double sc = I.h_row_scale ? I.h_row_scale[n] : 1.0;
+          s2[((size_t)w * nin_max + n) * cols + (i - i0)] = (float)(sc * sc);
+        }
+        const size_t o = (size_t)col * ktot;
+        c->unit_state_of_inst[b] = (int)o;
+        for (int k = 0; k < I.n_t; ++k) {
+          const Coef q = coefficients(d->scheme, I.omega[k], I.gamma[k], T);
+          split(q.m, coef[o + k], coef[ncolk + o + k]);
+          split(q.p, coef[2 * ncolk + o + k], coef[3 * ncolk + o + k]);
+          split(q.r, coef[4 * ncolk + o + k], coef[5 * ncolk + o + k]);
+          coef[6 * ncolk + o + k] = (float)I.c_out[k];
+          coef[7 * ncolk + o + k] = I.b_ext ? (float)I.b_ext[k] : 0.f;
+          split(I.x0[k], c->state0[o + k], c->state0[ncolk + o + k]);
+          split(I.x0[k] - I.xm1[k], c->state0[2 * ncolk + o + k], c->state0[3 * ncolk + o + k]);
+        }
+        c->flops += 2LL * g.nin * g.nt * g.nt + 4LL * g.nin * g.nt;
+      }
+    }
+  }
+  for (int b = 0; b < d->batch; ++b) {
+    c->kind.push_back(d->inst[b].kind);
+    c->nt.push_back(d->inst[b].n_t);
+  }
+  c->shared = true;
+  c->sh_kt = kt;
+  c->sh_jt = jt;
+  c->n_wg = (int)n_wg;
+  c->n_units = (int)ncol;
+  c->occ = 0;
+  c->state_floats = (int)ncolk;
+  c->lds_bytes = shared_lds_bytes(kt, jt);
+
+  const size_t meta_bytes = sizeof(SharedWg) * wgs.size() + sizeof(SharedSlot) * slots.size();
+  int r = dalloc(&c->dShA, sizeof(float) * (apool.size() + 64));
+  if (!r) r = dalloc(&c->dMeta, meta_bytes);
+  if (!r) r = dalloc(&c->dShS2, sizeof(float) * s2.size());
+  if (!r) r = dalloc(&c->dCoef, sizeof(float) * coef.size());
+  if (!r) r = dalloc(&c->dState, sizeof(float) * c->state0.size());
+  if (!r) r = dalloc(&c->dCtr, sizeof(unsigned int) * d->batch);
+  if (!r) r = dalloc(&c->dFlags, sizeof(int) * 2);
+  if (!r) r = dalloc(&c->dStep, sizeof(long long));
+  if (!r) r = dalloc(&c->dE, sizeof(float) * epool.size());
+  if (r) return r;
+  char* meta = (char*)c->dMeta;
+  SharedWg* dWg = (SharedWg*)meta;
+  SharedSlot* dSlot = (SharedSlot*)(meta + sizeof(SharedWg) * wgs.size());
+  HIP_TRY(hipMemcpyAsync(c->dShA, apool.data(), sizeof(float) * apool.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(dWg, wgs.data(), sizeof(SharedWg) * wgs.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(dSlot, slots.data(), sizeof(SharedSlot) * slots.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dShS2, s2.data(), sizeof(float) * s2.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dCoef, coef.data(), sizeof(float) * coef.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dE, epool.data(), sizeof(float) * epool.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  SharedParams& P = c->SP;
+  P.wg = dWg;
+  P.slot = dSlot;
+  P.A = c->dShA;
+  P.s2 = c->dShS2;
+  P.nin_max = nin_max;
+  P.cols = cols;
+  P.ktot = ktot;
+  P.x_hi = c->dState;
+  P.x_lo = P.x_hi + ncolk;
+  P.d_hi = P.x_lo + ncolk;
+  P.d_lo = P.d_hi + ncolk;
+  P.m_hi = c->dCoef;
+  P.m_lo = P.m_hi + ncolk;
+  P.p_hi = P.m_lo + ncolk;
+  P.p_lo = P.p_hi + ncolk;
+  P.r_hi = P.p_lo + ncolk;
+  P.r_lo = P.r_hi + ncolk;
+  P.c_out = P.r_lo + ncolk;
+  P.b_ext = P.c_out + ncolk;
+  P.e_ext = c->dE;
+  P.step_base = c->dStep;
+  P.flags = c->dFlags;
   return MODAL_OK;
 }
 
@@ -451,6 +665,20 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   c->flags = d->flags;
   c->fs = d->fs;
   c->chunk = d->chunk_steps;
+  {
+    std::vector<SharedGroup> groups = shared_groups(d);
+    if (!groups.empty()) {
+      int r = init_shared(c, d, groups, stream);
+      if (!r) r = modal_reset(c, stream_);
+      if (!r && hipStreamSynchronize(stream) != hipSuccess) r = fail(MODAL_EHIP, "hipStreamSynchronize");
+      if (r) {
+        free_ctx(c);
+        return r;
+      }
+      *out = c;
+      return MODAL_OK;
+    }
+  }
 
   // ---------------- instance layout
   std::vector<InstDev> inst(d->batch);
@@ -479,6 +707,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
       const long long f = (long long)D.nin * D.nt * D.ntp;
       h_floats += (f + 63) & ~63LL;  // 256-byte aligned instances
       c->coupling_bytes += 4LL * D.nin * D.nt * D.nt;
+      c->flops += 2LL * D.nin * D.nt * D.nt + 4LL * D.nin * D.nt;
       c->padded_bytes += 4 * f;
       choose_sweep(D.nt, D.ntp / 4, qs_of[b], J_of[b]);
       red_floats = std::max(red_floats, 2 * qs_of[b] * D.ntp);
@@ -748,11 +977,19 @@ static int enqueue_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride
   const int64_t chunk = c->chunk > 0 ? c->chunk : n_steps;
   for (int64_t done = 0; done < n_steps; done += chunk) {
     const int64_t k = std::min<int64_t>(chunk, n_steps - done);
-    StepParams P = c->P;
-    P.y = y + done;
-    P.y_stride = y_stride;
-    P.n_steps = (int)k;
-    HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
+    if (c->shared) {
+      SharedParams P = c->SP;
+      P.y = y + done;
+      P.y_stride = y_stride;
+      P.n_steps = (int)k;
+      HIP_TRY(launch_shared(P, c->sh_kt, c->sh_jt, c->n_wg, s));
+    } else {
+      StepParams P = c->P;
+      P.y = y + done;
+      P.y_stride = y_stride;
+      P.n_steps = (int)k;
+      HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
+    }
     HIP_TRY(launch_advance(c->dStep, (int)k, s));
   }
   return MODAL_OK;
@@ -807,6 +1044,7 @@ int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* s
 
 int modal_set_tangent(modal_ctx* c, int32_t b, const float* Hd, void* stream_) {
   if (!c || !Hd) return fail(MODAL_EINVAL, "NULL argument");
+  if (c->shared) return fail(MODAL_ESTATE, "tangents need a context created with MODAL_FLAG_GRAD");
   if (b < 0 || b >= c->batch || c->kind[b] != MODAL_KIND_VK)
     return fail(MODAL_EINVAL, "tangent needs a VK instance index");
   hipStream_t s = (hipStream_t)stream_;
@@ -972,7 +1210,7 @@ int modal_get_state(modal_ctx* c, double* x, double* xm1, void* stream_) {
   return MODAL_OK;
 }
 
-int modal_info(const modal_ctx* c, int64_t info[10]) {
+int modal_info(const modal_ctx* c, int64_t info[12]) {
   if (!c || !info) return fail(MODAL_EINVAL, "NULL argument");
   info[0] = c->n_wg;
   info[1] = c->n_units;
@@ -984,6 +1222,8 @@ int modal_info(const modal_ctx* c, int64_t info[10]) {
   info[7] = c->occ;
   info[8] = (int64_t)c->makespan;
   info[9] = (int64_t)c->mean_load;
+  info[10] = c->shared ? 1 : 0;
+  info[11] = c->flops;
   return MODAL_OK;
 }
 

@@ -21,6 +21,7 @@ FLAG_ASYNC = 1
 FLAG_GRAPH = 2
 FLAG_GRAD = 4
 FLAG_SPLIT_ANY = 8
+FLAG_NO_SHARED = 16
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSTABLE", -3: "ENOMEM", -4: "EHIP",
           -5: "ENONFINITE", -6: "ESTATE", -7: "EHANG"}
@@ -34,7 +35,8 @@ class modal_instance(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_t", C.c_int32), ("n_in", C.c_int32),
                 ("reserved", C.c_int32), ("omega", _dp), ("gamma", _dp), ("lam", _dp),
                 ("kappa", C.c_double), ("H", _fp), ("x0", _dp), ("xm1", _dp),
-                ("b_ext", _dp), ("e_ext", _fp), ("n_exc", C.c_int64), ("c_out", _dp)]
+                ("b_ext", _dp), ("e_ext", _fp), ("n_exc", C.c_int64), ("c_out", _dp),
+                ("h_row_scale", _dp)]
 
 
 class modal_desc(C.Structure):
@@ -164,6 +166,10 @@ def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_ste
                 s.H = H.ctypes.data_as(_fp)
             s.n_in = H.shape[0]
             keep.append(H)
+            if inst.get("h_row_scale") is not None:
+                sc = _d(inst["h_row_scale"], s.n_in)
+                keep.append(sc)
+                s.h_row_scale = sc.ctypes.data_as(_dp)
         else:
             s.n_in = 0
         if inst.get("e_ext") is not None:
@@ -191,8 +197,10 @@ class Sim:
 
     ``instances``: list of dicts with keys kind ('linear' | 'tension' | 'vk'),
     omega, gamma, x0, xm1, c [n_t]; lam, kappa (tension); Ht float32
-    [n_in, n_t, n_t] (vk, host numpy or a CUDA tensor); optional b_ext [n_t]
-    and e_ext [n_exc] (float32).
+    [n_in, n_t, n_t] (vk, host numpy or a CUDA tensor) and optional
+    h_row_scale [n_in] (the instance's tensor is h_row_scale[n] Ht[n];
+    instances given the same Ht object share it, see ``modal_init``);
+    optional b_ext [n_t] and e_ext [n_exc] (float32).
     """
 
     def __init__(self, instances, fs, scheme="sv", flags=0, max_workgroups=0,
@@ -263,11 +271,11 @@ class Sim:
         return x, xm
 
     def info(self):
-        v = (C.c_int64 * 10)()
+        v = (C.c_int64 * 12)()
         _check(lib.modal_info(self._ctx, v))
         keys = ("workgroups", "units", "split_instances", "coupling_bytes_per_step",
                 "padded_bytes_per_step", "steps", "lds_bytes", "workgroups_per_cu",
-                "plan_makespan", "plan_mean")
+                "plan_makespan", "plan_mean", "shared", "flops_per_step")
         return dict(zip(keys, list(v)))
 
     def close(self):

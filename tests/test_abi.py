@@ -43,6 +43,14 @@ def test_validation_errors(bad, code):
     assert e.value.status == code
 
 
+def test_row_scale_must_be_finite():
+    from paper_2505_05940_amd import modal
+    H = np.zeros((2, 4, 4), np.float32)
+    with pytest.raises(modal.ModalError) as e:
+        modal.Sim([_inst(kind="vk", Ht=H, h_row_scale=np.array([1.0, np.inf]))], 44100.0, stream=0)
+    assert e.value.status == "EINVAL"
+
+
 def test_tf_rejects_overdamped_modes():
     from paper_2505_05940_amd import modal
     with pytest.raises(modal.ModalError) as e:

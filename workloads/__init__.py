@@ -137,3 +137,32 @@ def plate_fit(seed: int = 4, n_t: int = 200, n_in: int | None = None, n_steps: i
     return dict(n_t=n_t, n_in=n_t if n_in is None else n_in, area=0.12, h=h, nu=nu, rho=rho,
                 base_aspect=0.75, strike=(0.37, 0.61, 1.0 * h, 0.1), out=(0.71, 0.29),
                 proj_grid=(200, 150), fs=FS, n_steps=n_steps, theta0=base, theta_target=target)
+
+
+def plate_group(seed: int = 6, batch: int = 48, n_t: int = 40, n_in: int | None = None,
+                n_steps: int = 44100, forced: int = 0) -> dict:
+    """A group of plates that share one coupling tensor up to per-row scales.
+
+    Base: the sine-family plate of ``plate_vk`` (exact integrals).  Member b
+    scales in-plane row n of the base's scaled tensor by row_scale[b][n]
+    ~ U[0.5, 1.5] (as a change of stiffness or of in-plane eigenvalues would),
+    its angular frequencies by U[0.97, 1.03] and decay rates by U[0.8, 1.25]
+    (one factor per member), and its initial displacement by U[0.5, 1.5].
+    The first ``forced`` members are also driven: b_ext ~ N(0, 1) per mode
+    (scaled by 10, displacements well under the thickness) times a seeded
+    noise burst of 2000 samples.
+    """
+    rng = np.random.default_rng(seed)
+    base = plate_vk(seed=seed + 1000, n_t=n_t, n_in=n_in, family="sine", grid=None,
+                    n_steps=n_steps)
+    members = []
+    for b in range(batch):
+        m = dict(row_scale=rng.uniform(0.5, 1.5, size=base["n_in"]),
+                 omega_factor=float(rng.uniform(0.97, 1.03)),
+                 gamma_factor=float(rng.uniform(0.8, 1.25)),
+                 amp_factor=float(rng.uniform(0.5, 1.5)))
+        if b < forced:
+            m["b_ext"] = 10.0 * rng.normal(size=n_t)
+            m["e_ext"] = rng.normal(size=2000).astype(np.float32)
+        members.append(m)
+    return dict(base=base, members=members, n_steps=n_steps, fs=FS)
