@@ -117,7 +117,8 @@ typedef struct {
  * recursion coefficients in FP64 and stores them as float-float pairs,
  * partitions the batch into per-workgroup work, allocates device memory and
  * uploads the coupling tensors and initial states on `stream`.
- * Shared-tensor path: when every instance is VK with n_t <= 64, the
+ * Shared-tensor path: when every instance is VK with n_t <= 64 and
+ * n_in <= 64, the
  * instances pass at most batch/16 distinct H pointers (so the tensors are
  * shared by 16 instances on average) and neither MODAL_FLAG_GRAD nor
  * MODAL_FLAG_NO_SHARED is set, each distinct tensor is stored once and the

@@ -123,6 +123,13 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Workgroup barrier for LDS traffic only: this wave's LDS operations are
+// complete and every wave has arrived.  Unlike __syncthreads it does not
+// wait for outstanding global loads, so prefetches stay in flight across it.
+__device__ __forceinline__ void block_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Timeout of a per-instance barrier in ticks of the 100 MHz wall clock.
 constexpr unsigned long long kBarrierTimeout = 400000000ull;  // 4 s
 

@@ -147,11 +147,13 @@ struct GradParams {
 // without talking to other workgroups.
 constexpr int kSharedWaves = 4;
 constexpr int kSharedMaxKT = 4;  // modes per instance <= 16 kSharedMaxKT
+constexpr int kSharedMaxNin = 64; // in-plane rows per instance on this path
 
 struct SharedWg {
   long long a_off;  // packed tensor of the group (floats)
   int nin, nt;      // in-plane rows, modes
-  int kt, kc;       // 16-row tiles and 4-wide K steps of the group
+  int kt, kc;       // 16-row tiles and 4-wide K steps (the launch's; rows and
+                    // columns past nt are zero)
 };
 
 struct SharedSlot {
@@ -177,8 +179,15 @@ struct SharedParams {
   const long long* step_base;
   int* flags;
 };
-__host__ __device__ inline size_t shared_lds_bytes(int kt, int jt) {
-  return sizeof(float) * (2 * (size_t)kt * 4 * kt * 64 + (size_t)kSharedWaves * 16 * kt * 16 * jt);
+// LDS: two staged tensor rows (each padded to whole rounds of the
+// workgroup's 16-byte loads), X of every wave in two layouts, squared row
+// scales [nin][cols]
+__host__ __device__ inline size_t shared_lds_bytes(int kt, int kc, int jt, int nin_max) {
+  const size_t nt = 64 * kSharedWaves;
+  const size_t row4 = (size_t)kt * ((kc + 3) / 4) * 64;
+  const size_t na = (row4 + nt - 1) / nt;
+  return 16 * 2 * na * nt +
+         sizeof(float) * (2 * (size_t)kSharedWaves * 16 * kt * 16 * jt + (size_t)nin_max * 64 * jt);
 }
 
 }  // namespace modal

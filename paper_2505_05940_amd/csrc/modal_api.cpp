@@ -26,7 +26,7 @@ hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, size_t lds)
 hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
                           const UnitDev* unit, int n_units, float* state, int state_floats,
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
-hipError_t launch_shared(const SharedParams& P, int kt, int jt, int n_wg, hipStream_t s);
+hipError_t launch_shared(const SharedParams& P, int kt, int kc, int jt, int n_wg, hipStream_t s);
 }  // namespace modal
 
 using namespace modal;
@@ -174,7 +174,7 @@ struct modal_ctx {
   bool tangent = false;
   // shared-tensor path
   bool shared = false;
-  int sh_kt = 0, sh_jt = 0;
+  int sh_kt = 0, sh_kc = 0, sh_jt = 0;
   long long flops = 0;
   float *dShA = nullptr, *dShS2 = nullptr;
   SharedParams SP{};
@@ -463,15 +463,16 @@ struct SharedGroup {
 };
 
 // Instances grouped by (H pointer, n_t, n_in); empty unless the batch takes
-// the shared-tensor path (every instance VK with n_t <= 16 kSharedMaxKT and
-// at least 16 instances per distinct tensor on average).
+// the shared-tensor path (every instance VK with n_t <= 16 kSharedMaxKT,
+// n_in <= kSharedMaxNin, and at least 16 instances per distinct tensor on
+// average).
 std::vector<SharedGroup> shared_groups(const modal_desc* d) {
   std::vector<SharedGroup> g;
   if (d->flags & (MODAL_FLAG_GRAD | MODAL_FLAG_NO_SHARED)) return g;
   std::map<std::tuple<const float*, int, int>, int> index;
   for (int b = 0; b < d->batch; ++b) {
     const modal_instance& I = d->inst[b];
-    if (I.kind != MODAL_KIND_VK || I.n_t > 16 * kSharedMaxKT) return {};
+    if (I.kind != MODAL_KIND_VK || I.n_t > 16 * kSharedMaxKT || I.n_in > kSharedMaxNin) return {};
     auto key = std::make_tuple(I.H, I.n_t, I.n_in);
     auto it = index.find(key);
     if (it == index.end()) {
@@ -501,6 +502,14 @@ int init_shared(modal_ctx* c, const modal_desc* d, std::vector<SharedGroup>& gro
     nin_max = std::max(nin_max, g.nin);
     wg2 += ((long long)g.members.size() + 127) / 128;
   }
+  // K steps of the launch: the groups' common count, else the widest
+  int kc = -1;
+  for (auto& g : groups) {
+    const int gkc = (g.nt + 3) / 4;
+    kc = kc < 0 || kc == gkc ? gkc : 4 * kt;
+  }
+  if (kc < 4 * kt - 3) kc = 4 * kt;
+  const int kc4 = (kc + 3) / 4;
   // two column tiles per wave once that still gives every CU a workgroup
   const int jt = wg2 >= prop.multiProcessorCount ? 2 : 1;
   const int cols = 64 * jt, ktot = 16 * kt;
@@ -540,22 +549,24 @@ int init_shared(modal_ctx* c, const modal_desc* d, std::vector<SharedGroup>& gro
     if (dmax > 1e-6f * hmax)
       return fail(MODAL_EINVAL, "H not symmetric in its last two indices (instance " +
                                     std::to_string(g.members[0]) + ")");
-    const int gkt = (g.nt + 15) / 16, gkc = (g.nt + 3) / 4;
+    // A[n][t][c4][l][e] = H[n][16 t + l%16][4 (4 c4 + e) + l/16], zero past n_t
+    const size_t row = (size_t)kt * kc4 * 64 * 4;
     const long long a_off = (long long)apool.size();
-    apool.resize(apool.size() + (((size_t)g.nin * gkt * gkc * 64 + 63) & ~(size_t)63), 0.f);
+    apool.resize(apool.size() + (((size_t)g.nin * row + 63) & ~(size_t)63), 0.f);
     for (int n = 0; n < g.nin; ++n)
-      for (int t = 0; t < gkt; ++t)
-        for (int cc = 0; cc < gkc; ++cc)
-          for (int l = 0; l < 64; ++l) {
-            const int k = 16 * t + l % 16, q = 4 * cc + l / 16;
-            apool[a_off + (((size_t)n * gkt + t) * gkc + cc) * 64 + l] =
-                k < g.nt && q < g.nt ? H[((size_t)n * g.nt + k) * g.nt + q] : 0.f;
-          }
+      for (int t = 0; t < kt; ++t)
+        for (int c4 = 0; c4 < kc4; ++c4)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 4; ++e) {
+              const int k = 16 * t + l % 16, q = 4 * (4 * c4 + e) + l / 16;
+              apool[a_off + n * row + (((size_t)t * kc4 + c4) * 64 + l) * 4 + e] =
+                  k < g.nt && q < g.nt ? H[((size_t)n * g.nt + k) * g.nt + q] : 0.f;
+            }
     c->coupling_bytes += 4LL * g.nin * g.nt * g.nt * (long long)g.members.size();
     for (size_t i0 = 0; i0 < g.members.size(); i0 += cols) {
       const long long w = (long long)wgs.size();
-      wgs.push_back(SharedWg{a_off, g.nin, g.nt, gkt, gkc});
-      c->padded_bytes += 4LL * g.nin * gkt * gkc * 64;
+      wgs.push_back(SharedWg{a_off, g.nin, g.nt, kt, kc});
+      c->padded_bytes += 4LL * g.nin * (long long)row;
       for (size_t i = i0; i < std::min(g.members.size(), i0 + cols); ++i) {
         const int b = g.members[i];
         const modal_instance& I = d->inst[b];
@@ -591,12 +602,13 @@ int init_shared(modal_ctx* c, const modal_desc* d, std::vector<SharedGroup>& gro
   }
   c->shared = true;
   c->sh_kt = kt;
+  c->sh_kc = kc;
   c->sh_jt = jt;
   c->n_wg = (int)n_wg;
   c->n_units = (int)ncol;
   c->occ = 0;
   c->state_floats = (int)ncolk;
-  c->lds_bytes = shared_lds_bytes(kt, jt);
+  c->lds_bytes = shared_lds_bytes(kt, kc, jt, nin_max);
 
   const size_t meta_bytes = sizeof(SharedWg) * wgs.size() + sizeof(SharedSlot) * slots.size();
   int r = dalloc(&c->dShA, sizeof(float) * (apool.size() + 64));
@@ -982,7 +994,7 @@ static int enqueue_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride
       P.y = y + done;
       P.y_stride = y_stride;
       P.n_steps = (int)k;
-      HIP_TRY(launch_shared(P, c->sh_kt, c->sh_jt, c->n_wg, s));
+      HIP_TRY(launch_shared(P, c->sh_kt, c->sh_kc, c->sh_jt, c->n_wg, s));
     } else {
       StepParams P = c->P;
       P.y = y + done;

@@ -10,11 +10,14 @@
 // product followed by per-column reductions.  The product runs on
 // v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and B[l/16][l%16]
 // and receives D[4 (l/16) + r][l%16] in accumulator r.  H0[n] is the A
-// operand, pre-packed per (n, 16-row tile t, 4-wide K step c) in lane order
-// so that a workgroup stages one row n with coalesced 16-byte loads into
-// LDS (double-buffered, the next row in flight while the current one is
-// multiplied); X (FP32 high part of the float-float state) is the B operand,
-// held in registers for the whole step.  Every column keeps its own
+// operand, pre-packed per (n, 16-row tile t, group of four 4-wide K steps)
+// with each lane's four operands adjacent, so that a workgroup stages one
+// row n with coalesced 16-byte loads into LDS (double-buffered; rows are
+// loaded two ahead of the one multiplied) and a wave reads its operands
+// with 16-byte LDS reads; X (FP32 high part of the float-float state) is the
+// B operand, held in registers for the whole step, and also kept in LDS in
+// accumulator order for the eta reductions; the squared row scales of the
+// workgroup's columns sit in LDS for the whole launch.  Every column keeps its own
 // float-float state and coefficients and the update is the increment form of
 // the forward kernel, so the only difference from it is the order of the
 // FP32 sums inside the contraction.
@@ -27,184 +30,220 @@ namespace modal {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-template <int KT, int JT>
-__global__ void __launch_bounds__(kWave * kSharedWaves) shared_kernel(SharedParams P) {
-  constexpr int KC = 4 * KT;                      // K steps of 4 at most
+// Sum of v over the four lanes l, l^16, l^32, l^48 (gfx950 lane swaps).
+__device__ __forceinline__ float quad_sum(float v) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
+// KT: 16-row tiles; KC: 4-wide K steps (compile time, packed rows padded to
+// a multiple of 4 steps); JT: 16-column tiles per wave.
+template <int KT, int KC, int JT>
+__global__ void __launch_bounds__(kWave * kSharedWaves, (KT == 4 && JT == 2) ? 1 : 2)
+    shared_kernel(SharedParams P) {
   constexpr int CW = 16 * JT;                     // columns per wave
-  constexpr int ABUF = KT * KC * 64;              // floats of one packed row n (max)
-  constexpr int NA = (ABUF / 4 + kWave * kSharedWaves - 1) / (kWave * kSharedWaves);
+  constexpr int NT = kWave * kSharedWaves;        // threads per workgroup
+  constexpr int KC4 = (KC + 3) / 4;               // 16-byte groups of K steps per lane
+  constexpr int ROW4 = KT * KC4 * 64;             // 16-byte slots of one packed row n
+  constexpr int NA = (ROW4 + NT - 1) / NT;        // 16-byte loads per thread per row
+  constexpr int ABUF4 = NA * NT;                  // staged row, padded to whole rounds
   extern __shared__ float4 lds4[];
-  float* Abuf = reinterpret_cast<float*>(lds4);   // [2][ABUF]
+  v4f* Abuf4 = reinterpret_cast<v4f*>(lds4);      // [2][ABUF4]
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
   const int col16 = lane & 15, quad = lane >> 4;
-  float* xs = Abuf + 2 * ABUF + wave * (16 * KT) * CW;  // this wave's X: [16 KT][CW]
+  float* xs = reinterpret_cast<float*>(Abuf4 + 2 * ABUF4) + wave * (16 * KT) * CW;  // [16 KT][CW]
+  v4f* xdl = reinterpret_cast<v4f*>(Abuf4 + 2 * ABUF4 + kSharedWaves * 4 * KT * CW) +
+             wave * JT * KT * 64;  // X in accumulator order: [j][t][lane]
+  float* S2 = reinterpret_cast<float*>(Abuf4 + 2 * ABUF4 + 2 * kSharedWaves * 4 * KT * CW);  // [nin][cols]
   const SharedWg W = P.wg[blockIdx.x];
-  const int kt = W.kt, kc = W.kc;
-  const int nA4 = kt * kc * 16;  // float4 per packed row n of this group
-  const float4* Ag = reinterpret_cast<const float4*>(P.A + W.a_off);
+  const v4f* Ag = reinterpret_cast<const v4f*>(P.A + W.a_off);
   const int wcol = wave * CW;
   const long long col0 = (long long)blockIdx.x * P.cols + wcol;  // first global column of the wave
 
-  // X^n of the wave's columns into LDS
+  // the workgroup's squared row scales, and X^n of the wave's columns, into LDS
+  for (int i = tid; i < W.nin * P.cols; i += NT)
+    S2[i] = P.s2[(long long)blockIdx.x * P.nin_max * P.cols + i];
   for (int i = lane; i < 16 * KT * CW; i += kWave) {
     const int k = i / CW, cc = i % CW;
     xs[i] = P.x_hi[(col0 + cc) * P.ktot + k];
   }
+#pragma unroll
+  for (int j = 0; j < JT; ++j)
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      const long long o = (col0 + 16 * j + col16) * P.ktot + 16 * t + 4 * quad;
+      const float4 x = ld4(P.x_hi + o);
+      xdl[(j * KT + t) * 64 + lane] = (v4f){x.x, x.y, x.z, x.w};
+    }
   SharedSlot sl[JT];
 #pragma unroll
   for (int j = 0; j < JT; ++j) sl[j] = P.slot[col0 + 16 * j + col16];
-  __builtin_amdgcn_wave_barrier();
-  wave_lds_sync();
+  __syncthreads();
   const long long base = *P.step_base;
 
   for (int s = 0; s < P.n_steps; ++s) {
     const long long nabs = base + s;
-    float Xb[JT][KC];
-    v4f Xd[JT][KT], F[JT][KT];
+    v4f F[JT][KT];
+    float bq[JT][KC];  // B operands: X[4 c + l/16][column], the whole step
 #pragma unroll
     for (int j = 0; j < JT; ++j) {
 #pragma unroll
-      for (int c = 0; c < KC; ++c) Xb[j][c] = xs[(4 * c + quad) * CW + 16 * j + col16];
+      for (int t = 0; t < KT; ++t) F[j][t] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          Xd[j][t][r] = xs[(16 * t + 4 * quad + r) * CW + 16 * j + col16];
-          F[j][t][r] = 0.f;
-        }
-      }
+      for (int c = 0; c < KC; ++c) bq[j][c] = xs[(4 * c + quad) * CW + 16 * j + col16];
     }
-    // stage row n = 0
-    float4 pre[NA];
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int idx = tid + kWave * kSharedWaves * i;
-      pre[i] = idx < nA4 ? Ag[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    // rows n are staged two ahead: A(n+1) waits in registers while row n
+    // is multiplied out of LDS and A(n+2) is in flight.  Loads are
+    // unconditional (index clamped) so nothing waits for them early.
+    v4f preA[NA], preB[NA];
+#define SH_LOAD(N, DST)                                                     \
+  {                                                                         \
+    const v4f* src_ = Ag + (long long)(N) * ROW4;                           \
+    _Pragma("unroll") for (int i = 0; i < NA; ++i)                          \
+      DST[i] = src_[min(tid + NT * i, ROW4 - 1)];                           \
+  }
+#define SH_STORE(N, SRC)                                                    \
+  {                                                                         \
+    v4f* dst_ = Abuf4 + ((N) & 1) * ABUF4;                                  \
+    _Pragma("unroll") for (int i = 0; i < NA; ++i) dst_[tid + NT * i] = SRC[i]; \
+  }
+// one in-plane row n: prefetch A(n+2) into AFTER, multiply row n out of LDS,
+// fold it into F, then stage A(n+1) from NEXT for the following row
+#define SH_ROW(N, NEXT, AFTER)                                                                  \
+  {                                                                                             \
+    const int n_ = (N);                                                                         \
+    SH_LOAD(min(n_ + 2, W.nin - 1), AFTER)                                                     \
+    const v4f* Ac = Abuf4 + (n_ & 1) * ABUF4 + lane;                                            \
+    v4f a[KT][KC4];                                                                             \
+    _Pragma("unroll") for (int t = 0; t < KT; ++t)                                              \
+    _Pragma("unroll") for (int c4 = 0; c4 < KC4; ++c4) a[t][c4] = Ac[(t * KC4 + c4) * 64];      \
+    v4f acc[JT][KT];                                                                            \
+    _Pragma("unroll") for (int j = 0; j < JT; ++j)                                              \
+    _Pragma("unroll") for (int t = 0; t < KT; ++t) acc[j][t] = (v4f){0.f, 0.f, 0.f, 0.f};       \
+    _Pragma("unroll") for (int c = 0; c < KC; ++c)                                              \
+    _Pragma("unroll") for (int t = 0; t < KT; ++t)                                              \
+    _Pragma("unroll") for (int j = 0; j < JT; ++j)                                              \
+      acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][c / 4][c % 4], bq[j][c], acc[j][t], 0, 0, 0); \
+    _Pragma("unroll") for (int j = 0; j < JT; ++j) {                                            \
+      float eta = 0.f;                                                                          \
+      _Pragma("unroll") for (int t = 0; t < KT; ++t) {                                          \
+        const v4f xd = xdl[(j * KT + t) * 64 + lane];                                           \
+        _Pragma("unroll") for (int r = 0; r < 4; ++r) eta = fmaf(acc[j][t][r], xd[r], eta);    \
+      }                                                                                         \
+      const float e = S2[n_ * P.cols + wcol + 16 * j + col16] * quad_sum(eta);                  \
+      _Pragma("unroll") for (int t = 0; t < KT; ++t)                                            \
+      _Pragma("unroll") for (int r = 0; r < 4; ++r) F[j][t][r] = fmaf(e, acc[j][t][r], F[j][t][r]); \
+    }                                                                                           \
+    SH_STORE(n_ + 1, NEXT)                                                                      \
+    block_lds_sync();                                                                           \
+  }
+    // (past the last row the prefetch repeats it and the stage goes to the
+    // buffer no row reads again before the next step restages row 0)
+    SH_LOAD(0, preA);
     __syncthreads();  // every wave is done with the previous step's buffers
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const int idx = tid + kWave * kSharedWaves * i;
-      if (idx < nA4) reinterpret_cast<float4*>(Abuf)[idx] = pre[i];
-    }
+    SH_STORE(0, preA);
+    SH_LOAD(min(1, W.nin - 1), preB);
     __syncthreads();
-    for (int n = 0; n < W.nin; ++n) {
-      const float* Ac = Abuf + (n & 1) * ABUF;
-      const bool more = n + 1 < W.nin;
-      if (more) {
-        const float4* src = Ag + (long long)(n + 1) * nA4;
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-          const int idx = tid + kWave * kSharedWaves * i;
-          if (idx < nA4) pre[i] = src[idx];
-        }
-      }
-      float s2[JT];
-#pragma unroll
-      for (int j = 0; j < JT; ++j)
-        s2[j] = P.s2[((long long)blockIdx.x * P.nin_max + n) * P.cols + wcol + 16 * j + col16];
-      v4f acc[JT][KT];
-#pragma unroll
-      for (int j = 0; j < JT; ++j)
-#pragma unroll
-        for (int t = 0; t < KT; ++t) acc[j][t] = (v4f){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        if (c < kc) {
-#pragma unroll
-          for (int t = 0; t < KT; ++t) {
-            if (t < kt) {
-              const float a = Ac[(t * kc + c) * 64 + lane];
-#pragma unroll
-              for (int j = 0; j < JT; ++j)
-                acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Xb[j][c], acc[j][t], 0, 0, 0);
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < JT; ++j) {
-        float eta = 0.f;
-#pragma unroll
-        for (int t = 0; t < KT; ++t)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) eta = fmaf(acc[j][t][r], Xd[j][t][r], eta);
-        eta += __shfl_xor(eta, 16, kWave);
-        eta += __shfl_xor(eta, 32, kWave);
-        const float e = s2[j] * eta;
-#pragma unroll
-        for (int t = 0; t < KT; ++t)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) F[j][t][r] = fmaf(e, acc[j][t][r], F[j][t][r]);
-      }
-      if (more) {
-        float4* dst = reinterpret_cast<float4*>(Abuf + ((n + 1) & 1) * ABUF);
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-          const int idx = tid + kWave * kSharedWaves * i;
-          if (idx < nA4) dst[idx] = pre[i];
-        }
-      }
-      __syncthreads();
+    int n = 0;
+    for (; n + 1 < W.nin; n += 2) {
+      SH_ROW(n, preB, preA)
+      SH_ROW(n + 1, preA, preB)
     }
-    // output y^n = c . X^n and the float-float update of every (mode, column)
+    if (n < W.nin) SH_ROW(n, preB, preA)
+#undef SH_ROW
+#undef SH_LOAD
+#undef SH_STORE
+    // output y^n = c . X^n and the float-float update of every (mode, column):
+    // one 4-mode group per (column tile j, row tile t), its state and
+    // coefficients loaded one group ahead of the arithmetic
     bool bad = false;
+    float ypart[JT];
+    float eo[JT];
 #pragma unroll
     for (int j = 0; j < JT; ++j) {
-      const long long col = col0 + 16 * j + col16;
-      const float e = nabs < sl[j].n_exc ? P.e_ext[sl[j].e_off + nabs] : 0.f;
-      float ypart = 0.f;
+      ypart[j] = 0.f;
+      eo[j] = nabs < sl[j].n_exc ? P.e_ext[sl[j].e_off + nabs] : 0.f;
+    }
+    struct Grp {
+      float4 xh, xl, dh, dl, mh, ml, ph, pl, rh, rl, b, cw;
+    };
+    auto grp_off = [&](int u) -> long long {
+      const int j = u / KT, t = u % KT;
+      return (col0 + 16 * j + col16) * P.ktot + 16 * t + 4 * quad;
+    };
+    auto grp_load = [&](long long o) -> Grp {
+      Grp g;
+      g.xh = ld4(P.x_hi + o); g.xl = ld4(P.x_lo + o); g.dh = ld4(P.d_hi + o); g.dl = ld4(P.d_lo + o);
+      g.mh = ld4(P.m_hi + o); g.ml = ld4(P.m_lo + o); g.ph = ld4(P.p_hi + o); g.pl = ld4(P.p_lo + o);
+      g.rh = ld4(P.r_hi + o); g.rl = ld4(P.r_lo + o); g.b = ld4(P.b_ext + o); g.cw = ld4(P.c_out + o);
+      return g;
+    };
+    Grp cur = grp_load(grp_off(0));
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        const int k = 16 * t + 4 * quad;
-        const long long o = col * P.ktot + k;
-        float4 xh = ld4(P.x_hi + o), xl = ld4(P.x_lo + o);
-        float4 dh = ld4(P.d_hi + o), dl = ld4(P.d_lo + o);
-        const float4 mh = ld4(P.m_hi + o), ml = ld4(P.m_lo + o);
-        const float4 ph = ld4(P.p_hi + o), pl = ld4(P.p_lo + o);
-        const float4 rh = ld4(P.r_hi + o), rl = ld4(P.r_lo + o);
-        const float4 b = ld4(P.b_ext + o), cw = ld4(P.c_out + o);
-        ypart += dot4(cw, xh);
-        ff_step(xh.x, xl.x, dh.x, dl.x, mh.x, ml.x, ph.x, pl.x, rh.x, rl.x, fmaf(b.x, e, -F[j][t][0]));
-        ff_step(xh.y, xl.y, dh.y, dl.y, mh.y, ml.y, ph.y, pl.y, rh.y, rl.y, fmaf(b.y, e, -F[j][t][1]));
-        ff_step(xh.z, xl.z, dh.z, dl.z, mh.z, ml.z, ph.z, pl.z, rh.z, rl.z, fmaf(b.z, e, -F[j][t][2]));
-        ff_step(xh.w, xl.w, dh.w, dl.w, mh.w, ml.w, ph.w, pl.w, rh.w, rl.w, fmaf(b.w, e, -F[j][t][3]));
-        bad |= !(isfinite(xh.x) && isfinite(xh.y) && isfinite(xh.z) && isfinite(xh.w));
-        st4(P.x_hi + o, xh);
-        st4(P.x_lo + o, xl);
-        st4(P.d_hi + o, dh);
-        st4(P.d_lo + o, dl);
-        float* xr = xs + k * CW + 16 * j + col16;
-        xr[0] = xh.x;
-        xr[CW] = xh.y;
-        xr[2 * CW] = xh.z;
-        xr[3 * CW] = xh.w;
-      }
-      ypart += __shfl_xor(ypart, 16, kWave);
-      ypart += __shfl_xor(ypart, 32, kWave);
-      if (quad == 0 && sl[j].out_row >= 0 && P.y)
-        P.y[(long long)sl[j].out_row * P.y_stride + s] = ypart;
+    for (int u = 0; u < JT * KT; ++u) {
+      const int j = u / KT, t = u % KT;
+      Grp nxt;
+      if (u + 1 < JT * KT) nxt = grp_load(grp_off(u + 1));
+      const long long o = grp_off(u);
+      const float e = eo[j];
+      float4 xh = cur.xh, xl = cur.xl, dh = cur.dh, dl = cur.dl;
+      ypart[j] += dot4(cur.cw, xh);
+      ff_step(xh.x, xl.x, dh.x, dl.x, cur.mh.x, cur.ml.x, cur.ph.x, cur.pl.x, cur.rh.x, cur.rl.x,
+              fmaf(cur.b.x, e, -F[j][t][0]));
+      ff_step(xh.y, xl.y, dh.y, dl.y, cur.mh.y, cur.ml.y, cur.ph.y, cur.pl.y, cur.rh.y, cur.rl.y,
+              fmaf(cur.b.y, e, -F[j][t][1]));
+      ff_step(xh.z, xl.z, dh.z, dl.z, cur.mh.z, cur.ml.z, cur.ph.z, cur.pl.z, cur.rh.z, cur.rl.z,
+              fmaf(cur.b.z, e, -F[j][t][2]));
+      ff_step(xh.w, xl.w, dh.w, dl.w, cur.mh.w, cur.ml.w, cur.ph.w, cur.pl.w, cur.rh.w, cur.rl.w,
+              fmaf(cur.b.w, e, -F[j][t][3]));
+      bad |= !(isfinite(xh.x) && isfinite(xh.y) && isfinite(xh.z) && isfinite(xh.w));
+      st4(P.x_hi + o, xh);
+      st4(P.x_lo + o, xl);
+      st4(P.d_hi + o, dh);
+      st4(P.d_lo + o, dl);
+      float* xr = xs + (16 * t + 4 * quad) * CW + 16 * j + col16;
+      xr[0] = xh.x;
+      xr[CW] = xh.y;
+      xr[2 * CW] = xh.z;
+      xr[3 * CW] = xh.w;
+      xdl[(j * KT + t) * 64 + lane] = (v4f){xh.x, xh.y, xh.z, xh.w};
+      if (u + 1 < JT * KT) cur = nxt;
+    }
+#pragma unroll
+    for (int j = 0; j < JT; ++j) {
+      const float yv = quad_sum(ypart[j]);
+      if (quad == 0 && sl[j].out_row >= 0 && P.y) P.y[(long long)sl[j].out_row * P.y_stride + s] = yv;
     }
     if (__any(bad) && lane == 0) atomicOr(&P.flags[1], 1);
     wave_lds_sync();  // the new X is visible to every lane of the wave
   }
 }
 
-// kt: 16-row tiles of the widest group (1..kSharedMaxKT); jt: 16-column
-// tiles per wave (1 or 2).
-hipError_t launch_shared(const SharedParams& P, int kt, int jt, int n_wg, hipStream_t s) {
-#define SH(K, J)                                                                              \
-  hipLaunchKernelGGL((shared_kernel<K, J>), dim3(n_wg), dim3(kWave * kSharedWaves),           \
-                     shared_lds_bytes(K, J), s, P)
-  if (jt == 1) {
-    if (kt <= 1) SH(1, 1); else if (kt == 2) SH(2, 1); else if (kt == 3) SH(3, 1); else SH(4, 1);
-  } else {
-    if (kt <= 1) SH(1, 2); else if (kt == 2) SH(2, 2); else if (kt == 3) SH(3, 2); else SH(4, 2);
+// kt: 16-row tiles of the widest group (1..kSharedMaxKT); kc: 4-wide K
+// steps of every group (4 kt - 3 .. 4 kt); jt: 16-column tiles per wave (1, 2).
+#define SH_KC(K, C)                                                                           \
+  if (kc == C) {                                                                              \
+    if (jt == 1)                                                                              \
+      hipLaunchKernelGGL((shared_kernel<K, C, 1>), dim3(n_wg), dim3(kWave * kSharedWaves),    \
+                         shared_lds_bytes(K, C, 1, P.nin_max), s, P);                         \
+    else                                                                                      \
+      hipLaunchKernelGGL((shared_kernel<K, C, 2>), dim3(n_wg), dim3(kWave * kSharedWaves),    \
+                         shared_lds_bytes(K, C, 2, P.nin_max), s, P);                         \
+    return hipGetLastError();                                                                 \
   }
-#undef SH
-  return hipGetLastError();
+#define SH_KT(K)                                                                              \
+  if (kt == K) {                                                                              \
+    SH_KC(K, 4 * K - 3) SH_KC(K, 4 * K - 2) SH_KC(K, 4 * K - 1) SH_KC(K, 4 * K)               \
+  }
+hipError_t launch_shared(const SharedParams& P, int kt, int kc, int jt, int n_wg, hipStream_t s) {
+  SH_KT(1) SH_KT(2) SH_KT(3) SH_KT(4)
+  return hipErrorInvalidValue;
 }
+#undef SH_KT
+#undef SH_KC
 
 }  // namespace modal

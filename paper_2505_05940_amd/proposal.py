@@ -69,12 +69,13 @@ def denormalize(z, base):
     return th
 
 
-def simulate(setup, thetas, n_steps, batch=4096):
+def simulate(setup, thetas, n_steps, batch=65536):
     """Outputs [n, n_steps] (CUDA float32) of the plates theta, by batches of
-    one persistent launch each."""
+    one launch each.  The plates share the setup's base tensor up to per-row
+    scales, so a batch runs on the library's dense (MFMA) path."""
     out = []
     for s in range(0, len(thetas), batch):
-        insts = [fit.plate_instance(setup, t) for t in thetas[s:s + batch]]
+        insts = [fit.plate_instance_shared(setup, t) for t in thetas[s:s + batch]]
         sim = modal.Sim(insts, setup.fs)
         out.append(sim.run(n_steps).clone())
         sim.close()

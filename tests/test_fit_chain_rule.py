@@ -28,6 +28,24 @@ def test_parameterised_plate_matches_oracle():
         assert np.abs(p["Ht"] - o["Ht"]).max() < 2e-7 * np.abs(o["Ht"]).max()
 
 
+def test_shared_form_matches_oracle():
+    """The base-tensor-plus-row-scale form of the parameterised plate (what
+    batches on the dense path receive) against the oracle's own plate."""
+    from paper_2505_05940_amd import fit
+    fw = W.plate_fit(n_t=16)
+    st = _setup(fw)
+    th_b = fw["theta_target"].copy()
+    th_b[2] = 0.55
+    for th in (fw["theta0"], th_b):
+        p = fit.plate_instance_shared(st, th)
+        o = OP.plate_from_theta(fw, th)
+        assert p["Ht"] is fit.base_tensor(st)
+        for k in ("omega", "gamma", "x0", "c"):
+            assert np.allclose(p[k], o[k], rtol=1e-12, atol=1e-14 * np.abs(o[k]).max()), k
+        Ht = p["Ht"].astype(float) * p["h_row_scale"][:, None, None]
+        assert np.abs(Ht - o["Ht"]).max() < 2e-7 * np.abs(o["Ht"]).max()
+
+
 def test_chain_rule_against_oracle_differences():
     from paper_2505_05940_amd import fit
     fw = W.plate_fit(n_t=10)
