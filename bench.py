@@ -7,6 +7,10 @@ one launch of the persistent step kernel (replayed from a hipGraph).  The
 metric is simulated instance.mode.samples per second: sum_b N_b x samples /
 wall time.  Inputs are resident in HBM before timing starts.
 
+The same line carries ``dense_path``: the shared-tensor (FP32 MFMA) path
+timed on a batch of proposal-style plates that share one coupling tensor up
+to per-row scales, with its own roofline against the FP32 matrix peak.
+
 Prints one JSON line (rank 0).  ``--gpus`` above 1 is refused: this path runs
 on one GPU; instances would shard across GPUs with no communication.
 """
@@ -25,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 KERNEL_SRC = os.path.join(ROOT, "paper_2505_05940_amd", "csrc", "step_kernel.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_b256.json")
 
@@ -81,6 +86,56 @@ def write_traffic(fetch_csv, write_csv, copy_mib, samples_per_step, launch):
     print(json.dumps(out, indent=1))
 
 
+def dense_path(batch, n_modes, samples, launches, seed):
+    """The shared-tensor (FP32 MFMA) path on proposal-style plates: one
+    coupling tensor for the batch up to per-row scales (stiffness and
+    aspect), parameters drawn from the proposal priors.  Inputs resident
+    before timing; launches timed with HIP events on the launch stream."""
+    import torch
+    import workloads as W
+    from paper_2505_05940_amd import fit, modal, proposal
+    setup = fit.PlateSetup(n_t=n_modes, n_in=n_modes)
+    base = W.plate_fit(n_t=n_modes)["theta0"]
+    th = proposal.sample_prior(np.random.default_rng(seed), batch, base)
+    insts = [fit.plate_instance_shared(setup, t) for t in th]
+    sim = modal.Sim(insts, 44100.0, flags=modal.FLAG_GRAPH | modal.FLAG_ASYNC, chunk_steps=samples)
+    del insts
+    info = sim.info()
+    assert info["shared"] == 1
+    y = torch.empty((batch, samples), device="cuda")
+    stream = torch.cuda.current_stream()
+    sim.run(samples, out=y)
+    sim.check()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(launches)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        sim.run(samples, out=y)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.check()
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    flops = info["flops_per_step"] * samples
+    achieved = flops / (launch_ms * 1e-3) / 1e12
+    sim.close()
+    return {
+        "workload": f"proposal-prior von Karman plates sharing one coupling tensor up to per-row "
+                    f"scales, B={batch}, N={n_modes} transverse = in-plane modes, 44.1 kHz, "
+                    f"{samples} samples per launch",
+        "value": batch * n_modes * samples * launches / wall,
+        "unit": "instance*mode*samples/s",
+        "instance_steps_per_s": batch * samples * launches / wall,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "modal::shared_kernel", "launch_ms": launch_ms,
+                     "algorithmic_flops_per_launch": flops},
+        "workgroups": info["workgroups"],
+    }
+
+
 def cpu_baseline(wls, n_inst, seconds, seed):
     """The FP64 oracle's time loop on a seeded sample of the batch (its
     coupling tensors built beforehand, untimed).  Each sampled instance runs
@@ -128,6 +183,10 @@ def main():
                     help="co-resident workgroups for the plan (0: the library default)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (with --max-workgroups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the shared-tensor (MFMA) path measurement")
+    ap.add_argument("--dense-batch", type=int, default=65536)
+    ap.add_argument("--dense-modes", type=int, default=40)
     ap.add_argument("--cpu-instances", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -236,6 +295,11 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
+    if not args.no_dense:
+        sim.close()
+        out["dense_path"] = dense_path(args.dense_batch, args.dense_modes, S, 3, args.seed)
+        print(f"[bench] dense path {out['dense_path']['roofline']['achieved']:.1f} TFLOP/s",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wls, args.cpu_instances, args.cpu_seconds, args.seed)
     print(json.dumps(out))
