@@ -70,7 +70,8 @@ enum {
                            workgroups are free (tests, tuning); by default
                            instances below 4 MB of tensor stay whole and a
                            slab must pay for its per-step exchange          */
-  MODAL_FLAG_NO_SHARED = 16 /* never use the shared-tensor (MFMA) path      */
+  MODAL_FLAG_NO_SHARED = 16, /* never use the shared-tensor (MFMA) path     */
+  MODAL_FLAG_NO_BLOCK = 32  /* ignore mode_class: store every tensor dense   */
 };
 
 /* One modal system.  All arrays are host memory. */
@@ -97,6 +98,16 @@ typedef struct {
                             h_row_scale[n] * H[n][k][j] (NULL = 1).  Instances
                             that pass the same H pointer (and n_t, n_in) share
                             one tensor up to these scales; see modal_init.   */
+  const uint8_t *mode_class; /* VK, optional [n_t] values 0..3: a partition of
+                            the modes (e.g. the parities of a plate mode's
+                            two indices).  When H is host memory and, for
+                            every in-plane row n and class i, the entries
+                            H[n][k][j] with class(k) = i vanish exactly
+                            outside a single class of j, the tensor is stored
+                            as one dense block per (n, i) and only those
+                            blocks are streamed (about a quarter of the bytes
+                            for plate parity classes).  Otherwise, and with
+                            MODAL_FLAG_GRAD or MODAL_FLAG_NO_BLOCK, ignored.  */
 } modal_instance;
 
 typedef struct {
@@ -161,8 +172,11 @@ int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
  * workgroup (both in streamed-byte units), [10] 1 on the shared-tensor path
  * (then [1] is the number of instance columns and [2], [8], [9] are 0),
  * [11] FP32 operations of the force per step (sum over VK instances of
- * 2 n_in n_t^2 + 4 n_in n_t). */
-int modal_info(const modal_ctx *c, int64_t info[12]);
+ * 2 n_in n_t^2 + 4 n_in n_t), [12] instances stored parity-blocked,
+ * [13] dense-equivalent tensor bytes per step (sum of 4 n_in n_t^2).
+ * [3] counts the entries of the stored representation: for a blocked
+ * instance, 4 bytes per entry of its stored blocks without padding. */
+int modal_info(const modal_ctx *c, int64_t info[14]);
 
 void modal_destroy(modal_ctx *c);
 

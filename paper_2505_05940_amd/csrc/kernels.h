@@ -25,6 +25,14 @@ struct InstDev {
   int out_row;         // row of y
   long long e_off;     // offset into the excitation pool
   long long n_exc;     // excitation length (0 = none)
+  // parity-blocked tensor (blk = 1): modes are stored grouped by class, class
+  // i on rows [cls[i], cls[i+1]) (each a multiple of 4, ntp = cls[4]); in-plane
+  // row n holds, for every class i, the block of rows of class i against
+  // the columns of class jmap[n][i] (or nothing if jmap < 0), w columns wide
+  int blk, w;
+  int cls[5];
+  int pad;
+  long long jmap_off;  // int4 offset of jmap[nin][4] in the block-map pool
 };
 
 // A slice of in-plane rows [row0, row1) of one instance, owned by one
@@ -83,6 +91,7 @@ __host__ __device__ inline GradLds grad_lds(float* base) {
 
 struct StepParams {
   const InstDev* inst;
+  const int4* jmap;     // block maps of parity-blocked instances
   const UnitDev* unit;
   const int* wg_begin;  // [n_wg + 1] unit ranges per workgroup
   const float* H;       // tensor pool

@@ -8,7 +8,9 @@
 #include <cstring>
 #include <map>
 #include <queue>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -172,6 +174,11 @@ struct modal_ctx {
   unsigned int* dGCtr = nullptr;
   long long ckpt_floats = 0, rec_floats = 0;
   bool tangent = false;
+  // parity-blocked tensors
+  int n_blocked = 0;
+  long long dense_bytes = 0;
+  int4* dJmap = nullptr;
+  std::vector<std::vector<int>> mode_slot;  // per instance: caller mode -> internal slot
   // shared-tensor path
   bool shared = false;
   int sh_kt = 0, sh_kc = 0, sh_jt = 0;
@@ -195,7 +202,7 @@ void free_ctx(modal_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   void* ptrs[] = {c->dH,   c->dMeta, c->dCoef, c->dState, c->dPart, c->dCtr, c->dFlags,
                   c->dStep, c->dE,   c->dHd,   c->dCkpt,  c->dRec,  c->dAdj, c->dAcc,
-                  c->dGPart, c->dGCtr, c->dShA, c->dShS2};
+                  c->dGPart, c->dGCtr, c->dShA, c->dShS2, c->dJmap};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -241,8 +248,11 @@ int validate(const modal_desc* d) {
       if (I.n_in < 1 || !I.H) return fail(MODAL_EINVAL, "VK needs n_in >= 1 and H" + at);
       if (I.h_row_scale && !finite_all(I.h_row_scale, I.n_in))
         return fail(MODAL_EINVAL, "non-finite h_row_scale" + at);
-    } else if (I.n_in != 0 || I.h_row_scale) {
-      return fail(MODAL_EINVAL, "n_in must be 0 and h_row_scale NULL unless VK" + at);
+      if (I.mode_class)
+        for (int k = 0; k < I.n_t; ++k)
+          if (I.mode_class[k] > 3) return fail(MODAL_EINVAL, "mode_class outside 0..3" + at);
+    } else if (I.n_in != 0 || I.h_row_scale || I.mode_class) {
+      return fail(MODAL_EINVAL, "n_in must be 0 and h_row_scale, mode_class NULL unless VK" + at);
     }
     if (I.kind == MODAL_KIND_TENSION) {
       if (!I.lambda || !finite_all(I.lambda, I.n_t) || !std::isfinite(I.kappa))
@@ -273,12 +283,126 @@ constexpr double kSplitSyncCost = 65536.0;
 // from step to step and a whole-instance workgroup outruns any slab barrier.
 constexpr double kMinSplitCost = 4.0 * 1048576.0;
 
+// ------------------------------------------------------ parity-blocked tensors
+// Internal layout of an instance whose tensor splits by mode class: modes
+// grouped by class (each class padded to a multiple of 4), and for every
+// in-plane row n and class i the single class jmap[n][i] of columns that
+// holds nonzero entries in the rows of class i (-1: none).
+struct BlockPlan {
+  bool ok = false;
+  int cls[5] = {0, 0, 0, 0, 0};
+  int w = 0, rmax = 0;
+  std::vector<int> slot_mode, mode_slot, jmap;
+  long long stored_bytes = 0;
+};
+
+// Checks that H has the block structure the classes imply, exactly (every
+// other entry is 0.0), and that it is finite and symmetric to 1e-6; any
+// failure leaves the instance dense, where the device check reports it.
+void analyze_blocks(const modal_instance& I, BlockPlan& bp) {
+  bp.ok = false;
+  const int nt = I.n_t, nin = I.n_in;
+  int cnt[4] = {0, 0, 0, 0};
+  for (int k = 0; k < nt; ++k) cnt[I.mode_class[k]]++;
+  int off = 0;
+  for (int i = 0; i < 4; ++i) {
+    bp.cls[i] = off;
+    const int R = round4(cnt[i]);
+    off += R;
+    bp.w = std::max(bp.w, R);
+  }
+  bp.cls[4] = off;
+  bp.rmax = bp.w;
+  if (off > kMaxModes) return;
+  bp.slot_mode.assign(off, -1);
+  bp.mode_slot.assign(nt, -1);
+  int fill[4] = {0, 0, 0, 0};
+  for (int k = 0; k < nt; ++k) {
+    const int i = I.mode_class[k];
+    const int sl = bp.cls[i] + fill[i]++;
+    bp.slot_mode[sl] = k;
+    bp.mode_slot[k] = sl;
+  }
+  bp.jmap.assign((size_t)nin * 4, -1);
+  bp.stored_bytes = 0;
+  float hmax = 0.f, dmax = 0.f;
+  const uint8_t* ck = I.mode_class;
+  for (int n = 0; n < nin; ++n) {
+    bool nz[4][4] = {};
+    const float* Hn = I.H + (size_t)n * nt * nt;
+    for (int p = 0; p < nt; ++p) {
+      const float* row = Hn + (size_t)p * nt;
+      bool* nzp = nz[ck[p]];
+      for (int q = 0; q < nt; ++q) {
+        const float v = row[q];
+        if (!std::isfinite(v)) return;
+        if (v != 0.f) {
+          nzp[ck[q]] = true;
+          hmax = std::max(hmax, std::fabs(v));
+        }
+      }
+      for (int q = p + 1; q < nt; ++q) dmax = std::max(dmax, std::fabs(row[q] - Hn[(size_t)q * nt + p]));
+    }
+    for (int i = 0; i < 4; ++i) {
+      if (cnt[i] == 0) continue;
+      int found = -1;
+      for (int j = 0; j < 4; ++j)
+        if (nz[i][j]) {
+          if (found >= 0) return;  // two column classes in one block row
+          found = j;
+        }
+      bp.jmap[(size_t)n * 4 + i] = found;
+      if (found >= 0) bp.stored_bytes += 4LL * cnt[i] * cnt[found];
+    }
+  }
+  if (dmax > 1e-6f * hmax) return;
+  bp.ok = true;
+}
+
+// Analyses every VK instance that carries mode classes and host tensors, on
+// all host threads (largest first).
+void plan_blocks(const modal_desc* d, std::vector<BlockPlan>& plans) {
+  plans.assign(d->batch, BlockPlan{});
+  if (d->flags & (MODAL_FLAG_GRAD | MODAL_FLAG_NO_BLOCK)) return;
+  std::vector<int> todo;
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    if (I.kind != MODAL_KIND_VK || !I.mode_class) continue;
+    hipPointerAttribute_t attr;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&attr, I.H) == hipSuccess)
+      on_device = attr.type == hipMemoryTypeDevice;
+    else
+      (void)hipGetLastError();
+    if (!on_device) todo.push_back(b);
+  }
+  std::stable_sort(todo.begin(), todo.end(), [&](int a, int b) {
+    return (double)d->inst[a].n_in * d->inst[a].n_t * d->inst[a].n_t >
+           (double)d->inst[b].n_in * d->inst[b].n_t * d->inst[b].n_t;
+  });
+  std::atomic<size_t> next{0};
+  auto work = [&]() {
+    for (size_t i = next++; i < todo.size(); i = next++) analyze_blocks(d->inst[todo[i]], plans[todo[i]]);
+  };
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned nth = (unsigned)std::min<size_t>(hw, todo.size());
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nth; ++t) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
+}
+
 // Planning cost of an instance in streamed-byte units: per in-plane row the
 // bytes of its tensor row plus the row's reduction; per step a fixed cost
-// for the state update and output.
-void unit_costs(const modal_instance& I, double& row_cost, double& fixed_cost) {
+// for the state update and output.  A blocked instance streams its blocks
+// and reduces once per block.
+void unit_costs(const modal_instance& I, double& row_cost, double& fixed_cost,
+                const BlockPlan* bp = nullptr) {
   const int ntp = round4(I.n_t);
-  if (I.kind == MODAL_KIND_VK) {
+  if (I.kind == MODAL_KIND_VK && bp && bp->ok) {
+    row_cost = 4.0 * bp->cls[4] * bp->w + 4.0 * 2048.0;
+    fixed_cost = 8192.0;
+  } else if (I.kind == MODAL_KIND_VK) {
     row_cost = 4.0 * I.n_t * ntp + 4096.0;
     fixed_cost = 8192.0;
   } else {
@@ -372,7 +496,7 @@ bool plan_batch(const modal_desc* d, const std::vector<double>& row_cost,
 // floats).  Device sources are copied directly; host sources are padded into
 // two pinned staging buffers that alternate with the asynchronous copies.
 int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>& inst,
-                   hipStream_t stream) {
+                   const std::vector<BlockPlan>& plans, hipStream_t stream) {
   const size_t kStage = 64u << 20;
   float* stage[2] = {nullptr, nullptr};
   hipEvent_t done[2] = {nullptr, nullptr};
@@ -398,6 +522,56 @@ int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>
     const modal_instance& I = d->inst[b];
     if (I.kind != MODAL_KIND_VK) continue;
     const InstDev& D = inst[b];
+    if (D.blk) {
+      // blocks gathered on the host threads, staged like dense rows of w
+      if (!stage[0]) {
+        for (int i = 0; i < 2; ++i) {
+          UP_TRY(hipHostMalloc((void**)&stage[i], kStage, hipHostMallocDefault));
+          UP_TRY(hipEventCreateWithFlags(&done[i], hipEventDisableTiming));
+        }
+      }
+      const BlockPlan& bp = plans[b];
+      const size_t rows = (size_t)D.nin * D.ntp;
+      const size_t rows_per = std::max<size_t>(1, kStage / (sizeof(float) * D.w));
+      for (size_t r0 = 0; r0 < rows; r0 += rows_per) {
+        const size_t nr = std::min(rows_per, rows - r0);
+        if (used[slot]) UP_TRY(hipEventSynchronize(done[slot]));
+        float* dst = stage[slot];
+        auto fill_rows = [&](size_t a, size_t z) {
+          for (size_t r = a; r < z; ++r) {
+            float* out = dst + r * D.w;
+            const size_t rr = r0 + r;
+            const int n = (int)(rr / D.ntp), sl = (int)(rr % D.ntp);
+            const int p = bp.slot_mode[sl];
+            int ci = 0;
+            while (ci < 3 && sl >= bp.cls[ci + 1]) ++ci;
+            const int tj = bp.jmap[(size_t)n * 4 + ci];
+            if (p < 0 || tj < 0) {
+              std::memset(out, 0, sizeof(float) * D.w);
+              continue;
+            }
+            const float* row = I.H + ((size_t)n * D.nt + p) * D.nt;
+            const double sc = I.h_row_scale ? I.h_row_scale[n] : 1.0;
+            for (int s = 0; s < D.w; ++s) {
+              const int sq = bp.cls[tj] + s;
+              const int q = sq < bp.cls[tj + 1] ? bp.slot_mode[sq] : -1;
+              out[s] = q < 0 ? 0.f : (I.h_row_scale ? (float)(sc * (double)row[q]) : row[q]);
+            }
+          }
+        };
+        const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (unsigned t = 1; t < nth; ++t) th.emplace_back(fill_rows, nr * t / nth, nr * (t + 1) / nth);
+        fill_rows(0, nr / nth);
+        for (auto& t : th) t.join();
+        UP_TRY(hipMemcpyAsync(c->dH + D.h_off + r0 * D.w, dst, sizeof(float) * nr * D.w,
+                              hipMemcpyHostToDevice, stream));
+        UP_TRY(hipEventRecord(done[slot], stream));
+        used[slot] = true;
+        slot ^= 1;
+      }
+      continue;
+    }
     hipPointerAttribute_t attr;
     bool on_device = false;
     if (hipPointerGetAttributes(&attr, I.H) == hipSuccess)
@@ -699,6 +873,10 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   std::vector<double> row_cost(d->batch), fixed_cost(d->batch);
   int red_floats = 0;
   std::vector<int> qs_of(d->batch, 1), J_of(d->batch, 1);
+  std::vector<BlockPlan> plans;
+  plan_blocks(d, plans);
+  std::vector<int> jmap_pool;
+  c->mode_slot.assign(d->batch, {});
   for (int b = 0; b < d->batch; ++b) {
     const modal_instance& I = d->inst[b];
     InstDev& D = inst[b];
@@ -706,6 +884,16 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
     D.nt = I.n_t;
     D.nin = I.kind == MODAL_KIND_VK ? I.n_in : 0;
     D.ntp = round4(I.n_t);
+    if (plans[b].ok) {
+      const BlockPlan& bp = plans[b];
+      D.ntp = bp.cls[4];
+      D.blk = 1;
+      D.w = bp.w;
+      for (int i = 0; i < 5; ++i) D.cls[i] = bp.cls[i];
+      D.jmap_off = (long long)jmap_pool.size() / 4;
+      jmap_pool.insert(jmap_pool.end(), bp.jmap.begin(), bp.jmap.end());
+      c->mode_slot[b] = bp.mode_slot;
+    }
     D.mode_off = mode_floats;
     mode_floats += D.ntp;
     D.kappa = (float)I.kappa;
@@ -716,15 +904,26 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
     D.h_off = 0;
     if (I.kind == MODAL_KIND_VK) {
       D.h_off = h_floats;
-      const long long f = (long long)D.nin * D.nt * D.ntp;
-      h_floats += (f + 63) & ~63LL;  // 256-byte aligned instances
-      c->coupling_bytes += 4LL * D.nin * D.nt * D.nt;
+      c->dense_bytes += 4LL * D.nin * D.nt * D.nt;
       c->flops += 2LL * D.nin * D.nt * D.nt + 4LL * D.nin * D.nt;
-      c->padded_bytes += 4 * f;
-      choose_sweep(D.nt, D.ntp / 4, qs_of[b], J_of[b]);
-      red_floats = std::max(red_floats, 2 * qs_of[b] * D.ntp);
+      if (D.blk) {
+        const long long f = (long long)D.nin * D.ntp * D.w;
+        h_floats += (f + 63) & ~63LL;
+        c->coupling_bytes += plans[b].stored_bytes;
+        c->padded_bytes += 4 * f;
+        c->n_blocked++;
+        choose_sweep(plans[b].rmax, D.w / 4, qs_of[b], J_of[b]);
+        red_floats = std::max(red_floats, 2 * qs_of[b] * D.w);
+      } else {
+        const long long f = (long long)D.nin * D.nt * D.ntp;
+        h_floats += (f + 63) & ~63LL;  // 256-byte aligned instances
+        c->coupling_bytes += 4LL * D.nin * D.nt * D.nt;
+        c->padded_bytes += 4 * f;
+        choose_sweep(D.nt, D.ntp / 4, qs_of[b], J_of[b]);
+        red_floats = std::max(red_floats, 2 * qs_of[b] * D.ntp);
+      }
     }
-    unit_costs(I, row_cost[b], fixed_cost[b]);
+    unit_costs(I, row_cost[b], fixed_cost[b], &plans[b]);
   }
   c->mode_floats = mode_floats;
   c->nw = d->waves == 0 ? 4 : d->waves;
@@ -852,16 +1051,18 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
     const int o = inst[b].mode_off;
     c->nt[b] = I.n_t;
     c->inst_mode_off[b] = o;
+    const std::vector<int>& ms = c->mode_slot[b];
     for (int k = 0; k < I.n_t; ++k) {
+      const int e = o + (ms.empty() ? k : ms[k]);  // internal slot of caller mode k
       const Coef q = coefficients(d->scheme, I.omega[k], I.gamma[k], T);
-      split(q.m, m_hi[o + k], m_lo[o + k]);
-      split(q.p, p_hi[o + k], p_lo[o + k]);
-      split(q.r, r_hi[o + k], r_lo[o + k]);
-      cw[o + k] = (float)I.c_out[k];
-      lam[o + k] = I.lambda ? (float)I.lambda[k] : 0.f;
-      bx[o + k] = I.b_ext ? (float)I.b_ext[k] : 0.f;
-      split(I.x0[k], xinit[o + k], xinit[mode_floats + o + k]);
-      split(I.x0[k] - I.xm1[k], xinit[2 * mode_floats + o + k], xinit[3 * mode_floats + o + k]);
+      split(q.m, m_hi[e], m_lo[e]);
+      split(q.p, p_hi[e], p_lo[e]);
+      split(q.r, r_hi[e], r_lo[e]);
+      cw[e] = (float)I.c_out[k];
+      lam[e] = I.lambda ? (float)I.lambda[k] : 0.f;
+      bx[e] = I.b_ext ? (float)I.b_ext[k] : 0.f;
+      split(I.x0[k], xinit[e], xinit[mode_floats + e]);
+      split(I.x0[k] - I.xm1[k], xinit[2 * mode_floats + e], xinit[3 * mode_floats + e]);
     }
   }
   c->state0.assign(4 * (size_t)state_floats, 0.f);
@@ -892,6 +1093,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   ALLOC(c->dFlags, sizeof(int) * (2 + 2 * d->batch));
   ALLOC(c->dStep, sizeof(long long));
   ALLOC(c->dE, sizeof(float) * (size_t)(e_floats + 1));
+  ALLOC(c->dJmap, sizeof(int) * (jmap_pool.size() + 4));
 #undef ALLOC
   auto bail = [&](int r) {
     free_ctx(c);
@@ -905,8 +1107,11 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   } while (0)
   HIP_TRY_C(hipMemsetAsync(c->dH, 0, sizeof(float) * (size_t)(h_floats + 64), stream));
   {
-    int r = upload_tensors(c, d, inst, stream);
+    int r = upload_tensors(c, d, inst, plans, stream);
     if (r) return bail(r);
+    if (!jmap_pool.empty())
+      HIP_TRY_C(hipMemcpyAsync(c->dJmap, jmap_pool.data(), sizeof(int) * jmap_pool.size(),
+                               hipMemcpyHostToDevice, stream));
   }
   char* meta = (char*)c->dMeta;
   InstDev* dInst = (InstDev*)meta;
@@ -942,6 +1147,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   }
   StepParams& P = c->P;
   P.inst = dInst;
+  P.jmap = c->dJmap;
   P.unit = dUnit;
   P.wg_begin = dWg;
   P.H = c->dH;
@@ -1211,8 +1417,10 @@ int modal_get_state(modal_ctx* c, double* x, double* xm1, void* stream_) {
   const size_t S = c->state_floats;
   size_t o = 0;
   for (int b = 0; b < c->batch; ++b) {
-    const int so = c->unit_state_of_inst[b];
+    const int so0 = c->unit_state_of_inst[b];
+    const std::vector<int>* ms = b < (int)c->mode_slot.size() && !c->mode_slot[b].empty() ? &c->mode_slot[b] : nullptr;
     for (int k = 0; k < c->nt[b]; ++k, ++o) {
+      const int so = so0 + (ms ? (*ms)[k] - k : 0);
       const double xv = (double)st[so + k] + (double)st[S + so + k];
       const double dv = (double)st[2 * S + so + k] + (double)st[3 * S + so + k];
       x[o] = xv;
@@ -1222,7 +1430,7 @@ int modal_get_state(modal_ctx* c, double* x, double* xm1, void* stream_) {
   return MODAL_OK;
 }
 
-int modal_info(const modal_ctx* c, int64_t info[12]) {
+int modal_info(const modal_ctx* c, int64_t info[14]) {
   if (!c || !info) return fail(MODAL_EINVAL, "NULL argument");
   info[0] = c->n_wg;
   info[1] = c->n_units;
@@ -1236,6 +1444,8 @@ int modal_info(const modal_ctx* c, int64_t info[12]) {
   info[9] = (int64_t)c->mean_load;
   info[10] = c->shared ? 1 : 0;
   info[11] = c->flops;
+  info[12] = c->n_blocked;
+  info[13] = c->shared ? c->coupling_bytes : c->dense_bytes;
   return MODAL_OK;
 }
 

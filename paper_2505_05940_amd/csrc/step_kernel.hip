@@ -1,9 +1,9 @@
 // Persistent time-stepping kernel for batches of modal systems (gfx950).
 //
-// One workgroup is one 64-lane wave.  A workgroup owns a fixed list of work
-// units for the whole launch; a unit is either a whole instance or a slab of
+// A workgroup (one or four 64-lane waves) owns a fixed list of work units
+// for the whole launch; a unit is either a whole instance or a slab of
 // in-plane rows of a von Karman instance whose coupling tensor is split over
-// several workgroups.  Per audio sample (paper: Sec. 2.2, modal oscillator
+// several workgroups; the waves of a workgroup share a unit's rows.  Per audio sample (paper: Sec. 2.2, modal oscillator
 // update) each unit
 //   1. publishes q^n (fp32 high part) to LDS and writes the output sample
 //      y^n = sum_k c_k q_k^n (modal-to-physical transform at one point),
@@ -123,6 +123,155 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
   }
 }
 
+// ---------------------------------------------- parity-blocked von Karman rows
+// Rows [row0, row1) of an instance stored parity-blocked: modes are grouped
+// by class (class i on internal modes [cls[i], cls[i+1])), and in-plane row
+// n holds, per class i, the rows of class i against the columns of class
+// j = jmap[n][i] only (every other entry of those rows is zero), w columns
+// wide.  The sweep is the dense one applied to each (n, i) block in turn:
+// blocks of qs stored rows, lane slot v = lane + 64 j reading float4 v of
+// the block, buffer resources sized to the valid rows, the next block's
+// loads issued before the current one is used.  Accumulating along the
+// stored rows of block (n, i) gives V[n, k] for the modes k of class j
+// (Ht symmetric), so at the end of each block the slot accumulators are
+// reduced over the qs sub-rows through LDS onto the lanes owning those
+// modes; at the end of row n, eta_n and the force follow as in the dense
+// sweep.  The loader walks (n, i, block) one block ahead of the arithmetic
+// and hands each block's target range and end-of-class/row flags along.
+struct BlkMeta {
+  int q0;     // first stored row (internal mode) of the block
+  int tc;     // first float4 column group of the target class
+  int tlen;   // float4 column groups of the target class
+  int flags;  // 1: last block of its class, 2: last of its row, 4: last overall
+};
+
+__device__ __forceinline__ int sel4(const int4 v, int i) {
+  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+template <int GM>
+__device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict__ jm,
+                            const InstDev& I, int qs, int row0, int row1, const float* Xs,
+                            float* red, float4 (&Fa)[GM], int G, int lane) {
+  constexpr int J = kSweepLoads;
+  if (row1 <= row0) return;
+  const int ntp = I.ntp, w = I.w;
+  const int nc = w >> 2;
+  const int qsnc = qs * nc;
+  const int nc_modes = ntp >> 2;
+  int voff[J], sub[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int v = lane + kWave * j;
+    voff[j] = 16 * v;
+    sub[j] = v < qsnc ? v / nc : 0;
+  }
+  int co[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) co[i] = I.cls[i];
+  const long long row_floats = (long long)ntp * w;
+  const int blk_bytes = 4 * qs * w;
+  // loader position: row ln, class li, block lb; jv = jmap of row ln
+  int ln = row0, li = 0, lb = 0;
+  int4 jv = jm[row0];
+  auto has_block = [&](int i) { return co[i + 1] > co[i] && sel4(jv, i) >= 0; };
+  auto to_data = [&]() {  // first (row, class) at or after (ln, li) with a block
+    while (ln < row1) {
+      while (li < 4 && !has_block(li)) ++li;
+      if (li < 4) return;
+      if (++ln < row1) jv = jm[ln];
+      li = 0;
+    }
+  };
+  to_data();
+  if (ln >= row1) return;  // no stored block in these rows
+  auto load = [&](float4 (&h)[J], BlkMeta& m) {
+    const bool live = ln < row1;
+    const float* bp = Hb;
+    int bytes = 0;
+    m = BlkMeta{0, 0, 0, 0};
+    if (live) {
+      const int R = co[li + 1] - co[li];
+      const int nb = (R + qs - 1) / qs;
+      const int q0 = co[li] + lb * qs;
+      bp = Hb + (long long)ln * row_floats + (long long)q0 * w;
+      bytes = 4 * min(qs, R - lb * qs) * w;
+      const int tj = sel4(jv, li);
+      m.q0 = q0;
+      m.tc = co[tj] >> 2;
+      m.tlen = (co[tj + 1] - co[tj]) >> 2;
+      if (++lb == nb) {
+        m.flags = 1;
+        lb = 0;
+        ++li;
+        while (li < 4 && !has_block(li)) ++li;
+        if (li == 4) {
+          m.flags |= 2;
+          li = 0;
+          if (++ln < row1) jv = jm[ln];
+          to_data();
+          if (ln >= row1) m.flags |= 4;
+        }
+      }
+    }
+    const v4i r = buf_rsrc(bp, bytes);
+#pragma unroll
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+  };
+  float4 ha[J], hb[J], acc[J], V[GM];
+  BlkMeta ma, mb;
+#pragma unroll
+  for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
+#pragma unroll
+  for (int g = 0; g < GM; ++g) V[g] = f4(0.f);
+  int par = 0;
+  auto step = [&](float4 (&hc)[J], const BlkMeta& mc, float4 (&hn)[J], BlkMeta& mn) -> bool {
+    load(hn, mn);
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = fma4(hc[j], Xs[min(mc.q0 + sub[j], ntp - 1)], acc[j]);
+    if (mc.flags & 1) {
+      // block row of class i done: reduce over sub-rows onto the target modes
+      float* rb = red + (par & 1) * qs * w;
+      ++par;
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+        if (voff[j] < blk_bytes) st4(rb + (voff[j] >> 2), acc[j]);
+      wave_lds_sync();
+#pragma unroll
+      for (int g = 0; g < GM; ++g) {
+        const int k4 = lane + kWave * g;
+        const int c4 = k4 - mc.tc;
+        if (g < G && c4 >= 0 && c4 < mc.tlen) {
+          float4 sum = ld4(rb + 4 * c4);
+          for (int t = 1; t < qs; ++t) sum = add4(sum, ld4(rb + t * w + 4 * c4));
+          V[g] = add4(V[g], sum);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
+    }
+    if (mc.flags & 2) {
+      // row n done: eta_n and the force
+      float eta = 0.f;
+#pragma unroll
+      for (int g = 0; g < GM; ++g) {
+        const int k4 = lane + kWave * g;
+        if (g < G && k4 < nc_modes) eta += dot4(V[g], ld4(Xs + 4 * k4));
+      }
+      eta = wave_sum(eta);
+#pragma unroll
+      for (int g = 0; g < GM; ++g) {
+        Fa[g] = fma4(V[g], eta, Fa[g]);
+        V[g] = f4(0.f);
+      }
+    }
+    return !(mc.flags & 4);
+  };
+  load(ha, ma);
+  while (step(ha, ma, hb, mb) && step(hb, mb, ha, ma)) {
+  }
+}
+
 // Per-mode state update of the float4 groups owned by this lane.
 template <int GM>
 __device__ __forceinline__ void update_groups(const StepParams& P, const InstDev& I, int soff,
@@ -239,7 +388,10 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
         __syncthreads();  // q^n in LDS
         const int R = U.row1 - U.row0;
         const int r0 = U.row0 + (R * wave) / NW, r1 = U.row0 + (R * (wave + 1)) / NW;
-        vk_rows<GM>(P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa, G, lane);
+        if (I.blk)
+          vk_rows_blk<GM>(P.H + I.h_off, P.jmap + I.jmap_off, I, U.qs, r0, r1, Xs, red, Fa, G, lane);
+        else
+          vk_rows<GM>(P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa, G, lane);
         if (NW > 1) {
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
@@ -328,7 +480,7 @@ __global__ void advance_kernel(long long* step_base, int n_steps) {
 // their bit patterns); a non-finite entry reports +inf in both.
 __global__ void check_kernel(const float* H, const InstDev* inst, int* out) {
   const InstDev I = inst[blockIdx.y];
-  if (I.kind != KIND_VK) return;
+  if (I.kind != KIND_VK || I.blk) return;  // blocked tensors are checked on the host
   const long long total = (long long)I.nin * I.nt * I.nt;
   float dmax = 0.f, hmax = 0.f;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;

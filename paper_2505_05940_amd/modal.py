@@ -22,6 +22,7 @@ FLAG_GRAPH = 2
 FLAG_GRAD = 4
 FLAG_SPLIT_ANY = 8
 FLAG_NO_SHARED = 16
+FLAG_NO_BLOCK = 32
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSTABLE", -3: "ENOMEM", -4: "EHIP",
           -5: "ENONFINITE", -6: "ESTATE", -7: "EHANG"}
@@ -36,7 +37,7 @@ class modal_instance(C.Structure):
                 ("reserved", C.c_int32), ("omega", _dp), ("gamma", _dp), ("lam", _dp),
                 ("kappa", C.c_double), ("H", _fp), ("x0", _dp), ("xm1", _dp),
                 ("b_ext", _dp), ("e_ext", _fp), ("n_exc", C.c_int64), ("c_out", _dp),
-                ("h_row_scale", _dp)]
+                ("h_row_scale", _dp), ("mode_class", C.POINTER(C.c_uint8))]
 
 
 class modal_desc(C.Structure):
@@ -170,6 +171,11 @@ def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_ste
                 sc = _d(inst["h_row_scale"], s.n_in)
                 keep.append(sc)
                 s.h_row_scale = sc.ctypes.data_as(_dp)
+            if inst.get("mode_class") is not None:
+                mc = np.ascontiguousarray(inst["mode_class"], dtype=np.uint8)
+                assert mc.shape == (n,)
+                keep.append(mc)
+                s.mode_class = mc.ctypes.data_as(C.POINTER(C.c_uint8))
         else:
             s.n_in = 0
         if inst.get("e_ext") is not None:
@@ -200,6 +206,7 @@ class Sim:
     [n_in, n_t, n_t] (vk, host numpy or a CUDA tensor) and optional
     h_row_scale [n_in] (the instance's tensor is h_row_scale[n] Ht[n];
     instances given the same Ht object share it, see ``modal_init``);
+    optional mode_class [n_t] (uint8 0..3, the tensor's block structure);
     optional b_ext [n_t] and e_ext [n_exc] (float32).
     """
 
@@ -271,11 +278,12 @@ class Sim:
         return x, xm
 
     def info(self):
-        v = (C.c_int64 * 12)()
+        v = (C.c_int64 * 14)()
         _check(lib.modal_info(self._ctx, v))
         keys = ("workgroups", "units", "split_instances", "coupling_bytes_per_step",
                 "padded_bytes_per_step", "steps", "lds_bytes", "workgroups_per_cu",
-                "plan_makespan", "plan_mean", "shared", "flops_per_step")
+                "plan_makespan", "plan_mean", "shared", "flops_per_step", "blocked_instances",
+                "dense_bytes_per_step")
         return dict(zip(keys, list(v)))
 
     def close(self):

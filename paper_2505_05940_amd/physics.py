@@ -210,6 +210,16 @@ def string_instance(wl):
                 kappa=wl["EA"] / (2.0 * wl["L"]) / wl["rhoA"], x0=x0, xm1=x0.copy(), c=c)
 
 
+def mode_classes(m, q):
+    """Parity class 2 (m mod 2) + (q mod 2) of each transverse plate mode.
+    With sine in-plane modes, each coupling integral over x (over y) is a sum
+    of integrals of sin(k pi x / L) with k = a +- m_p +- m_q, all of one
+    parity, which vanish for even k; so for in-plane row n the entries between
+    modes of classes i and j vanish unless i xor j is fixed by (a_n, b_n):
+    one block of columns per class of rows."""
+    return (2 * (np.asarray(m) % 2) + (np.asarray(q) % 2)).astype(np.uint8)
+
+
 def plate_instance(wl, threads=0):
     """von Karman plate instance with the scaled tensor
     Ht = sqrt(E/(2 rho)) H / zeta^2 (rho volumetric) in float32."""
@@ -241,5 +251,8 @@ def plate_instance(wl, threads=0):
         xo, yo = wl["out_rel"][0] * Lx, wl["out_rel"][1] * Ly
     x0 = plate_initial(m, q, Lx, Ly, wl["proj_grid"], xc, yc, amp, rad)
     c = plate_pickup(m, q, Lx, Ly, xo, yo)
-    return dict(kind="vk", omega=omega, gamma=gamma, lam=lam, Ht=Ht, x0=x0,
-                xm1=x0.copy(), c=c, Lx=Lx, Ly=Ly, m=m, q=q)
+    out = dict(kind="vk", omega=omega, gamma=gamma, lam=lam, Ht=Ht, x0=x0,
+               xm1=x0.copy(), c=c, Lx=Lx, Ly=Ly, m=m, q=q)
+    if wl["inplane"] == "sine":
+        out["mode_class"] = mode_classes(m, q)
+    return out

@@ -1,0 +1,115 @@
+"""Parity-blocked coupling tensors (sine in-plane plates stored one block
+per in-plane row and mode class) against the FP64 oracle, which always uses
+the dense tensor.  Bar: relative L2 error of each output signal <= 1e-5."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import instances as OI
+from oracle import simulate as OS
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel_l2(y, ref):
+    return float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2505_05940_amd import modal, physics
+    return modal, physics
+
+
+def _ragged():
+    """Sizes with empty and one-mode classes, widths that are and are not
+    multiples of 4, single-row and multi-row in-plane counts."""
+    out = []
+    for i, (nt, nin) in enumerate([(3, 2), (5, 7), (17, 9), (33, 33), (40, 20), (64, 64), (65, 30),
+                                   (90, 90)]):
+        wl = W.plate_vk(seed=200 + i, n_t=nt, n_in=nin, family="sine", grid=None, n_steps=3000)
+        wl["strike"]["amplitude"] = 2e-3
+        out.append(wl)
+    return out
+
+
+@pytest.fixture(scope="module")
+def ragged_refs():
+    wls = _ragged()
+    return wls, [OS.run(OI.plate_instance(w), 3000, w["fs"]) for w in wls]
+
+
+@pytest.mark.parametrize("max_wg,waves", [(0, 4), (0, 1), (7, 4), (3, 1)])
+def test_blocked_ragged_batch(gpu, ragged_refs, max_wg, waves):
+    modal, physics = gpu
+    wls, refs = ragged_refs
+    insts = [physics.plate_instance(w) for w in wls]
+    _say(f"case: blocked ragged batch of {len(insts)}, max_workgroups={max_wg}, waves={waves}")
+    sim = modal.Sim(insts, 44100.0, max_workgroups=max_wg, waves=waves, flags=modal.FLAG_SPLIT_ANY)
+    info = sim.info()
+    assert info["blocked_instances"] == len(insts), info
+    assert info["coupling_bytes_per_step"] < 0.35 * info["dense_bytes_per_step"], info
+    if max_wg:
+        assert info["split_instances"] >= 1
+    y = sim.run(3000).double().cpu().numpy()
+    for b, ref in enumerate(refs):
+        assert rel_l2(y[b], ref) < TOL, (b, wls[b]["n_t"], rel_l2(y[b], ref))
+    # the dense layout of the same batch agrees
+    yd = modal.Sim(insts, 44100.0, max_workgroups=max_wg, waves=waves,
+                   flags=modal.FLAG_SPLIT_ANY | modal.FLAG_NO_BLOCK).run(3000).double().cpu().numpy()
+    for b in range(len(insts)):
+        assert rel_l2(yd[b], y[b]) < 2 * TOL
+
+
+def test_blocked_state_and_resume(gpu):
+    """State readback goes through the mode permutation; runs resume."""
+    modal, physics = gpu
+    wl = W.plate_vk(seed=210, n_t=37, n_in=21, family="sine", grid=None, n_steps=400)
+    p = physics.plate_instance(wl)
+    o = OI.plate_instance(wl)
+    _say("case: blocked 37/21, state readback and resume")
+    sim = modal.Sim([p], 44100.0)
+    assert sim.info()["blocked_instances"] == 1
+    a = sim.run(250).cpu().numpy()
+    b = sim.run(150).cpu().numpy()
+    x, xm = sim.state()
+    _, st = OS.run(o, 400, 44100.0, return_states=True)
+    assert rel_l2(x, st[400]) < TOL and rel_l2(xm, st[399]) < TOL
+    sim.reset()
+    assert np.array_equal(sim.run(400).cpu().numpy(), np.concatenate([a, b], axis=1))
+
+
+def test_benchmark_batch_sampled(gpu):
+    """The 256-plate benchmark batch at its full size, in the launch
+    configuration the benchmark times (library default shape, 441-sample
+    launches): sampled instances against the oracle over two launches."""
+    modal, physics = gpu
+    import torch
+    wls = W.plate_batch(seed=3, batch=256)
+    _say("case: benchmark batch 256 plates, default launch, 2 x 441 steps")
+    insts = [physics.plate_instance(w) for w in wls]
+    sim = modal.Sim(insts, 44100.0, flags=modal.FLAG_GRAPH | modal.FLAG_ASYNC, chunk_steps=441)
+    info = sim.info()
+    assert info["blocked_instances"] == 256
+    del insts
+    y = torch.empty((256, 882), device="cuda")
+    sim.run(441, out=y[:, :441])
+    sim.run(441, out=y[:, 441:])
+    sim.check()
+    y = y.double().cpu().numpy()
+    n = np.array([w["n_t"] for w in wls])
+    for b in (int(np.argmin(n)), int(np.argsort(n)[128]), int(np.argmax(n))):
+        ref = OS.run(OI.plate_instance(wls[b]), 882, wls[b]["fs"])
+        _say(f"  instance {b} (N={n[b]}): rel L2 {rel_l2(y[b], ref):.2e}")
+        assert rel_l2(y[b], ref) < TOL, (b, n[b], rel_l2(y[b], ref))
