@@ -137,7 +137,8 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
 // reduced over the qs sub-rows through LDS onto the lanes owning those
 // modes; at the end of row n, eta_n and the force follow as in the dense
 // sweep.  The loader walks (n, i, block) one block ahead of the arithmetic
-// and hands each block's target range and end-of-class/row flags along.
+// and hands each block's target range and end-of-class/row flags along;
+// blocks are loaded two ahead of the arithmetic.
 struct BlkMeta {
   int q0;     // first stored row (internal mode) of the block
   int tc;     // first float4 column group of the target class
@@ -218,13 +219,15 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
 #pragma unroll
     for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
   };
-  float4 ha[J], hb[J], acc[J], V[GM];
-  BlkMeta ma, mb;
+  float4 ha[J], hb[J], hc3[J], acc[J], V[GM];
+  BlkMeta ma, mb, mc3;
 #pragma unroll
   for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
 #pragma unroll
   for (int g = 0; g < GM; ++g) V[g] = f4(0.f);
   int par = 0;
+  // consumes block `hc` after issuing the loads of the block two ahead into
+  // `hn` (three buffers in turn keep two blocks in flight per wave)
   auto step = [&](float4 (&hc)[J], const BlkMeta& mc, float4 (&hn)[J], BlkMeta& mn) -> bool {
     load(hn, mn);
 #pragma unroll
@@ -268,7 +271,8 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
     return !(mc.flags & 4);
   };
   load(ha, ma);
-  while (step(ha, ma, hb, mb) && step(hb, mb, ha, ma)) {
+  load(hb, mb);
+  while (step(ha, ma, hc3, mc3) && step(hb, mb, ha, ma) && step(hc3, mc3, hb, mb)) {
   }
 }
 
