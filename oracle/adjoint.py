@@ -103,7 +103,11 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None):
     """Gradients of L with dL/dy^n = ybar[n].
 
     Returns dict: m, p, r (per mode), x0, xm1 (per mode), c (per mode),
-    scale (force scale s, the nonlinearity's prefactor), theta (if Hdot).
+    scale (force scale s, the nonlinearity's prefactor), theta (if Hdot),
+    and for a von Karman instance row (per in-plane mode n): dL/d log s_n for
+    a factor s_n on row n of the scaled tensor.  That factor scales V_n and
+    eta_n together, so the force term eta_n V_n goes as s_n^2 and
+    dL/d log s_n = -2 sum over steps of eta_n (V_n . u).
     """
     g, p, r = _coeffs(inst, fs, scheme)
     m = g + p - 1.0
@@ -114,6 +118,8 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None):
     db_next = np.zeros(n)  # db^{n+2}
     gm, gp, gr, gc = (np.zeros(n) for _ in range(4))
     gs, gth = 0.0, 0.0
+    vk = inst["kind"] == "vk"
+    grow = np.zeros(inst["Ht"].shape[0]) if vk else None
     for k in range(n_steps - 1, -1, -1):
         db = qb - p * db_next          # db^{k+1}
         u = r * db
@@ -123,6 +129,10 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None):
         gr += db * (_ext(inst, k, X) - Fs[k])
         gc += ybar[k] * X
         gs -= u @ Fs[k]
+        if vk:
+            n_in = inst["Ht"].shape[0]
+            V = (inst["Ht"].reshape(n_in * n, n) @ X).reshape(n_in, n)
+            grow = grow - 2.0 * (V @ X) * (V @ u)
         if Hdot is not None:
             n_in = Hdot.shape[0]
             V = (inst["Ht"].reshape(n_in * n, n) @ X).reshape(n_in, n)
@@ -133,7 +143,7 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None):
         qb = ybar[k] * c + qb + m * db - _jvp(inst, X, u)
         db_next = db
     d0b = -p * db_next  # d^0 only feeds d^1
-    return dict(m=gm, p=gp, r=gr, c=gc, x0=qb + d0b, xm1=-d0b, scale=gs, theta=gth)
+    return dict(m=gm, p=gp, r=gr, c=gc, x0=qb + d0b, xm1=-d0b, scale=gs, theta=gth, row=grow)
 
 
 def sv_omega_gamma_grads(g, omega, gamma, T):

@@ -82,6 +82,27 @@ def test_reverse_gradient_matches_complex_step(kind):
     assert abs(cs - g["scale"]) <= 1e-7 * abs(cs), (cs, g["scale"])
 
 
+def test_row_scale_gradient_matches_complex_step():
+    """dL/d log s_n for a factor s_n on row n of the scaled tensor, and its
+    sum over rows against the whole-tensor direction Hdot = Ht."""
+    fs, steps = 44100.0, 400
+    inst = _vk_small(steps=steps)
+    w = np.linspace(1, 2, steps) / np.abs(inst["x0"]).max() ** 2
+    y, *_ = adjoint.forward(inst, steps, fs)
+    g = adjoint.reverse(inst, steps, fs, _loss_grad(y.real, w), Hdot=inst["Ht"])
+    for n in (0, 2, 5):
+        def L(t, n=n):
+            i2 = dict(inst)
+            Ht = np.array(inst["Ht"], dtype=complex)
+            Ht[n] *= np.exp(t)
+            i2["Ht"] = Ht
+            yy = adjoint.forward(i2, steps, fs)[0]
+            return 0.5 * np.sum(w * yy * yy)
+        cs = adjoint.complex_step(L, 0.0)
+        assert abs(cs - g["row"][n]) <= 1e-7 * abs(cs), (n, cs, g["row"][n])
+    assert abs(g["row"].sum() - g["theta"]) <= 1e-10 * abs(g["theta"])
+
+
 def test_tensor_direction_matches_complex_step():
     fs, steps = 44100.0, 300
     inst = _vk_small(steps=steps)
