@@ -198,13 +198,16 @@ int modal_set_tangent(modal_ctx *c, int32_t inst, const float *Hd, void *stream)
  *   g_x0, g_xm1       dL/d q^0_k, dL/d q^-1_k
  *   g_scale [batch]   dL/d log s for a factor s on the nonlinear force
  *   g_theta [batch]   dL/d theta through the tangent tensor (0 without one)
+ *   g_row             dL/d log s_n for a factor s_n on row n of the scaled
+ *                     tensor, per in-plane row of every VK instance in batch
+ *                     order ([sum of n_in over VK instances])
  * Needs a context created with MODAL_FLAG_GRAD (else ESTATE).  Leaves the
  * context reset to its initial state.  Errors: EINVAL, ENOMEM, EHIP,
  * ENONFINITE, EHANG. */
 int modal_grad(modal_ctx *c, int64_t n_steps, const float *dL_dy, int64_t y_stride,
                int32_t ckpt_every, double *g_omega, double *g_gamma, double *g_c,
                double *g_x0, double *g_xm1, double *g_scale, double *g_theta,
-               void *stream);
+               double *g_row, void *stream);
 
 /* Host-only preview of the work partition modal_init would make for `d`
  * with n_workgroups co-resident workgroups (validates d like modal_init; no

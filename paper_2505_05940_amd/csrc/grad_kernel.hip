@@ -22,7 +22,7 @@ template <int GM, bool TAN>
 __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__ Hdb, int nt,
                          int ntp, int qs, int row0, int row1, const float* Xs, const float* Us,
                          float* red, float4 (&Ju)[GM], float4 (&Fa)[GM], float& tsum, int G,
-                         int lane) {
+                         int lane, float* rrow) {
   // Same sweep as the forward kernel (contiguous blocks of qs stored rows,
   // per-block buffer resources, next block loaded ahead) with two
   // right-hand sides, q and u, and optionally the tangent tensor times q.
@@ -116,6 +116,8 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
     }
     eta = wave_sum(eta);
     w = wave_sum(w);
+    // row-scale gradient term of this step (summed over steps afterwards)
+    if (rrow && lane == 0) rrow[n] = -2.f * eta * w;
     if (TAN) {
       etad = wave_sum(etad);
       vdu = wave_sum(vdu);
@@ -258,8 +260,9 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
         __syncthreads();  // q^n, u^n in LDS
         const int R = U.row1 - U.row0;
         const int r0 = U.row0 + (R * wave) / NW, r1 = U.row0 + (R * (wave + 1)) / NW;
+        float* rrow = P.rrec ? P.rrec + (long long)s * P.rows_total + I.row_off : nullptr;
         vk_rows2<GM, TAN>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs, r0, r1,
-                          Xs, Us, red, Ju, Fa, tsum, G, lane);
+                          Xs, Us, red, Ju, Fa, tsum, G, lane, rrow);
         if (NW > 1) {
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
@@ -363,6 +366,17 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
   }
 }
 
+// Adds the per-row records of one segment (steps in record order) to the
+// float-float row accumulators acc[2][rows].
+__global__ void row_sum_kernel(const float* rrec, int seg_len, int rows, float* acc) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  ff a{acc[r], acc[rows + r]};
+  for (int s = 0; s < seg_len; ++s) a = ff_add(a, ff{rrec[(long long)s * rows + r], 0.f});
+  acc[r] = a.hi;
+  acc[rows + r] = a.lo;
+}
+
 // Copies checkpoint `slot` ([4][mode_floats]) into every unit's state and
 // rewinds the step counter and the forward arrival counters to `step`.
 __global__ void restore_kernel(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
@@ -414,6 +428,12 @@ hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, size_t lds)
 #undef GO_T
 #undef GO_NW
 #undef GO
+}
+
+hipError_t launch_row_sum(const float* rrec, int seg_len, int rows, float* acc, hipStream_t s) {
+  if (rows < 1) return hipSuccess;
+  hipLaunchKernelGGL(row_sum_kernel, dim3((rows + 255) / 256), dim3(256), 0, s, rrec, seg_len, rows, acc);
+  return hipGetLastError();
 }
 
 hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,

@@ -31,7 +31,7 @@ struct InstDev {
   // the columns of class jmap[n][i] (or nothing if jmap < 0), w columns wide
   int blk, w;
   int cls[5];
-  int pad;
+  int row_off;         // VK: offset of its in-plane rows in per-row pools
   long long jmap_off;  // int4 offset of jmap[nin][4] in the block-map pool
 };
 
@@ -146,6 +146,10 @@ struct GradParams {
   int* flags;
   long long done_before;  // reverse steps completed before this launch
   int red_floats;
+  // per-row record of -2 eta_n (V_n . u) for every reverse step of the
+  // segment: [seg_len][rows_total] (rows of all VK instances); NULL = none
+  float* rrec;
+  int rows_total;
 };
 
 // ------------------------------------------------------------ shared tensor

@@ -29,6 +29,7 @@ hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, co
                           const UnitDev* unit, int n_units, float* state, int state_floats,
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
 hipError_t launch_shared(const SharedParams& P, int kt, int kc, int jt, int n_wg, hipStream_t s);
+hipError_t launch_row_sum(const float* rrec, int seg_len, int rows, float* acc, hipStream_t s);
 }  // namespace modal
 
 using namespace modal;
@@ -174,6 +175,10 @@ struct modal_ctx {
   unsigned int* dGCtr = nullptr;
   long long ckpt_floats = 0, rec_floats = 0;
   bool tangent = false;
+  // per-row (in-plane) gradient pools: rows of all VK instances
+  int rows_total = 0;
+  float *dRrec = nullptr, *dRacc = nullptr;
+  long long rrec_floats = 0;
   // parity-blocked tensors
   int n_blocked = 0;
   long long dense_bytes = 0;
@@ -202,7 +207,7 @@ void free_ctx(modal_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   void* ptrs[] = {c->dH,   c->dMeta, c->dCoef, c->dState, c->dPart, c->dCtr, c->dFlags,
                   c->dStep, c->dE,   c->dHd,   c->dCkpt,  c->dRec,  c->dAdj, c->dAcc,
-                  c->dGPart, c->dGCtr, c->dShA, c->dShS2, c->dJmap};
+                  c->dGPart, c->dGCtr, c->dShA, c->dShS2, c->dJmap, c->dRrec, c->dRacc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -904,6 +909,8 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
     D.h_off = 0;
     if (I.kind == MODAL_KIND_VK) {
       D.h_off = h_floats;
+      D.row_off = c->rows_total;
+      c->rows_total += D.nin;
       c->dense_bytes += 4LL * D.nin * D.nt * D.nt;
       c->flops += 2LL * D.nin * D.nt * D.nt + 4LL * D.nin * D.nt;
       if (D.blk) {
@@ -1282,7 +1289,7 @@ int modal_set_tangent(modal_ctx* c, int32_t b, const float* Hd, void* stream_) {
 
 int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_stride, int32_t ckpt_every,
                double* g_omega, double* g_gamma, double* g_c, double* g_x0, double* g_xm1,
-               double* g_scale, double* g_theta, void* stream_) {
+               double* g_scale, double* g_theta, double* g_row, void* stream_) {
   if (!c) return fail(MODAL_EINVAL, "ctx is NULL");
   if (!(c->flags & MODAL_FLAG_GRAD)) return fail(MODAL_ESTATE, "context not created with MODAL_FLAG_GRAD");
   if (n_steps < 1 || n_steps > (1LL << 31) - 1 || !ybar || y_stride < n_steps)
@@ -1309,6 +1316,15 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     if (r) return r;
     c->rec_floats = 2LL * K * mf;
   }
+  if (g_row && c->rows_total > 0 && c->rrec_floats < (long long)K * c->rows_total) {
+    if (c->dRrec) HIP_TRY(hipFree(c->dRrec));
+    c->dRrec = nullptr;
+    c->rrec_floats = 0;
+    int r = dalloc(&c->dRrec, sizeof(float) * (size_t)K * c->rows_total);
+    if (!r && !c->dRacc) r = dalloc(&c->dRacc, sizeof(float) * 2 * (size_t)c->rows_total);
+    if (r) return r;
+    c->rrec_floats = (long long)K * c->rows_total;
+  }
   if (!c->dAdj) {
     int r = dalloc(&c->dAdj, sizeof(float) * 4 * (size_t)sf);
     if (!r) r = dalloc(&c->dAcc, sizeof(float) * 12 * (size_t)sf);
@@ -1330,6 +1346,8 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   HIP_TRY(hipMemsetAsync(c->dAdj, 0, sizeof(float) * 4 * (size_t)sf, s));
   HIP_TRY(hipMemsetAsync(c->dAcc, 0, sizeof(float) * 12 * (size_t)sf, s));
   HIP_TRY(hipMemsetAsync(c->dGCtr, 0, sizeof(unsigned int) * c->batch, s));
+  const bool rows_on = g_row && c->rows_total > 0;
+  if (rows_on) HIP_TRY(hipMemsetAsync(c->dRacc, 0, sizeof(float) * 2 * (size_t)c->rows_total, s));
   GradParams G{};
   const StepParams& F = c->P;
   G.inst = F.inst;
@@ -1352,6 +1370,8 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   G.ctr = c->dGCtr;
   G.flags = F.flags;
   G.red_floats = 3 * c->red_floats;
+  G.rrec = rows_on ? c->dRrec : nullptr;
+  G.rows_total = c->rows_total;
   for (long long seg = nseg - 1; seg >= 0; --seg) {
     const long long s0 = seg * K;
     const int len = (int)std::min<long long>(K, n_steps - s0);
@@ -1368,9 +1388,18 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     G.seg_len = len;
     G.done_before = n_steps - s0 - len;
     HIP_TRY(launch_grad(G, c->gm, c->tangent, c->nw, c->n_wg, c->grad_lds, s));
+    if (rows_on) HIP_TRY(launch_row_sum(c->dRrec, len, c->rows_total, c->dRacc, s));
   }
   r = modal_check(c, stream_);
   if (r) return r;
+  if (g_row) {
+    std::vector<float> ra(2 * (size_t)c->rows_total);
+    if (rows_on)
+      HIP_TRY(hipMemcpyAsync(ra.data(), c->dRacc, sizeof(float) * ra.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < c->rows_total; ++i)
+      g_row[i] = (double)ra[i] + (double)ra[(size_t)c->rows_total + i];
+  }
   std::vector<float> acc(12 * (size_t)sf), adj(4 * (size_t)sf);
   HIP_TRY(hipMemcpyAsync(acc.data(), c->dAcc, sizeof(float) * acc.size(), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(adj.data(), c->dAdj, sizeof(float) * adj.size(), hipMemcpyDeviceToHost, s));

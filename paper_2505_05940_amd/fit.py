@@ -154,8 +154,16 @@ def chain_rule(setup, theta, inst, g, h_rel=1e-6):
     dD = np.sum(gw * lam ** 2 / (2 * om)) + g["scale"] / Dh
     dd1 = np.sum(gg)
     dd3 = np.sum(gg * lam)
-    # aspect: frequencies, damping, coupling rows, excitation and pickup
-    da = np.sum(gw * (2 * Dh * lam + T0h) * dlam / (2 * om)) + np.sum(gg * d3 * dlam) + g["theta"]
+    # aspect: frequencies, damping, coupling rows, excitation and pickup; the
+    # coupling rows scale as 1/zeta_n^2(a), so with per-row gradients
+    # dL/d log s_n the tensor term is sum_n (d log s_n/da) dL/d log s_n
+    if g.get("row") is not None and len(g["row"]):
+        _, _, ai, bi = setup.modes
+        kappa = -_dlam_da(ai, bi, a, setup.area) / _lam(ai, bi, a, setup.area)
+        tensor_term = float(np.sum(kappa * g["row"]))
+    else:
+        tensor_term = g["theta"]
+    da = np.sum(gw * (2 * Dh * lam + T0h) * dlam / (2 * om)) + np.sum(gg * d3 * dlam) + tensor_term
     eps = h_rel * a
     xp, cp = _excitation(setup, a + eps)
     xm, cm = _excitation(setup, a - eps)
@@ -170,7 +178,9 @@ class ModalFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta: torch.Tensor, setup: PlateSetup, n_steps: int, ckpt: int = 512):
         th = theta.detach().double().cpu().numpy().reshape(-1, 5)
-        insts = [plate_instance(setup, t) for t in th]
+        # base tensor + row scales: no per-plate tensor build; the library
+        # stores each plate's scaled copy for the gradient kernels
+        insts = [plate_instance_shared(setup, t) for t in th]
         sim = modal.Sim(insts, setup.fs, flags=modal.FLAG_GRAD)
         y = sim.run(n_steps).clone()
         ctx.save = (sim, insts, th, setup, n_steps, ckpt)
@@ -179,8 +189,8 @@ class ModalFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gy):
         sim, insts, th, setup, n_steps, ckpt = ctx.save
-        for b, inst in enumerate(insts):
-            sim.set_tangent(b, aspect_tangent(setup, inst, th[b][2]))
+        # the aspect derivative of the tensor is a per-row rescaling, taken
+        # from the per-row gradients (no tangent tensor)
         g = sim.grad(n_steps, gy.contiguous().float(), ckpt_every=ckpt)
         out = np.stack([chain_rule(setup, th[b], insts[b],
                                    {k: (v[b] if isinstance(v, list) else v[b]) for k, v in g.items()})
@@ -221,13 +231,20 @@ def from_unconstrained(z):
 def fit(target: torch.Tensor, theta0, setup: PlateSetup, n_steps: int, iters: int = 100,
         lr: float = 0.05, tol: float = 0.1, loss_fn=mrstft_loss, callback=None):
     """Adam with a one-cycle cosine schedule on unconstrained parameters,
-    batched over rows of theta0.  Stops early when every loss is below tol.
-    Returns (theta [B,5], losses [B], iterations, history)."""
+    batched over rows of theta0.  A row that reaches tol is frozen there;
+    the loop stops when every row has.  Returns (theta [B,5] and losses [B]
+    of each row's best iterate, iterations, loss history)."""
     z = torch.tensor(np.stack([to_unconstrained(t) for t in np.atleast_2d(theta0)]),
                      dtype=torch.float64, requires_grad=True)
+    B = z.shape[0]
     opt = torch.optim.Adam([z], lr=lr)
     hist = []
     tgt = target.reshape(-1, target.shape[-1])
+    best_L = np.full(B, np.inf)
+    best_th = from_unconstrained(z).detach().numpy().copy()
+    frozen = np.zeros(B, bool)
+    z_frozen = z.detach().clone()
+    it = 0
     for it in range(iters):
         for gparam in opt.param_groups:
             gparam["lr"] = one_cycle_cosine(it, iters, lr)
@@ -235,12 +252,21 @@ def fit(target: torch.Tensor, theta0, setup: PlateSetup, n_steps: int, iters: in
         theta = from_unconstrained(z)
         y = ModalFn.apply(theta, setup, n_steps)
         L = loss_fn(y, tgt.expand_as(y), reduce=False)
-        hist.append(L.detach().cpu().numpy())
+        Ln = L.detach().cpu().numpy()
+        hist.append(Ln)
+        better = Ln < best_L
+        best_L[better] = Ln[better]
+        best_th[better] = theta.detach().numpy()[better]
         if callback:
             callback(it, theta.detach(), L.detach())
-        if bool((L < tol).all()):
-            return theta.detach().numpy(), L.detach().cpu().numpy(), it, hist
+        newly = (Ln < tol) & ~frozen
+        z_frozen[torch.from_numpy(newly)] = z.detach()[torch.from_numpy(newly)]
+        frozen |= newly
+        if frozen.all():
+            return best_th, best_L, it, hist
         L.sum().backward()
         opt.step()
-    theta = from_unconstrained(z).detach()
-    return theta.numpy(), hist[-1], iters, hist
+        with torch.no_grad():  # frozen rows stay where they reached tol
+            fz = torch.from_numpy(frozen)
+            z[fz] = z_frozen[fz]
+    return best_th, best_L, iters, hist

@@ -69,7 +69,7 @@ def _load():
     lib.modal_destroy.restype = None
     lib.modal_last_error.restype = C.c_char_p
     lib.modal_grad.argtypes = [vp, C.c_int64, _fp, C.c_int64, C.c_int32, _dp, _dp, _dp, _dp, _dp,
-                               _dp, _dp, vp]
+                               _dp, _dp, _dp, vp]
     lib.modal_grad.restype = C.c_int
     lib.modal_set_tangent.argtypes = [vp, C.c_int32, _fp, vp]
     lib.modal_set_tangent.restype = C.c_int
@@ -220,6 +220,9 @@ class Sim:
         _check(lib.modal_init(C.byref(self._ctx), C.byref(desc), _stream_handle(stream)))
         self.modes_total = sum(self.n_t)
         self.scheme = scheme
+        self.n_in = [int(i["Ht"].shape[0]) if i["kind"] == "vk" else 0 for i in instances]
+        self._row_off = np.concatenate([[0], np.cumsum(self.n_in)[:-1]]).astype(int)
+        self.rows_total = int(sum(self.n_in))
 
     def run(self, n_steps, out=None):
         """Advance by n_steps; returns y [batch, n_steps] float32 on the GPU."""
@@ -249,22 +252,25 @@ class Sim:
     def grad(self, n_steps, dL_dy, ckpt_every=0):
         """Reverse-mode gradient of L over the first n_steps outputs from the
         initial state; dL_dy is a CUDA float32 tensor [batch, >= n_steps].
-        Returns per-instance lists of numpy arrays (omega, gamma, c, x0, xm1)
-        and [batch] arrays (scale = dL/dlog s, theta)."""
+        Returns per-instance lists of numpy arrays (omega, gamma, c, x0, xm1,
+        and row = dL/dlog s_n per in-plane row of a vk instance) and [batch]
+        arrays (scale = dL/dlog s, theta)."""
         assert dL_dy.is_cuda and dL_dy.dtype.itemsize == 4 and dL_dy.stride(1) == 1
         M = self.modes_total
         out = {k: np.zeros(M) for k in ("omega", "gamma", "c", "x0", "xm1")}
         scale = np.zeros(self.batch)
         theta = np.zeros(self.batch)
+        row = np.zeros(max(1, self.rows_total))
         _check(lib.modal_grad(self._ctx, n_steps, C.cast(C.c_void_p(dL_dy.data_ptr()), _fp),
                               dL_dy.stride(0), ckpt_every,
                               *(out[k].ctypes.data_as(_dp) for k in ("omega", "gamma", "c", "x0", "xm1")),
                               scale.ctypes.data_as(_dp), theta.ctypes.data_as(_dp),
-                              _stream_handle(self._stream)))
+                              row.ctypes.data_as(_dp), _stream_handle(self._stream)))
         splits = np.cumsum(self.n_t)[:-1]
         res = {k: np.split(v, splits) for k, v in out.items()}
         res["scale"] = scale
         res["theta"] = theta
+        res["row"] = [row[o:o + n] if n else np.zeros(0) for o, n in zip(self._row_off, self.n_in)]
         return res
 
     def reset(self):

@@ -82,9 +82,25 @@ def simulate(setup, thetas, n_steps, batch=65536):
     return torch.cat(out)
 
 
-def features(y):
-    f = logmel_features(y)
-    return (f - f.mean(dim=1, keepdim=True)) / f.std(dim=1, keepdim=True).clamp_min(1e-6)
+def features(y, chunk=16384):
+    """Standardised 8 x 128 log-mel features of each row of y (CUDA float32),
+    computed in chunks of rows."""
+    out = []
+    for s in range(0, y.shape[0], chunk):
+        f = logmel_features(y[s:s + chunk])
+        out.append((f - f.mean(dim=1, keepdim=True)) / f.std(dim=1, keepdim=True).clamp_min(1e-6))
+    return torch.cat(out)
+
+
+def param_error(th, th_ref, base):
+    """Mean |difference| of normalised parameters per row (prior spread ~ 0.5)."""
+    return np.mean(np.abs(normalize(th, base) - normalize(th_ref, base)), axis=1)
+
+
+def predict(net, X, batch=1024):
+    """Network outputs (normalised parameters) for the rows of X, as numpy."""
+    return np.concatenate([net.forward(X[s:s + batch]).detach().cpu().numpy()
+                           for s in range(0, X.shape[0], batch)])
 
 
 def train(net, X, Z, epochs=60, batch=1024, lr=1e-3, seed=0, log=None):
@@ -108,7 +124,11 @@ def train(net, X, Z, epochs=60, batch=1024, lr=1e-3, seed=0, log=None):
     return last
 
 
-def run(args):
+def run(args, stream=None):
+    """The experiment; progress lines and the final JSON go to `stream`
+    (default stdout).  Returns the result dict."""
+    import sys
+    stream = stream or sys.stdout
     torch.manual_seed(0)
     fw = dict(n_t=args.modes, n_in=args.modes)
     setup = fit.PlateSetup(n_t=args.modes, n_in=args.modes)
@@ -116,7 +136,7 @@ def run(args):
     wl = W.plate_fit(n_t=args.modes)
     base = wl["theta0"]
     rng = np.random.default_rng(5)
-    log = lambda m: print(f"[proposal] {m}", flush=True)
+    log = lambda m: print(f"[proposal] {m}", file=stream, flush=True)
     t0 = time.time()
     th_train = sample_prior(rng, args.train, base)
     X = []
@@ -137,42 +157,65 @@ def run(args):
     rng_t = np.random.default_rng(50)
     th_test = sample_prior(rng_t, args.test, base)
     y_tgt = simulate(setup, th_test, args.steps)
-    z_hat = net.forward(features(y_tgt)).detach().cpu().numpy()
+    z_hat = predict(net, features(y_tgt))
     th_prop = denormalize(z_hat, base)
     prop_err = float(np.mean(np.abs(normalize(th_prop, base) - normalize(th_test, base))))
     log(f"proposal mean |z error| {prop_err:.3f} (prior spread about 0.5)")
     results = {}
-    for arm, th0 in (("default", np.tile(prior_center(base), (args.test, 1))), ("proposal", th_prop)):
+    arms = [a for a in (("default", np.tile(prior_center(base), (args.test, 1))), ("proposal", th_prop))
+            if a[0] in args.arms.split(",")]
+    for arm, th0 in arms:
+        torch.cuda.synchronize()
         t0 = time.time()
-        done_at = np.full(args.test, -1)
+        if arm == "proposal":  # inference counts towards this arm's wall time
+            predict(net, features(y_tgt))
+            torch.cuda.synchronize()
+        t_first = np.full(args.test, np.nan)
 
         def cb(it, theta, L):
-            ok = (L.cpu().numpy() < args.tol) & (done_at < 0)
-            done_at[ok] = it
+            ok = (L.cpu().numpy() < args.tol) & np.isnan(t_first)
+            t_first[ok] = time.time() - t0
         th, L, iters, _ = fit.fit(y_tgt, th0, setup, args.steps, iters=args.iters, lr=args.lr,
                                   tol=args.tol, callback=cb)
         wall = time.time() - t0
-        results[arm] = dict(success_rate=float(np.mean(done_at >= 0)), wall_s=wall,
-                            iterations=int(iters), final_loss_median=float(np.median(L)))
+        done = ~np.isnan(t_first)
+        results[arm] = dict(success_rate=float(np.mean(done)), wall_s=wall, iterations=int(iters),
+                            final_loss_median=float(np.median(L)),
+                            time_to_target_median_s=float(np.median(t_first[done])) if done.any() else None,
+                            time_to_half_s=float(np.sort(np.where(done, t_first, np.inf))[args.test // 2])
+                            if np.mean(done) >= 0.5 else None,
+                            param_error_start=float(np.mean(param_error(th0, th_test, base))),
+                            param_error_end=float(np.mean(param_error(th, th_test, base))))
         log(f"{arm}: {results[arm]}")
     out = dict(train=args.train, steps=args.steps, modes=args.modes, epochs=args.epochs,
                test=args.test, gen_s=t_gen, train_s=t_train, mlp_mse=mse, proposal_z_err=prop_err,
                arms=results)
-    print(json.dumps(out))
+    print(json.dumps(out), file=stream, flush=True)
     return out
+
+
+def bench_args(**kw):
+    """The experiment's proposal arm as the benchmark runs it: 200 000
+    simulated plates, 60 epochs, 64 held-out targets fitted from the
+    network's guesses (the plain-fit arm is left to the full experiment)."""
+    a = dict(modes=40, steps=11025, train=200000, gen_batch=65536, epochs=60, test=64, iters=60,
+             lr=0.01, tol=0.1, verbose=False, arms="proposal")
+    a.update(kw)
+    return argparse.Namespace(**a)
 
 
 def main():
     ap = argparse.ArgumentParser(description="train the proposal network and compare fits")
     ap.add_argument("--modes", type=int, default=40)
     ap.add_argument("--steps", type=int, default=11025)
-    ap.add_argument("--train", type=int, default=16384)
-    ap.add_argument("--gen-batch", type=int, default=4096)
+    ap.add_argument("--train", type=int, default=200000)
+    ap.add_argument("--gen-batch", type=int, default=65536)
     ap.add_argument("--epochs", type=int, default=60)
-    ap.add_argument("--test", type=int, default=32)
+    ap.add_argument("--test", type=int, default=64)
     ap.add_argument("--iters", type=int, default=60)
-    ap.add_argument("--lr", type=float, default=0.05)
+    ap.add_argument("--lr", type=float, default=0.01)
     ap.add_argument("--tol", type=float, default=0.1)
+    ap.add_argument("--arms", default="default,proposal", help="fit arms to run")
     ap.add_argument("--verbose", action="store_true")
     run(ap.parse_args())
 

@@ -34,7 +34,7 @@ def _oracle_grads(oinst, steps, g, Hdot=None):
     r = OA.reverse(oinst, steps, 44100.0, g, Hdot=Hdot)
     om, ga = OA.sv_omega_gamma_grads(r, oinst["omega"], oinst["gamma"], 1 / 44100.0)
     return dict(omega=om, gamma=ga, c=r["c"], x0=r["x0"], xm1=r["xm1"], scale=r["scale"],
-                theta=r["theta"])
+                theta=r["theta"], row=r["row"])
 
 
 def _cases():
@@ -67,6 +67,8 @@ def test_grad_matches_oracle(gpu, max_wg, ckpt, waves):
         for k in ("omega", "gamma", "c", "x0", "xm1"):
             assert rel(res[k][b], ref[k]) < TOL, (b, k, rel(res[k][b], ref[k]))
         assert rel([res["scale"][b]], [ref["scale"]]) < TOL, (b, res["scale"][b], ref["scale"])
+        if ref["row"] is not None:  # per-row scale gradients of the vK instance
+            assert rel(res["row"][b], ref["row"]) < TOL, (b, rel(res["row"][b], ref["row"]))
     # the context is left at its initial state
     y1 = sim.run(50).cpu().numpy()
     sim.reset()
