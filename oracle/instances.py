@@ -51,6 +51,28 @@ def plate_geometry(wl):
     return np.sqrt(S / a), np.sqrt(S * a)
 
 
+def plate_berger_instance(wl):
+    """Tension-modulated (Berger) plate (Sec. 2.1, tension equation and the
+    modal string/membrane expansion): f_mu = tau lambda_mu q_mu sum lambda q^2
+    with normalised modes and tau_membrane = E h / (2 Lx Ly (1 - nu^2));
+    divided by the areal density, kappa = tau / rho_s."""
+    Lx, Ly = plate_geometry(wl)
+    h, E, nu, rho = wl["h"], wl["E"], wl["nu"], wl["rho"]
+    D = E * h ** 3 / (12.0 * (1.0 - nu ** 2))
+    rho_s = rho * h
+    m, q, lam = modes.plate_modes(Lx, Ly, wl["n_t"])
+    omega = scheme.omega_from(lam, D, wl["T0"], rho_s)
+    gamma = _gamma(wl, omega, lam, rho_s)
+    st = wl["strike"]
+    nx, ny = wl["proj_grid"]
+    x0 = excitation.plate_strike_modal(m, q, Lx, Ly, nx, ny, st["xc"], st["yc"], st["amplitude"],
+                                       st["radius"])
+    c = excitation.plate_output(m, q, Lx, Ly, *wl["out"])
+    tau = E * h / (2.0 * Lx * Ly * (1.0 - nu ** 2))
+    return dict(kind="tension", omega=omega, gamma=gamma, lam=lam, kappa=tau / rho_s,
+                x0=x0, xm1=x0.copy(), c=c, Lx=Lx, Ly=Ly, m=m, q=q)
+
+
 def plate_instance(wl, H=None):
     """von Karman plate.  H (unscaled, [n_in, n_t, n_t]) may be passed in to
     avoid rebuilding it; otherwise it is computed by the midpoint rule on

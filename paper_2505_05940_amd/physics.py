@@ -210,6 +210,25 @@ def string_instance(wl):
                 kappa=wl["EA"] / (2.0 * wl["L"]) / wl["rhoA"], x0=x0, xm1=x0.copy(), c=c)
 
 
+def plate_berger_instance(wl):
+    """Tension-modulated (Berger) plate: plate modes, omega from bending
+    stiffness and pre-tension, and kappa = tau / rho_s with the membrane
+    tension tau = E h / (2 Lx Ly (1 - nu^2))."""
+    Lx, Ly = plate_size(wl)
+    E, h, nu, rho = wl["E"], wl["h"], wl["nu"], wl["rho"]
+    rs = rho * h
+    m, q, lam = plate_eigs(Lx, Ly, wl["n_t"])
+    omega = np.sqrt((bending_stiffness(E, h, nu) * lam * lam + wl["T0"] * lam) / rs)
+    gamma = damping(wl, omega, lam, rs)
+    st = wl["strike"]
+    x0 = plate_initial(m, q, Lx, Ly, wl["proj_grid"], st["xc"], st["yc"], st["amplitude"],
+                       st["radius"])
+    c = plate_pickup(m, q, Lx, Ly, *wl["out"])
+    tau = E * h / (2.0 * Lx * Ly * (1.0 - nu * nu))
+    return dict(kind="tension", omega=omega, gamma=gamma, lam=lam, kappa=tau / rs, x0=x0,
+                xm1=x0.copy(), c=c)
+
+
 def mode_classes(m, q):
     """Parity class 2 (m mod 2) + (q mod 2) of each transverse plate mode.
     With sine in-plane modes, each coupling integral over x (over y) is a sum

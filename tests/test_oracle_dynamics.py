@@ -109,6 +109,28 @@ def test_plate_projection_parseval():
     assert abs(np.sum(X ** 2) / (dA * np.sum(w0 ** 2)) - 1) < 1e-3
 
 
+def test_berger_tension_term_is_the_gradient_energy():
+    """The Berger force's sum lambda q^2 equals the plate's gradient energy
+    int |grad w|^2 = -int w lap(w) (w = 0 on the edges), by midpoint
+    quadrature of the modal field; and the force is the gradient of
+    kappa/4 (sum lambda q^2)^2."""
+    wl = W.plate_berger(n_t=12, n_steps=10)
+    inst = instances.plate_berger_instance(wl)
+    rng = np.random.default_rng(4)
+    qv = rng.normal(size=12)
+    x, y, dA = modes.midpoint_grid(inst["Lx"], inst["Ly"], 400, 300)
+    d = modes.plate_phi_derivs(inst["m"], inst["q"], inst["Lx"], inst["Ly"], x, y)
+    w = qv @ d["phi"]
+    lap = qv @ (d["xx"] + d["yy"])
+    energy = -np.sum(w * lap) * dA
+    assert abs(energy - np.sum(inst["lam"] * qv ** 2)) < 1e-4 * energy
+    F = simulate.modal_force(inst, qv)
+    V = lambda v: inst["kappa"] / 4 * np.sum(inst["lam"] * v ** 2) ** 2
+    e = 1e-6
+    g = np.array([(V(qv + e * np.eye(12)[k]) - V(qv - e * np.eye(12)[k])) / (2 * e) for k in range(12)])
+    assert np.allclose(F, g, rtol=1e-6, atol=1e-9 * np.abs(g).max())
+
+
 def test_batch_geometry_puts_top_mode_at_target():
     from oracle import scheme
     for wl in W.plate_batch(batch=4):

@@ -166,3 +166,12 @@ def plate_group(seed: int = 6, batch: int = 48, n_t: int = 40, n_in: int | None 
             m["e_ext"] = rng.normal(size=2000).astype(np.float32)
         members.append(m)
     return dict(base=base, members=members, n_steps=n_steps, fs=FS)
+
+
+def plate_berger(seed: int = 2, n_t: int = 40, n_steps: int = 44100) -> dict:
+    """Tension-modulated (Berger) plate: the single plate's geometry,
+    material, damping and seeded strike/pickup (``plate_vk``), with the
+    nonlinearity of the tension equation instead of von Karman coupling."""
+    wl = plate_vk(seed=seed, n_t=n_t, n_in=0, n_steps=n_steps, family="sine", grid=None)
+    wl["model"] = "berger"
+    return wl
