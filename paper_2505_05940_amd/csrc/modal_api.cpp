@@ -361,6 +361,21 @@ void analyze_blocks(const modal_instance& I, BlockPlan& bp) {
     }
   }
   if (dmax > 1e-6f * hmax) return;
+  // An exactly symmetric tensor stores one block of each transposed pair:
+  // (i, j) with i < j stands for (j, i) too (flag 8), whose entry becomes -1.
+  if (dmax == 0.f) {
+    for (int n = 0; n < nin; ++n) {
+      int* jm = &bp.jmap[(size_t)n * 4];
+      for (int i = 0; i < 4; ++i) {
+        const int j = jm[i];
+        if (j >= 0 && j < 4 && j > i && jm[j] == i) {
+          jm[i] = j | 8;
+          jm[j] = -1;
+          bp.stored_bytes -= 4LL * cnt[j] * cnt[i];
+        }
+      }
+    }
+  }
   bp.ok = true;
 }
 
@@ -550,7 +565,8 @@ int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>
             const int p = bp.slot_mode[sl];
             int ci = 0;
             while (ci < 3 && sl >= bp.cls[ci + 1]) ++ci;
-            const int tj = bp.jmap[(size_t)n * 4 + ci];
+            const int je = bp.jmap[(size_t)n * 4 + ci];
+            const int tj = je < 0 ? -1 : (je & 7);
             if (p < 0 || tj < 0) {
               std::memset(out, 0, sizeof(float) * D.w);
               continue;
@@ -920,7 +936,8 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
         c->padded_bytes += 4 * f;
         c->n_blocked++;
         choose_sweep(plans[b].rmax, D.w / 4, qs_of[b], J_of[b]);
-        red_floats = std::max(red_floats, 2 * qs_of[b] * D.w);
+        // reduction double buffer, per-slot row dot partials, row-dot vector
+        red_floats = std::max(red_floats, 2 * qs_of[b] * D.w + kSweepLoads * kWave + D.ntp);
       } else {
         const long long f = (long long)D.nin * D.nt * D.ntp;
         h_floats += (f + 63) & ~63LL;  // 256-byte aligned instances

@@ -138,12 +138,19 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
 // modes; at the end of row n, eta_n and the force follow as in the dense
 // sweep.  The loader walks (n, i, block) one block ahead of the arithmetic
 // and hands each block's target range and end-of-class/row flags along;
-// blocks are loaded two ahead of the arithmetic.
+// each block's loads are issued before the previous one is used.
+// When an in-plane row's blocks come in transposed pairs ((i, j) and (j, i),
+// i != j) only (i, j) is stored (jmap entry j | 8): its stored rows also
+// give V for class i by row dot products with q over class j, reduced over
+// each row's float4 groups through LDS and collected per row in an LDS
+// vector (vrow) that joins V at the end of the in-plane row.
 struct BlkMeta {
   int q0;     // first stored row (internal mode) of the block
   int tc;     // first float4 column group of the target class
   int tlen;   // float4 column groups of the target class
-  int flags;  // 1: last block of its class, 2: last of its row, 4: last overall
+  int flags;  // 1: last block of its class, 2: last of its row, 4: last overall,
+              // 8: the block also stands for its transpose (row dot products)
+  int rows;   // valid stored rows in the block
 };
 
 __device__ __forceinline__ int sel4(const int4 v, int i) {
@@ -172,10 +179,15 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
   for (int i = 0; i < 5; ++i) co[i] = I.cls[i];
   const long long row_floats = (long long)ntp * w;
   const int blk_bytes = 4 * qs * w;
+  float* rd = red + 2 * qs * w;  // [kSweepLoads * 64] per-slot row dot partials
+  float* vrow = rd + J * kWave;  // [ntp] row-dot part of V for the current row
+  for (int k = lane; k < ntp; k += kWave) vrow[k] = 0.f;
   // loader position: row ln, class li, block lb; jv = jmap of row ln
   int ln = row0, li = 0, lb = 0;
   int4 jv = jm[row0];
   auto has_block = [&](int i) { return co[i + 1] > co[i] && sel4(jv, i) >= 0; };
+  // tensor rows n are stored with blocks indexed by class; a paired block's
+  // partner (-1) is skipped like an empty one
   auto to_data = [&]() {  // first (row, class) at or after (ln, li) with a block
     while (ln < row1) {
       while (li < 4 && !has_block(li)) ++li;
@@ -190,19 +202,22 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
     const bool live = ln < row1;
     const float* bp = Hb;
     int bytes = 0;
-    m = BlkMeta{0, 0, 0, 0};
+    m = BlkMeta{0, 0, 0, 0, 0};
     if (live) {
       const int R = co[li + 1] - co[li];
       const int nb = (R + qs - 1) / qs;
       const int q0 = co[li] + lb * qs;
+      m.rows = min(qs, R - lb * qs);
       bp = Hb + (long long)ln * row_floats + (long long)q0 * w;
-      bytes = 4 * min(qs, R - lb * qs) * w;
-      const int tj = sel4(jv, li);
+      bytes = 4 * m.rows * w;
+      const int je = sel4(jv, li);
+      const int tj = je & 7;
       m.q0 = q0;
       m.tc = co[tj] >> 2;
       m.tlen = (co[tj + 1] - co[tj]) >> 2;
+      if (je & 8) m.flags = 8;
       if (++lb == nb) {
-        m.flags = 1;
+        m.flags |= 1;
         lb = 0;
         ++li;
         while (li < 4 && !has_block(li)) ++li;
@@ -219,19 +234,33 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
 #pragma unroll
     for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
   };
-  float4 ha[J], hb[J], hc3[J], acc[J], V[GM];
-  BlkMeta ma, mb, mc3;
+  float4 ha[J], hb[J], acc[J], V[GM];
+  BlkMeta ma, mb;
 #pragma unroll
   for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
 #pragma unroll
   for (int g = 0; g < GM; ++g) V[g] = f4(0.f);
   int par = 0;
-  // consumes block `hc` after issuing the loads of the block two ahead into
-  // `hn` (three buffers in turn keep two blocks in flight per wave)
+  // consumes block `hc` after issuing the loads of the next block into `hn`
   auto step = [&](float4 (&hc)[J], const BlkMeta& mc, float4 (&hn)[J], BlkMeta& mn) -> bool {
     load(hn, mn);
 #pragma unroll
     for (int j = 0; j < J; ++j) acc[j] = fma4(hc[j], Xs[min(mc.q0 + sub[j], ntp - 1)], acc[j]);
+    if (mc.flags & 8) {
+      // transposed contribution: V[q0 + t] += sum_c S[t][c] q[class j][c]
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int v = lane + kWave * j;
+        const int c4 = min(v - sub[j] * nc, mc.tlen - 1);  // float4 column group of slot v
+        rd[v] = dot4(hc[j], ld4(Xs + 4 * (mc.tc + c4)));
+      }
+      wave_lds_sync();
+      if (lane < mc.rows) {
+        float sum = 0.f;
+        for (int c = 0; c < nc; ++c) sum += rd[lane * nc + c];
+        vrow[mc.q0 + lane] += sum;
+      }
+    }
     if (mc.flags & 1) {
       // block row of class i done: reduce over sub-rows onto the target modes
       float* rb = red + (par & 1) * qs * w;
@@ -254,12 +283,17 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
       for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
     }
     if (mc.flags & 2) {
-      // row n done: eta_n and the force
+      // row n done: V gets the row-dot part, then eta_n and the force
+      wave_lds_sync();
       float eta = 0.f;
 #pragma unroll
       for (int g = 0; g < GM; ++g) {
         const int k4 = lane + kWave * g;
-        if (g < G && k4 < nc_modes) eta += dot4(V[g], ld4(Xs + 4 * k4));
+        if (g < G && k4 < nc_modes) {
+          V[g] = add4(V[g], ld4(vrow + 4 * k4));
+          st4(vrow + 4 * k4, f4(0.f));
+          eta += dot4(V[g], ld4(Xs + 4 * k4));
+        }
       }
       eta = wave_sum(eta);
 #pragma unroll
@@ -271,8 +305,7 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
     return !(mc.flags & 4);
   };
   load(ha, ma);
-  load(hb, mb);
-  while (step(ha, ma, hc3, mc3) && step(hb, mb, ha, ma) && step(hc3, mc3, hb, mb)) {
+  while (step(ha, ma, hb, mb) && step(hb, mb, ha, ma)) {
   }
 }
 
