@@ -35,7 +35,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_b256.json")
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the step kernel's source with comments and blank space removed
+    (a change of code, not of comments, voids a traffic record)."""
+    import re
+    src = open(KERNEL_SRC).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    src = re.sub(r"\s+", " ", src)
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def measured_traffic(samples_per_step, launch):

@@ -5,9 +5,9 @@
  * FP32 accumulation, FP32 master weights, Adam).
  *
  * It maps spectral features of a target sound to initial physical
- * parameters for gradient fitting (paper: Sec. 4 names a more structured
+ * parameters for gradient fitting (paper: Sec. 5 names a more structured
  * initialisation as the remedy for the sensitivity of physical-parameter
- * fits to their starting point; Sec. 3.3 reports that sensitivity).
+ * fits to their starting point; Sec. 4.3 reports that sensitivity).
  *
  * Conventions as in modal.h: status codes (MODAL_*), streams as void*,
  * device pointers are HIP device memory.  Parameters are laid out layer by

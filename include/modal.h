@@ -3,9 +3,9 @@
  *
  * The library steps batches of independent modal systems, one audio sample
  * per step, each mode a damped oscillator driven by an external force and a
- * nonlinear modal force (paper: Sec. 2.2, modal oscillator equation
+ * nonlinear modal force (paper: Sec. 3.2, modal oscillator equation
  *   q'' + 2 gamma q' + omega^2 q = f_ext - f_nl ).
- * Nonlinear forces (paper: Sec. 2.1):
+ * Nonlinear forces (paper: Sec. 3.1):
  *   MODAL_KIND_TENSION  tension-modulated string / membrane (modal
  *                       string-membrane equation with normalised modes):
  *                       f_k = kappa lambda_k q_k sum_j lambda_j q_j^2
@@ -14,7 +14,7 @@
  *                       eta_n = sum_kj Ht[n][k][j] q_k q_j,
  *                       f_k   = sum_{n,j} Ht[n][k][j] q_j eta_n
  *   MODAL_KIND_LINEAR   f_nl = 0.
- * Schemes (paper: Sec. 2.2): Stormer-Verlet (modal oscillator update) and the
+ * Schemes (paper: Sec. 3.2): Stormer-Verlet (modal oscillator update) and the
  * impulse-invariant transfer-function recursion (df update), both written as
  *   q^{n+1} = g q^n + p q^{n-1} + r (f_ext^n - f_nl^n).
  *
@@ -186,7 +186,7 @@ void modal_destroy(modal_ctx *c);
 int modal_set_tangent(modal_ctx *c, int32_t inst, const float *Hd, void *stream);
 
 /* Reverse-mode gradient of a loss L(y) over the first n_steps outputs of
- * every instance, run from the initial state (paper: Sec. 3.3, fitting by
+ * every instance, run from the initial state (paper: Sec. 4.3, fitting by
  * propagating gradients through the time integrator).  dL_dy is device
  * memory [batch][y_stride] (FP32).  The forward pass is recomputed from
  * float-float checkpoints taken every ckpt_every steps (0 = 512); each
@@ -220,7 +220,7 @@ int modal_plan(const modal_desc *d, int32_t n_workgroups, int64_t out[4]);
 const char *modal_last_error(void);
 
 /* Host FP64 builder of the scaled coupling tensor for the sine in-plane
- * family (paper: Sec. 2.1, coupling-coefficient equations; modes
+ * family (paper: Sec. 3.1, coupling-coefficient equations; modes
  * Phi_i = 2/sqrt(Lx Ly) sin(m_i pi x/Lx) sin(q_i pi y/Ly), Psi_n likewise
  * with (a_n, b_n)):
  *   out[n][i][j] = scale_n * int Psi_n L(Phi_i, Phi_j) dS

@@ -7,11 +7,11 @@ it, and this package imports nothing from the product.  The two share only the
 seeded parameter draws in ``workloads``.
 
 Everything here is plain, slow and written to be checked against the paper by
-eye: modes and eigenvalues (Sec. 2, eigenvalue problem), the in-plane (Airy)
+eye: modes and eigenvalues (Sec. 3, eigenvalue problem), the in-plane (Airy)
 eigenpairs, the coupling tensor H by quadrature (coupling-coefficient
 equations), the modal ODE coefficients, the Stormer-Verlet and
-transfer-function recursions (Sec. 2.2), the tension-modulated and von Karman
-modal forces (Sec. 2.1), and the reverse-mode gradient of the time loop.
+transfer-function recursions (Sec. 3.2), the tension-modulated and von Karman
+modal forces (Sec. 3.1), and the reverse-mode gradient of the time loop.
 
 Functions whose values no test pins independently are marked
 "parity unpinned" in their docstrings.

@@ -1,8 +1,8 @@
 """Reverse-mode gradient of the time loop (back-propagation through time),
 FP64, plus the complex-step derivative it is checked against.
 
-Paper, Sec. 3.3 (plate experiments): parameters are fitted by propagating
-gradients through the time integrator.  The loop of Sec. 2.2 in increment
+Paper, Sec. 4.3 (plate experiments): parameters are fitted by propagating
+gradients through the time integrator.  The loop of Sec. 3.2 in increment
 form, d = q^n - q^{n-1}, is
     y^n     = c . q^n
     d^{n+1} = m q^n - p d^n + r (f_ext^n - F(q^n))

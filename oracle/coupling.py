@@ -1,6 +1,6 @@
 """Coupling tensors of the von Karman plate.
 
-Paper, Sec. 2.1, coupling-coefficient equations:
+Paper, Sec. 3.1, coupling-coefficient equations:
 
     H^k_{ij} = int_S Psi_k L(Phi_i, Phi_j) dS / (|Psi_k| |Phi_i| |Phi_j|)
     C^s_{ij} = int_S Phi_s L(Phi_i, Psi_j) dS / (|Phi_s| |Phi_i| |Psi_j|)
@@ -110,9 +110,9 @@ def coupling_sine_exact(Lx, Ly, n_t, n_in):
 def scale_coupling(H, zeta4, E, rho):
     """Scaled tensor H~[n,p,q] = sqrt(E / (2 rho)) H[n,p,q] / zeta_n^2.
 
-    From the von Karman modal force (Sec. 2.1, nonlinear plate equation)
+    From the von Karman modal force (Sec. 3.1, nonlinear plate equation)
     f_s = E/(2 rho) sum_n zeta_n^-4 (sum_qr H^n_qr X_q X_r)(sum_p C^s_pn X_p)
-    with C^s_pn = H^n_ps (simply supported identity, Sec. 3.3): with H~,
+    with C^s_pn = H^n_ps (simply supported identity, Sec. 4.3): with H~,
     eta_n = sum_pq H~[n,p,q] X_p X_q and f_k = sum_{n,q} H~[n,k,q] X_q eta_n.
     rho is the volumetric density.
     """

@@ -1,6 +1,6 @@
 """In-plane (Airy stress function) eigenpairs Psi_n, zeta_n^4.
 
-Paper, Sec. 2.1 (coupling coefficients): Psi and zeta^4 are the
+Paper, Sec. 3.1 (coupling coefficients): Psi and zeta^4 are the
 eigenfunctions and eigenvalues of the Airy stress function operator, i.e.
 Delta Delta Psi = zeta^4 Psi on the plate.  The paper does not state the
 in-plane boundary conditions.  Two families are provided:

@@ -1,7 +1,7 @@
 """Oracle-side construction of instances from the seeded workload parameters.
 
-Follows the paper's chain: modes and eigenvalues (Sec. 2), coupling tensors
-(Sec. 2.1), omega and gamma (Sec. 2.2), then the initial state and output
+Follows the paper's chain: modes and eigenvalues (Sec. 3), coupling tensors
+(Sec. 3.1), omega and gamma (Sec. 3.2), then the initial state and output
 weights of the workload's excitation and pickup point.
 """
 from __future__ import annotations
@@ -21,7 +21,7 @@ def _gamma(wl, omega, lam, rho_s):
 
 
 def string_instance(wl):
-    """Kirchhoff-Carrier string: tau = EA / (2L) (Sec. 2.1), kappa = tau/rhoA."""
+    """Kirchhoff-Carrier string: tau = EA / (2L) (Sec. 3.1), kappa = tau/rhoA."""
     k, lam = modes.string_modes(wl["L"], wl["n_modes"])
     omega = scheme.omega_from(lam, wl["EI"], wl["T0"], wl["rhoA"])
     gamma = _gamma(wl, omega, lam, wl["rhoA"])
@@ -52,7 +52,7 @@ def plate_geometry(wl):
 
 
 def plate_berger_instance(wl):
-    """Tension-modulated (Berger) plate (Sec. 2.1, tension equation and the
+    """Tension-modulated (Berger) plate (Sec. 3, tension equation; Sec. 3.1,
     modal string/membrane expansion): f_mu = tau lambda_mu q_mu sum lambda q^2
     with normalised modes and tau_membrane = E h / (2 Lx Ly (1 - nu^2));
     divided by the areal density, kappa = tau / rho_s."""

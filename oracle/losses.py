@@ -1,4 +1,4 @@
-"""FP64 spectral losses (paper, Sec. 3.3 loss functions), written plainly
+"""FP64 spectral losses (paper, Sec. 4.3 loss functions), written plainly
 with numpy FFTs for checking the torch implementation.
 
 |STFT|: frames of n_fft samples every n_fft/4 samples after reflect-padding

@@ -1,6 +1,6 @@
 """Transverse modes of a fixed string and a simply supported rectangular plate.
 
-Paper, Sec. 2 (eigenvalue problem): Laplacian eigenpairs, Delta Phi = -lambda
+Paper, Sec. 3 (eigenvalue problem): Laplacian eigenpairs, Delta Phi = -lambda
 Phi, analytic for a string fixed at both ends and a simply supported
 rectangle.  Modes are L2-normalised so that the integral of Phi^2 over the
 domain is one.

@@ -1,6 +1,6 @@
 """Oracle-side plate built from the five fitted parameters
 theta = (T0/rho_s, D/rho_s, aspect a = Ly/Lx, d1/(2 rho_s), d3/(2 rho_s))
-(paper, Sec. 3.3: density-normalised parameters; Sec. 2.2: omega^2 =
+(paper, Sec. 4.3: density-normalised parameters; Sec. 3.2: omega^2 =
 (D lambda^2 + T0 lambda)/rho_s and gamma = (d1 + d3 lambda)/(2 rho_s)).
 
 Fixed: area S (Lx = sqrt(S/a), Ly = sqrt(S a)), thickness, Poisson ratio,

@@ -1,6 +1,6 @@
 """Modal ODE coefficients and the two time-stepping schemes.
 
-Paper, Sec. 2.2 (integration in time).  Each mode obeys
+Paper, Sec. 3.2 (integration in time).  Each mode obeys
     q'' + 2 gamma q' + omega^2 q = f_ext - f_nl          (modal oscillator)
 with omega^2 = (D lambda^2 + T0 lambda) / rho_s and
 gamma = (d1 + d3 lambda) / (2 rho_s), where rho_s is the mass per unit area
@@ -29,7 +29,7 @@ def gamma_affine_omega(omega, g0, g1):
 
 def sv_coefficients(omega, gamma, T):
     """Stormer-Verlet recursion q+ = g q + p q- + r (f_ext - f_nl)
-    (Sec. 2.2, modal oscillator update):
+    (Sec. 3.2, modal oscillator update):
         r = 2 T^2 / (2 + 2 gamma T)
         g = r (2 / T^2 - omega^2)
         p = r (-1 / T^2 + 2 gamma / (2 T)).
@@ -43,7 +43,7 @@ def sv_coefficients(omega, gamma, T):
 
 
 def tf_coefficients(omega, gamma, T):
-    """Impulse-invariant recursion (Sec. 2.2, transfer function and its
+    """Impulse-invariant recursion (Sec. 3.2, transfer function and its
     update) written as q+ = g q + p q- + r (f_ext - f_nl).
 
     The discrete transfer function has denominator z^2 + a1 z + a2 with

@@ -1,11 +1,11 @@
 """FP64 time loop of the modal system with the nonlinear modal force.
 
-Paper, Sec. 2.2: q^{n+1} = g . q^n + p . q^{n-1} + r . (f_ext^n - f_nl^n)
+Paper, Sec. 3.2: q^{n+1} = g . q^n + p . q^{n-1} + r . (f_ext^n - f_nl^n)
 (Stormer-Verlet, modal oscillator update; the impulse-invariant recursion
 has the same shape with other coefficients).  Output y^n = sum_k c_k q_k^n
-(modal to physical transform at one point, Sec. 3.1).
+(modal to physical transform at one point, Sec. 4.1).
 
-Nonlinear forces (Sec. 2.1):
+Nonlinear forces (Sec. 3.1):
 * tension-modulated string / membrane (modal string-membrane equation): with
   normalised modes, f_nl,mu = kappa lambda_mu q_mu sum_nu lambda_nu q_nu^2,
   kappa = tau / rho_s.

@@ -1,5 +1,5 @@
 // Host FP64 builder of the scaled von Karman coupling tensor for the sine
-// in-plane family (paper: Sec. 2.1, coupling-coefficient equations).
+// in-plane family (paper: Sec. 3.1, coupling-coefficient equations).
 //
 // With Phi_i = c sin(al_i x) sin(be_i y), c = 2/sqrt(Lx Ly), al = m pi/Lx,
 // be = q pi/Ly, the von Karman operator (paper: von Karman operator

@@ -1,7 +1,7 @@
 // Reverse (adjoint) sweep of the modal time loop over one recorded segment.
 //
 // Back-propagation through the increment-form recursion of the step kernel
-// (paper: Sec. 3.3 fits by propagating gradients through the integrator):
+// (paper: Sec. 4.3 fits by propagating gradients through the integrator):
 //   db^{n+1} = qb^{n+1} - p db^{n+2},  u^n = r db^{n+1},
 //   qb^n     = ybar^n c + qb^{n+1} + m db^{n+1} - J(q^n) u^n,
 // with J = dF/dq symmetric.  For the von Karman force one pass over a row of

@@ -69,10 +69,10 @@ struct Coef {
 };
 
 // Per-mode recursion q+ = g q + p q- + r f, returned as (m = g + p - 1, p, r).
-// Stormer-Verlet (paper: Sec. 2.2): r = 2T^2/(2 + 2 gamma T),
+// Stormer-Verlet (paper: Sec. 3.2): r = 2T^2/(2 + 2 gamma T),
 // g = r (2/T^2 - omega^2), p = r (-1/T^2 + gamma/T); hence
 // p = -(1 - gamma T)/(1 + gamma T) and m = -r omega^2 exactly.
-// Transfer function (impulse invariance, Sec. 2.2, denominator
+// Transfer function (impulse invariance, Sec. 3.2, denominator
 // z^2 + a1 z + a2): g = -a1 = 2 e^{-gamma T} cos(w T), p = -a2 = -e^{-2 gamma T},
 // r = T e^{-gamma T} sin(w T)/w with w = sqrt(omega^2 - gamma^2) (force per
 // unit mass), and m = -(1 - e^{-gamma T})^2 - 4 e^{-gamma T} sin^2(w T/2).

@@ -2,7 +2,7 @@
 // (gfx950, FP32 MFMA).
 //
 // With Ht_b[n][k][q] = s_b[n] H0[n][k][q] for every instance b of a group,
-// the von Karman force of the nonlinear plate equation (paper: Sec. 2.1) is
+// the von Karman force of the nonlinear plate equation (paper: Sec. 3.1) is
 //   V0[n][k][b] = sum_q H0[n][k][q] X[q][b]          (one product per n)
 //   eta0[n][b]  = sum_k V0[n][k][b] X[k][b]
 //   F[k][b]     = sum_n s_b[n]^2 eta0[n][b] V0[n][k][b]

@@ -3,11 +3,11 @@
 // A workgroup (one or four 64-lane waves) owns a fixed list of work units
 // for the whole launch; a unit is either a whole instance or a slab of
 // in-plane rows of a von Karman instance whose coupling tensor is split over
-// several workgroups; the waves of a workgroup share a unit's rows.  Per audio sample (paper: Sec. 2.2, modal oscillator
+// several workgroups; the waves of a workgroup share a unit's rows.  Per audio sample (paper: Sec. 3.2, modal oscillator
 // update) each unit
 //   1. publishes q^n (fp32 high part) to LDS and writes the output sample
 //      y^n = sum_k c_k q_k^n (modal-to-physical transform at one point),
-//   2. evaluates its share of the nonlinear modal force (Sec. 2.1):
+//   2. evaluates its share of the nonlinear modal force (Sec. 3.1):
 //        von Karman, one pass over its rows of Ht:  V[n,k] = sum_j Ht[n][j][k] q_j
 //        (Ht symmetric in its last two indices), eta_n = sum_k V[n,k] q_k,
 //        F_k += eta_n V[n,k];

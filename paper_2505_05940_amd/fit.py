@@ -1,6 +1,6 @@
 """Physical-parameter fitting through the GPU time loop.
 
-Paper, Sec. 3.3: parameters are fitted by propagating gradients through the
+Paper, Sec. 4.3: parameters are fitted by propagating gradients through the
 time integrator (BPTT), in density-normalised form (D^ = D/rho_s,
 T0^ = T0/rho_s), with the damping kept in the stable half plane, using Adam
 with a one-cycle cosine learning-rate schedule and a spectral loss.

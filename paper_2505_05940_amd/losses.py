@@ -1,6 +1,6 @@
 """Spectral losses and features on the caller's side of the C ABI (torch).
 
-Paper, Sec. 3.3 (loss functions): with Y = |STFT(x)| and Yh = |STFT(xh)|,
+Paper, Sec. 4.3 (loss functions): with Y = |STFT(x)| and Yh = |STFT(xh)|,
     L_log = || log(Y + eps) - log(Yh + eps) ||_1
     L_sc  = || Y - Yh ||_F / || Y ||_F.
 The multi-resolution loss used here averages L_sc + L_log over FFT sizes

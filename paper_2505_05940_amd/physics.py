@@ -1,10 +1,10 @@
 """Host FP64 precompute that feeds the time loop: modes, in-plane
 eigenpairs, coupling tensors, modal coefficients, excitation and pickup.
 
-Paper: Sec. 2 (eigenvalue problem: analytic Laplacian modes of a fixed
-string and a simply supported rectangle), Sec. 2.1 (tension-modulated force
+Paper: Sec. 3 (eigenvalue problem: analytic Laplacian modes of a fixed
+string and a simply supported rectangle), Sec. 3.1 (tension-modulated force
 constant tau; von Karman coupling coefficients H from the Airy-function
-eigenpairs Psi, zeta^4), Sec. 2.2 (omega^2 = (D lambda^2 + T0 lambda)/rho_s,
+eigenpairs Psi, zeta^4), Sec. 3.2 (omega^2 = (D lambda^2 + T0 lambda)/rho_s,
 gamma = (d1 + d3 lambda)/(2 rho_s)).  FP64 throughout; the scaled tensor is
 handed to the GPU in FP32.
 

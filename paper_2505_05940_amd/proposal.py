@@ -2,8 +2,8 @@
 
 The paper fits physical parameters by gradient descent and reports that
 these fits are sensitive to initialisation, falling back on many random
-restarts (Sec. 3.3) and naming a more structured initialisation as the open
-problem (Sec. 4).  Here a small MLP, trained on (spectral features,
+restarts (Sec. 4.3) and naming a more structured initialisation as the open
+problem (Sec. 5).  Here a small MLP, trained on (spectral features,
 parameters) pairs that the batched time-stepping kernel generates from
 seeded priors, maps a target sound's features to a starting point; gradient
 fitting then refines it, and the plain fit from the prior centre is both the

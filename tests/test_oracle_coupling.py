@@ -1,5 +1,5 @@
 """Pins of the oracle's modes, in-plane eigenpairs and coupling tensors
-(Sec. 2 eigenvalue problem; Sec. 2.1 coupling coefficients) against closed
+(Sec. 3 eigenvalue problem; Sec. 3.1 coupling coefficients) against closed
 forms, brute force, textbook values and the paper's H-C identity."""
 import json
 import os
@@ -166,7 +166,7 @@ def test_H_brute_force_tiny_grid():
 
 
 def test_H_C_identity():
-    """C^j_{ik} = H^k_{ij} for modes vanishing on the edges (Sec. 3.3): the
+    """C^j_{ik} = H^k_{ij} for modes vanishing on the edges (Sec. 4.3): the
     independently integrated C tends to H as the grid is refined."""
     for fam in ("sine", "clamped"):
         errs = []

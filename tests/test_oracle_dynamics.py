@@ -1,4 +1,4 @@
-"""Pins of the oracle's nonlinear time loop (Sec. 2.1-2.2): an independent
+"""Pins of the oracle's nonlinear time loop (Sec. 3.1-2.2): an independent
 8th-order integrator (the paper's own DOP853 comparison, Fig. 1), energy
 behaviour, invariances, and the workload constructions."""
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the oracle's time-stepping schemes (Sec. 2.2) against closed forms,
+"""Pins of the oracle's time-stepping schemes (Sec. 3.2) against closed forms,
 an independent high-order integrator, and exact discrete energy identities."""
 import numpy as np
 import pytest

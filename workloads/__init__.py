@@ -8,9 +8,9 @@ derived (for example a plate area chosen so that the highest simulated mode
 sits at a given frequency) is named here as a target and derived separately by
 each consumer.
 
-The workloads follow the paper's own experiments (Sec. 3.2 benchmarks: von
+The workloads follow the paper's own experiments (Sec. 4.2 benchmarks: von
 Karman and tension-modulated models at 10/50/100 modes, 1 s at 44.1 kHz;
-Sec. 3.3 inverse modelling) at the sizes of the five benchmark configurations.
+Sec. 4.3 inverse modelling) at the sizes of the five benchmark configurations.
 """
 from __future__ import annotations
 
@@ -109,7 +109,7 @@ def plate_batch(seed: int = 3, batch: int = 256, n_lo: int = 50,
 
 def plate_sweep(n_t: int, seed: int = 2, n_steps: int = 44100) -> dict:
     """The paper's benchmark shapes: the single-plate geometry at 10/50/100
-    modes (Sec. 3.2, Fig. 2), sine in-plane family, 1 s at 44.1 kHz."""
+    modes (Sec. 4.2, Fig. 2), sine in-plane family, 1 s at 44.1 kHz."""
     return plate_vk(seed=seed, n_t=n_t, n_steps=n_steps, family="sine")
 
 
