@@ -143,6 +143,48 @@ def dense_path(batch, n_modes, samples, launches, seed):
     }
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def linear_path(batch, n_modes, seed):
+    """Linear strings (closed-form path) for one second at 44.1 kHz, with the
+    step-by-step recursion of the same batch timed beside it.  FP64
+    operations per (mode, sample) counted as 20: two complex products
+    advance the pole powers (12), two real parts of complex products and
+    their sum accumulate the output (8)."""
+    import torch
+    import workloads as W
+    from paper_2505_05940_amd import modal
+    wl = W.linear_batch(seed=seed, batch=batch, n_modes=n_modes, n_steps=44100, forced=batch // 8)
+    insts = wl["instances"]
+    modes = int(sum(len(i["omega"]) for i in insts))
+    res = {}
+    for name, flags in (("closed_form", 0), ("recursion", modal.FLAG_RECURSE)):
+        sim = modal.Sim(insts, 44100.0, flags=flags)
+        y = torch.empty((batch, 44100), device="cuda")
+        sim.run(441, out=y)
+        sim.reset()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        sim.run(44100, out=y)
+        b.record()
+        torch.cuda.synchronize()
+        res[name] = a.elapsed_time(b) * 1e-3
+        sim.close()
+    t = res["closed_form"]
+    achieved = 20.0 * modes * 44100 / t / 1e12
+    return {
+        "workload": f"{batch} linear stiff strings, {modes} modes in all, 44100 samples, "
+                    f"{batch // 8} with a 1000-sample forcing",
+        "value": modes * 44100 / t, "unit": "instance*mode*samples/s",
+        "seconds": t, "recursion_seconds": res["recursion"],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "modal::lin_sum_kernel (FP64)"},
+    }
+
+
 def fit_wall_time():
     """Wall time to the target spectral loss: a proposal network is trained
     on 200 000 plates simulated by the dense path (60 epochs), then 64
@@ -214,6 +256,8 @@ def main():
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the shared-tensor (MFMA) path measurement")
     ap.add_argument("--dense-batch", type=int, default=65536)
+    ap.add_argument("--no-linear", action="store_true",
+                    help="skip the linear closed-form path measurement")
     ap.add_argument("--no-fit", action="store_true",
                     help="skip the fit wall-time measurement (proposal + gradient fitting)")
     ap.add_argument("--dense-modes", type=int, default=40)
@@ -330,6 +374,10 @@ def main():
         out["dense_path"] = dense_path(args.dense_batch, args.dense_modes, S, 3, args.seed)
         print(f"[bench] dense path {out['dense_path']['roofline']['achieved']:.1f} TFLOP/s",
               file=sys.stderr, flush=True)
+    if not args.no_linear:
+        out["linear_path"] = linear_path(4096, 100, args.seed)
+        print(f"[bench] linear path: {out['linear_path']['seconds']:.3f} s closed form, "
+              f"{out['linear_path']['recursion_seconds']:.3f} s recursion", file=sys.stderr, flush=True)
     if not args.no_fit:
         out["config"]["fit_wall_time_s"], out["fit"] = fit_wall_time()
         print(f"[bench] fit: {out['fit']}", file=sys.stderr, flush=True)

@@ -71,7 +71,8 @@ enum {
                            instances below 4 MB of tensor stay whole and a
                            slab must pay for its per-step exchange          */
   MODAL_FLAG_NO_SHARED = 16, /* never use the shared-tensor (MFMA) path     */
-  MODAL_FLAG_NO_BLOCK = 32  /* ignore mode_class: store every tensor dense   */
+  MODAL_FLAG_NO_BLOCK = 32, /* ignore mode_class: store every tensor dense  */
+  MODAL_FLAG_RECURSE = 64   /* step linear batches through the recursion too */
 };
 
 /* One modal system.  All arrays are host memory. */
@@ -137,6 +138,13 @@ typedef struct {
  * share it (MFMA); otherwise every instance streams its own (scaled) copy.
  * Both paths compute the same recursion; they differ only in the FP32
  * rounding inside the force (order of sums, where the row scale is applied).
+ * Linear path: when every instance is MODAL_KIND_LINEAR (and neither
+ * MODAL_FLAG_GRAD nor MODAL_FLAG_RECURSE is set), each mode's recursion is
+ * solved in closed form from the roots of its characteristic polynomial and
+ * modal_run evaluates the outputs of all requested steps in parallel in
+ * FP64 (free response plus the excitation convolved with the impulse
+ * response); MODAL_FLAG_GRAPH has no effect there.  A mode with a double
+ * root keeps the batch on the recursion.
  * Errors: EINVAL (NULL/size/kind/finite/symmetry), EUNSTABLE (a mode's
  * characteristic roots outside the unit circle; also gamma < 0 or, for TF,
  * omega <= gamma), ENOMEM, EHIP.  On error *out is NULL. */
@@ -169,8 +177,9 @@ int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
  * [5] steps taken so far, [6] dynamic LDS bytes per workgroup,
  * [7] co-resident workgroups per CU used for the plan, [8] planned cost of
  * the most loaded workgroup and [9] the mean planned cost per co-resident
- * workgroup (both in streamed-byte units), [10] 1 on the shared-tensor path
- * (then [1] is the number of instance columns and [2], [8], [9] are 0),
+ * workgroup (both in streamed-byte units), [10] the path: 0 persistent
+ * recursion, 1 shared tensor (then [1] is the number of instance columns
+ * and [2], [8], [9] are 0), 2 linear closed form,
  * [11] FP32 operations of the force per step (sum over VK instances of
  * 2 n_in n_t^2 + 4 n_in n_t), [12] instances stored parity-blocked,
  * [13] dense-equivalent tensor bytes per step (sum of 4 n_in n_t^2).

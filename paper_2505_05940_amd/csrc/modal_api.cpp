@@ -30,6 +30,13 @@ hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, co
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
 hipError_t launch_shared(const SharedParams& P, int kt, int kc, int jt, int n_wg, hipStream_t s);
 hipError_t launch_row_sum(const float* rrec, int seg_len, int rows, float* acc, hipStream_t s);
+hipError_t launch_lin_sum(const double4* zpol, const double4* pq, const int* mode_off, const long long* j0,
+                          const int* len, int max_len, long long stride, int batch, double* out,
+                          hipStream_t s);
+hipError_t launch_lin_conv(const double* free, const double* h, long long stride, const long long* hj0,
+                           const float* e_ext, const long long* e_off, const long long* n_exc,
+                           long long base, int n_steps, int batch, float* y, long long y_stride,
+                           hipStream_t s);
 }  // namespace modal
 
 using namespace modal;
@@ -184,6 +191,17 @@ struct modal_ctx {
   long long dense_bytes = 0;
   int4* dJmap = nullptr;
   std::vector<std::vector<int>> mode_slot;  // per instance: caller mode -> internal slot
+  // linear closed-form path: per mode (log|z1|, arg z1, log|z2|, arg z2), free
+  // and forced output coefficients; runs are evaluated at absolute steps
+  bool linear = false;
+  std::vector<std::complex<double>> lz1, lz2, lA, lB, lC;  // per mode (caller order)
+  std::vector<double> lc, lb;                               // output and force weights
+  std::vector<std::vector<float>> le;                       // excitation per instance
+  double4 *dZpol = nullptr, *dPQf = nullptr, *dPQh = nullptr;
+  int* dLinMode = nullptr;
+  long long* dLinMeta = nullptr;   // j0, hj0, e_off, n_exc per instance, then lens
+  double* dLinWork = nullptr;
+  long long lin_work = 0;
   // shared-tensor path
   bool shared = false;
   int sh_kt = 0, sh_kc = 0, sh_jt = 0;
@@ -207,7 +225,8 @@ void free_ctx(modal_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   void* ptrs[] = {c->dH,   c->dMeta, c->dCoef, c->dState, c->dPart, c->dCtr, c->dFlags,
                   c->dStep, c->dE,   c->dHd,   c->dCkpt,  c->dRec,  c->dAdj, c->dAcc,
-                  c->dGPart, c->dGCtr, c->dShA, c->dShS2, c->dJmap, c->dRrec, c->dRacc};
+                  c->dGPart, c->dGCtr, c->dShA, c->dShS2, c->dJmap, c->dRrec, c->dRacc,
+                  c->dZpol, c->dPQf, c->dPQh, c->dLinMode, c->dLinMeta, c->dLinWork};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -650,6 +669,139 @@ int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>
   return MODAL_OK;
 }
 
+// ------------------------------------------------------------ linear batches
+// Roots of z^2 - g z - p for every mode of an all-linear batch, the free
+// response q^n = A z1^n + B z2^n from q^0, q^-1, and the impulse response
+// h(j) = C (z1^j - z2^j) with C = r / (z1 - z2).  False (recursion path) when
+// a mode has a double or nearly double root.
+bool linear_modes(const modal_desc* d, modal_ctx* c) {
+  using cd = std::complex<double>;
+  const double T = 1.0 / d->fs;
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    for (int k = 0; k < I.n_t; ++k) {
+      const Coef q = coefficients(d->scheme, I.omega[k], I.gamma[k], T);
+      const double g = q.m - q.p + 1.0, p = q.p;
+      const cd disc = cd(g * g + 4.0 * p, 0.0);
+      const cd sq = std::sqrt(disc);
+      const cd z1 = 0.5 * (g + sq), z2 = 0.5 * (g - sq);
+      // A and B lose about eps / |z1 - z2| relative accuracy by cancellation;
+      // near-double roots (critically damped modes) keep the recursion
+      if (std::abs(z1 - z2) <= 1e-6 * std::max(std::abs(z1), 1e-300)) return false;
+      const cd A = (I.xm1[k] * z1 * z2 - I.x0[k] * z1) / (z2 - z1);
+      c->lz1.push_back(z1);
+      c->lz2.push_back(z2);
+      c->lA.push_back(A);
+      c->lB.push_back(I.x0[k] - A);
+      c->lC.push_back(q.r / (z1 - z2));
+      c->lc.push_back(I.c_out[k]);
+      c->lb.push_back(I.b_ext ? I.b_ext[k] : 0.0);
+    }
+    c->le.emplace_back(I.e_ext, I.e_ext + I.n_exc);
+  }
+  return true;
+}
+
+int init_linear(modal_ctx* c, const modal_desc* d, hipStream_t stream) {
+  const size_t M = c->lz1.size();
+  auto lpol = [](std::complex<double> z, double& lm, double& ag) {
+    const double a = std::abs(z);
+    lm = a > 0 ? std::log(a) : -1e300;
+    ag = std::arg(z);
+  };
+  std::vector<double4> zpol(M), pqf(M), pqh(M);
+  for (size_t k = 0; k < M; ++k) {
+    lpol(c->lz1[k], zpol[k].x, zpol[k].y);
+    lpol(c->lz2[k], zpol[k].z, zpol[k].w);
+    const std::complex<double> P = c->lc[k] * c->lA[k], Q = c->lc[k] * c->lB[k];
+    const std::complex<double> H = c->lc[k] * c->lb[k] * c->lC[k];
+    pqf[k] = make_double4(P.real(), P.imag(), Q.real(), Q.imag());
+    pqh[k] = make_double4(H.real(), H.imag(), -H.real(), -H.imag());
+  }
+  std::vector<int> moff(d->batch + 1, 0);
+  std::vector<float> epool(1, 0.f);
+  std::vector<long long> eoff(d->batch), nexc(d->batch);
+  for (int b = 0; b < d->batch; ++b) {
+    moff[b + 1] = moff[b] + d->inst[b].n_t;
+    eoff[b] = (long long)epool.size();
+    nexc[b] = d->inst[b].n_exc;
+    epool.insert(epool.end(), c->le[b].begin(), c->le[b].end());
+  }
+  int r = dalloc(&c->dZpol, sizeof(double4) * M);
+  if (!r) r = dalloc(&c->dPQf, sizeof(double4) * M);
+  if (!r) r = dalloc(&c->dPQh, sizeof(double4) * M);
+  if (!r) r = dalloc(&c->dLinMode, sizeof(int) * (d->batch + 1));
+  if (!r) r = dalloc(&c->dLinMeta, sizeof(long long) * 6 * (size_t)d->batch);
+  if (!r) r = dalloc(&c->dE, sizeof(float) * epool.size());
+  if (!r) r = dalloc(&c->dFlags, sizeof(int) * 2);
+  if (!r) r = dalloc(&c->dCtr, sizeof(unsigned int) * d->batch);
+  if (!r) r = dalloc(&c->dStep, sizeof(long long));
+  if (r) return r;
+  HIP_TRY(hipMemcpyAsync(c->dZpol, zpol.data(), sizeof(double4) * M, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dPQf, pqf.data(), sizeof(double4) * M, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dPQh, pqh.data(), sizeof(double4) * M, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dLinMode, moff.data(), sizeof(int) * moff.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dE, epool.data(), sizeof(float) * epool.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dLinMeta + 2 * (size_t)d->batch, eoff.data(), sizeof(long long) * d->batch,
+                         hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dLinMeta + 3 * (size_t)d->batch, nexc.data(), sizeof(long long) * d->batch,
+                         hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  for (int b = 0; b < d->batch; ++b) {
+    c->kind.push_back(d->inst[b].kind);
+    c->nt.push_back(d->inst[b].n_t);
+  }
+  c->linear = true;
+  c->state_floats = 0;
+  return MODAL_OK;
+}
+
+// Outputs of steps [base, base + n) of every instance: the free response and
+// the excitation convolved with the impulse response, both in FP64.
+int run_linear(modal_ctx* c, int64_t n, float* y, int64_t y_stride, hipStream_t s) {
+  const int B = c->batch;
+  const long long base = c->steps;
+  long long max_exc = 0;
+  for (int b = 0; b < B; ++b) max_exc = std::max<long long>(max_exc, (long long)c->le[b].size());
+  const long long stride = n + max_exc;
+  if (c->lin_work < 2 * B * stride) {
+    if (c->dLinWork) HIP_TRY(hipFree(c->dLinWork));
+    c->dLinWork = nullptr;
+    c->lin_work = 0;
+    int r = dalloc(&c->dLinWork, sizeof(double) * 2 * (size_t)B * stride);
+    if (r) return r;
+    c->lin_work = 2 * (long long)B * stride;
+  }
+  std::vector<long long> j0(B, base), hj0(B);
+  std::vector<int> flen(B, (int)n), hlen(B);
+  int hmax = 0;
+  for (int b = 0; b < B; ++b) {
+    const long long ne = (long long)c->le[b].size();
+    hj0[b] = std::max<long long>(1, base - ne + 1);
+    hlen[b] = ne > 0 ? (int)std::max<long long>(0, base + n - hj0[b]) : 0;
+    hmax = std::max(hmax, hlen[b]);
+  }
+  // meta: [0] j0 (free), [1] hj0, [2] e_off, [3] n_exc, [4] lens (free, h) as ints
+  HIP_TRY(hipMemcpyAsync(c->dLinMeta, j0.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->dLinMeta + B, hj0.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s));
+  std::vector<int> lens(2 * (size_t)B);
+  for (int b = 0; b < B; ++b) {
+    lens[b] = flen[b];
+    lens[B + b] = hlen[b];
+  }
+  int* dlens = reinterpret_cast<int*>(c->dLinMeta + 4 * (size_t)B);
+  HIP_TRY(hipMemcpyAsync(dlens, lens.data(), sizeof(int) * lens.size(), hipMemcpyHostToDevice, s));
+  double* wfree = c->dLinWork;
+  double* wh = c->dLinWork + (size_t)B * stride;
+  HIP_TRY(launch_lin_sum(c->dZpol, c->dPQf, c->dLinMode, c->dLinMeta, dlens, (int)n, stride, B, wfree, s));
+  HIP_TRY(launch_lin_sum(c->dZpol, c->dPQh, c->dLinMode, c->dLinMeta + B, dlens + B, hmax, stride, B, wh, s));
+  HIP_TRY(launch_lin_conv(wfree, wh, stride, c->dLinMeta + B, c->dE, c->dLinMeta + 2 * (size_t)B,
+                          c->dLinMeta + 3 * (size_t)B, base, (int)n, B, y, y_stride, s));
+  // the host vectors above must outlive the asynchronous copies
+  HIP_TRY(hipStreamSynchronize(s));
+  return MODAL_OK;
+}
+
 // ------------------------------------------------------------ shared tensor
 struct SharedGroup {
   const float* H;
@@ -872,6 +1024,21 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   c->flags = d->flags;
   c->fs = d->fs;
   c->chunk = d->chunk_steps;
+  {
+    bool all_linear = !(d->flags & (MODAL_FLAG_GRAD | MODAL_FLAG_RECURSE));
+    for (int b = 0; b < d->batch && all_linear; ++b) all_linear = d->inst[b].kind == MODAL_KIND_LINEAR;
+    if (all_linear && linear_modes(d, c)) {
+      int r = init_linear(c, d, stream);
+      if (r) {
+        free_ctx(c);
+        return r;
+      }
+      *out = c;
+      return MODAL_OK;
+    }
+    c->lz1.clear(); c->lz2.clear(); c->lA.clear(); c->lB.clear(); c->lC.clear();
+    c->lc.clear(); c->lb.clear(); c->le.clear();
+  }
   {
     std::vector<SharedGroup> groups = shared_groups(d);
     if (!groups.empty()) {
@@ -1207,6 +1374,11 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
 int modal_reset(modal_ctx* c, void* stream_) {
   if (!c) return fail(MODAL_EINVAL, "ctx is NULL");
   hipStream_t s = (hipStream_t)stream_;
+  if (c->linear) {
+    HIP_TRY(hipMemsetAsync(c->dFlags, 0, sizeof(int) * 2, s));
+    c->steps = 0;
+    return MODAL_OK;
+  }
   HIP_TRY(hipMemcpyAsync(c->dState, c->state0.data(), sizeof(float) * c->state0.size(),
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(c->dCtr, 0, sizeof(unsigned int) * c->batch, s));
@@ -1255,6 +1427,12 @@ int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* s
   if (n_steps == 0) return MODAL_OK;
   if (!y || y_stride < n_steps) return fail(MODAL_EINVAL, "y NULL or y_stride < n_steps");
   hipStream_t s = (hipStream_t)stream_;
+  if (c->linear) {  // closed form at absolute steps: no persistent state, no graph
+    int r = run_linear(c, n_steps, y, y_stride, s);
+    if (r) return r;
+    c->steps += n_steps;
+    return MODAL_OK;
+  }
   if (c->flags & MODAL_FLAG_GRAPH) {
     hipGraphExec_t exec = nullptr;
     for (auto& g : c->graphs)
@@ -1458,6 +1636,27 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
 int modal_get_state(modal_ctx* c, double* x, double* xm1, void* stream_) {
   if (!c || !x || !xm1) return fail(MODAL_EINVAL, "NULL argument");
   hipStream_t s = (hipStream_t)stream_;
+  if (c->linear) {
+    HIP_TRY(hipStreamSynchronize(s));
+    const long long n = c->steps;
+    size_t o = 0;
+    for (int b = 0; b < c->batch; ++b)
+      for (int k = 0; k < c->nt[b]; ++k, ++o) {
+        for (int back = 0; back < 2; ++back) {
+          const long long t = n - back;
+          std::complex<double> v = c->lA[o] * std::pow(c->lz1[o], (double)t) +
+                                   c->lB[o] * std::pow(c->lz2[o], (double)t);
+          const std::vector<float>& e = c->le[b];
+          for (long long m = 0; m < std::min<long long>((long long)e.size(), t); ++m) {
+            const double lag = (double)(t - m);
+            v += c->lb[o] * (double)e[m] * c->lC[o] *
+                 (std::pow(c->lz1[o], lag) - std::pow(c->lz2[o], lag));
+          }
+          (back == 0 ? x : xm1)[o] = v.real();
+        }
+      }
+    return MODAL_OK;
+  }
   std::vector<float> st(c->state0.size());
   HIP_TRY(hipMemcpyAsync(st.data(), c->dState, sizeof(float) * st.size(), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1489,7 +1688,7 @@ int modal_info(const modal_ctx* c, int64_t info[14]) {
   info[7] = c->occ;
   info[8] = (int64_t)c->makespan;
   info[9] = (int64_t)c->mean_load;
-  info[10] = c->shared ? 1 : 0;
+  info[10] = c->shared ? 1 : (c->linear ? 2 : 0);
   info[11] = c->flops;
   info[12] = c->n_blocked;
   info[13] = c->shared ? c->coupling_bytes : c->dense_bytes;

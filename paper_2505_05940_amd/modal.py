@@ -23,6 +23,7 @@ FLAG_GRAD = 4
 FLAG_SPLIT_ANY = 8
 FLAG_NO_SHARED = 16
 FLAG_NO_BLOCK = 32
+FLAG_RECURSE = 64
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSTABLE", -3: "ENOMEM", -4: "EHIP",
           -5: "ENONFINITE", -6: "ESTATE", -7: "EHANG"}
@@ -288,9 +289,11 @@ class Sim:
         _check(lib.modal_info(self._ctx, v))
         keys = ("workgroups", "units", "split_instances", "coupling_bytes_per_step",
                 "padded_bytes_per_step", "steps", "lds_bytes", "workgroups_per_cu",
-                "plan_makespan", "plan_mean", "shared", "flops_per_step", "blocked_instances",
+                "plan_makespan", "plan_mean", "path", "flops_per_step", "blocked_instances",
                 "dense_bytes_per_step")
-        return dict(zip(keys, list(v)))
+        out = dict(zip(keys, list(v)))
+        out["shared"] = int(out["path"] == 1)  # 0 recursion, 1 shared tensor, 2 linear closed form
+        return out
 
     def close(self):
         if self._ctx:

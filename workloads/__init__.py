@@ -175,3 +175,34 @@ def plate_berger(seed: int = 2, n_t: int = 40, n_steps: int = 44100) -> dict:
     wl = plate_vk(seed=seed, n_t=n_t, n_in=0, n_steps=n_steps, family="sine", grid=None)
     wl["model"] = "berger"
     return wl
+
+
+def linear_batch(seed: int = 9, batch: int = 64, n_modes: int = 60, n_steps: int = 44100,
+                 forced: int = 8) -> dict:
+    """Linear (stiff) strings for the closed-form path: fundamental
+    f0 ~ U[80, 800] Hz, inharmonicity B ~ U[0, 1e-4] (f_k = k f0 sqrt(1 + B k^2)),
+    modes kept below 12 kHz; decay rates gamma_k = s0 + s2 omega_k^2 with
+    s0 ~ U[0.5, 3] /s and s2 ~ U[0.5, 5] 1e-8 s; released from rest with
+    q^0_k = sin(k pi x_p) / k^2 for x_p ~ U[0.1, 0.4] (scaled to 1 mm);
+    pickup c_k = sin(k pi x_o), x_o ~ U[0.5, 0.9]; the first `forced` strings
+    are also driven by b_k = sin(k pi x_e) times a 1000-sample noise burst."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(batch):
+        f0 = rng.uniform(80, 800)
+        B = rng.uniform(0, 1e-4)
+        k = np.arange(1, n_modes + 1)
+        f = k * f0 * np.sqrt(1 + B * k * k)
+        k = k[f < 12000.0]
+        f = f[f < 12000.0]
+        w = 2 * np.pi * f
+        s0, s2 = rng.uniform(0.5, 3.0), rng.uniform(0.5, 5.0) * 1e-8
+        xp, xo, xe = rng.uniform(0.1, 0.4), rng.uniform(0.5, 0.9), rng.uniform(0.1, 0.9)
+        x0 = 1e-3 * np.sin(k * np.pi * xp) / k ** 2
+        inst = dict(kind="linear", omega=w, gamma=s0 + s2 * w * w, x0=x0, xm1=x0.copy(),
+                    c=np.sin(k * np.pi * xo))
+        if b < forced:
+            inst["b_ext"] = np.sin(k * np.pi * xe)
+            inst["e_ext"] = (1e3 * rng.normal(size=1000)).astype(np.float32)
+        out.append(inst)
+    return dict(instances=out, n_steps=n_steps, fs=FS)
