@@ -203,4 +203,42 @@ __host__ __device__ inline size_t shared_lds_bytes(int kt, int kc, int jt, int n
          sizeof(float) * (2 * (size_t)kSharedWaves * 16 * kt * 16 * jt + (size_t)nin_max * 64 * jt);
 }
 
+// ---------------------------------------------------------- linear batches
+constexpr int kLinWaves = 2;  // waves per closed-form workgroup
+constexpr int kLinRun = 32;   // steps per lane (strided by 64)
+
+// One mode: both roots of z^2 - g z - p as (log|z|, arg(z)/pi), their 64th
+// powers, and the recurrence y(n + 64) = a y(n) - b y(n - 64) that every
+// combination of the two root terms satisfies.  conj: z2 = conj(z1), only
+// root 1 is evaluated (its amplitude carries the factor 2).
+struct LinMode {
+  double2 s1, s2;
+  double a, b;
+  double lm1, f1, lm2, f2;
+  int conj, pad;
+};
+
+// A run of output samples of one instance from one amplitude set: sample i
+// (< len) is the sum over modes [m0, m1) of Re(P1 z1^(e0+i) + P2 z2^(e0+i)),
+// written to out[out_off + i].
+struct LinSeg {
+  int m0, mc, m1, pad;  // modes [m0, mc) complex-conjugate pairs, [mc, m1) real pairs
+  long long amp_off;
+  long long e0;
+  long long out_off;
+  long long len;
+};
+
+// Per mode, what the amplitude sets are built from.
+struct LinInit {
+  double2 z1, z2, A, B, C;
+  double c, b;
+  long long e_off, n_exc;
+  int conj, pad;
+};
+
+struct LinForced {
+  long long inst, e_off, n_exc;
+};
+
 }  // namespace modal

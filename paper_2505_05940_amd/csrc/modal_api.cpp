@@ -30,13 +30,15 @@ hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, co
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
 hipError_t launch_shared(const SharedParams& P, int kt, int kc, int jt, int n_wg, hipStream_t s);
 hipError_t launch_row_sum(const float* rrec, int seg_len, int rows, float* acc, hipStream_t s);
-hipError_t launch_lin_sum(const double4* zpol, const double4* pq, const int* mode_off, const long long* j0,
-                          const int* len, int max_len, long long stride, int batch, double* out,
-                          hipStream_t s);
-hipError_t launch_lin_conv(const double* free, const double* h, long long stride, const long long* hj0,
-                           const float* e_ext, const long long* e_off, const long long* n_exc,
-                           long long base, int n_steps, int batch, float* y, long long y_stride,
-                           hipStream_t s);
+hipError_t launch_lin_sum(const LinMode* modes, const double4* amp, const double2* ztab, const LinSeg* segs,
+                          int n_segs, long long max_len, float* out, hipStream_t s);
+hipError_t launch_lin_sum_f64(const LinMode* modes, const double4* amp, const double2* ztab,
+                              const LinSeg* segs, int n_segs, long long max_len, double* out, hipStream_t s);
+hipError_t launch_lin_amp(const LinInit* init, const LinMode* modes, int M, const float* e_ext, double4* amp,
+                          double2* ztab, hipStream_t s);
+hipError_t launch_lin_conv(const LinForced* forced, int n_forced, const double* h, long long h_stride,
+                           const float* e_ext, long long base, long long n_steps, long long window,
+                           float* y, long long y_stride, hipStream_t s);
 }  // namespace modal
 
 using namespace modal;
@@ -191,17 +193,24 @@ struct modal_ctx {
   long long dense_bytes = 0;
   int4* dJmap = nullptr;
   std::vector<std::vector<int>> mode_slot;  // per instance: caller mode -> internal slot
-  // linear closed-form path: per mode (log|z1|, arg z1, log|z2|, arg z2), free
-  // and forced output coefficients; runs are evaluated at absolute steps
+  // linear closed-form path: per mode roots, amplitude sets [free | post |
+  // impulse], and the output-space impulse response of every forced instance
+  // over its excitation window; runs are evaluated at absolute steps
   bool linear = false;
   std::vector<std::complex<double>> lz1, lz2, lA, lB, lC;  // per mode (caller order)
   std::vector<double> lc, lb;                               // output and force weights
+  std::vector<char> lconj;                                  // complex-conjugate root pair
   std::vector<std::vector<float>> le;                       // excitation per instance
-  double4 *dZpol = nullptr, *dPQf = nullptr, *dPQh = nullptr;
-  int* dLinMode = nullptr;
-  long long* dLinMeta = nullptr;   // j0, hj0, e_off, n_exc per instance, then lens
-  double* dLinWork = nullptr;
-  long long lin_work = 0;
+  std::vector<int> lin_moff, lin_mc;  // device mode ranges; [moff, mc) conjugate pairs
+  LinMode* dLinModes = nullptr;
+  LinInit* dLinInit = nullptr;
+  double4* dLinAmp = nullptr;
+  double2* dLinTab = nullptr;  // z1^l, l < 64, per mode
+  LinSeg* dLinSeg = nullptr;
+  LinForced* dLinForced = nullptr;
+  double* dLinH = nullptr;
+  int n_forced = 0;
+  long long lin_h_stride = 1, lin_max_exc = 0;
   // shared-tensor path
   bool shared = false;
   int sh_kt = 0, sh_kc = 0, sh_jt = 0;
@@ -226,7 +235,8 @@ void free_ctx(modal_ctx* c) {
   void* ptrs[] = {c->dH,   c->dMeta, c->dCoef, c->dState, c->dPart, c->dCtr, c->dFlags,
                   c->dStep, c->dE,   c->dHd,   c->dCkpt,  c->dRec,  c->dAdj, c->dAcc,
                   c->dGPart, c->dGCtr, c->dShA, c->dShS2, c->dJmap, c->dRrec, c->dRacc,
-                  c->dZpol, c->dPQf, c->dPQh, c->dLinMode, c->dLinMeta, c->dLinWork};
+                  c->dLinModes, c->dLinInit, c->dLinAmp, c->dLinSeg, c->dLinForced, c->dLinH,
+                  c->dLinTab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -688,6 +698,8 @@ bool linear_modes(const modal_desc* d, modal_ctx* c) {
       // A and B lose about eps / |z1 - z2| relative accuracy by cancellation;
       // near-double roots (critically damped modes) keep the recursion
       if (std::abs(z1 - z2) <= 1e-6 * std::max(std::abs(z1), 1e-300)) return false;
+      // a root at zero (a mode that stops after one step) has no logarithm
+      if (std::min(std::abs(z1), std::abs(z2)) < 1e-150) return false;
       const cd A = (I.xm1[k] * z1 * z2 - I.x0[k] * z1) / (z2 - z1);
       c->lz1.push_back(z1);
       c->lz2.push_back(z2);
@@ -696,6 +708,7 @@ bool linear_modes(const modal_desc* d, modal_ctx* c) {
       c->lC.push_back(q.r / (z1 - z2));
       c->lc.push_back(I.c_out[k]);
       c->lb.push_back(I.b_ext ? I.b_ext[k] : 0.0);
+      c->lconj.push_back(g * g + 4.0 * p < 0.0);
     }
     c->le.emplace_back(I.e_ext, I.e_ext + I.n_exc);
   }
@@ -703,51 +716,98 @@ bool linear_modes(const modal_desc* d, modal_ctx* c) {
 }
 
 int init_linear(modal_ctx* c, const modal_desc* d, hipStream_t stream) {
+  using cd = std::complex<double>;
+  const int B = d->batch;
   const size_t M = c->lz1.size();
-  auto lpol = [](std::complex<double> z, double& lm, double& ag) {
-    const double a = std::abs(z);
-    lm = a > 0 ? std::log(a) : -1e300;
-    ag = std::arg(z);
-  };
-  std::vector<double4> zpol(M), pqf(M), pqh(M);
-  for (size_t k = 0; k < M; ++k) {
-    lpol(c->lz1[k], zpol[k].x, zpol[k].y);
-    lpol(c->lz2[k], zpol[k].z, zpol[k].w);
-    const std::complex<double> P = c->lc[k] * c->lA[k], Q = c->lc[k] * c->lB[k];
-    const std::complex<double> H = c->lc[k] * c->lb[k] * c->lC[k];
-    pqf[k] = make_double4(P.real(), P.imag(), Q.real(), Q.imag());
-    pqh[k] = make_double4(H.real(), H.imag(), -H.real(), -H.imag());
-  }
-  std::vector<int> moff(d->batch + 1, 0);
   std::vector<float> epool(1, 0.f);
-  std::vector<long long> eoff(d->batch), nexc(d->batch);
-  for (int b = 0; b < d->batch; ++b) {
-    moff[b + 1] = moff[b] + d->inst[b].n_t;
+  std::vector<long long> eoff(B);
+  c->lin_moff.assign(B + 1, 0);
+  std::vector<LinForced> forced;
+  for (int b = 0; b < B; ++b) {
+    c->lin_moff[b + 1] = c->lin_moff[b] + d->inst[b].n_t;
     eoff[b] = (long long)epool.size();
-    nexc[b] = d->inst[b].n_exc;
+    const long long ne = (long long)c->le[b].size();
     epool.insert(epool.end(), c->le[b].begin(), c->le[b].end());
+    if (ne > 0) forced.push_back({b, eoff[b], ne});
+    c->lin_max_exc = std::max(c->lin_max_exc, ne);
   }
-  int r = dalloc(&c->dZpol, sizeof(double4) * M);
-  if (!r) r = dalloc(&c->dPQf, sizeof(double4) * M);
-  if (!r) r = dalloc(&c->dPQh, sizeof(double4) * M);
-  if (!r) r = dalloc(&c->dLinMode, sizeof(int) * (d->batch + 1));
-  if (!r) r = dalloc(&c->dLinMeta, sizeof(long long) * 6 * (size_t)d->batch);
+  // device order within an instance: complex-conjugate pairs first
+  std::vector<int> src;
+  src.reserve(M);
+  c->lin_mc.assign(B, 0);
+  for (int b = 0; b < B; ++b) {
+    for (int k = c->lin_moff[b]; k < c->lin_moff[b + 1]; ++k)
+      if (c->lconj[k]) src.push_back(k);
+    c->lin_mc[b] = (int)src.size();
+    for (int k = c->lin_moff[b]; k < c->lin_moff[b + 1]; ++k)
+      if (!c->lconj[k]) src.push_back(k);
+  }
+  std::vector<LinMode> modes(M);
+  std::vector<LinInit> init(M);
+  for (int b = 0; b < B; ++b)
+    for (int slot = c->lin_moff[b]; slot < c->lin_moff[b + 1]; ++slot) {
+      const int k = src[slot];
+      const cd z1 = c->lz1[k], z2 = c->lz2[k];
+      const double lm1 = std::log(std::abs(z1)), lm2 = std::log(std::abs(z2));
+      const cd s1 = std::polar(std::exp(64.0 * lm1), 64.0 * std::arg(z1));
+      const cd s2 = std::polar(std::exp(64.0 * lm2), 64.0 * std::arg(z2));
+      LinMode& m = modes[slot];
+      m.s1 = make_double2(s1.real(), s1.imag());
+      m.s2 = make_double2(s2.real(), s2.imag());
+      m.a = (s1 + s2).real();
+      m.b = (s1 * s2).real();
+      m.lm1 = lm1;
+      m.f1 = std::arg(z1) / M_PI;
+      m.lm2 = lm2;
+      m.f2 = std::arg(z2) / M_PI;
+      m.conj = c->lconj[k];
+      m.pad = 0;
+      LinInit& I = init[slot];
+      auto d2 = [](cd v) { return make_double2(v.real(), v.imag()); };
+      I.z1 = d2(z1);
+      I.z2 = d2(z2);
+      I.A = d2(c->lA[k]);
+      I.B = d2(c->lB[k]);
+      I.C = d2(c->lC[k]);
+      I.c = c->lc[k];
+      I.b = c->lb[k];
+      I.e_off = eoff[b];
+      I.n_exc = (long long)c->le[b].size();
+      I.conj = c->lconj[k];
+      I.pad = 0;
+    }
+  c->n_forced = (int)forced.size();
+  c->lin_h_stride = std::max<long long>(1, c->lin_max_exc);
+  std::vector<LinSeg> hseg;
+  for (int f = 0; f < c->n_forced; ++f) {
+    const int b = (int)forced[f].inst;
+    hseg.push_back({c->lin_moff[b], c->lin_mc[b], c->lin_moff[b + 1], 0, 2 * (long long)M, 1,
+                    f * c->lin_h_stride, forced[f].n_exc - 1});
+  }
+  int r = dalloc(&c->dLinModes, sizeof(LinMode) * std::max<size_t>(M, 1));
+  if (!r) r = dalloc(&c->dLinInit, sizeof(LinInit) * std::max<size_t>(M, 1));
+  if (!r) r = dalloc(&c->dLinAmp, sizeof(double4) * 3 * std::max<size_t>(M, 1));
+  if (!r) r = dalloc(&c->dLinTab, sizeof(double2) * 64 * std::max<size_t>(M, 1));
+  if (!r) r = dalloc(&c->dLinSeg, sizeof(LinSeg) * std::max<size_t>(2 * (size_t)B, hseg.size()));
+  if (!r) r = dalloc(&c->dLinForced, sizeof(LinForced) * std::max<size_t>(forced.size(), 1));
+  if (!r) r = dalloc(&c->dLinH, sizeof(double) * std::max<size_t>(1, forced.size() * c->lin_h_stride));
   if (!r) r = dalloc(&c->dE, sizeof(float) * epool.size());
   if (!r) r = dalloc(&c->dFlags, sizeof(int) * 2);
-  if (!r) r = dalloc(&c->dCtr, sizeof(unsigned int) * d->batch);
-  if (!r) r = dalloc(&c->dStep, sizeof(long long));
   if (r) return r;
-  HIP_TRY(hipMemcpyAsync(c->dZpol, zpol.data(), sizeof(double4) * M, hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(c->dPQf, pqf.data(), sizeof(double4) * M, hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(c->dPQh, pqh.data(), sizeof(double4) * M, hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(c->dLinMode, moff.data(), sizeof(int) * moff.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dLinModes, modes.data(), sizeof(LinMode) * M, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(c->dLinInit, init.data(), sizeof(LinInit) * M, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipMemcpyAsync(c->dE, epool.data(), sizeof(float) * epool.size(), hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(c->dLinMeta + 2 * (size_t)d->batch, eoff.data(), sizeof(long long) * d->batch,
-                         hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(c->dLinMeta + 3 * (size_t)d->batch, nexc.data(), sizeof(long long) * d->batch,
-                         hipMemcpyHostToDevice, stream));
+  if (!forced.empty())
+    HIP_TRY(hipMemcpyAsync(c->dLinForced, forced.data(), sizeof(LinForced) * forced.size(),
+                           hipMemcpyHostToDevice, stream));
+  if (!hseg.empty())
+    HIP_TRY(hipMemcpyAsync(c->dLinSeg, hseg.data(), sizeof(LinSeg) * hseg.size(), hipMemcpyHostToDevice,
+                           stream));
+  HIP_TRY(launch_lin_amp(c->dLinInit, c->dLinModes, (int)M, c->dE, c->dLinAmp, c->dLinTab, stream));
+  HIP_TRY(launch_lin_sum_f64(c->dLinModes, c->dLinAmp, c->dLinTab, c->dLinSeg, (int)hseg.size(), c->lin_max_exc - 1,
+                             c->dLinH, stream));
   HIP_TRY(hipStreamSynchronize(stream));
-  for (int b = 0; b < d->batch; ++b) {
+  for (int b = 0; b < B; ++b) {
     c->kind.push_back(d->inst[b].kind);
     c->nt.push_back(d->inst[b].n_t);
   }
@@ -756,48 +816,37 @@ int init_linear(modal_ctx* c, const modal_desc* d, hipStream_t stream) {
   return MODAL_OK;
 }
 
-// Outputs of steps [base, base + n) of every instance: the free response and
-// the excitation convolved with the impulse response, both in FP64.
+// Outputs of steps [base, base + n) of every instance.  An unforced instance
+// is one free-response segment; a forced one is split at the end of its
+// excitation: before it, the free response plus the excitation convolved with
+// the impulse response, from it on, the response to the state the excitation
+// left (the post amplitude set).
 int run_linear(modal_ctx* c, int64_t n, float* y, int64_t y_stride, hipStream_t s) {
+  if (n <= 0) return MODAL_OK;
   const int B = c->batch;
-  const long long base = c->steps;
-  long long max_exc = 0;
-  for (int b = 0; b < B; ++b) max_exc = std::max<long long>(max_exc, (long long)c->le[b].size());
-  const long long stride = n + max_exc;
-  if (c->lin_work < 2 * B * stride) {
-    if (c->dLinWork) HIP_TRY(hipFree(c->dLinWork));
-    c->dLinWork = nullptr;
-    c->lin_work = 0;
-    int r = dalloc(&c->dLinWork, sizeof(double) * 2 * (size_t)B * stride);
-    if (r) return r;
-    c->lin_work = 2 * (long long)B * stride;
-  }
-  std::vector<long long> j0(B, base), hj0(B);
-  std::vector<int> flen(B, (int)n), hlen(B);
-  int hmax = 0;
+  const long long base = c->steps, end = base + n;
+  const long long M = (long long)c->lz1.size();
+  std::vector<LinSeg> seg;
+  seg.reserve(2 * (size_t)B);
   for (int b = 0; b < B; ++b) {
+    const int m0 = c->lin_moff[b], mc = c->lin_mc[b], m1 = c->lin_moff[b + 1];
+    const long long row = (long long)b * y_stride;
     const long long ne = (long long)c->le[b].size();
-    hj0[b] = std::max<long long>(1, base - ne + 1);
-    hlen[b] = ne > 0 ? (int)std::max<long long>(0, base + n - hj0[b]) : 0;
-    hmax = std::max(hmax, hlen[b]);
+    if (ne == 0) {
+      seg.push_back({m0, mc, m1, 0, 0, base, row, n});
+      continue;
+    }
+    const long long w_end = std::min(end, ne);
+    if (w_end > base) seg.push_back({m0, mc, m1, 0, 0, base, row, w_end - base});
+    const long long p0 = std::max(base, ne);
+    if (end > p0) seg.push_back({m0, mc, m1, 0, M, p0 - ne, row + (p0 - base), end - p0});
   }
-  // meta: [0] j0 (free), [1] hj0, [2] e_off, [3] n_exc, [4] lens (free, h) as ints
-  HIP_TRY(hipMemcpyAsync(c->dLinMeta, j0.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(c->dLinMeta + B, hj0.data(), sizeof(long long) * B, hipMemcpyHostToDevice, s));
-  std::vector<int> lens(2 * (size_t)B);
-  for (int b = 0; b < B; ++b) {
-    lens[b] = flen[b];
-    lens[B + b] = hlen[b];
-  }
-  int* dlens = reinterpret_cast<int*>(c->dLinMeta + 4 * (size_t)B);
-  HIP_TRY(hipMemcpyAsync(dlens, lens.data(), sizeof(int) * lens.size(), hipMemcpyHostToDevice, s));
-  double* wfree = c->dLinWork;
-  double* wh = c->dLinWork + (size_t)B * stride;
-  HIP_TRY(launch_lin_sum(c->dZpol, c->dPQf, c->dLinMode, c->dLinMeta, dlens, (int)n, stride, B, wfree, s));
-  HIP_TRY(launch_lin_sum(c->dZpol, c->dPQh, c->dLinMode, c->dLinMeta + B, dlens + B, hmax, stride, B, wh, s));
-  HIP_TRY(launch_lin_conv(wfree, wh, stride, c->dLinMeta + B, c->dE, c->dLinMeta + 2 * (size_t)B,
-                          c->dLinMeta + 3 * (size_t)B, base, (int)n, B, y, y_stride, s));
-  // the host vectors above must outlive the asynchronous copies
+  HIP_TRY(hipMemcpyAsync(c->dLinSeg, seg.data(), sizeof(LinSeg) * seg.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_lin_sum(c->dLinModes, c->dLinAmp, c->dLinTab, c->dLinSeg, (int)seg.size(), n, y, s));
+  const long long window = std::min(end, c->lin_max_exc) - base;
+  HIP_TRY(launch_lin_conv(c->dLinForced, c->n_forced, c->dLinH, c->lin_h_stride, c->dE, base, n, window, y,
+                          y_stride, s));
+  // the host segment list must outlive the asynchronous copy
   HIP_TRY(hipStreamSynchronize(s));
   return MODAL_OK;
 }

@@ -80,3 +80,44 @@ def test_double_root_keeps_the_recursion(gpu):
     assert sim.info()["path"] == 0
     y = sim.run(500).double().cpu().numpy()[0]
     assert rel_l2(y, OS.run(dict(inst), 500, fs)) < TOL
+
+
+def _sv_disc(w, gam, fs=44100.0):
+    T = 1 / fs
+    r = T * T / (1 + gam * T)
+    p = -(1 - gam * T) / (1 + gam * T)
+    g = r * (2 / T ** 2 - w * w)
+    return g * g + 4 * p, g, p
+
+
+def test_real_roots_groups_and_windows(gpu):
+    """Real root pairs (positive, negative and of both signs) beside more than
+    64 complex-conjugate pairs in one forced instance, and an unforced
+    instance, run in uneven windows that split at the end of the excitation
+    and inside a 64-step lane stride."""
+    modal = gpu
+    fs = 44100.0
+    rng = np.random.default_rng(21)
+    w = 2 * np.pi * np.linspace(100.0, 11000.0, 70)
+    gam = 1.0 + 2e-8 * w * w
+    # overdamped: two positive roots; two negative roots; one of each sign
+    w = np.concatenate([w, [600.0, 80000.0, 1000.0]])
+    gam = np.concatenate([gam, [2e4, 4e4, 5e4]])
+    disc, g, p = _sv_disc(w, gam)
+    assert (disc[:70] < 0).all() and (disc[70:] > 0).all()
+    assert g[70] > 0 and g[71] < 0 and p[72] > 0
+    n = len(w)
+    x0 = 1e-3 * rng.normal(size=n)
+    forced = dict(kind="linear", omega=w, gamma=gam, x0=x0, xm1=0.9 * x0, c=rng.normal(size=n),
+                  b_ext=rng.normal(size=n), e_ext=(1e2 * rng.normal(size=300)).astype(np.float32))
+    free = dict(kind="linear", omega=w[::2].copy(), gamma=gam[::2].copy(), x0=x0[::2].copy(),
+                xm1=x0[::2].copy(), c=np.ones(len(w[::2])))
+    insts = [forced, free]
+    sim = modal.Sim(insts, fs)
+    assert sim.info()["path"] == 2
+    print("case: real roots, 73 modes, windows 100/37/163/2700", flush=True)
+    y = np.concatenate([sim.run(k).double().cpu().numpy() for k in (100, 37, 163, 2700)], axis=1)
+    for i in range(2):
+        ref = OS.run(dict(insts[i]), 3000, fs)
+        assert rel_l2(y[i], ref) < TOL, (i, rel_l2(y[i], ref))
+        assert np.abs(y[i, :400] - ref[:400]).max() < TOL * np.abs(ref[:400]).max()
