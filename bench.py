@@ -180,6 +180,7 @@ def linear_path(batch, n_modes, seed):
                     f"{batch // 8} with a 1000-sample forcing",
         "value": modes * 44100 / t, "unit": "instance*mode*samples/s",
         "seconds": t, "recursion_seconds": res["recursion"],
+        "time_basis": "whole closed-form run (sum and convolution kernels, segment upload)",
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "kernel": "modal::lin_sum_kernel (FP64)"},
