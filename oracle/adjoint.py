@@ -21,6 +21,10 @@ with V = H~ q per in-plane row, eta = V . q:
 A force scale s (F proportional to s) gets dL/ds = -sum_n u^n . F^n / s; a
 tensor direction Hdot gets dL/dtheta = -sum_n u^n . dF^n with
 dF_k = sum_i (Vdot_i . q) V_ik + eta_i Vdot_ik, Vdot = Hdot q.
+The gradient with respect to every entry of the tensor (each entry taken as
+an independent parameter, Sec. 4.3 fits of the coupling tensor) follows from
+d eta_i / dH~[i][a][b] = q_a q_b and d V_ik / dH~[i][a][b] = delta_ka q_b:
+    dL/dH~[i][a][b] = -sum_n ((V_i . u) q_a + eta_i u_a) q_b   (at step n).
 """
 from __future__ import annotations
 
@@ -99,7 +103,7 @@ def forward(inst, n_steps, fs, scheme="sv"):
     return y, Xs, ds, Fs
 
 
-def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None):
+def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None, full_tensor=False):
     """Gradients of L with dL/dy^n = ybar[n].
 
     Returns dict: m, p, r (per mode), x0, xm1 (per mode), c (per mode),
@@ -108,6 +112,7 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None):
     a factor s_n on row n of the scaled tensor.  That factor scales V_n and
     eta_n together, so the force term eta_n V_n goes as s_n^2 and
     dL/d log s_n = -2 sum over steps of eta_n (V_n . u).
+    With full_tensor, also H: dL/dH~ entry by entry, [n_in][n][n].
     """
     g, p, r = _coeffs(inst, fs, scheme)
     m = g + p - 1.0
@@ -120,6 +125,7 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None):
     gs, gth = 0.0, 0.0
     vk = inst["kind"] == "vk"
     grow = np.zeros(inst["Ht"].shape[0]) if vk else None
+    gH = np.zeros(inst["Ht"].shape) if (vk and full_tensor) else None
     for k in range(n_steps - 1, -1, -1):
         db = qb - p * db_next          # db^{k+1}
         u = r * db
@@ -133,6 +139,10 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None):
             n_in = inst["Ht"].shape[0]
             V = (inst["Ht"].reshape(n_in * n, n) @ X).reshape(n_in, n)
             grow = grow - 2.0 * (V @ X) * (V @ u)
+            if gH is not None:
+                eta, w = V @ X, V @ u
+                for i in range(n_in):
+                    gH[i] -= np.outer(w[i] * X + eta[i] * u, X)
         if Hdot is not None:
             n_in = Hdot.shape[0]
             V = (inst["Ht"].reshape(n_in * n, n) @ X).reshape(n_in, n)
@@ -143,7 +153,7 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None):
         qb = ybar[k] * c + qb + m * db - _jvp(inst, X, u)
         db_next = db
     d0b = -p * db_next  # d^0 only feeds d^1
-    return dict(m=gm, p=gp, r=gr, c=gc, x0=qb + d0b, xm1=-d0b, scale=gs, theta=gth, row=grow)
+    return dict(m=gm, p=gp, r=gr, c=gc, x0=qb + d0b, xm1=-d0b, scale=gs, theta=gth, row=grow, H=gH)
 
 
 def sv_omega_gamma_grads(g, omega, gamma, T):
