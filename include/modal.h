@@ -210,13 +210,36 @@ int modal_set_tangent(modal_ctx *c, int32_t inst, const float *Hd, void *stream)
  *   g_row             dL/d log s_n for a factor s_n on row n of the scaled
  *                     tensor, per in-plane row of every VK instance in batch
  *                     order ([sum of n_in over VK instances])
+ *   g_H [batch]       host array of device pointers, one per instance (NULL
+ *                     entries to skip; non-NULL only for VK instances): the
+ *                     gradient with respect to every entry of the tensor the
+ *                     dynamics uses (the scaled tensor, row scales included),
+ *                     each entry an independent parameter (paper: Sec. 4.3,
+ *                     fitting the coupling coefficients H):
+ *                       g_H[b][n][i][j] = -sum over steps of
+ *                                         ((V_n . u) q_i + eta_n u_i) q_j,
+ *                     FP32 device memory [n_in][n_t][n_t], overwritten (the
+ *                     caller owns it).  Per checkpoint segment, one product
+ *                     over the segment's steps per in-plane row.
  * Needs a context created with MODAL_FLAG_GRAD (else ESTATE).  Leaves the
  * context reset to its initial state.  Errors: EINVAL, ENOMEM, EHIP,
  * ENONFINITE, EHANG. */
 int modal_grad(modal_ctx *c, int64_t n_steps, const float *dL_dy, int64_t y_stride,
                int32_t ckpt_every, double *g_omega, double *g_gamma, double *g_c,
                double *g_x0, double *g_xm1, double *g_scale, double *g_theta,
-               double *g_row, void *stream);
+               double *g_row, float *const *g_H, void *stream);
+
+/* Replaces the coupling tensor of VK instance `inst` by H ([n_in][n_t][n_t],
+ * FP32, host or device memory, copied): the tensor the dynamics uses, row
+ * scales given at init not applied again (paper: Sec. 4.3, fitting the
+ * coupling coefficients H, where the tensor itself is the parameter).  H must
+ * be exactly symmetric in its last two indices, as the coupling coefficients
+ * are (checked; the kernels contract rows by that symmetry); a fit keeps it
+ * so by stepping with the symmetric part of g_H.  The state is left as it
+ * is.  ESTATE on the shared-tensor and linear paths and for parity-blocked
+ * instances (MODAL_FLAG_GRAD keeps tensors dense); EINVAL for a bad index or
+ * an asymmetric tensor (the stored tensor is then unchanged). */
+int modal_set_tensor(modal_ctx *c, int32_t inst, const float *H, void *stream);
 
 /* Host-only preview of the work partition modal_init would make for `d`
  * with n_workgroups co-resident workgroups (validates d like modal_init; no

@@ -22,7 +22,7 @@ template <int GM, bool TAN>
 __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__ Hdb, int nt,
                          int ntp, int qs, int row0, int row1, const float* Xs, const float* Us,
                          float* red, float4 (&Ju)[GM], float4 (&Fa)[GM], float& tsum, int G,
-                         int lane, float* rrow) {
+                         int lane, float* rrow, float* teta, float* tw) {
   // Same sweep as the forward kernel (contiguous blocks of qs stored rows,
   // per-block buffer resources, next block loaded ahead) with two
   // right-hand sides, q and u, and optionally the tangent tensor times q.
@@ -118,6 +118,11 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
     w = wave_sum(w);
     // row-scale gradient term of this step (summed over steps afterwards)
     if (rrow && lane == 0) rrow[n] = -2.f * eta * w;
+    // eta_n and V_n . u of this step for the full tensor gradient
+    if (teta && lane == 0) {
+      teta[n] = eta;
+      tw[n] = w;
+    }
     if (TAN) {
       etad = wave_sum(etad);
       vdu = wave_sum(vdu);
@@ -247,6 +252,7 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
           if (I.kind == KIND_VK) {
             st4(Xs + 4 * k4, x4);
             st4(Us + 4 * k4, u4);
+            if (P.urec && U.slab == 0) st4(P.urec + ro + 4 * k4, u4);
           } else if (I.kind == KIND_TENSION) {
             const float4 l = ld4(P.lam + I.mode_off + 4 * k4);
             const float4 lx = make_float4(l.x * x4.x, l.y * x4.y, l.z * x4.z, l.w * x4.w);
@@ -261,8 +267,10 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
         const int R = U.row1 - U.row0;
         const int r0 = U.row0 + (R * wave) / NW, r1 = U.row0 + (R * (wave + 1)) / NW;
         float* rrow = P.rrec ? P.rrec + (long long)s * P.rows_total + I.row_off : nullptr;
+        float* teta = P.trec ? P.trec + (n - P.seg_base) * 2LL * P.rows_total + I.row_off : nullptr;
+        float* tw = teta ? teta + P.rows_total : nullptr;
         vk_rows2<GM, TAN>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs, r0, r1,
-                          Xs, Us, red, Ju, Fa, tsum, G, lane, rrow);
+                          Xs, Us, red, Ju, Fa, tsum, G, lane, rrow, teta, tw);
         if (NW > 1) {
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
@@ -364,6 +372,100 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
       __syncthreads();  // flag reused
     }
   }
+}
+
+// Full tensor gradient of one segment: for in-plane row n (blockIdx.y) of job
+// blockIdx.z, the 64 x 64 output tile blockIdx.x gets
+//   out[n][i][j] -= sum_s a_i^s q_j^s,   a_i^s = (V_n . u)^s q_i^s + eta_n^s u_i^s,
+// a product over the segment's steps: 16 steps of a and q staged in LDS per
+// round, a 4 x 4 block of the tile per thread.
+__global__ void __launch_bounds__(256) tensor_grad_kernel(const TGradJob* __restrict__ jobs,
+                                                          const float* __restrict__ rec_x,
+                                                          const float* __restrict__ urec,
+                                                          const float* __restrict__ trec, int mode_floats,
+                                                          int rows_total, int seg_len) {
+  const TGradJob J = jobs[blockIdx.z];
+  const int n = blockIdx.y;
+  const int tiles = (J.nt + kTgTile - 1) / kTgTile;
+  if (n >= J.nin || (int)blockIdx.x >= tiles * tiles) return;
+  const int i0 = (blockIdx.x / tiles) * kTgTile, j0 = (blockIdx.x % tiles) * kTgTile;
+  __shared__ float4 As4[kTgChunk][kTgTile / 4], Bs4[kTgChunk][kTgTile / 4];
+  float* As = reinterpret_cast<float*>(As4);
+  float* Bs = reinterpret_cast<float*>(Bs4);
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  float acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+  for (int c0 = 0; c0 < seg_len; c0 += kTgChunk) {
+#pragma unroll
+    for (int r = 0; r < (kTgChunk * kTgTile) / 256; ++r) {
+      const int e = tid + 256 * r;
+      const int sl = e / kTgTile, k = e % kTgTile;
+      const int st = c0 + sl;
+      float av = 0.f, bv = 0.f;
+      if (st < seg_len) {
+        const long long xo = (long long)st * mode_floats + J.mode_off;
+        const long long to = (long long)st * 2 * rows_total + J.row_off + n;
+        if (i0 + k < J.nt) av = trec[to + rows_total] * rec_x[xo + i0 + k] + trec[to] * urec[xo + i0 + k];
+        if (j0 + k < J.nt) bv = rec_x[xo + j0 + k];
+      }
+      As[e] = av;
+      Bs[e] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < kTgChunk; ++sl) {
+      const float4 a = As4[sl][ty], b = Bs4[sl][tx];
+      const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(av[x], bv[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int i = i0 + 4 * ty + x;
+    if (i >= J.nt) continue;
+    float* o = J.out + ((long long)n * J.nt + i) * J.nt;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int j = j0 + 4 * tx + y;
+      if (j < J.nt) o[j] -= acc[x][y];
+    }
+  }
+}
+
+// Sets *bad when H[n][i][j] != H[n][j][i] for any entry (exact comparison);
+// H is [nin][nt][nt].
+__global__ void sym_check_kernel(const float* __restrict__ H, int nin, int nt, int* bad) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)nt * nt;
+  if (e >= per * nin) return;
+  const long long n = e / per;
+  const int i = (int)((e % per) / nt), j = (int)(e % nt);
+  if (j <= i) return;
+  if (H[n * per + (long long)i * nt + j] != H[n * per + (long long)j * nt + i]) atomicOr(bad, 1);
+}
+
+hipError_t launch_sym_check(const float* H, int nin, int nt, int* bad, hipStream_t s) {
+  const long long total = (long long)nin * nt * nt;
+  if (total < 1) return hipSuccess;
+  hipLaunchKernelGGL(sym_check_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, H, nin, nt, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_tensor_grad(const TGradJob* jobs, int n_jobs, int max_nin, int max_nt, const float* rec_x,
+                              const float* urec, const float* trec, int mode_floats, int rows_total,
+                              int seg_len, hipStream_t s) {
+  if (n_jobs < 1 || max_nin < 1 || max_nt < 1 || seg_len < 1) return hipSuccess;
+  const int tiles = (max_nt + kTgTile - 1) / kTgTile;
+  hipLaunchKernelGGL(tensor_grad_kernel, dim3(tiles * tiles, max_nin, n_jobs), dim3(256), 0, s, jobs, rec_x,
+                     urec, trec, mode_floats, rows_total, seg_len);
+  return hipGetLastError();
 }
 
 // Adds the per-row records of one segment (steps in record order) to the

@@ -150,7 +150,22 @@ struct GradParams {
   // segment: [seg_len][rows_total] (rows of all VK instances); NULL = none
   float* rrec;
   int rows_total;
+  // records for the full tensor gradient (NULL = none), in forward step order
+  // like rec_x: u^n per mode [seg_len][mode_floats], and eta_n, V_n . u per
+  // in-plane row [seg_len][2][rows_total]
+  float* urec;
+  float* trec;
 };
+
+// One instance's share of the full tensor gradient: out[n][i][j] (caller
+// layout, n < nin, i, j < nt) -= sum over the segment's steps of
+// ((V_n . u) q_i + eta_n u_i) q_j.
+struct TGradJob {
+  float* out;
+  int nt, nin, mode_off, row_off;
+};
+constexpr int kTgTile = 64;   // output tile edge (i and j)
+constexpr int kTgChunk = 16;  // steps staged in LDS per round
 
 // ------------------------------------------------------------ shared tensor
 // Batches whose instances share one coupling tensor up to a per-row scale

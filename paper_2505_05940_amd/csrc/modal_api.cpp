@@ -30,6 +30,10 @@ hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, co
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
 hipError_t launch_shared(const SharedParams& P, int kt, int kc, int jt, int n_wg, hipStream_t s);
 hipError_t launch_row_sum(const float* rrec, int seg_len, int rows, float* acc, hipStream_t s);
+hipError_t launch_sym_check(const float* H, int nin, int nt, int* bad, hipStream_t s);
+hipError_t launch_tensor_grad(const TGradJob* jobs, int n_jobs, int max_nin, int max_nt, const float* rec_x,
+                              const float* urec, const float* trec, int mode_floats, int rows_total,
+                              int seg_len, hipStream_t s);
 hipError_t launch_lin_sum(const LinMode* modes, const double4* amp, const double2* ztab, const LinSeg* segs,
                           int n_segs, long long max_len, float* out, hipStream_t s);
 hipError_t launch_lin_sum_f64(const LinMode* modes, const double4* amp, const double2* ztab,
@@ -188,6 +192,11 @@ struct modal_ctx {
   int rows_total = 0;
   float *dRrec = nullptr, *dRacc = nullptr;
   long long rrec_floats = 0;
+  // full tensor gradient: u and (eta, V.u) records of a segment, job list
+  float *dUrec = nullptr, *dTrec = nullptr;
+  long long urec_floats = 0, trec_floats = 0;
+  TGradJob* dTJobs = nullptr;
+  int tjobs_cap = 0;
   // parity-blocked tensors
   int n_blocked = 0;
   long long dense_bytes = 0;
@@ -236,7 +245,7 @@ void free_ctx(modal_ctx* c) {
                   c->dStep, c->dE,   c->dHd,   c->dCkpt,  c->dRec,  c->dAdj, c->dAcc,
                   c->dGPart, c->dGCtr, c->dShA, c->dShS2, c->dJmap, c->dRrec, c->dRacc,
                   c->dLinModes, c->dLinInit, c->dLinAmp, c->dLinSeg, c->dLinForced, c->dLinH,
-                  c->dLinTab};
+                  c->dLinTab, c->dUrec, c->dTrec, c->dTJobs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -1531,9 +1540,50 @@ int modal_set_tangent(modal_ctx* c, int32_t b, const float* Hd, void* stream_) {
   return MODAL_OK;
 }
 
+int modal_set_tensor(modal_ctx* c, int32_t b, const float* H, void* stream_) {
+  if (!c || !H) return fail(MODAL_EINVAL, "NULL argument");
+  if (c->shared || c->linear) return fail(MODAL_ESTATE, "the context keeps no per-instance tensor");
+  if (b < 0 || b >= c->batch || c->kind[b] != MODAL_KIND_VK)
+    return fail(MODAL_EINVAL, "set_tensor needs a VK instance index");
+  const InstDev& D = c->inst_host[b];
+  if (D.blk) return fail(MODAL_ESTATE, "the instance's tensor is stored parity-blocked");
+  hipStream_t s = (hipStream_t)stream_;
+  // the kernels use the symmetry of every row in its last two indices
+  hipPointerAttribute_t attr;
+  bool on_device = false;
+  if (hipPointerGetAttributes(&attr, H) == hipSuccess)
+    on_device = attr.type == hipMemoryTypeDevice;
+  else
+    (void)hipGetLastError();
+  bool symmetric = true;
+  if (on_device) {
+    int bad = 0;
+    // the first per-instance check slot (used only while modal_init runs)
+    HIP_TRY(hipMemsetAsync(c->dFlags + 2, 0, sizeof(int), s));
+    HIP_TRY(launch_sym_check(H, D.nin, D.nt, c->dFlags + 2, s));
+    HIP_TRY(hipMemcpyAsync(&bad, c->dFlags + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    symmetric = bad == 0;
+  } else {
+    const size_t per = (size_t)D.nt * D.nt;
+    for (int n = 0; n < D.nin && symmetric; ++n)
+      for (int i = 0; i < D.nt && symmetric; ++i)
+        for (int j = i + 1; j < D.nt; ++j)
+          if (H[n * per + (size_t)i * D.nt + j] != H[n * per + (size_t)j * D.nt + i]) {
+            symmetric = false;
+            break;
+          }
+  }
+  if (!symmetric) return fail(MODAL_EINVAL, "tensor is not symmetric in its last two indices");
+  HIP_TRY(hipMemcpy2DAsync(c->dH + D.h_off, sizeof(float) * D.ntp, H, sizeof(float) * D.nt,
+                           sizeof(float) * D.nt, (size_t)D.nin * D.nt, hipMemcpyDefault, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MODAL_OK;
+}
+
 int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_stride, int32_t ckpt_every,
                double* g_omega, double* g_gamma, double* g_c, double* g_x0, double* g_xm1,
-               double* g_scale, double* g_theta, double* g_row, void* stream_) {
+               double* g_scale, double* g_theta, double* g_row, float* const* g_H, void* stream_) {
   if (!c) return fail(MODAL_EINVAL, "ctx is NULL");
   if (!(c->flags & MODAL_FLAG_GRAD)) return fail(MODAL_ESTATE, "context not created with MODAL_FLAG_GRAD");
   if (n_steps < 1 || n_steps > (1LL << 31) - 1 || !ybar || y_stride < n_steps)
@@ -1568,6 +1618,49 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     if (!r && !c->dRacc) r = dalloc(&c->dRacc, sizeof(float) * 2 * (size_t)c->rows_total);
     if (r) return r;
     c->rrec_floats = (long long)K * c->rows_total;
+  }
+  // full tensor gradient jobs (instances with an output buffer)
+  std::vector<TGradJob> tjobs;
+  int tj_nin = 0, tj_nt = 0;
+  if (g_H) {
+    for (int b = 0; b < c->batch; ++b) {
+      if (!g_H[b]) continue;
+      if (c->kind[b] != MODAL_KIND_VK) return fail(MODAL_EINVAL, "g_H given for an instance that is not VK");
+      const InstDev& D = c->inst_host[b];
+      tjobs.push_back({g_H[b], D.nt, D.nin, D.mode_off, D.row_off});
+      tj_nin = std::max(tj_nin, D.nin);
+      tj_nt = std::max(tj_nt, D.nt);
+    }
+  }
+  const bool tens_on = !tjobs.empty();
+  if (tens_on) {
+    if (c->urec_floats < (long long)K * mf) {
+      if (c->dUrec) HIP_TRY(hipFree(c->dUrec));
+      c->dUrec = nullptr;
+      c->urec_floats = 0;
+      int r = dalloc(&c->dUrec, sizeof(float) * (size_t)K * mf);
+      if (r) return r;
+      c->urec_floats = (long long)K * mf;
+    }
+    if (c->trec_floats < 2LL * K * c->rows_total) {
+      if (c->dTrec) HIP_TRY(hipFree(c->dTrec));
+      c->dTrec = nullptr;
+      c->trec_floats = 0;
+      int r = dalloc(&c->dTrec, sizeof(float) * 2 * (size_t)K * c->rows_total);
+      if (r) return r;
+      c->trec_floats = 2LL * K * c->rows_total;
+    }
+    if (c->tjobs_cap < (int)tjobs.size()) {
+      if (c->dTJobs) HIP_TRY(hipFree(c->dTJobs));
+      c->dTJobs = nullptr;
+      c->tjobs_cap = 0;
+      int r = dalloc(&c->dTJobs, sizeof(TGradJob) * tjobs.size());
+      if (r) return r;
+      c->tjobs_cap = (int)tjobs.size();
+    }
+    HIP_TRY(hipMemcpyAsync(c->dTJobs, tjobs.data(), sizeof(TGradJob) * tjobs.size(), hipMemcpyHostToDevice, s));
+    for (const TGradJob& j : tjobs)
+      HIP_TRY(hipMemsetAsync(j.out, 0, sizeof(float) * (size_t)j.nin * j.nt * j.nt, s));
   }
   if (!c->dAdj) {
     int r = dalloc(&c->dAdj, sizeof(float) * 4 * (size_t)sf);
@@ -1616,6 +1709,8 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   G.red_floats = 3 * c->red_floats;
   G.rrec = rows_on ? c->dRrec : nullptr;
   G.rows_total = c->rows_total;
+  G.urec = tens_on ? c->dUrec : nullptr;
+  G.trec = tens_on ? c->dTrec : nullptr;
   for (long long seg = nseg - 1; seg >= 0; --seg) {
     const long long s0 = seg * K;
     const int len = (int)std::min<long long>(K, n_steps - s0);
@@ -1633,6 +1728,9 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     G.done_before = n_steps - s0 - len;
     HIP_TRY(launch_grad(G, c->gm, c->tangent, c->nw, c->n_wg, c->grad_lds, s));
     if (rows_on) HIP_TRY(launch_row_sum(c->dRrec, len, c->rows_total, c->dRacc, s));
+    if (tens_on)
+      HIP_TRY(launch_tensor_grad(c->dTJobs, (int)tjobs.size(), tj_nin, tj_nt, c->dRec, c->dUrec, c->dTrec, mf,
+                                 c->rows_total, len, s));
   }
   r = modal_check(c, stream_);
   if (r) return r;

@@ -270,3 +270,56 @@ def fit(target: torch.Tensor, theta0, setup: PlateSetup, n_steps: int, iters: in
             fz = torch.from_numpy(frozen)
             z[fz] = z_frozen[fz]
     return best_th, best_L, iters, hist
+
+
+def symmetric_part(G: torch.Tensor) -> torch.Tensor:
+    """(G + G^T) / 2 over the last two indices: the gradient with respect to a
+    coupling tensor constrained, like the coupling coefficients, to be
+    symmetric in its last two indices."""
+    return 0.5 * (G + G.transpose(-1, -2))
+
+
+def fit_tensor(inst: dict, target: torch.Tensor, H0, n_steps: int, iters: int = 100,
+               lr: float = 0.05, loss_fn=mrstft_loss, ckpt: int = 512, fs: float = 44100.0,
+               callback=None):
+    """Fits the coupling tensor of one von Karman instance, everything else
+    fixed, to a target output (paper: Sec. 4.3, the coupling coefficients H
+    optimised from a random normal start to match the displacement at a fixed
+    point over 17 640 steps).
+
+    H0: the start, [n_in, n_t, n_t] symmetric in its last two indices.  Each
+    iteration replaces the instance's tensor (modal_set_tensor), runs the
+    forward pass, takes dL/dy of the loss by torch autograd, and runs
+    modal_grad with the full tensor gradient; Adam steps on its symmetric
+    part, which keeps H exactly symmetric.  lr is relative to the rms entry
+    of H0; the schedule is the one-cycle cosine of the parameter fits.
+    Returns (best H as a CUDA tensor, best loss, loss history)."""
+    H = torch.tensor(np.asarray(H0, np.float32), device="cuda", requires_grad=True)
+    sim = modal.Sim([dict(inst, Ht=np.asarray(H0, np.float32))], fs, flags=modal.FLAG_GRAD)
+    rms = float(H.detach().pow(2).mean().sqrt())
+    opt = torch.optim.Adam([H], lr=lr * rms)
+    tgt = target.reshape(1, -1).to(H.device)
+    hist = []
+    best_L, best_H = math.inf, H.detach().clone()
+    try:
+        for it in range(iters):
+            for gparam in opt.param_groups:
+                gparam["lr"] = one_cycle_cosine(it, iters, lr * rms)
+            sim.set_tensor(0, H.detach())
+            sim.reset()
+            y = sim.run(n_steps).clone().requires_grad_(True)
+            L = loss_fn(y, tgt)
+            L.backward()
+            Ln = float(L.detach())
+            hist.append(Ln)
+            if Ln < best_L:
+                best_L, best_H = Ln, H.detach().clone()
+            if callback:
+                callback(it, Ln)
+            g = sim.grad(n_steps, y.grad.float().contiguous(), ckpt_every=ckpt, tensor=True)
+            H.grad = symmetric_part(g["H"][0])
+            opt.step()
+            opt.zero_grad(set_to_none=True)
+    finally:
+        sim.close()
+    return best_H, best_L, hist

@@ -70,10 +70,12 @@ def _load():
     lib.modal_destroy.restype = None
     lib.modal_last_error.restype = C.c_char_p
     lib.modal_grad.argtypes = [vp, C.c_int64, _fp, C.c_int64, C.c_int32, _dp, _dp, _dp, _dp, _dp,
-                               _dp, _dp, _dp, vp]
+                               _dp, _dp, _dp, C.POINTER(vp), vp]
     lib.modal_grad.restype = C.c_int
     lib.modal_set_tangent.argtypes = [vp, C.c_int32, _fp, vp]
     lib.modal_set_tangent.restype = C.c_int
+    lib.modal_set_tensor.argtypes = [vp, C.c_int32, _fp, vp]
+    lib.modal_set_tensor.restype = C.c_int
     lib.modal_plan.argtypes = [C.POINTER(modal_desc), C.c_int32, C.POINTER(C.c_int64)]
     lib.modal_plan.restype = C.c_int
     lib.modal_vk_coupling_sine.argtypes = [C.c_double, C.c_double, C.c_int32, _ip, _ip,
@@ -250,28 +252,56 @@ class Sim:
         _check(lib.modal_set_tangent(self._ctx, b, ptr, _stream_handle(self._stream)))
         del keep
 
-    def grad(self, n_steps, dL_dy, ckpt_every=0):
+    def set_tensor(self, b, H):
+        """Replace the coupling tensor of VK instance b (float32 [n_in, n_t, n_t],
+        CUDA tensor or host array)."""
+        if hasattr(H, "data_ptr"):
+            assert H.dtype.itemsize == 4 and H.is_contiguous()
+            ptr = C.cast(C.c_void_p(H.data_ptr()), _fp)
+            keep = H
+        else:
+            keep = np.ascontiguousarray(H, dtype=np.float32)
+            ptr = keep.ctypes.data_as(_fp)
+        _check(lib.modal_set_tensor(self._ctx, b, ptr, _stream_handle(self._stream)))
+        del keep
+
+    def grad(self, n_steps, dL_dy, ckpt_every=0, tensor=False):
         """Reverse-mode gradient of L over the first n_steps outputs from the
         initial state; dL_dy is a CUDA float32 tensor [batch, >= n_steps].
         Returns per-instance lists of numpy arrays (omega, gamma, c, x0, xm1,
         and row = dL/dlog s_n per in-plane row of a vk instance) and [batch]
-        arrays (scale = dL/dlog s, theta)."""
+        arrays (scale = dL/dlog s, theta).  tensor=True (or a list of booleans
+        per instance) adds H: per instance a CUDA float32 tensor
+        [n_in, n_t, n_t] with dL/dHt entry by entry (None where not asked or
+        not vk)."""
         assert dL_dy.is_cuda and dL_dy.dtype.itemsize == 4 and dL_dy.stride(1) == 1
         M = self.modes_total
         out = {k: np.zeros(M) for k in ("omega", "gamma", "c", "x0", "xm1")}
         scale = np.zeros(self.batch)
         theta = np.zeros(self.batch)
         row = np.zeros(max(1, self.rows_total))
+        gH = [None] * self.batch
+        ptrs = None
+        if tensor:
+            import torch
+            want = tensor if isinstance(tensor, (list, tuple)) else [True] * self.batch
+            for b in range(self.batch):
+                if want[b] and self.n_in[b] > 0:
+                    gH[b] = torch.empty((self.n_in[b], self.n_t[b], self.n_t[b]), dtype=torch.float32,
+                                        device=dL_dy.device)
+            ptrs = (C.c_void_p * self.batch)(*[(g.data_ptr() if g is not None else None) for g in gH])
         _check(lib.modal_grad(self._ctx, n_steps, C.cast(C.c_void_p(dL_dy.data_ptr()), _fp),
                               dL_dy.stride(0), ckpt_every,
                               *(out[k].ctypes.data_as(_dp) for k in ("omega", "gamma", "c", "x0", "xm1")),
                               scale.ctypes.data_as(_dp), theta.ctypes.data_as(_dp),
-                              row.ctypes.data_as(_dp), _stream_handle(self._stream)))
+                              row.ctypes.data_as(_dp), ptrs, _stream_handle(self._stream)))
         splits = np.cumsum(self.n_t)[:-1]
         res = {k: np.split(v, splits) for k, v in out.items()}
         res["scale"] = scale
         res["theta"] = theta
         res["row"] = [row[o:o + n] if n else np.zeros(0) for o, n in zip(self._row_off, self.n_in)]
+        if tensor:
+            res["H"] = gH
         return res
 
     def reset(self):
