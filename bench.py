@@ -187,6 +187,40 @@ def linear_path(batch, n_modes, seed):
     }
 
 
+def tensor_fit_rate(iters=4, starts=16):
+    """Coupling-tensor fit iterations on the single-plate geometry (40
+    transverse and 40 in-plane sine modes) over 17 640 steps (0.4 s), from a
+    random normal symmetric start: wall time per iteration (tensor upload,
+    forward pass, loss, adjoint with the full tensor gradient, Adam step) and
+    the loss after the iterations."""
+    import torch
+    import workloads as W
+    from paper_2505_05940_amd import fit, modal, physics
+    from paper_2505_05940_amd.losses import mrstft_loss
+    steps = 17640
+    wl = W.plate_vk(n_t=40, n_in=40, family="sine", grid=None, n_steps=steps)
+    p = physics.plate_instance(wl)
+    sim = modal.Sim([p], 44100.0)
+    target = sim.run(steps).clone()
+    sim.close()
+    rng = np.random.default_rng(0)
+    R = rng.normal(size=(starts,) + p["Ht"].shape)
+    H0 = (0.5 * (R + R.transpose(0, 1, 3, 2)) * np.sqrt(2 * np.mean(np.square(p["Ht"], dtype=float))))
+    H0 = H0.astype(np.float32)
+    res = {"workload": "coupling-tensor fit, 40/40-mode sine plate, 17640 steps, MR-STFT loss, "
+                       "random normal symmetric starts",
+           "parameters_per_start": int(np.prod(p["Ht"].shape)), "iterations": iters}
+    for name, h0 in (("one_start", H0[0]), (f"{starts}_starts", H0)):
+        fit.fit_tensor(p, target, h0, steps, iters=1, loss_fn=mrstft_loss)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, best, hist = fit.fit_tensor(p, target, h0, steps, iters=iters, loss_fn=mrstft_loss)
+        torch.cuda.synchronize()
+        res[name] = {"seconds_per_iteration": (time.perf_counter() - t0) / iters,
+                     "loss_first_mean": float(np.mean(hist[0])), "loss_best_mean": float(np.mean(best))}
+    return res
+
+
 def fit_wall_time():
     """Wall time to the target spectral loss: a proposal network is trained
     on 200 000 plates simulated by the dense path (60 epochs), then 64
@@ -260,6 +294,8 @@ def main():
     ap.add_argument("--dense-batch", type=int, default=65536)
     ap.add_argument("--no-linear", action="store_true",
                     help="skip the linear closed-form path measurement")
+    ap.add_argument("--no-tensor-fit", action="store_true",
+                    help="skip the coupling-tensor fit iteration timing")
     ap.add_argument("--no-fit", action="store_true",
                     help="skip the fit wall-time measurement (proposal + gradient fitting)")
     ap.add_argument("--dense-modes", type=int, default=40)
@@ -380,6 +416,10 @@ def main():
         out["linear_path"] = linear_path(4096, 100, args.seed)
         print(f"[bench] linear path: {out['linear_path']['seconds']:.3f} s closed form, "
               f"{out['linear_path']['recursion_seconds']:.3f} s recursion", file=sys.stderr, flush=True)
+    if not args.no_tensor_fit:
+        out["tensor_fit"] = tensor_fit_rate()
+        print(f"[bench] tensor fit: {out['tensor_fit']['one_start']['seconds_per_iteration']:.3f} s per "
+              f"iteration", file=sys.stderr, flush=True)
     if not args.no_fit:
         out["config"]["fit_wall_time_s"], out["fit"] = fit_wall_time()
         print(f"[bench] fit: {out['fit']}", file=sys.stderr, flush=True)

@@ -281,45 +281,60 @@ def symmetric_part(G: torch.Tensor) -> torch.Tensor:
 
 def fit_tensor(inst: dict, target: torch.Tensor, H0, n_steps: int, iters: int = 100,
                lr: float = 0.05, loss_fn=mrstft_loss, ckpt: int = 512, fs: float = 44100.0,
-               callback=None):
-    """Fits the coupling tensor of one von Karman instance, everything else
+               h_scale: float | None = None, callback=None):
+    """Fits the coupling tensor of a von Karman instance, everything else
     fixed, to a target output (paper: Sec. 4.3, the coupling coefficients H
     optimised from a random normal start to match the displacement at a fixed
-    point over 17 640 steps).
+    point over 17 640 steps, with several starts explored in parallel).
 
-    H0: the start, [n_in, n_t, n_t] symmetric in its last two indices.  Each
-    iteration replaces the instance's tensor (modal_set_tensor), runs the
-    forward pass, takes dL/dy of the loss by torch autograd, and runs
+    H0: one start [n_in, n_t, n_t] or B starts [B, n_in, n_t, n_t], each
+    symmetric in its last two indices; the starts run as one batch.  Each
+    iteration replaces the tensors (modal_set_tensor), runs the forward pass,
+    takes dL/dy of loss_fn(y_b, target) per start by torch autograd, and runs
     modal_grad with the full tensor gradient; Adam steps on its symmetric
-    part, which keeps H exactly symmetric.  lr is relative to the rms entry
-    of H0; the schedule is the one-cycle cosine of the parameter fits.
-    Returns (best H as a CUDA tensor, best loss, loss history)."""
-    H = torch.tensor(np.asarray(H0, np.float32), device="cuda", requires_grad=True)
-    sim = modal.Sim([dict(inst, Ht=np.asarray(H0, np.float32))], fs, flags=modal.FLAG_GRAD)
-    rms = float(H.detach().pow(2).mean().sqrt())
+    part, which keeps every H exactly symmetric.  lr is relative to h_scale
+    (default: the rms entry of H0); the schedule is the one-cycle cosine of
+    the parameter fits.
+    Returns (best H per start as a CUDA tensor shaped like H0, best loss per
+    start [B], loss history [iterations][B])."""
+    H0 = np.asarray(H0, np.float32)
+    single = H0.ndim == 3
+    H0 = H0[None] if single else H0
+    B = H0.shape[0]
+    H = torch.tensor(H0, device="cuda", requires_grad=True)
+    # a single instance has its in-plane rows spread over workgroups (slabs
+    # that exchange partial forces every step) rather than left on one
+    sim = modal.Sim([dict(inst, Ht=H0[b]) for b in range(B)], fs,
+                    flags=modal.FLAG_GRAD | modal.FLAG_SPLIT_ANY)
+    rms = float(H.detach().pow(2).mean().sqrt()) if h_scale is None else float(h_scale)
     opt = torch.optim.Adam([H], lr=lr * rms)
     tgt = target.reshape(1, -1).to(H.device)
     hist = []
-    best_L, best_H = math.inf, H.detach().clone()
+    best_L = np.full(B, np.inf)
+    best_H = H.detach().clone()
     try:
         for it in range(iters):
             for gparam in opt.param_groups:
                 gparam["lr"] = one_cycle_cosine(it, iters, lr * rms)
-            sim.set_tensor(0, H.detach())
+            for b in range(B):
+                sim.set_tensor(b, H.detach()[b])
             sim.reset()
             y = sim.run(n_steps).clone().requires_grad_(True)
-            L = loss_fn(y, tgt)
-            L.backward()
-            Ln = float(L.detach())
+            Ls = torch.stack([loss_fn(y[b:b + 1], tgt) for b in range(B)])
+            Ls.sum().backward()
+            Ln = Ls.detach().cpu().numpy()
             hist.append(Ln)
-            if Ln < best_L:
-                best_L, best_H = Ln, H.detach().clone()
+            better = Ln < best_L
+            best_L[better] = Ln[better]
+            best_H[torch.from_numpy(better).to(H.device)] = H.detach()[torch.from_numpy(better).to(H.device)]
             if callback:
                 callback(it, Ln)
             g = sim.grad(n_steps, y.grad.float().contiguous(), ckpt_every=ckpt, tensor=True)
-            H.grad = symmetric_part(g["H"][0])
+            H.grad = symmetric_part(torch.stack(g["H"]))
             opt.step()
             opt.zero_grad(set_to_none=True)
     finally:
         sim.close()
+    if single:
+        return best_H[0], float(best_L[0]), [float(h[0]) for h in hist]
     return best_H, best_L, hist

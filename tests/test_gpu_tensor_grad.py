@@ -135,3 +135,36 @@ def test_tensor_fit_from_random_start(gpu):
     assert best_L < 0.1 * hist[0], (best_L, hist[0])
     Hb = best_H.cpu().numpy()
     assert np.array_equal(Hb, Hb.transpose(0, 2, 1))
+
+
+def test_tensor_fit_parallel_starts(gpu):
+    """Several random starts as one batch: each start's first loss is the
+    oracle's at that start, and the starts run independently (the batch's
+    first start follows the single-start fit of the same start exactly)."""
+    modal, physics, torch = gpu
+    from paper_2505_05940_amd import fit
+    steps = 1500
+    wl = W.plate_vk(n_t=6, n_in=4, family="sine", grid=None, n_steps=steps)
+    wl["strike"]["amplitude"] = 1.5e-2
+    p = physics.plate_instance(wl)
+    o = OI.plate_instance(wl)
+    target = OS.run(o, steps, 44100.0)
+    rng = np.random.default_rng(1)
+    R = rng.normal(size=(3,) + o["Ht"].shape)
+    H0 = (0.5 * (R + R.transpose(0, 1, 3, 2)) * np.sqrt(2 * np.mean(o["Ht"] ** 2))).astype(np.float32)
+
+    def mse(y, t):
+        return ((y - t) ** 2).sum() / (t ** 2).sum()
+
+    print("case: tensor fit, 3 parallel starts, 1500 steps, 10 iterations", flush=True)
+    tt = torch.tensor(target, dtype=torch.float32, device="cuda")
+    hs = float(np.sqrt(np.mean(H0.astype(float) ** 2)))
+    best_H, best_L, hist = fit.fit_tensor(p, tt, H0, steps, iters=10, lr=0.05, loss_fn=mse, h_scale=hs)
+    assert best_H.shape == H0.shape and len(best_L) == 3 and len(hist) == 10
+    for b in range(3):
+        yb = OS.run(dict(o, Ht=H0[b].astype(float)), steps, 44100.0)
+        Lb = float(np.sum((yb - target) ** 2) / np.sum(target ** 2))
+        assert abs(hist[0][b] - Lb) < 1e-4 * Lb, (b, hist[0][b], Lb)
+    # the same start alone (its own work partition, so sums in another order)
+    _, _, h1 = fit.fit_tensor(p, tt, H0[0], steps, iters=10, lr=0.05, loss_fn=mse, h_scale=hs)
+    assert np.allclose([h[0] for h in hist], h1, rtol=1e-4, atol=0), ([h[0] for h in hist], h1)
