@@ -241,6 +241,30 @@ int modal_grad(modal_ctx *c, int64_t n_steps, const float *dL_dy, int64_t y_stri
  * an asymmetric tensor (the stored tensor is then unchanged). */
 int modal_set_tensor(modal_ctx *c, int32_t inst, const float *H, void *stream);
 
+/* Transfer-function response of linear modal systems (paper: Sec. 3.2,
+ * impulse-invariant transfer function; Sec. 4.3, linear string fits on a
+ * Bark-sampled magnitude response, with a second numerator coefficient and
+ * free output weights per mode):
+ *   H[b][k] = sum over modes mu of instance b of
+ *             w_mu (b1_mu z + b2_mu) / (z^2 + a1_mu z + a2_mu),  z = e^{i omega[k]}.
+ * All pointers are device memory: coef [modes][5] = (a1, a2, b1, b2, w) in
+ * FP64, modes of instance b at [mode_off[b], mode_off[b+1]) (int32
+ * [batch + 1]); omega [n_freq] in radians per sample; H [batch][n_freq][2]
+ * (real, imaginary) written.  Asynchronous on `stream`.  EINVAL for NULL
+ * pointers, batch outside [1, 65535] or n_freq < 1. */
+int modal_tf_response(const double *coef, const int32_t *mode_off, int32_t batch,
+                      const double *omega, int32_t n_freq, double *H, void *stream);
+
+/* Gradient of L = sum_{b,k} Re(conj(g[b][k]) H[b][k]) with g = dL_dH
+ * [batch][n_freq][2] (dL/dRe H, dL/dIm H), device memory, with respect to
+ * every mode's (a1, a2, b1, b2, w): g_coef [modes][5] (device, written; modes
+ * outside every instance's range are left as they are).  max_modes: the
+ * largest mode count of an instance.  Same layout and errors as
+ * modal_tf_response. */
+int modal_tf_grad(const double *coef, const int32_t *mode_off, int32_t batch, int32_t max_modes,
+                  const double *omega, int32_t n_freq, const double *dL_dH, double *g_coef,
+                  void *stream);
+
 /* Host-only preview of the work partition modal_init would make for `d`
  * with n_workgroups co-resident workgroups (validates d like modal_init; no
  * device calls): out[0] work units, [1] workgroups used, [2] planned cost of

@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(bdir, exist_ok=True)
     objs = []
     srcs = [("step_kernel.hip", True), ("grad_kernel.hip", True), ("shared_kernel.hip", True),
-            ("linear_kernel.hip", True),
+            ("linear_kernel.hip", True), ("tf_kernel.hip", True),
             ("modal_api.cpp", True),
             ("mlp_kernels.hip", True), ("mlp_api.cpp", True), ("coupling_host.cpp", False)]
     for src, hip in srcs:

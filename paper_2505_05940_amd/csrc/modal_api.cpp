@@ -30,6 +30,10 @@ hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, co
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
 hipError_t launch_shared(const SharedParams& P, int kt, int kc, int jt, int n_wg, hipStream_t s);
 hipError_t launch_row_sum(const float* rrec, int seg_len, int rows, float* acc, hipStream_t s);
+hipError_t launch_tf_response(const double* coef, const int* mode_off, int batch, const double* omega,
+                              int n_freq, double* H, hipStream_t s);
+hipError_t launch_tf_grad(const double* coef, const int* mode_off, int batch, int max_modes, const double* omega,
+                          int n_freq, const double* gH, double* g_coef, hipStream_t s);
 hipError_t launch_sym_check(const float* H, int nin, int nt, int* bad, hipStream_t s);
 hipError_t launch_tensor_grad(const TGradJob* jobs, int n_jobs, int max_nin, int max_nt, const float* rec_x,
                               const float* urec, const float* trec, int mode_floats, int rows_total,
@@ -1537,6 +1541,22 @@ int modal_set_tangent(modal_ctx* c, int32_t b, const float* Hd, void* stream_) {
                            sizeof(float) * D.nt, (size_t)D.nin * D.nt, hipMemcpyDefault, s));
   HIP_TRY(hipStreamSynchronize(s));
   c->tangent = true;
+  return MODAL_OK;
+}
+
+int modal_tf_response(const double* coef, const int32_t* mode_off, int32_t batch, const double* omega,
+                      int32_t n_freq, double* H, void* stream_) {
+  if (!coef || !mode_off || !omega || !H) return fail(MODAL_EINVAL, "NULL argument");
+  if (batch < 1 || batch > 65535 || n_freq < 1) return fail(MODAL_EINVAL, "batch or n_freq");
+  HIP_TRY(launch_tf_response(coef, mode_off, batch, omega, n_freq, H, (hipStream_t)stream_));
+  return MODAL_OK;
+}
+
+int modal_tf_grad(const double* coef, const int32_t* mode_off, int32_t batch, int32_t max_modes,
+                  const double* omega, int32_t n_freq, const double* dL_dH, double* g_coef, void* stream_) {
+  if (!coef || !mode_off || !omega || !dL_dH || !g_coef) return fail(MODAL_EINVAL, "NULL argument");
+  if (batch < 1 || batch > 65535 || n_freq < 1 || max_modes < 0) return fail(MODAL_EINVAL, "batch, n_freq or max_modes");
+  HIP_TRY(launch_tf_grad(coef, mode_off, batch, max_modes, omega, n_freq, dL_dH, g_coef, (hipStream_t)stream_));
   return MODAL_OK;
 }
 

@@ -81,8 +81,10 @@ def _load():
     lib.modal_vk_coupling_sine.argtypes = [C.c_double, C.c_double, C.c_int32, _ip, _ip,
                                            C.c_int32, _ip, _ip, C.c_int32, C.c_int32,
                                            _dp, _fp, C.c_int32]
+    lib.modal_tf_response.argtypes = [vp, vp, C.c_int32, vp, C.c_int32, vp, vp]
+    lib.modal_tf_grad.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, C.c_int32, vp, vp, vp]
     for f in ("modal_init", "modal_run", "modal_check", "modal_reset", "modal_get_state",
-              "modal_info", "modal_vk_coupling_sine"):
+              "modal_info", "modal_vk_coupling_sine", "modal_tf_response", "modal_tf_grad"):
         getattr(lib, f).restype = C.c_int
     return lib
 

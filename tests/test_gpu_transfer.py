@@ -1,0 +1,83 @@
+"""Transfer-function response and gradient kernels (modal_tf_response,
+modal_tf_grad, through the C ABI) against the FP64 oracle, and the
+transfer-function fit of a synthetic linear string.  Both sides compute in
+FP64: bar 1e-11 relative."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import scheme
+from oracle import simulate as OS
+from oracle import transfer as OT
+
+pytestmark = pytest.mark.gpu
+
+FS = 44100.0
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2505_05940_amd import transfer
+    return transfer, torch
+
+
+def _coef(n, rng):
+    omega = 2 * np.pi * np.sort(rng.uniform(60, 12000, n))
+    gamma = rng.uniform(0.5, 300, n)
+    g, p, b1 = scheme.tf_coefficients(omega, gamma, 1 / FS)
+    return np.stack([-g, -p, b1, rng.normal(size=n) * b1, rng.normal(size=n)], axis=1)
+
+
+def test_response_and_gradient_match_the_oracle(gpu):
+    transfer, torch = gpu
+    rng = np.random.default_rng(8)
+    sizes = [5, 70, 1]
+    coefs = [_coef(n, rng) for n in sizes]
+    Om = OT.bark_grid(300, 40, 16000, FS)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    dev = "cuda"
+    coef = torch.tensor(np.concatenate(coefs), device=dev, requires_grad=True)
+    print("case: tf response and gradient, modes 5/70/1, 300 frequencies", flush=True)
+    H = transfer.TfResponse.apply(coef, torch.tensor(off, device=dev), torch.tensor(Om, device=dev), 70)
+    g = rng.normal(size=(3, 300, 2))
+    (H * torch.tensor(g, device=dev)).sum().backward()
+    Hc = H.detach().cpu().numpy()
+    Gc = coef.grad.cpu().numpy()
+    for b in range(3):
+        ref = OT.response(*coefs[b].T, Om)
+        got = Hc[b, :, 0] + 1j * Hc[b, :, 1]
+        assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max(), b
+        gref = OT.response_grad(*coefs[b].T, Om, g[b, :, 0] + 1j * g[b, :, 1])
+        gg = Gc[off[b]:off[b + 1]]
+        for j in range(5):
+            assert np.abs(gg[:, j] - gref[:, j]).max() <= 1e-11 * np.abs(gref[:, j]).max(), (b, j)
+
+
+def test_fit_recovers_pitch_and_inharmonicity(gpu):
+    """A plucked stiff string simulated by the oracle (transfer-function
+    scheme, 1 s); the fit starts 0.5 % flat and 5 % off in stiffness, with the
+    damping off by a factor of two, and recovers the fundamental and the
+    inharmonicity from the Bark-sampled LPC envelope alone."""
+    transfer, torch = gpu
+    f0, B, n = 220.0, 1e-4, 40
+    T0 = (2 * f0) ** 2
+    D = B * T0 / math.pi ** 2
+    th = np.array([T0, D, 2.0, 2e-5])
+    mu = np.arange(1, n + 1)
+    lam = (mu * np.pi) ** 2
+    omega = np.sqrt(D * lam ** 2 + T0 * lam)
+    gamma = 0.5 * (th[2] + th[3] * lam)
+    x0 = 1e-3 * np.sin(mu * np.pi * 0.27) / mu ** 2
+    inst = dict(kind="linear", omega=omega, gamma=gamma, x0=x0, xm1=x0.copy(), c=np.sin(mu * np.pi * 0.71))
+    y = OS.run(inst, 44100, FS, scheme="tf")
+    start = np.array([T0 * 0.995 ** 2, D * 0.95, 4.0, 1e-5])
+    print("case: tf fit, 40-mode string, 600 iterations", flush=True)
+    theta, w, beta, hist = transfer.fit_tf(y, FS, n, start, iters=600)
+    f_fit = math.sqrt(theta[0]) / 2
+    B_fit = theta[1] * math.pi ** 2 / theta[0]
+    assert abs(f_fit - f0) < 0.1 * abs(math.sqrt(start[0]) / 2 - f0), f_fit
+    assert abs(B_fit - B) < 0.15 * B, B_fit
+    assert min(hist) < 0.6 * hist[0]
