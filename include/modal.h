@@ -122,7 +122,12 @@ typedef struct {
                                    an upper bound, capped by co-residency     */
   int32_t chunk_steps;          /* steps per kernel launch; 0 = whole run     */
   int32_t waves;                /* waves (64 lanes) per workgroup sharing a
-                                   work unit's rows: 0 = default (4), 1 or 4  */
+                                   work unit's rows: 1, 4 or 8, or 0 = default
+                                   (8 for a batch of at most one instance per
+                                   CU whose tensors are all small, when its
+                                   reduction space fits the LDS; else 4).
+                                   The reverse kernel takes fewer waves when
+                                   its larger reduction space does not fit.  */
 } modal_desc;
 
 /* Validates the description (before any device work), computes the per-mode

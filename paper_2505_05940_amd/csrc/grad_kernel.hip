@@ -501,7 +501,7 @@ hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, int n_
                        hipStream_t s) {
 #define GL(G, T, W) hipLaunchKernelGGL((grad_kernel<G, T, W>), dim3(n_wg), dim3(kWave * W), lds, s, P)
 #define GL_NW(G, T) \
-  if (nw == 1) GL(G, T, 1); else GL(G, T, 4);
+  if (nw == 1) GL(G, T, 1); else if (nw == 8) GL(G, T, 8); else GL(G, T, 4);
 #define GL_T(G) \
   if (tangent) { GL_NW(G, true) } else { GL_NW(G, false) }
   if (gm <= 1) {
@@ -521,7 +521,7 @@ hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, size_t lds)
 #define GO(G, T, W) \
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<G, T, W>, kWave * W, lds)
 #define GO_NW(G, T) \
-  { if (nw == 1) { GO(G, T, 1); } else { GO(G, T, 4); } }
+  { if (nw == 1) { GO(G, T, 1); } else if (nw == 8) { GO(G, T, 8); } else { GO(G, T, 4); } }
 #define GO_T(G) \
   { if (tangent) { GO_NW(G, true) } else { GO_NW(G, false) } }
   if (gm <= 1) GO_T(1)

@@ -559,6 +559,8 @@ hipError_t launch_step(const StepParams& P, int gm, int nw, int n_wg, size_t lds
 #define SL(G, W) hipLaunchKernelGGL((step_kernel<G, W>), dim3(n_wg), dim3(kWave * W), lds_bytes, s, P)
   if (nw == 1) {
     if (gm <= 1) SL(1, 1); else if (gm <= 2) SL(2, 1); else SL(4, 1);
+  } else if (nw == 8) {
+    if (gm <= 1) SL(1, 8); else if (gm <= 2) SL(2, 8); else SL(4, 8);
   } else {
     if (gm <= 1) SL(1, 4); else if (gm <= 2) SL(2, 4); else SL(4, 4);
   }
@@ -580,6 +582,11 @@ hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes) 
     if (gm <= 1) SO(1, 1);
     if (gm <= 2) SO(2, 1);
     SO(4, 1);
+  }
+  if (nw == 8) {
+    if (gm <= 1) SO(1, 8);
+    if (gm <= 2) SO(2, 8);
+    SO(4, 8);
   }
   if (gm <= 1) SO(1, 4);
   if (gm <= 2) SO(2, 4);

@@ -50,7 +50,7 @@ def ragged_refs():
     return wls, [OS.run(OI.plate_instance(w), 3000, w["fs"]) for w in wls]
 
 
-@pytest.mark.parametrize("max_wg,waves", [(0, 4), (0, 1), (7, 4), (3, 1)])
+@pytest.mark.parametrize("max_wg,waves", [(0, 4), (0, 1), (7, 4), (3, 1), (7, 8)])
 def test_blocked_ragged_batch(gpu, ragged_refs, max_wg, waves):
     modal, physics = gpu
     wls, refs = ragged_refs

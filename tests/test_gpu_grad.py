@@ -44,7 +44,8 @@ def _cases():
     return wl_vk, wl_kc
 
 
-@pytest.mark.parametrize("max_wg,ckpt,waves", [(0, 0, 4), (3, 128, 4), (3, 128, 1), (0, 200, 1)])
+@pytest.mark.parametrize("max_wg,ckpt,waves", [(0, 0, 4), (3, 128, 4), (3, 128, 1), (0, 200, 1),
+                                               (3, 128, 8), (0, 0, 8)])
 def test_grad_matches_oracle(gpu, max_wg, ckpt, waves):
     modal, physics, torch = gpu
     wl_vk, wl_kc = _cases()

@@ -78,11 +78,11 @@ def _ragged_batch():
     return out
 
 
-@pytest.mark.parametrize("max_wg,waves", [(0, 4), (0, 1), (7, 4), (7, 1), (3, 4)])
+@pytest.mark.parametrize("max_wg,waves", [(0, 4), (0, 1), (7, 4), (7, 1), (3, 4), (0, 8), (7, 8)])
 def test_ragged_batch_split_and_packed(gpu, max_wg, waves):
     """max_workgroups 7 and 3 force instances to be cut into row slabs that
-    exchange partial forces every step, next to instances packed whole; one
-    or four waves per workgroup share a unit's rows."""
+    exchange partial forces every step, next to instances packed whole; one,
+    four or eight waves per workgroup share a unit's rows."""
     modal, physics = gpu
     wls = _ragged_batch()
     steps = 3000
