@@ -163,9 +163,12 @@ struct modal_ctx {
   int batch = 0, scheme = 0, flags = 0, chunk = 0;
   double fs = 0;
   int n_wg = 0, n_units = 0, n_split = 0, occ = 0, gm = 1, nw = 4;
-  int nw_grad = 4;  // waves of the reverse kernel (its reduction space is larger)
+  // waves of the reverse kernel without and with a tangent tensor (its
+  // reduction space per wave holds two or three reduced vectors per row)
+  int nw_grad[2] = {4, 4};
+  size_t grad_lds_v[2] = {0, 0};
   double makespan = 0, mean_load = 0;
-  size_t lds_bytes = 0, grad_lds = 0;
+  size_t lds_bytes = 0;
   long long coupling_bytes = 0, padded_bytes = 0, steps = 0;
   int state_floats = 0, mode_floats = 0;
   std::vector<int> nt, unit_state_of_inst, inst_mode_off;
@@ -1209,22 +1212,22 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   int occ = 0;
   HIP_TRY(step_occupancy(&occ, c->gm, c->nw, c->lds_bytes));
   c->red_floats = red_floats;
-  c->nw_grad = c->nw;
-  c->grad_lds = grad_lds_bytes(c->nw_grad, 3 * red_floats);
   if (d->flags & MODAL_FLAG_GRAD) {
     // the reverse kernel (with or without a tangent) must fit as many
     // co-resident workgroups as the plan uses; it shares the step kernel's
     // partition but may divide a unit's rows among fewer waves when its
     // reduction space does not fit the LDS with as many
-    int og = 0, ot = 0;
-    for (;;) {
-      c->grad_lds = grad_lds_bytes(c->nw_grad, 3 * red_floats);
-      HIP_TRY(grad_occupancy(&og, c->gm, false, c->nw_grad, c->grad_lds));
-      HIP_TRY(grad_occupancy(&ot, c->gm, true, c->nw_grad, c->grad_lds));
-      if (std::min(og, ot) >= 1 || c->nw_grad == 1) break;
-      c->nw_grad = c->nw_grad == 8 ? 4 : 1;
+    for (int tan = 0; tan < 2; ++tan) {
+      int o = 0;
+      c->nw_grad[tan] = c->nw;
+      for (;;) {
+        c->grad_lds_v[tan] = grad_lds_bytes(c->nw_grad[tan], (tan ? 3 : 2) * red_floats);
+        HIP_TRY(grad_occupancy(&o, c->gm, tan == 1, c->nw_grad[tan], c->grad_lds_v[tan]));
+        if (o >= 1 || c->nw_grad[tan] == 1) break;
+        c->nw_grad[tan] = c->nw_grad[tan] == 8 ? 4 : 1;
+      }
+      occ = std::min(occ, o);
     }
-    occ = std::min(occ, std::min(og, ot));
   }
   if (occ < 1) {
     free_ctx(c);
@@ -1749,7 +1752,7 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   G.part = c->dGPart;
   G.ctr = c->dGCtr;
   G.flags = F.flags;
-  G.red_floats = 3 * c->red_floats;
+  G.red_floats = (c->tangent ? 3 : 2) * c->red_floats;
   G.rrec = rows_on ? c->dRrec : nullptr;
   G.rows_total = c->rows_total;
   G.urec = tens_on ? c->dUrec : nullptr;
@@ -1769,7 +1772,7 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     G.seg_base = s0;
     G.seg_len = len;
     G.done_before = n_steps - s0 - len;
-    HIP_TRY(launch_grad(G, c->gm, c->tangent, c->nw_grad, c->n_wg, c->grad_lds, s));
+    HIP_TRY(launch_grad(G, c->gm, c->tangent, c->nw_grad[c->tangent], c->n_wg, c->grad_lds_v[c->tangent], s));
     if (rows_on) HIP_TRY(launch_row_sum(c->dRrec, len, c->rows_total, c->dRacc, s));
     if (tens_on)
       HIP_TRY(launch_tensor_grad(c->dTJobs, (int)tjobs.size(), tj_nin, tj_nt, c->dRec, c->dUrec, c->dTrec, mf,
