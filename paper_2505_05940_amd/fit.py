@@ -302,10 +302,10 @@ def fit_tensor(inst: dict, target: torch.Tensor, H0, n_steps: int, iters: int = 
     H0 = H0[None] if single else H0
     B = H0.shape[0]
     H = torch.tensor(H0, device="cuda", requires_grad=True)
-    # a single instance has its in-plane rows spread over workgroups (slabs
-    # that exchange partial forces every step) rather than left on one
-    sim = modal.Sim([dict(inst, Ht=H0[b]) for b in range(B)], fs,
-                    flags=modal.FLAG_GRAD | modal.FLAG_SPLIT_ANY)
+    # each start on one workgroup whose waves share its rows: a small plate's
+    # step is latency-bound, and a slab exchange between workgroups costs more
+    # than it saves
+    sim = modal.Sim([dict(inst, Ht=H0[b]) for b in range(B)], fs, flags=modal.FLAG_GRAD)
     rms = float(H.detach().pow(2).mean().sqrt()) if h_scale is None else float(h_scale)
     opt = torch.optim.Adam([H], lr=lr * rms)
     tgt = target.reshape(1, -1).to(H.device)
