@@ -195,6 +195,14 @@ struct modal_ctx {
         *dGPart = nullptr;
   unsigned int* dGCtr = nullptr;
   long long ckpt_floats = 0, rec_floats = 0;
+  // Checkpoints recorded by the forward runs of a gradient context, every
+  // kRunCkpt steps from step 0: valid for the steps [0, ckpt_upto) run with
+  // the current tensors unless broken (a gap, or a buffer that had to grow
+  // mid-run); modal_grad with the same spacing reuses them instead of running
+  // the forward pass again.
+  long long ckpt_upto = 0;
+  bool ckpt_broken = false;
+  bool run_ckpt = false;  // the run being enqueued records checkpoints
   bool tangent = false;
   // per-row (in-plane) gradient pools: rows of all VK instances
   int rows_total = 0;
@@ -326,6 +334,10 @@ int validate(const modal_desc* d) {
   }
   return MODAL_OK;
 }
+
+// Checkpoint spacing of forward runs in gradient contexts (modal_grad's
+// default).
+constexpr int kRunCkpt = 512;
 
 // Per-step cost of the exchange and barrier of one slab of a split instance,
 // in streamed-byte units (release fence, arrival, wait, acquire and reading
@@ -1473,6 +1485,7 @@ int modal_reset(modal_ctx* c, void* stream_) {
   HIP_TRY(hipMemsetAsync(c->dFlags, 0, sizeof(int) * 2, s));
   HIP_TRY(hipMemsetAsync(c->dStep, 0, sizeof(long long), s));
   c->steps = 0;
+  c->ckpt_broken = false;  // checkpoints of [0, ckpt_upto) stay valid
   return MODAL_OK;
 }
 
@@ -1491,6 +1504,10 @@ static int enqueue_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride
       P.y = y + done;
       P.y_stride = y_stride;
       P.n_steps = (int)k;
+      if (c->run_ckpt) {
+        P.ckpt = c->dCkpt;
+        P.ckpt_every = kRunCkpt;
+      }
       HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
     }
     HIP_TRY(launch_advance(c->dStep, (int)k, s));
@@ -1521,6 +1538,29 @@ int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* s
     c->steps += n_steps;
     return MODAL_OK;
   }
+  // gradient contexts record checkpoints while they run forward from step 0
+  c->run_ckpt = false;
+  if ((c->flags & MODAL_FLAG_GRAD) && !(c->flags & MODAL_FLAG_GRAPH) && !c->shared) {
+    if (c->ckpt_broken || c->steps > c->ckpt_upto) {
+      c->ckpt_broken = true;
+    } else {
+      const long long need = (c->steps + n_steps + kRunCkpt - 1) / kRunCkpt * 4LL * c->mode_floats;
+      if (c->ckpt_floats < need && c->steps > 0) {
+        c->ckpt_broken = true;  // growing would lose the slots already taken
+      } else {
+        if (c->ckpt_floats < need) {
+          if (c->dCkpt) HIP_TRY(hipFree(c->dCkpt));
+          c->dCkpt = nullptr;
+          c->ckpt_floats = 0;
+          c->ckpt_upto = 0;
+          int r = dalloc(&c->dCkpt, sizeof(float) * (size_t)need);
+          if (r) return r;
+          c->ckpt_floats = need;
+        }
+        c->run_ckpt = true;
+      }
+    }
+  }
   if (c->flags & MODAL_FLAG_GRAPH) {
     hipGraphExec_t exec = nullptr;
     for (auto& g : c->graphs)
@@ -1542,8 +1582,11 @@ int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* s
     }
     HIP_TRY(hipGraphLaunch(exec, s));
   } else {
+    const bool recorded = c->run_ckpt;
     int r = enqueue_run(c, n_steps, y, y_stride, s);
+    c->run_ckpt = false;
     if (r) return r;
+    if (recorded) c->ckpt_upto = std::max(c->ckpt_upto, c->steps + n_steps);
   }
   c->steps += n_steps;
   if (c->flags & MODAL_FLAG_ASYNC) return MODAL_OK;
@@ -1624,6 +1667,7 @@ int modal_set_tensor(modal_ctx* c, int32_t b, const float* H, void* stream_) {
   HIP_TRY(hipMemcpy2DAsync(c->dH + D.h_off, sizeof(float) * D.ntp, H, sizeof(float) * D.nt,
                            sizeof(float) * D.nt, (size_t)D.nin * D.nt, hipMemcpyDefault, s));
   HIP_TRY(hipStreamSynchronize(s));
+  c->ckpt_upto = 0;  // recorded checkpoints belong to the old tensor
   return MODAL_OK;
 }
 
@@ -1639,11 +1683,16 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   const long long nseg = (n_steps + K - 1) / K;
   hipStream_t s = (hipStream_t)stream_;
   const int mf = c->mode_floats, sf = c->state_floats;
+  // checkpoints of the last forward runs, if they cover the steps with this
+  // spacing, replace the forward pass
+  const bool reuse = K == kRunCkpt && !c->ckpt_broken && c->ckpt_upto >= n_steps &&
+                     !(c->flags & MODAL_FLAG_GRAPH) && c->ckpt_floats >= nseg * 4LL * mf;
   // buffers (grown on demand)
   if (c->ckpt_floats < nseg * 4LL * mf) {
     if (c->dCkpt) HIP_TRY(hipFree(c->dCkpt));
     c->dCkpt = nullptr;
     c->ckpt_floats = 0;
+    c->ckpt_upto = 0;
     int r = dalloc(&c->dCkpt, sizeof(float) * (size_t)(nseg * 4LL * mf));
     if (r) return r;
     c->ckpt_floats = nseg * 4LL * mf;
@@ -1715,16 +1764,19 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     if (!r) r = dalloc(&c->dGCtr, sizeof(unsigned int) * c->batch);
     if (r) return r;
   }
-  // forward from the initial state with checkpoints
+  // forward from the initial state with checkpoints (unless the last runs
+  // recorded them)
   int r = modal_reset(c, stream_);
   if (r) return r;
-  {
+  if (!reuse) {
     StepParams P = c->P;
     P.y = nullptr;
     P.ckpt = c->dCkpt;
     P.ckpt_every = K;
     P.n_steps = (int)n_steps;
     HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
+    // slots now hold this spacing's checkpoints
+    c->ckpt_upto = K == kRunCkpt ? std::max<long long>(c->ckpt_upto, n_steps) : 0;
   }
   HIP_TRY(hipMemsetAsync(c->dAdj, 0, sizeof(float) * 4 * (size_t)sf, s));
   HIP_TRY(hipMemsetAsync(c->dAcc, 0, sizeof(float) * 12 * (size_t)sf, s));

@@ -128,3 +128,50 @@ def test_grad_matches_central_differences(gpu):
         fd32 = (Lg[0] - Lg[1]) / (2 * h)
         assert abs(fd64 - adj) < 1e-3 * abs(fd64), (k, fd64, adj)
         assert abs(fd32 - adj) < 5e-3 * abs(adj), (k, fd32, adj)
+
+
+@pytest.mark.parametrize("max_wg", [0, 3])
+def test_grad_reuses_the_checkpoints_of_forward_runs(gpu, max_wg):
+    """A gradient context records checkpoints while it runs forward from step
+    0; modal_grad with the same spacing then skips its own forward pass.  The
+    result is bit-identical to the gradient of a fresh context, also when the
+    run came in pieces, and a tensor replacement voids the recorded
+    checkpoints."""
+    modal, physics, torch = gpu
+    wl_vk, wl_kc = _cases()
+    steps = 1300
+    pinsts = [physics.plate_instance(wl_vk), physics.string_instance(wl_kc)]
+    rng = np.random.default_rng(9)
+    g = torch.tensor(rng.normal(size=(2, steps)) * 1e3, dtype=torch.float32, device="cuda")
+    print(f"case: checkpoint reuse, max_wg={max_wg}", flush=True)
+
+    def fresh(insts):
+        s = modal.Sim(insts, 44100.0, flags=modal.FLAG_GRAD | modal.FLAG_SPLIT_ANY, max_workgroups=max_wg)
+        r = s.grad(steps, g)
+        s.close()
+        return r
+
+    ref = fresh(pinsts)
+    sim = modal.Sim(pinsts, 44100.0, flags=modal.FLAG_GRAD | modal.FLAG_SPLIT_ANY, max_workgroups=max_wg)
+    sim.run(steps)
+    a = sim.grad(steps, g)
+    sim.run(300)
+    sim.run(steps - 300)
+    b = sim.grad(steps, g)
+    for r in (a, b):
+        for k in ("omega", "gamma", "c", "x0", "xm1", "row"):
+            for i in range(2):
+                assert np.array_equal(r[k][i], ref[k][i]), (k, i)
+    # another spacing runs its own forward pass
+    c = sim.grad(steps, g, ckpt_every=100)
+    assert max(rel(c["omega"][i], ref["omega"][i]) for i in range(2)) < 1e-6
+    # a new tensor after the run: the recorded checkpoints are not used
+    H2 = (pinsts[0]["Ht"] * 0.8).astype(np.float32)
+    sim.run(steps)
+    sim.set_tensor(0, H2)
+    d = sim.grad(steps, g)
+    ref2 = fresh([dict(pinsts[0], Ht=H2), pinsts[1]])
+    for k in ("omega", "x0", "row"):
+        for i in range(2):
+            assert np.array_equal(d[k][i], ref2[k][i]), (k, i)
+    sim.close()
