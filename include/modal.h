@@ -226,6 +226,11 @@ int modal_set_tangent(modal_ctx *c, int32_t inst, const float *Hd, void *stream)
  *                     FP32 device memory [n_in][n_t][n_t], overwritten (the
  *                     caller owns it).  Per checkpoint segment, one product
  *                     over the segment's steps per in-plane row.
+ * A context created with MODAL_FLAG_GRAD (and without MODAL_FLAG_GRAPH)
+ * records these checkpoints, every 512 steps, while modal_run steps it
+ * forward from step 0; with ckpt_every 0 or 512, modal_grad then reuses them
+ * for the first n_steps if they cover them, and skips its own forward pass
+ * (same result, bit for bit).  modal_set_tensor voids them.
  * Needs a context created with MODAL_FLAG_GRAD (else ESTATE).  Leaves the
  * context reset to its initial state.  Errors: EINVAL, ENOMEM, EHIP,
  * ENONFINITE, EHANG. */
