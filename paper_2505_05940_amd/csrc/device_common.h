@@ -83,6 +83,35 @@ __device__ __forceinline__ float dot4(float4 a, float4 b) {
   return fmaf(a.w, b.w, fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)));
 }
 __device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+// sum over t < n of the float4 at p + t * stride (LDS), with four partial
+// sums so that four reads are in flight before the first add waits
+__device__ __forceinline__ float4 sum_strided4(const float* p, int n, int stride) {
+  float4 s0 = ld4(p), s1 = make_float4(0.f, 0.f, 0.f, 0.f), s2 = s1, s3 = s1;
+  int t = 1;
+  for (; t + 3 < n; t += 4) {
+    s1 = add4(s1, ld4(p + t * stride));
+    s2 = add4(s2, ld4(p + (t + 1) * stride));
+    s3 = add4(s3, ld4(p + (t + 2) * stride));
+    s0 = add4(s0, ld4(p + (t + 3) * stride));
+  }
+  for (; t < n; ++t) s1 = add4(s1, ld4(p + t * stride));
+  return add4(add4(s0, s1), add4(s2, s3));
+}
+
+// sum of n consecutive floats (LDS), four partial sums
+__device__ __forceinline__ float sum_run(const float* p, int n) {
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int c = 0;
+  for (; c + 3 < n; c += 4) {
+    s0 += p[c];
+    s1 += p[c + 1];
+    s2 += p[c + 2];
+    s3 += p[c + 3];
+  }
+  for (; c < n; ++c) s0 += p[c];
+  return (s0 + s1) + (s2 + s3);
+}
 typedef float v4f __attribute__((ext_vector_type(4)));
 // streaming 16-byte load with the non-temporal hint (read once per step)
 __device__ __forceinline__ float4 ldnt4(const float* p) {

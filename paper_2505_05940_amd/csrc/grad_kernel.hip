@@ -96,13 +96,9 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
       V[g] = W[g] = f4(0.f);
       const int k4 = lane + kWave * g;
       if (g < G && k4 < nc) {
-        float4 sv = ld4(rb + 4 * k4), sw = ld4(rb + slab + 4 * k4);
-        float4 sd = TAN ? ld4(rb + 2 * slab + 4 * k4) : f4(0.f);
-        for (int t = 1; t < qs; ++t) {
-          sv = add4(sv, ld4(rb + t * ntp + 4 * k4));
-          sw = add4(sw, ld4(rb + slab + t * ntp + 4 * k4));
-          if (TAN) sd = add4(sd, ld4(rb + 2 * slab + t * ntp + 4 * k4));
-        }
+        const float4 sv = sum_strided4(rb + 4 * k4, qs, ntp);
+        const float4 sw = sum_strided4(rb + slab + 4 * k4, qs, ntp);
+        const float4 sd = TAN ? sum_strided4(rb + 2 * slab + 4 * k4, qs, ntp) : f4(0.f);
         V[g] = sv;
         W[g] = sw;
         const float4 x = ld4(Xs + 4 * k4), u = ld4(Us + 4 * k4);

@@ -28,11 +28,15 @@ struct InstDev {
   // parity-blocked tensor (blk = 1): modes are stored grouped by class, class
   // i on rows [cls[i], cls[i+1]) (each a multiple of 4, ntp = cls[4]); in-plane
   // row n holds, for every class i, the block of rows of class i against
-  // the columns of class jmap[n][i] (or nothing if jmap < 0), w columns wide
+  // the columns of class j = jmap[n][i] & 7 (or nothing if jmap < 0), as wide
+  // as class j, at float offset boff[n][i] from the instance's start; w is
+  // the widest class.  A map entry also holds bit 3 (the block stands for its
+  // transpose too), the rows per piece qs = min(rows, 256 / (width / 4)) in
+  // bits 4..12 and the number of pieces from bit 13.
   int blk, w;
   int cls[5];
   int row_off;         // VK: offset of its in-plane rows in per-row pools
-  long long jmap_off;  // int4 offset of jmap[nin][4] in the block-map pool
+  long long jmap_off;  // int4 offset of the map [nin][2] (jmap[4], boff[4]) in its pool
 };
 
 // A slice of in-plane rows [row0, row1) of one instance, owned by one

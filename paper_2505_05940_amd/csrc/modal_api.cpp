@@ -357,6 +357,11 @@ struct BlockPlan {
   int cls[5] = {0, 0, 0, 0, 0};
   int w = 0, rmax = 0;
   std::vector<int> slot_mode, mode_slot, jmap;
+  // float offset of block (n, i) from the instance's start (stored blocks
+  // only: rows of class i, as wide as its column class), rows laid out in
+  // order, and the stored floats in all
+  std::vector<int> boff;
+  long long floats = 0;
   long long stored_bytes = 0;
 };
 
@@ -435,6 +440,19 @@ void analyze_blocks(const modal_instance& I, BlockPlan& bp) {
       }
     }
   }
+  bp.boff.assign((size_t)nin * 4, 0);
+  long long pos = 0;
+  for (int n = 0; n < nin; ++n)
+    for (int i = 0; i < 4; ++i) {
+      const int je = bp.jmap[(size_t)n * 4 + i];
+      const int R = bp.cls[i + 1] - bp.cls[i];
+      if (je < 0 || R == 0) continue;
+      const int tj = je & 7;
+      bp.boff[(size_t)n * 4 + i] = (int)pos;
+      pos += (long long)R * (bp.cls[tj + 1] - bp.cls[tj]);
+      if (pos > (1LL << 31) - 1) return;  // offsets are 32-bit
+    }
+  bp.floats = pos;
   bp.ok = true;
 }
 
@@ -479,7 +497,7 @@ void unit_costs(const modal_instance& I, double& row_cost, double& fixed_cost,
                 const BlockPlan* bp = nullptr) {
   const int ntp = round4(I.n_t);
   if (I.kind == MODAL_KIND_VK && bp && bp->ok) {
-    row_cost = 4.0 * bp->cls[4] * bp->w + 4.0 * 2048.0;
+    row_cost = 4.0 * (double)bp->floats / std::max(1, I.n_in) + 4.0 * 2048.0;
     fixed_cost = 8192.0;
   } else if (I.kind == MODAL_KIND_VK) {
     row_cost = 4.0 * I.n_t * ntp + 4096.0;
@@ -602,7 +620,8 @@ int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>
     if (I.kind != MODAL_KIND_VK) continue;
     const InstDev& D = inst[b];
     if (D.blk) {
-      // blocks gathered on the host threads, staged like dense rows of w
+      // blocks gathered on the host threads, whole in-plane rows staged in
+      // order (each block as wide as its column class)
       if (!stage[0]) {
         for (int i = 0; i < 2; ++i) {
           UP_TRY(hipHostMalloc((void**)&stage[i], kStage, hipHostMallocDefault));
@@ -610,45 +629,65 @@ int upload_tensors(modal_ctx* c, const modal_desc* d, const std::vector<InstDev>
         }
       }
       const BlockPlan& bp = plans[b];
-      const size_t rows = (size_t)D.nin * D.ntp;
-      const size_t rows_per = std::max<size_t>(1, kStage / (sizeof(float) * D.w));
-      for (size_t r0 = 0; r0 < rows; r0 += rows_per) {
-        const size_t nr = std::min(rows_per, rows - r0);
+      const int nin = D.nin;
+      std::vector<long long> rs((size_t)nin + 1, 0);  // first float of each in-plane row
+      for (int n = 0; n < nin; ++n) {
+        long long sz = 0;
+        for (int i = 0; i < 4; ++i) {
+          const int je = bp.jmap[(size_t)n * 4 + i];
+          const int R = bp.cls[i + 1] - bp.cls[i];
+          if (je >= 0 && R > 0) sz += (long long)R * (bp.cls[(je & 7) + 1] - bp.cls[je & 7]);
+        }
+        rs[n + 1] = rs[n] + sz;
+      }
+      const long long stage_floats = (long long)(kStage / sizeof(float));
+      for (int n0 = 0; n0 < nin;) {
+        int n1 = n0 + 1;
+        while (n1 < nin && rs[n1 + 1] - rs[n0] <= stage_floats) ++n1;
+        if (rs[n1] - rs[n0] > stage_floats) {
+          cleanup();
+          return fail(MODAL_ENOMEM, "an in-plane row's blocks exceed the staging buffer");
+        }
         if (used[slot]) UP_TRY(hipEventSynchronize(done[slot]));
         float* dst = stage[slot];
-        auto fill_rows = [&](size_t a, size_t z) {
-          for (size_t r = a; r < z; ++r) {
-            float* out = dst + r * D.w;
-            const size_t rr = r0 + r;
-            const int n = (int)(rr / D.ntp), sl = (int)(rr % D.ntp);
-            const int p = bp.slot_mode[sl];
-            int ci = 0;
-            while (ci < 3 && sl >= bp.cls[ci + 1]) ++ci;
-            const int je = bp.jmap[(size_t)n * 4 + ci];
-            const int tj = je < 0 ? -1 : (je & 7);
-            if (p < 0 || tj < 0) {
-              std::memset(out, 0, sizeof(float) * D.w);
-              continue;
-            }
-            const float* row = I.H + ((size_t)n * D.nt + p) * D.nt;
+        auto fill_rows = [&](int a, int z) {
+          for (int n = a; n < z; ++n) {
+            const float* Hn = I.H + (size_t)n * D.nt * D.nt;
             const double sc = I.h_row_scale ? I.h_row_scale[n] : 1.0;
-            for (int s = 0; s < D.w; ++s) {
-              const int sq = bp.cls[tj] + s;
-              const int q = sq < bp.cls[tj + 1] ? bp.slot_mode[sq] : -1;
-              out[s] = q < 0 ? 0.f : (I.h_row_scale ? (float)(sc * (double)row[q]) : row[q]);
+            for (int i = 0; i < 4; ++i) {
+              const int je = bp.jmap[(size_t)n * 4 + i];
+              const int R = bp.cls[i + 1] - bp.cls[i];
+              if (je < 0 || R == 0) continue;
+              const int tj = je & 7;
+              const int W = bp.cls[tj + 1] - bp.cls[tj];
+              float* out = dst + (bp.boff[(size_t)n * 4 + i] - rs[n0]);
+              for (int r = 0; r < R; ++r, out += W) {
+                const int p = bp.slot_mode[bp.cls[i] + r];
+                if (p < 0) {
+                  std::memset(out, 0, sizeof(float) * W);
+                  continue;
+                }
+                const float* row = Hn + (size_t)p * D.nt;
+                for (int s2 = 0; s2 < W; ++s2) {
+                  const int q = bp.slot_mode[bp.cls[tj] + s2];
+                  out[s2] = q < 0 ? 0.f : (I.h_row_scale ? (float)(sc * (double)row[q]) : row[q]);
+                }
+              }
             }
           }
         };
-        const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        const int nr = n1 - n0;
+        const unsigned nth = (unsigned)std::max(1, std::min({16, nr, (int)std::thread::hardware_concurrency()}));
         std::vector<std::thread> th;
-        for (unsigned t = 1; t < nth; ++t) th.emplace_back(fill_rows, nr * t / nth, nr * (t + 1) / nth);
-        fill_rows(0, nr / nth);
+        for (unsigned t = 1; t < nth; ++t) th.emplace_back(fill_rows, n0 + (int)(nr * t / nth), n0 + (int)(nr * (t + 1) / nth));
+        fill_rows(n0, n0 + (int)(nr / nth));
         for (auto& t : th) t.join();
-        UP_TRY(hipMemcpyAsync(c->dH + D.h_off + r0 * D.w, dst, sizeof(float) * nr * D.w,
+        UP_TRY(hipMemcpyAsync(c->dH + D.h_off + rs[n0], dst, sizeof(float) * (size_t)(rs[n1] - rs[n0]),
                               hipMemcpyHostToDevice, stream));
         UP_TRY(hipEventRecord(done[slot], stream));
         used[slot] = true;
         slot ^= 1;
+        n0 = n1;
       }
       continue;
     }
@@ -1158,7 +1197,19 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
       D.w = bp.w;
       for (int i = 0; i < 5; ++i) D.cls[i] = bp.cls[i];
       D.jmap_off = (long long)jmap_pool.size() / 4;
-      jmap_pool.insert(jmap_pool.end(), bp.jmap.begin(), bp.jmap.end());
+      for (int n = 0; n < D.nin; ++n) {
+        for (int i = 0; i < 4; ++i) {  // with each stored block's rows per piece and pieces
+        int je = bp.jmap[(size_t)n * 4 + i];
+        const int R = bp.cls[i + 1] - bp.cls[i];
+        if (je >= 0 && R > 0) {
+          const int tlen = (bp.cls[(je & 7) + 1] - bp.cls[je & 7]) / 4;
+          const int qs = std::min(R, (kSweepLoads * kWave) / tlen);
+          je |= (qs << 4) | (((R + qs - 1) / qs) << 13);
+        }
+        jmap_pool.push_back(je);
+      }
+        jmap_pool.insert(jmap_pool.end(), bp.boff.begin() + 4 * n, bp.boff.begin() + 4 * n + 4);
+      }
       c->mode_slot[b] = bp.mode_slot;
     }
     D.mode_off = mode_floats;
@@ -1176,14 +1227,15 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
       c->dense_bytes += 4LL * D.nin * D.nt * D.nt;
       c->flops += 2LL * D.nin * D.nt * D.nt + 4LL * D.nin * D.nt;
       if (D.blk) {
-        const long long f = (long long)D.nin * D.ntp * D.w;
+        const long long f = plans[b].floats;
         h_floats += (f + 63) & ~63LL;
         c->coupling_bytes += plans[b].stored_bytes;
         c->padded_bytes += 4 * f;
         c->n_blocked++;
         choose_sweep(plans[b].rmax, D.w / 4, qs_of[b], J_of[b]);
-        // reduction double buffer, per-slot row dot partials, row-dot vector
-        red_floats = std::max(red_floats, 2 * qs_of[b] * D.w + kSweepLoads * kWave + D.ntp);
+        // reduction double buffer (two pieces' slot layouts), per-slot row dot
+        // partials, row-dot vector
+        red_floats = std::max(red_floats, 2 * 4 * kSweepLoads * kWave + kSweepLoads * kWave + D.ntp);
       } else {
         const long long f = (long long)D.nin * D.nt * D.ntp;
         h_floats += (f + 63) & ~63LL;  // 256-byte aligned instances

@@ -104,8 +104,7 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
       V[g] = f4(0.f);
       const int k4 = lane + kWave * g;
       if (g < G && k4 < nc) {
-        float4 s = ld4(rb + 4 * k4);
-        for (int t = 1; t < qs; ++t) s = add4(s, ld4(rb + t * ntp + 4 * k4));
+        const float4 s = sum_strided4(rb + 4 * k4, qs, ntp);
         V[g] = s;
         eta += dot4(s, ld4(Xs + 4 * k4));
       }
@@ -127,11 +126,13 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
 // Rows [row0, row1) of an instance stored parity-blocked: modes are grouped
 // by class (class i on internal modes [cls[i], cls[i+1])), and in-plane row
 // n holds, per class i, the rows of class i against the columns of class
-// j = jmap[n][i] only (every other entry of those rows is zero), w columns
-// wide.  The sweep is the dense one applied to each (n, i) block in turn:
-// blocks of qs stored rows, lane slot v = lane + 64 j reading float4 v of
-// the block, buffer resources sized to the valid rows, the next block's
-// loads issued before the current one is used.  Accumulating along the
+// j = jmap[n][i] only (every other entry of those rows is zero), as a block
+// as wide as class j (padded to 4) at its own offset (the second int4 of the
+// row's map entry).  The sweep is the dense one applied to each (n, i) block
+// in turn: pieces of qs = min(rows, 256 / (width / 4)) stored rows, lane slot
+// v = lane + 64 j reading float4 v of the piece (sub-row v / (width / 4)),
+// buffer resources sized to the valid rows, the next piece's loads issued
+// before the current one is used.  Accumulating along the
 // stored rows of block (n, i) gives V[n, k] for the modes k of class j
 // (Ht symmetric), so at the end of each block the slot accumulators are
 // reduced over the qs sub-rows through LDS onto the lanes owning those
@@ -151,6 +152,7 @@ struct BlkMeta {
   int flags;  // 1: last block of its class, 2: last of its row, 4: last overall,
               // 8: the block also stands for its transpose (row dot products)
   int rows;   // valid stored rows in the block
+  int qs;     // sub-rows of the block's slot layout (256 / tlen, at most the class)
 };
 
 __device__ __forceinline__ int sel4(const int4 v, int i) {
@@ -159,40 +161,36 @@ __device__ __forceinline__ int sel4(const int4 v, int i) {
 
 template <int GM>
 __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict__ jm,
-                            const InstDev& I, int qs, int row0, int row1, const float* Xs,
+                            const InstDev& I, int row0, int row1, const float* Xs,
                             float* red, float4 (&Fa)[GM], int G, int lane) {
   constexpr int J = kSweepLoads;
+  constexpr int kSlotFloats = 4 * J * kWave;  // floats of one piece's slot layout
   if (row1 <= row0) return;
-  const int ntp = I.ntp, w = I.w;
-  const int nc = w >> 2;
-  const int qsnc = qs * nc;
+  const int ntp = I.ntp;
   const int nc_modes = ntp >> 2;
-  int voff[J], sub[J];
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int v = lane + kWave * j;
-    voff[j] = 16 * v;
-    sub[j] = v < qsnc ? v / nc : 0;
-  }
   int co[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) co[i] = I.cls[i];
-  const long long row_floats = (long long)ntp * w;
-  const int blk_bytes = 4 * qs * w;
-  float* rd = red + 2 * qs * w;  // [kSweepLoads * 64] per-slot row dot partials
-  float* vrow = rd + J * kWave;  // [ntp] row-dot part of V for the current row
+  float* rd = red + 2 * kSlotFloats;  // [kSweepLoads * 64] per-slot row dot partials
+  float* vrow = rd + J * kWave;       // [ntp] row-dot part of V for the current row
   for (int k = lane; k < ntp; k += kWave) vrow[k] = 0.f;
-  // loader position: row ln, class li, block lb; jv = jmap of row ln
+  // loader position: row ln, class li, piece lb; jv, jo = map entries and
+  // block offsets of row ln
   int ln = row0, li = 0, lb = 0;
-  int4 jv = jm[row0];
+  int4 jv = jm[2 * row0], jo = jm[2 * row0 + 1];
   auto has_block = [&](int i) { return co[i + 1] > co[i] && sel4(jv, i) >= 0; };
-  // tensor rows n are stored with blocks indexed by class; a paired block's
-  // partner (-1) is skipped like an empty one
+  // a paired block's partner (-1) is skipped like an empty one
+  auto next_row = [&]() {
+    if (++ln < row1) {
+      jv = jm[2 * ln];
+      jo = jm[2 * ln + 1];
+    }
+  };
   auto to_data = [&]() {  // first (row, class) at or after (ln, li) with a block
     while (ln < row1) {
       while (li < 4 && !has_block(li)) ++li;
       if (li < 4) return;
-      if (++ln < row1) jv = jm[ln];
+      next_row();
       li = 0;
     }
   };
@@ -202,19 +200,19 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
     const bool live = ln < row1;
     const float* bp = Hb;
     int bytes = 0;
-    m = BlkMeta{0, 0, 0, 0, 0};
+    m = BlkMeta{0, 0, 0, 0, 0, 1};
     if (live) {
       const int R = co[li + 1] - co[li];
-      const int nb = (R + qs - 1) / qs;
-      const int q0 = co[li] + lb * qs;
-      m.rows = min(qs, R - lb * qs);
-      bp = Hb + (long long)ln * row_floats + (long long)q0 * w;
-      bytes = 4 * m.rows * w;
       const int je = sel4(jv, li);
       const int tj = je & 7;
-      m.q0 = q0;
       m.tc = co[tj] >> 2;
       m.tlen = (co[tj + 1] - co[tj]) >> 2;
+      m.qs = (je >> 4) & 511;  // min(R, 256 / tlen), from the map entry
+      const int nb = je >> 13;  // pieces of the block
+      m.q0 = co[li] + lb * m.qs;
+      m.rows = min(m.qs, R - lb * m.qs);
+      bp = Hb + sel4(jo, li) + (long long)lb * m.qs * 4 * m.tlen;
+      bytes = 16 * m.rows * m.tlen;
       if (je & 8) m.flags = 8;
       if (++lb == nb) {
         m.flags |= 1;
@@ -224,7 +222,7 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
         if (li == 4) {
           m.flags |= 2;
           li = 0;
-          if (++ln < row1) jv = jm[ln];
+          next_row();
           to_data();
           if (ln >= row1) m.flags |= 4;
         }
@@ -232,7 +230,7 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
     }
     const v4i r = buf_rsrc(bp, bytes);
 #pragma unroll
-    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, 16 * (lane + kWave * j));
   };
   float4 ha[J], hb[J], acc[J], V[GM];
   BlkMeta ma, mb;
@@ -244,6 +242,12 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
   // consumes block `hc` after issuing the loads of the next block into `hn`
   auto step = [&](float4 (&hc)[J], const BlkMeta& mc, float4 (&hn)[J], BlkMeta& mn) -> bool {
     load(hn, mn);
+    // sub-row of each slot in this block's layout: v / tlen (v < 256, so the
+    // rounded reciprocal with half a slot of margin floors exactly)
+    const float inv = __builtin_amdgcn_rcpf((float)mc.tlen);
+    int sub[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) sub[j] = (int)(((float)(lane + kWave * j) + 0.5f) * inv);
 #pragma unroll
     for (int j = 0; j < J; ++j) acc[j] = fma4(hc[j], Xs[min(mc.q0 + sub[j], ntp - 1)], acc[j]);
     if (mc.flags & 8) {
@@ -251,32 +255,29 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         const int v = lane + kWave * j;
-        const int c4 = min(v - sub[j] * nc, mc.tlen - 1);  // float4 column group of slot v
+        const int c4 = min(v - sub[j] * mc.tlen, mc.tlen - 1);  // float4 column group of slot v
         rd[v] = dot4(hc[j], ld4(Xs + 4 * (mc.tc + c4)));
       }
       wave_lds_sync();
-      if (lane < mc.rows) {
-        float sum = 0.f;
-        for (int c = 0; c < nc; ++c) sum += rd[lane * nc + c];
-        vrow[mc.q0 + lane] += sum;
-      }
+      if (lane < mc.rows) vrow[mc.q0 + lane] += sum_run(rd + lane * mc.tlen, mc.tlen);
     }
     if (mc.flags & 1) {
       // block row of class i done: reduce over sub-rows onto the target modes
-      float* rb = red + (par & 1) * qs * w;
+      float* rb = red + (par & 1) * kSlotFloats;
       ++par;
+      const int wj = 4 * mc.tlen;
 #pragma unroll
-      for (int j = 0; j < J; ++j)
-        if (voff[j] < blk_bytes) st4(rb + (voff[j] >> 2), acc[j]);
+      for (int j = 0; j < J; ++j) {
+        const int v = lane + kWave * j;
+        if (v < mc.qs * mc.tlen) st4(rb + 4 * v, acc[j]);
+      }
       wave_lds_sync();
 #pragma unroll
       for (int g = 0; g < GM; ++g) {
         const int k4 = lane + kWave * g;
         const int c4 = k4 - mc.tc;
         if (g < G && c4 >= 0 && c4 < mc.tlen) {
-          float4 sum = ld4(rb + 4 * c4);
-          for (int t = 1; t < qs; ++t) sum = add4(sum, ld4(rb + t * w + 4 * c4));
-          V[g] = add4(V[g], sum);
+          V[g] = add4(V[g], sum_strided4(rb + 4 * c4, mc.qs, wj));
         }
       }
 #pragma unroll
@@ -426,7 +427,7 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
         const int R = U.row1 - U.row0;
         const int r0 = U.row0 + (R * wave) / NW, r1 = U.row0 + (R * (wave + 1)) / NW;
         if (I.blk)
-          vk_rows_blk<GM>(P.H + I.h_off, P.jmap + I.jmap_off, I, U.qs, r0, r1, Xs, red, Fa, G, lane);
+          vk_rows_blk<GM>(P.H + I.h_off, P.jmap + I.jmap_off, I, r0, r1, Xs, red, Fa, G, lane);
         else
           vk_rows<GM>(P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa, G, lane);
         if (NW > 1) {
