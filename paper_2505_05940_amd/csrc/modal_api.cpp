@@ -1259,7 +1259,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   // Waves per workgroup.  A batch of small instances, at most one per CU, is
   // bound by the latency of each step rather than by bytes: eight waves share
   // a unit's rows when their reduction space fits the LDS (a single 40/40
-  // plate steps in 12.9 us instead of 21.8 us).  Larger batches stream with
+  // plate steps in 10.4 us instead of 16.2 us).  Larger batches stream with
   // four waves and three workgroups per CU.
   c->nw = d->waves == 0 ? 4 : d->waves;
   if (d->waves == 0 && d->batch <= prop.multiProcessorCount) {
