@@ -18,7 +18,7 @@
 
 namespace modal {
 
-template <int GM, bool TAN>
+template <int GM, bool TAN, int DEPTH>
 __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__ Hdb, int nt,
                          int ntp, int qs, int row0, int row1, const float* Xs, const float* Us,
                          float* red, float4 (&Ju)[GM], float4 (&Fa)[GM], float& tsum, int G,
@@ -135,7 +135,14 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
     return ++n < row1;
   };
   load(ha, hda);
-  while (step(ha, hda, hb, hdb) && step(hb, hdb, ha, hda)) {
+  if (DEPTH == 2) {
+    while (step(ha, hda, hb, hdb) && step(hb, hdb, ha, hda)) {
+    }
+  } else {  // three buffers: two blocks' loads in flight
+    float4 hx[J], hdx[J];
+    load(hb, hdb);
+    while (step(ha, hda, hx, hdx) && step(hb, hdb, ha, hda) && step(hx, hdx, hb, hdb)) {
+    }
   }
 }
 
@@ -265,7 +272,7 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
         float* rrow = P.rrec ? P.rrec + (long long)s * P.rows_total + I.row_off : nullptr;
         float* teta = P.trec ? P.trec + (n - P.seg_base) * 2LL * P.rows_total + I.row_off : nullptr;
         float* tw = teta ? teta + P.rows_total : nullptr;
-        vk_rows2<GM, TAN>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs, r0, r1,
+        vk_rows2<GM, TAN, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs, r0, r1,
                           Xs, Us, red, Ju, Fa, tsum, G, lane, rrow, teta, tw);
         if (NW > 1) {
 #pragma unroll

@@ -40,8 +40,10 @@ namespace modal {
 // At the end of a row the slot accumulators are reduced over the qs
 // sub-rows through LDS (double buffered by row parity) into V[n, :] on the
 // lanes owning each float4 column group (k4 = lane + 64 g), and eta_n and
-// the force follow: F += eta_n V[n, :].
-template <int GM>
+// the force follow: F += eta_n V[n, :].  DEPTH buffers (2 or 3) keep
+// DEPTH - 1 blocks' loads in flight; three serve small latency-bound units
+// whose rows are only a block or two long.
+template <int GM, int DEPTH>
 __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, int row0,
                         int row1, const float* Xs, float* red, float4 (&Fa)[GM], int G,
                         int lane) {
@@ -118,7 +120,14 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
     return ++n < row1;
   };
   load(ha);
-  while (step(ha, hb) && step(hb, ha)) {
+  if (DEPTH == 2) {
+    while (step(ha, hb) && step(hb, ha)) {
+    }
+  } else {
+    float4 hx[J];
+    load(hb);
+    while (step(ha, hx) && step(hb, ha) && step(hx, hb)) {
+    }
   }
 }
 
@@ -429,7 +438,7 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
         if (I.blk)
           vk_rows_blk<GM>(P.H + I.h_off, P.jmap + I.jmap_off, I, r0, r1, Xs, red, Fa, G, lane);
         else
-          vk_rows<GM>(P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa, G, lane);
+          vk_rows<GM, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa, G, lane);
         if (NW > 1) {
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
