@@ -22,6 +22,8 @@ whose backward runs modal_grad, followed by the FP64 chain rule to theta.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -192,9 +194,12 @@ class ModalFn(torch.autograd.Function):
         # the aspect derivative of the tensor is a per-row rescaling, taken
         # from the per-row gradients (no tangent tensor)
         g = sim.grad(n_steps, gy.contiguous().float(), ckpt_every=ckpt)
-        out = np.stack([chain_rule(setup, th[b], insts[b],
-                                   {k: (v[b] if isinstance(v, list) else v[b]) for k, v in g.items()})
-                        for b in range(len(insts))])
+        # the per-plate chain rules (each projects the strike at two aspects)
+        # run on host threads; numpy releases the interpreter lock in them
+        def one(b):
+            return chain_rule(setup, th[b], insts[b], {k: v[b] for k, v in g.items()})
+        with ThreadPoolExecutor(max_workers=max(1, min(16, len(insts), os.cpu_count() or 1))) as ex:
+            out = np.stack(list(ex.map(one, range(len(insts)))))
         sim.close()
         return torch.tensor(out, dtype=torch.float64).reshape(-1, 5), None, None, None
 
