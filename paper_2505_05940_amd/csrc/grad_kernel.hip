@@ -146,8 +146,6 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
   }
 }
 
-__device__ __forceinline__ ff ldff(const float* hi, const float* lo, int i) { return {hi[i], lo[i]}; }
-
 __device__ __forceinline__ void acc_add(float* acc, int k, int sf, int i, ff v) {
   ff a{acc[(2 * k) * (long long)sf + i], acc[(2 * k + 1) * (long long)sf + i]};
   a = ff_add(a, v);
@@ -155,17 +153,30 @@ __device__ __forceinline__ void acc_add(float* acc, int k, int sf, int i, ff v) 
   acc[(2 * k + 1) * (long long)sf + i] = a.lo;
 }
 
-// db^{n+1} and u^n of one mode from the adjoint state.
-__device__ __forceinline__ void adj_pre(const GradParams& P, int so, int mo, ff& db, ff& u) {
-  const ff qb = ldff(P.qb_hi, P.qb_lo, so);
-  const ff dn = ldff(P.db_hi, P.db_lo, so);
-  const ff pp = ldff(P.p_hi, P.p_lo, mo);
-  const ff t = ff_mul(pp, dn);
-  db = ff_add(qb, {-t.hi, -t.lo});
-  u = ff_mul(ldff(P.r_hi, P.r_lo, mo), db);
+// u^n = r db^{n+1}, db^{n+1} = qb^{n+1} - p db^{n+2}, of four consecutive
+// modes from the adjoint state (the high parts of u).
+__device__ __forceinline__ float4 adj_u4(const GradParams& P, int so, int mo) {
+  const float4 qh4 = ld4(P.qb_hi + so), ql4 = ld4(P.qb_lo + so);
+  const float4 dh4 = ld4(P.db_hi + so), dl4 = ld4(P.db_lo + so);
+  const float4 ph4 = ld4(P.p_hi + mo), pl4 = ld4(P.p_lo + mo);
+  const float4 rh4 = ld4(P.r_hi + mo), rl4 = ld4(P.r_lo + mo);
+  const float qh[4] = {qh4.x, qh4.y, qh4.z, qh4.w}, ql[4] = {ql4.x, ql4.y, ql4.z, ql4.w};
+  const float dh[4] = {dh4.x, dh4.y, dh4.z, dh4.w}, dl[4] = {dl4.x, dl4.y, dl4.z, dl4.w};
+  const float ph[4] = {ph4.x, ph4.y, ph4.z, ph4.w}, pl[4] = {pl4.x, pl4.y, pl4.z, pl4.w};
+  const float rh[4] = {rh4.x, rh4.y, rh4.z, rh4.w}, rl[4] = {rl4.x, rl4.y, rl4.z, rl4.w};
+  float us[4];
+#pragma unroll
+  for (int e4 = 0; e4 < 4; ++e4) {
+    const ff t = ff_mul({ph[e4], pl[e4]}, {dh[e4], dl[e4]});
+    const ff db = ff_add({qh[e4], ql[e4]}, {-t.hi, -t.lo});
+    us[e4] = ff_mul({rh[e4], rl[e4]}, db).hi;
+  }
+  return make_float4(us[0], us[1], us[2], us[3]);
 }
 
-// Finishes step n for the modes of one unit given the full J u and F.
+// Finishes step n for the modes of one unit given the full J u and F.  The
+// adjoint state, coefficients and accumulators of a lane's four modes move
+// as float4 (per-unit state and per-mode arrays start on multiples of 4).
 template <int GM>
 __device__ void adj_post(const GradParams& P, const InstDev& I, const UnitDev& U, long long n,
                          const float4 (&Ju)[GM], const float4 (&F)[GM], int G, int lane) {
@@ -173,42 +184,82 @@ __device__ void adj_post(const GradParams& P, const InstDev& I, const UnitDev& U
   const float e = n < I.n_exc ? P.e_ext[I.e_off + n] : 0.f;
   const float yb = P.ybar[(long long)I.out_row * P.ybar_stride + n];
   const long long ro = (n - P.seg_base) * P.mode_floats + I.mode_off;
-  const int sf = P.state_floats;
+  const long long sf = P.state_floats;
   const bool accumulate = U.slab == 0;
 #pragma unroll
   for (int g = 0; g < GM; ++g) {
     const int k4 = lane + kWave * g;
     if (!(g < G && k4 < nc)) continue;
+    const int so = U.state_off + 4 * k4;
+    const int mo = I.mode_off + 4 * k4;
     const float4 x4 = ld4(P.rec_x + ro + 4 * k4), d4 = ld4(P.rec_d + ro + 4 * k4);
-    const float4 b4 = ld4(P.b_ext + I.mode_off + 4 * k4);
-    const float4 c4 = ld4(P.c_out + I.mode_off + 4 * k4);
+    const float4 b4 = ld4(P.b_ext + mo), c4 = ld4(P.c_out + mo);
+    const float4 qh4 = ld4(P.qb_hi + so), ql4 = ld4(P.qb_lo + so);
+    const float4 dh4 = ld4(P.db_hi + so), dl4 = ld4(P.db_lo + so);
+    const float4 ph4 = ld4(P.p_hi + mo), pl4 = ld4(P.p_lo + mo);
+    const float4 rh4 = ld4(P.r_hi + mo), rl4 = ld4(P.r_lo + mo);
+    const float4 mh4 = ld4(P.m_hi + mo), ml4 = ld4(P.m_lo + mo);
+    float4 ah[5], al[5];
+    if (accumulate) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        ah[k] = ld4(P.acc + (2 * k) * sf + so);
+        al[k] = ld4(P.acc + (2 * k + 1) * sf + so);
+      }
+    }
     const float xs[4] = {x4.x, x4.y, x4.z, x4.w}, ds[4] = {d4.x, d4.y, d4.z, d4.w};
     const float bs[4] = {b4.x, b4.y, b4.z, b4.w}, cs[4] = {c4.x, c4.y, c4.z, c4.w};
     const float js[4] = {Ju[g].x, Ju[g].y, Ju[g].z, Ju[g].w};
     const float fs[4] = {F[g].x, F[g].y, F[g].z, F[g].w};
+    const float qh[4] = {qh4.x, qh4.y, qh4.z, qh4.w}, ql[4] = {ql4.x, ql4.y, ql4.z, ql4.w};
+    const float dh[4] = {dh4.x, dh4.y, dh4.z, dh4.w}, dl[4] = {dl4.x, dl4.y, dl4.z, dl4.w};
+    const float phs[4] = {ph4.x, ph4.y, ph4.z, ph4.w}, pls[4] = {pl4.x, pl4.y, pl4.z, pl4.w};
+    const float rhs[4] = {rh4.x, rh4.y, rh4.z, rh4.w}, rls[4] = {rl4.x, rl4.y, rl4.z, rl4.w};
+    const float mhs[4] = {mh4.x, mh4.y, mh4.z, mh4.w}, mls[4] = {ml4.x, ml4.y, ml4.z, ml4.w};
+    float ahs[5][4], als[5][4];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      ahs[k][0] = ah[k].x; ahs[k][1] = ah[k].y; ahs[k][2] = ah[k].z; ahs[k][3] = ah[k].w;
+      als[k][0] = al[k].x; als[k][1] = al[k].y; als[k][2] = al[k].z; als[k][3] = al[k].w;
+    }
+    float oqh[4], oql[4], odh[4], odl[4];
 #pragma unroll
     for (int e4 = 0; e4 < 4; ++e4) {
-      const int so = U.state_off + 4 * k4 + e4;
-      const int mo = I.mode_off + 4 * k4 + e4;
-      ff db, u;
-      adj_pre(P, so, mo, db, u);
+      // db^{n+1} = qb^{n+1} - p db^{n+2},  u^n = r db^{n+1}
+      const ff t = ff_mul({phs[e4], pls[e4]}, {dh[e4], dl[e4]});
+      const ff db = ff_add({qh[e4], ql[e4]}, {-t.hi, -t.lo});
+      const ff u = ff_mul({rhs[e4], rls[e4]}, db);
       if (accumulate) {
-        acc_add(P.acc, 0, sf, so, ff_mul_f(db, xs[e4]));
-        acc_add(P.acc, 1, sf, so, ff_mul_f(db, -ds[e4]));
-        acc_add(P.acc, 2, sf, so, ff_mul_f(db, fmaf(bs[e4], e, -fs[e4])));
-        acc_add(P.acc, 3, sf, so, two_prod(yb, xs[e4]));
-        acc_add(P.acc, 4, sf, so, ff_mul_f(u, -fs[e4]));
+        const ff v[5] = {ff_mul_f(db, xs[e4]), ff_mul_f(db, -ds[e4]), ff_mul_f(db, fmaf(bs[e4], e, -fs[e4])),
+                         two_prod(yb, xs[e4]), ff_mul_f(u, -fs[e4])};
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const ff a = ff_add({ahs[k][e4], als[k][e4]}, v[k]);
+          ahs[k][e4] = a.hi;
+          als[k][e4] = a.lo;
+        }
       }
       // qb^n = ybar c + qb^{n+1} + m db^{n+1} - (J u)
-      ff qb = ldff(P.qb_hi, P.qb_lo, so);
-      qb = ff_add(qb, ff_mul(ldff(P.m_hi, P.m_lo, mo), db));
+      ff qb = {qh[e4], ql[e4]};
+      qb = ff_add(qb, ff_mul({mhs[e4], mls[e4]}, db));
       qb = ff_add(qb, two_prod(yb, cs[e4]));
       qb = ff_add(qb, {-js[e4], 0.f});
-      P.qb_hi[so] = qb.hi;
-      P.qb_lo[so] = qb.lo;
-      P.db_hi[so] = db.hi;
-      P.db_lo[so] = db.lo;
+      oqh[e4] = qb.hi;
+      oql[e4] = qb.lo;
+      odh[e4] = db.hi;
+      odl[e4] = db.lo;
     }
+    if (accumulate) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        st4(P.acc + (2 * k) * sf + so, make_float4(ahs[k][0], ahs[k][1], ahs[k][2], ahs[k][3]));
+        st4(P.acc + (2 * k + 1) * sf + so, make_float4(als[k][0], als[k][1], als[k][2], als[k][3]));
+      }
+    }
+    st4(P.qb_hi + so, make_float4(oqh[0], oqh[1], oqh[2], oqh[3]));
+    st4(P.qb_lo + so, make_float4(oql[0], oql[1], oql[2], oql[3]));
+    st4(P.db_hi + so, make_float4(odh[0], odh[1], odh[2], odh[3]));
+    st4(P.db_lo + so, make_float4(odl[0], odl[1], odl[2], odl[3]));
   }
 }
 
@@ -245,13 +296,7 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
         const int k4 = lane + kWave * g;
         if (wave == 0 && g < G && k4 < nc) {
           const float4 x4 = ld4(P.rec_x + ro + 4 * k4);
-          float us[4];
-          for (int e4 = 0; e4 < 4; ++e4) {
-            ff db, uu;
-            adj_pre(P, U.state_off + 4 * k4 + e4, I.mode_off + 4 * k4 + e4, db, uu);
-            us[e4] = uu.hi;
-          }
-          const float4 u4 = make_float4(us[0], us[1], us[2], us[3]);
+          const float4 u4 = adj_u4(P, U.state_off + 4 * k4, I.mode_off + 4 * k4);
           if (I.kind == KIND_VK) {
             st4(Xs + 4 * k4, x4);
             st4(Us + 4 * k4, u4);
