@@ -164,6 +164,10 @@ def run(args, stream=None):
     results = {}
     arms = [a for a in (("default", np.tile(prior_center(base), (args.test, 1))), ("proposal", th_prop))
             if a[0] in args.arms.split(",")]
+    # untimed warm-up of the fit path (the loss's FFT plans, first kernel
+    # launches), as the step benchmark's warm-up steps
+    fit.fit(y_tgt[:2], th_prop[:2], setup, args.steps, iters=1, lr=args.lr, tol=args.tol)
+    torch.cuda.synchronize()
     for arm, th0 in arms:
         torch.cuda.synchronize()
         t0 = time.time()
