@@ -221,6 +221,50 @@ def tensor_fit_rate(iters=4, starts=16):
     return res
 
 
+def single_instance_rates():
+    """One instance at a time, as in the paper's benchmark (Sec. 4.2, Fig. 2):
+    wall time of one modal_run over 1 s of audio at 44.1 kHz (the KC string:
+    0.5 s) after a 441-step warm-up, HIP events on the launch stream, and the
+    real-time factor (audio seconds per wall second); then the gradient of a
+    200/200-mode plate over 1 s (forward with checkpoints, recompute and
+    reverse sweep)."""
+    import torch
+    import workloads as W
+    from paper_2505_05940_amd import modal, physics
+    cases = [("KC string, 30 modes", physics.string_instance(W.string_kc(n_modes=30)), 22050)]
+    for n in (10, 50, 100):
+        cases.append((f"vK plate, {n}/{n} modes", physics.plate_instance(W.plate_sweep(n)), 44100))
+    for n in (10, 50, 100):
+        cases.append((f"Berger plate, {n} modes", physics.plate_berger_instance(W.plate_berger(n_t=n)), 44100))
+    out = []
+    for name, inst, steps in cases:
+        sim = modal.Sim([inst], 44100.0)
+        y = torch.empty((1, steps), device="cuda")
+        sim.run(441, out=y)
+        sim.reset()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        sim.run(steps, out=y)
+        b.record()
+        torch.cuda.synchronize()
+        t = a.elapsed_time(b) * 1e-3
+        out.append({"case": name, "audio_s": steps / 44100.0, "wall_s": t,
+                    "realtime_factor": steps / 44100.0 / t, "us_per_step": 1e6 * t / steps})
+        sim.close()
+    p200 = physics.plate_instance(W.plate_vk(n_t=200, family="sine", grid=None))
+    sim = modal.Sim([p200], 44100.0, flags=modal.FLAG_GRAD)
+    g = torch.full((1, 44100), 1e3, device="cuda")
+    sim.grad(441, g[:, :441].contiguous())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.grad(44100, g)
+    torch.cuda.synchronize()
+    grad_s = time.perf_counter() - t0
+    sim.close()
+    return {"runs": out, "gradient_200_modes_1s_wall_s": grad_s}
+
+
 def fit_wall_time():
     """Wall time to the target spectral loss: a proposal network is trained
     on 200 000 plates simulated by the dense path (60 epochs), then 64
@@ -294,6 +338,8 @@ def main():
     ap.add_argument("--dense-batch", type=int, default=65536)
     ap.add_argument("--no-linear", action="store_true",
                     help="skip the linear closed-form path measurement")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-instance real-time factors")
     ap.add_argument("--no-tensor-fit", action="store_true",
                     help="skip the coupling-tensor fit iteration timing")
     ap.add_argument("--no-fit", action="store_true",
@@ -416,6 +462,11 @@ def main():
         out["linear_path"] = linear_path(4096, 100, args.seed)
         print(f"[bench] linear path: {out['linear_path']['seconds']:.3f} s closed form, "
               f"{out['linear_path']['recursion_seconds']:.3f} s recursion", file=sys.stderr, flush=True)
+    if not args.no_single:
+        out["single_instance"] = single_instance_rates()
+        print("[bench] single instances: " + ", ".join(
+            f"{r['case']} {r['realtime_factor']:.1f}x" for r in out["single_instance"]["runs"]),
+            file=sys.stderr, flush=True)
     if not args.no_tensor_fit:
         out["tensor_fit"] = tensor_fit_rate()
         print(f"[bench] tensor fit: {out['tensor_fit']['one_start']['seconds_per_iteration']:.3f} s per "

@@ -339,6 +339,20 @@ int validate(const modal_desc* d) {
 // default).
 constexpr int kRunCkpt = 512;
 
+// A batch of at most one instance per CU whose dense tensors together stay
+// below this many bytes per step is bound by each step's latency, not by
+// HBM: it runs dense (no parity blocks), with 8 waves per workgroup, each
+// instance cut into slabs of about kLatencyRows in-plane rows (at most
+// kLatencyMaxSlabs, no more than CUs / batch, and only in batches of at most
+// kLatencyMaxSplitBatch instances), one slab per workgroup.
+// Measured on single sine-family plates: 100/100 modes step in 12.2 us this
+// way (15 slabs), against 82 us blocked on the byte-balanced plan; 50/50 in
+// 9.2 us against 39.6 us.
+constexpr double kLatencyBytes = 64.0 * 1048576.0;
+constexpr int kLatencyRows = 6;
+constexpr int kLatencyMaxSlabs = 16;
+constexpr int kLatencyMaxSplitBatch = 16;  // larger latency-bound batches keep instances whole
+
 // Per-step cost of the exchange and barrier of one slab of a split instance,
 // in streamed-byte units (release fence, arrival, wait, acquire and reading
 // every slab's partial force: microseconds of one wave's streaming time).
@@ -1184,8 +1198,21 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   std::vector<double> row_cost(d->batch), fixed_cost(d->batch);
   int red_floats = 0;
   std::vector<int> qs_of(d->batch, 1), J_of(d->batch, 1);
+  int dev0 = 0;
+  HIP_TRY(hipGetDevice(&dev0));
+  hipDeviceProp_t prop0;
+  HIP_TRY(hipGetDeviceProperties(&prop0, dev0));
+  bool latency = d->waves == 0 && d->max_workgroups == 0 && !(d->flags & MODAL_FLAG_SPLIT_ANY) &&
+                 d->batch <= prop0.multiProcessorCount;
+  if (latency) {
+    double dense = 0.0;
+    for (int b = 0; b < d->batch; ++b)
+      if (d->inst[b].kind == MODAL_KIND_VK) dense += 4.0 * d->inst[b].n_in * (double)d->inst[b].n_t * d->inst[b].n_t;
+    latency = dense <= kLatencyBytes;
+  }
   std::vector<BlockPlan> plans;
-  plan_blocks(d, plans);
+  if (!latency) plan_blocks(d, plans);
+  else plans.assign(d->batch, BlockPlan{});
   std::vector<int> jmap_pool;
   c->mode_slot.assign(d->batch, {});
   for (int b = 0; b < d->batch; ++b) {
@@ -1269,8 +1296,9 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   c->nw = d->waves == 0 ? 4 : d->waves;
   if (d->waves == 0 && d->batch <= prop.multiProcessorCount) {
     bool small = true;
-    for (int b = 0; b < d->batch && small; ++b)
-      small = row_cost[b] * (inst[b].kind == KIND_VK ? inst[b].nin : 1) < kMinSplitCost;
+    if (!latency)
+      for (int b = 0; b < d->batch && small; ++b)
+        small = row_cost[b] * (inst[b].kind == KIND_VK ? inst[b].nin : 1) < kMinSplitCost;
     int o8 = 0;
     if (small) HIP_TRY(step_occupancy(&o8, c->gm, 8, step_lds_bytes(8, red_floats)));
     if (o8 >= 1) c->nw = 8;
@@ -1320,7 +1348,35 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   std::vector<Unit> units;
   std::vector<int> bin_of;
   std::vector<double> load;
-  if (!plan_batch(d, row_cost, fixed_cost, total, n_bins, units, bin_of, load)) {
+  if (latency) {
+    // one slab per workgroup, instances cut into slabs of about kLatencyRows
+    // rows; only for a few instances: with many, the per-step exchanges of
+    // all their slabs cost more than the rows they spread (64 plates at
+    // 40/40 in 4 slabs each step in 16 us instead of 12)
+    const int cap_slabs = d->batch > kLatencyMaxSplitBatch
+                              ? 1
+                              : std::max(1, std::min(kLatencyMaxSlabs, prop.multiProcessorCount / d->batch));
+    for (int b = 0; b < d->batch; ++b) {
+      const int rows = inst[b].kind == KIND_VK ? inst[b].nin : 1;
+      const int S = inst[b].kind == KIND_VK
+                        ? std::max(1, std::min(cap_slabs, (rows + kLatencyRows / 2) / kLatencyRows))
+                        : 1;
+      for (int sl = 0; sl < S; ++sl) {
+        const int r0 = (int)((long long)rows * sl / S), r1 = (int)((long long)rows * (sl + 1) / S);
+        const double cost = (S > 1 ? kSplitSyncCost : 0.0) + fixed_cost[b] + (r1 - r0) * row_cost[b];
+        units.push_back({b, r0, r1, sl, cost});
+        bin_of.push_back((int)load.size());
+        load.push_back(cost);
+      }
+    }
+    if ((int)load.size() > n_bins) {
+      units.clear();
+      bin_of.clear();
+      load.clear();
+      latency = false;
+    }
+  }
+  if (!latency && !plan_batch(d, row_cost, fixed_cost, total, n_bins, units, bin_of, load)) {
     free_ctx(c);
     return fail(MODAL_EINVAL, "batch does not fit the workgroup budget");
   }

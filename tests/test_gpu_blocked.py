@@ -73,13 +73,15 @@ def test_blocked_ragged_batch(gpu, ragged_refs, max_wg, waves):
 
 
 def test_blocked_state_and_resume(gpu):
-    """State readback goes through the mode permutation; runs resume."""
+    """State readback goes through the mode permutation; runs resume.  (An
+    explicit wave count keeps the byte-balanced plan, which stores the
+    tensor parity-blocked; a lone small plate would otherwise run dense.)"""
     modal, physics = gpu
     wl = W.plate_vk(seed=210, n_t=37, n_in=21, family="sine", grid=None, n_steps=400)
     p = physics.plate_instance(wl)
     o = OI.plate_instance(wl)
     _say("case: blocked 37/21, state readback and resume")
-    sim = modal.Sim([p], 44100.0)
+    sim = modal.Sim([p], 44100.0, waves=4)
     assert sim.info()["blocked_instances"] == 1
     a = sim.run(250).cpu().numpy()
     b = sim.run(150).cpu().numpy()
