@@ -275,11 +275,15 @@ int modal_tf_grad(const double *coef, const int32_t *mode_off, int32_t batch, in
                   const double *omega, int32_t n_freq, const double *dL_dH, double *g_coef,
                   void *stream);
 
-/* Host-only preview of the work partition modal_init would make for `d`
- * with n_workgroups co-resident workgroups (validates d like modal_init; no
- * device calls): out[0] work units, [1] workgroups used, [2] planned cost of
- * the most loaded workgroup, [3] mean cost per workgroup (streamed-byte
- * units).  EINVAL if the batch cannot be partitioned. */
+/* Host-only preview of the byte-balanced work partition modal_init makes
+ * for `d` with n_workgroups co-resident workgroups (validates d like
+ * modal_init; no device calls): out[0] work units, [1] workgroups used, [2]
+ * planned cost of the most loaded workgroup, [3] mean cost per workgroup
+ * (streamed-byte units).  A latency-bound batch (at most one instance per
+ * CU, dense tensors under 64 MB per step, default waves and workgroups, no
+ * MODAL_FLAG_SPLIT_ANY) is planned by modal_init with one slab per
+ * workgroup instead, which this preview does not show.  EINVAL if the batch
+ * cannot be partitioned. */
 int modal_plan(const modal_desc *d, int32_t n_workgroups, int64_t out[4]);
 
 /* Message for the last failure on the calling thread ("" if none). */
