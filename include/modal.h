@@ -150,6 +150,14 @@ typedef struct {
  * FP64 (free response plus the excitation convolved with the impulse
  * response); MODAL_FLAG_GRAPH has no effect there.  A mode with a double
  * root keeps the batch on the recursion.
+ * Streaming path plans: a latency-bound batch (at most one instance per CU,
+ * dense tensors under 64 MB per step, waves and max_workgroups 0, no
+ * MODAL_FLAG_SPLIT_ANY) keeps its tensors dense, takes 8 waves per
+ * workgroup and, in batches of at most 16 instances, cuts each instance
+ * into slabs of about 6 in-plane rows, one per workgroup.  Any other batch
+ * is packed onto the co-resident workgroups by streamed bytes, with
+ * sine-family tensors stored parity-blocked (mode_class given, forward
+ * only).
  * Errors: EINVAL (NULL/size/kind/finite/symmetry), EUNSTABLE (a mode's
  * characteristic roots outside the unit circle; also gamma < 0 or, for TF,
  * omega <= gamma), ENOMEM, EHIP.  On error *out is NULL. */
