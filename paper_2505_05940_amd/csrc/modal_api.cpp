@@ -203,6 +203,13 @@ struct modal_ctx {
   long long ckpt_upto = 0;
   bool ckpt_broken = false;
   bool run_ckpt = false;  // the run being enqueued records checkpoints
+  // With them, while it fits kRecAllBytes, the whole trajectory (q and d per
+  // step, FP32 high parts, laid out like a segment's record): modal_grad then
+  // skips the segment recomputes too.  Valid for [0, rec_upto).
+  float* dRecAll = nullptr;
+  long long recall_cap = 0;  // steps the buffer holds
+  long long rec_upto = 0;
+  bool run_rec = false;
   bool tangent = false;
   // per-row (in-plane) gradient pools: rows of all VK instances
   int rows_total = 0;
@@ -261,7 +268,7 @@ void free_ctx(modal_ctx* c) {
                   c->dStep, c->dE,   c->dHd,   c->dCkpt,  c->dRec,  c->dAdj, c->dAcc,
                   c->dGPart, c->dGCtr, c->dShA, c->dShS2, c->dJmap, c->dRrec, c->dRacc,
                   c->dLinModes, c->dLinInit, c->dLinAmp, c->dLinSeg, c->dLinForced, c->dLinH,
-                  c->dLinTab, c->dUrec, c->dTrec, c->dTJobs};
+                  c->dLinTab, c->dUrec, c->dTrec, c->dTJobs, c->dRecAll};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -338,6 +345,8 @@ int validate(const modal_desc* d) {
 // Checkpoint spacing of forward runs in gradient contexts (modal_grad's
 // default).
 constexpr int kRunCkpt = 512;
+// Largest whole-trajectory record a gradient context keeps (bytes).
+constexpr double kRecAllBytes = 2.0 * 1073741824.0;
 
 // A batch of at most one instance per CU whose dense tensors together stay
 // below this many bytes per step is bound by each step's latency, not by
@@ -1620,6 +1629,11 @@ static int enqueue_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride
         P.ckpt = c->dCkpt;
         P.ckpt_every = kRunCkpt;
       }
+      if (c->run_rec) {
+        P.rec_x = c->dRecAll;
+        P.rec_d = c->dRecAll + (size_t)c->recall_cap * c->mode_floats;
+        P.rec_base = 0;
+      }
       HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
     }
     HIP_TRY(launch_advance(c->dStep, (int)k, s));
@@ -1673,6 +1687,23 @@ int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* s
       }
     }
   }
+  // and the whole trajectory, contiguous from step 0, while it fits
+  c->run_rec = false;
+  if (c->run_ckpt && c->steps <= c->rec_upto &&
+      (double)(c->steps + n_steps) * 2.0 * c->mode_floats * sizeof(float) <= kRecAllBytes) {
+    if (c->recall_cap >= c->steps + n_steps) {
+      c->run_rec = true;
+    } else if (c->steps == 0) {
+      if (c->dRecAll) HIP_TRY(hipFree(c->dRecAll));
+      c->dRecAll = nullptr;
+      c->recall_cap = 0;
+      c->rec_upto = 0;
+      int r = dalloc(&c->dRecAll, sizeof(float) * 2 * (size_t)n_steps * c->mode_floats);
+      if (r) return r;
+      c->recall_cap = n_steps;
+      c->run_rec = true;
+    }
+  }
   if (c->flags & MODAL_FLAG_GRAPH) {
     hipGraphExec_t exec = nullptr;
     for (auto& g : c->graphs)
@@ -1694,11 +1725,13 @@ int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* s
     }
     HIP_TRY(hipGraphLaunch(exec, s));
   } else {
-    const bool recorded = c->run_ckpt;
+    const bool recorded = c->run_ckpt, recorded_all = c->run_rec;
     int r = enqueue_run(c, n_steps, y, y_stride, s);
     c->run_ckpt = false;
+    c->run_rec = false;
     if (r) return r;
     if (recorded) c->ckpt_upto = std::max(c->ckpt_upto, c->steps + n_steps);
+    if (recorded_all) c->rec_upto = std::max(c->rec_upto, c->steps + n_steps);
   }
   c->steps += n_steps;
   if (c->flags & MODAL_FLAG_ASYNC) return MODAL_OK;
@@ -1779,7 +1812,8 @@ int modal_set_tensor(modal_ctx* c, int32_t b, const float* H, void* stream_) {
   HIP_TRY(hipMemcpy2DAsync(c->dH + D.h_off, sizeof(float) * D.ntp, H, sizeof(float) * D.nt,
                            sizeof(float) * D.nt, (size_t)D.nin * D.nt, hipMemcpyDefault, s));
   HIP_TRY(hipStreamSynchronize(s));
-  c->ckpt_upto = 0;  // recorded checkpoints belong to the old tensor
+  c->ckpt_upto = 0;  // recorded checkpoints and trajectory belong to the old tensor
+  c->rec_upto = 0;
   return MODAL_OK;
 }
 
@@ -1905,8 +1939,9 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   G.m_hi = F.m_hi; G.m_lo = F.m_lo; G.p_hi = F.p_hi; G.p_lo = F.p_lo;
   G.r_hi = F.r_hi; G.r_lo = F.r_lo;
   G.c_out = F.c_out; G.lam = F.lam; G.b_ext = F.b_ext; G.e_ext = F.e_ext;
-  G.rec_x = c->dRec;
-  G.rec_d = c->dRec + (size_t)K * mf;
+  // the whole trajectory recorded by the last runs, if it covers the steps,
+  // replaces the segment recomputes
+  const bool reuse_rec = reuse && c->dRecAll && c->rec_upto >= n_steps;
   G.mode_floats = mf;
   G.ybar = ybar;
   G.ybar_stride = y_stride;
@@ -1924,22 +1959,29 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   for (long long seg = nseg - 1; seg >= 0; --seg) {
     const long long s0 = seg * K;
     const int len = (int)std::min<long long>(K, n_steps - s0);
-    HIP_TRY(launch_restore(c->dCkpt, seg, mf, F.inst, F.unit, c->n_units, c->dState, sf, c->dStep, s0,
-                           c->dCtr, s));
-    StepParams P = c->P;
-    P.y = nullptr;
-    P.rec_x = c->dRec;
-    P.rec_d = c->dRec + (size_t)K * mf;
-    P.rec_base = s0;
-    P.n_steps = len;
-    HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
+    if (reuse_rec) {
+      G.rec_x = c->dRecAll + (size_t)s0 * mf;
+      G.rec_d = c->dRecAll + (size_t)(c->recall_cap + s0) * mf;
+    } else {
+      HIP_TRY(launch_restore(c->dCkpt, seg, mf, F.inst, F.unit, c->n_units, c->dState, sf, c->dStep, s0,
+                             c->dCtr, s));
+      StepParams P = c->P;
+      P.y = nullptr;
+      P.rec_x = c->dRec;
+      P.rec_d = c->dRec + (size_t)K * mf;
+      P.rec_base = s0;
+      P.n_steps = len;
+      HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
+      G.rec_x = c->dRec;
+      G.rec_d = c->dRec + (size_t)K * mf;
+    }
     G.seg_base = s0;
     G.seg_len = len;
     G.done_before = n_steps - s0 - len;
     HIP_TRY(launch_grad(G, c->gm, c->tangent, c->nw_grad[c->tangent], c->n_wg, c->grad_lds_v[c->tangent], s));
     if (rows_on) HIP_TRY(launch_row_sum(c->dRrec, len, c->rows_total, c->dRacc, s));
     if (tens_on)
-      HIP_TRY(launch_tensor_grad(c->dTJobs, (int)tjobs.size(), tj_nin, tj_nt, c->dRec, c->dUrec, c->dTrec, mf,
+      HIP_TRY(launch_tensor_grad(c->dTJobs, (int)tjobs.size(), tj_nin, tj_nt, G.rec_x, c->dUrec, c->dTrec, mf,
                                  c->rows_total, len, s));
   }
   r = modal_check(c, stream_);
