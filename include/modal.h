@@ -238,7 +238,9 @@ int modal_set_tangent(modal_ctx *c, int32_t inst, const float *Hd, void *stream)
  * records these checkpoints, every 512 steps, while modal_run steps it
  * forward from step 0; with ckpt_every 0 or 512, modal_grad then reuses them
  * for the first n_steps if they cover them, and skips its own forward pass
- * (same result, bit for bit).  modal_set_tensor voids them.
+ * (same result, bit for bit).  While it fits 2 GB, such a run also records
+ * the whole trajectory, and modal_grad then skips the segment recomputes
+ * too.  modal_set_tensor voids both.
  * Needs a context created with MODAL_FLAG_GRAD (else ESTATE).  Leaves the
  * context reset to its initial state.  Errors: EINVAL, ENOMEM, EHIP,
  * ENONFINITE, EHANG. */
