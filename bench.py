@@ -35,10 +35,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_b256.json")
 
 
 def kernel_hash() -> str:
-    """Hash of the step kernel's source with comments and blank space removed
-    (a change of code, not of comments, voids a traffic record)."""
+    """Hash of the step kernel's source and the headers it includes, with
+    comments and blank space removed (a change of code, not of comments,
+    voids a traffic record)."""
     import re
-    src = open(KERNEL_SRC).read()
+    d = os.path.dirname(KERNEL_SRC)
+    src = "".join(open(os.path.join(d, f)).read() for f in ("kernels.h", "device_common.h"))
+    src += open(KERNEL_SRC).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     src = re.sub(r"//[^\n]*", "", src)
     src = re.sub(r"\s+", " ", src)

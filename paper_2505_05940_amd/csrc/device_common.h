@@ -167,7 +167,10 @@ constexpr unsigned long long kBarrierTimeout = 400000000ull;  // 4 s
 __device__ inline bool wait_counter(unsigned int* ctr, unsigned int target, int* flags) {
   const unsigned long long t0 = wall_clock64();
   while (true) {
-    unsigned int v = __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    // relaxed polling: the caller's acquire fence after a successful wait
+    // orders the reads of the published partials, so the loop itself does no
+    // cache invalidation per poll
+    unsigned int v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((int)(v - target) >= 0) return true;
     if (__hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     if (wall_clock64() - t0 > kBarrierTimeout) {
