@@ -56,20 +56,24 @@ struct UnitDev {
 // row-reduction region of red_floats per wave.  A wave that has finished its
 // row sweep parks its partial force in the first ntp floats of its own region
 // (red_floats >= 2 ntp for every instance), where wave 0 sums them.
+// A workgroup that owns a single unit for the whole launch may also keep that
+// unit's state and its instance's per-mode coefficients resident in LDS: 13
+// arrays of res_stride floats after the reduction regions (X hi, X lo, d hi,
+// d lo, m hi, m lo, p hi, p lo, r hi, r lo, b, c, lambda).
+constexpr int kResArrays = 13;
 struct StepLds {
-  float *xs, *red;
+  float *xs, *red, *res;
   int* flag;
 };
-__host__ __device__ inline size_t step_lds_bytes(int nw, int red_floats) {
-  return sizeof(float) * ((size_t)kMaxModes + 4 + (size_t)nw * red_floats);
+__host__ __device__ inline size_t step_lds_bytes(int nw, int red_floats, int res_stride = 0) {
+  return sizeof(float) * ((size_t)kMaxModes + 4 + (size_t)nw * red_floats + (size_t)kResArrays * res_stride);
 }
 __host__ __device__ inline StepLds step_lds(float* base, int nw, int red_floats) {
-  (void)nw;
-  (void)red_floats;
   StepLds L;
   L.xs = base;
   L.flag = reinterpret_cast<int*>(base + kMaxModes);
   L.red = reinterpret_cast<float*>(L.flag + 4);
+  L.res = L.red + (size_t)nw * red_floats;
   return L;
 }
 
@@ -114,6 +118,10 @@ struct StepParams {
   int n_steps;              // steps of this launch
   int red_floats;           // LDS floats reserved for the reduction buffer
   int mode_floats;          // length of each per-mode array
+  // > 0: every workgroup owns exactly one unit, and holds its state and
+  // coefficients in LDS (kResArrays arrays of res_stride >= ntp floats) from
+  // the start of the launch, writing the state back at its end
+  int res_stride;
   // checkpoints of the float-float state at steps that are multiples of
   // ckpt_every: [slot][4][mode_floats] (X hi, X lo, d hi, d lo); NULL = none
   float* ckpt;

@@ -1,6 +1,6 @@
 // Persistent time-stepping kernel for batches of modal systems (gfx950).
 //
-// A workgroup (one or four 64-lane waves) owns a fixed list of work units
+// A workgroup (one, four or eight 64-lane waves) owns a fixed list of work units
 // for the whole launch; a unit is either a whole instance or a slab of
 // in-plane rows of a von Karman instance whose coupling tensor is split over
 // several workgroups; the waves of a workgroup share a unit's rows.  Per audio sample (paper: Sec. 3.2, modal oscillator
@@ -319,40 +319,44 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
   }
 }
 
-// Per-mode state update of the float4 groups owned by this lane.
+// Where one unit's state and its instance's per-mode coefficients live: in
+// global memory, or resident in LDS for the whole launch.
+struct ModeRefs {
+  float *xh, *xl, *dh, *dl;
+  const float *mh, *ml, *ph, *pl, *rh, *rl, *b, *c, *lam;
+};
+
+// Per-mode state update of the float4 groups owned by this lane; e is this
+// step's excitation sample.
 template <int GM>
-__device__ __forceinline__ void update_groups(const StepParams& P, const InstDev& I, int soff,
-                                              const float4 (&F)[GM], long long n,
-                                              int G, int lane) {
-  const int nc = I.ntp >> 2;
-  float e = 0.f;
-  if (n < I.n_exc) e = P.e_ext[I.e_off + n];
+__device__ __forceinline__ void update_groups(const ModeRefs& M, int nc, float e,
+                                              const float4 (&F)[GM], int G, int lane,
+                                              int* flags) {
   bool bad = false;
 #pragma unroll
   for (int g = 0; g < GM; ++g) {
     const int k4 = lane + kWave * g;
     if (g < G && k4 < nc) {
-      const int so = soff + 4 * k4;
-      const int mo = I.mode_off + 4 * k4;
-      float4 xh = ld4(P.x_hi + so), xl = ld4(P.x_lo + so);
-      float4 dh = ld4(P.d_hi + so), dl = ld4(P.d_lo + so);
-      const float4 mh = ld4(P.m_hi + mo), ml = ld4(P.m_lo + mo);
-      const float4 ph = ld4(P.p_hi + mo), pl = ld4(P.p_lo + mo);
-      const float4 rh = ld4(P.r_hi + mo), rl = ld4(P.r_lo + mo);
-      const float4 b = ld4(P.b_ext + mo);
+      const int o = 4 * k4;
+      float4 xh = ld4(M.xh + o), xl = ld4(M.xl + o);
+      float4 dh = ld4(M.dh + o), dl = ld4(M.dl + o);
+      const float4 mh = ld4(M.mh + o), ml = ld4(M.ml + o);
+      const float4 ph = ld4(M.ph + o), pl = ld4(M.pl + o);
+      const float4 rh = ld4(M.rh + o), rl = ld4(M.rl + o);
+      const float4 b = ld4(M.b + o);
       const float4 f = F[g];
       ff_step(xh.x, xl.x, dh.x, dl.x, mh.x, ml.x, ph.x, pl.x, rh.x, rl.x, fmaf(b.x, e, -f.x));
       ff_step(xh.y, xl.y, dh.y, dl.y, mh.y, ml.y, ph.y, pl.y, rh.y, rl.y, fmaf(b.y, e, -f.y));
       ff_step(xh.z, xl.z, dh.z, dl.z, mh.z, ml.z, ph.z, pl.z, rh.z, rl.z, fmaf(b.z, e, -f.z));
       ff_step(xh.w, xl.w, dh.w, dl.w, mh.w, ml.w, ph.w, pl.w, rh.w, rl.w, fmaf(b.w, e, -f.w));
       bad |= !(isfinite(xh.x) && isfinite(xh.y) && isfinite(xh.z) && isfinite(xh.w));
-      st4(P.x_hi + so, xh);
-      st4(P.x_lo + so, xl);
-      st4(P.d_hi + so, dh);
-      st4(P.d_lo + so, dl);
+      st4(M.xh + o, xh);
+      st4(M.xl + o, xl);
+      st4(M.dh + o, dh);
+      st4(M.dl + o, dl);
     }
   }
-  if (__any(bad) && lane == 0) atomicOr(&P.flags[1], 1);
+  if (__any(bad) && lane == 0) atomicOr(&flags[1], 1);
 }
 
 // GM: float4 column groups per lane the launch supports (modes <= 256 GM).
@@ -360,7 +364,13 @@ __device__ __forceinline__ void update_groups(const StepParams& P, const InstDev
 // each sweeping its share with its own LDS reduction region; the per-wave
 // partial forces are summed through those regions by wave 0, which also owns
 // the output, the exchange with other workgroups and the state update.
-template <int GM, int NW>
+// RES: each workgroup owns exactly one unit, whose state and coefficients
+// wave 0 copies to LDS before the first step and whose state it writes back
+// after the last, so that a step's output, update and recording touch no
+// global memory besides the excitation sample and the output (small,
+// latency-bound launches, where each global round trip is a large part of a
+// step).  Only wave 0 reads or writes these arrays, so they need no barrier.
+template <int GM, int NW, bool RES>
 __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
   extern __shared__ float4 lds4[];
   StepLds L = step_lds(reinterpret_cast<float*>(lds4), NW, P.red_floats);
@@ -372,28 +382,96 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
   const int u1 = P.wg_begin[blockIdx.x + 1];
   const long long base = *P.step_base;
 
+  auto refs = [&](const UnitDev& U, const InstDev& I) {
+    ModeRefs M;
+    if constexpr (RES) {
+      float* R = L.res;
+      const int S = P.res_stride;
+      M.xh = R;
+      M.xl = R + S;
+      M.dh = R + 2 * S;
+      M.dl = R + 3 * S;
+      M.mh = R + 4 * S;
+      M.ml = R + 5 * S;
+      M.ph = R + 6 * S;
+      M.pl = R + 7 * S;
+      M.rh = R + 8 * S;
+      M.rl = R + 9 * S;
+      M.b = R + 10 * S;
+      M.c = R + 11 * S;
+      M.lam = R + 12 * S;
+    } else {
+      M.xh = P.x_hi + U.state_off;
+      M.xl = P.x_lo + U.state_off;
+      M.dh = P.d_hi + U.state_off;
+      M.dl = P.d_lo + U.state_off;
+      M.mh = P.m_hi + I.mode_off;
+      M.ml = P.m_lo + I.mode_off;
+      M.ph = P.p_hi + I.mode_off;
+      M.pl = P.p_lo + I.mode_off;
+      M.rh = P.r_hi + I.mode_off;
+      M.rl = P.r_lo + I.mode_off;
+      M.b = P.b_ext + I.mode_off;
+      M.c = P.c_out + I.mode_off;
+      M.lam = P.lam + I.mode_off;
+    }
+    return M;
+  };
+  // resident state: copy in before the first step, write back after the last
+  // (or when a barrier gives up); the host sizes res_stride >= ntp
+  auto res_copy = [&](bool in) {
+    if (!RES || wave != 0 || u1 <= u0) return;
+    const UnitDev U = P.unit[u0];
+    const InstDev I = P.inst[U.inst];
+    const int nc = I.ntp >> 2;
+    float* R = L.res;
+    const int S = P.res_stride;
+    float* gs[4] = {P.x_hi + U.state_off, P.x_lo + U.state_off, P.d_hi + U.state_off,
+                    P.d_lo + U.state_off};
+    const float* gc[9] = {P.m_hi, P.m_lo, P.p_hi, P.p_lo, P.r_hi, P.r_lo, P.b_ext, P.c_out, P.lam};
+    for (int k4 = lane; k4 < nc; k4 += kWave) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (in)
+          st4(R + a * S + 4 * k4, ld4(gs[a] + 4 * k4));
+        else
+          st4(gs[a] + 4 * k4, ld4(R + a * S + 4 * k4));
+      }
+      if (in) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) st4(R + (4 + a) * S + 4 * k4, ld4(gc[a] + I.mode_off + 4 * k4));
+      }
+    }
+  };
+  res_copy(true);
+
   for (int s = 0; s < P.n_steps; ++s) {
     const long long n = base + s;
     // ---------------- phase 1: output, force, and update of whole units
     for (int u = u0; u < u1; ++u) {
       const UnitDev U = P.unit[u];
       const InstDev I = P.inst[U.inst];
+      const ModeRefs M = refs(U, I);
       const int nc = I.ntp >> 2;
       const int G = (nc + kWave - 1) / kWave;
       float spart = 0.f;
+      // the excitation sample is fetched first so that its latency overlaps
+      // the force evaluation
+      float e = 0.f;
+      if (wave == 0 && n < I.n_exc) e = P.e_ext[I.e_off + n];
       if (wave == 0) {
         float ypart = 0.f;
 #pragma unroll
         for (int g = 0; g < GM; ++g) {
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc) {
-            const float4 xh = ld4(P.x_hi + U.state_off + 4 * k4);
-            const float4 c = ld4(P.c_out + I.mode_off + 4 * k4);
+            const float4 xh = ld4(M.xh + 4 * k4);
+            const float4 c = ld4(M.c + 4 * k4);
             ypart += dot4(c, xh);
             if (I.kind == KIND_VK) {
               st4(Xs + 4 * k4, xh);
             } else if (I.kind == KIND_TENSION) {
-              const float4 l = ld4(P.lam + I.mode_off + 4 * k4);
+              const float4 l = ld4(M.lam + 4 * k4);
               const float4 lx = make_float4(l.x * xh.x, l.y * xh.y, l.z * xh.z, l.w * xh.w);
               spart += dot4(lx, xh);
             }
@@ -407,11 +485,10 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
             for (int g = 0; g < GM; ++g) {
               const int k4 = lane + kWave * g;
               if (g < G && k4 < nc) {
-                const int so = U.state_off + 4 * k4;
-                st4(cp + 4 * k4, ld4(P.x_hi + so));
-                st4(cp + P.mode_floats + 4 * k4, ld4(P.x_lo + so));
-                st4(cp + 2 * P.mode_floats + 4 * k4, ld4(P.d_hi + so));
-                st4(cp + 3 * P.mode_floats + 4 * k4, ld4(P.d_lo + so));
+                st4(cp + 4 * k4, ld4(M.xh + 4 * k4));
+                st4(cp + P.mode_floats + 4 * k4, ld4(M.xl + 4 * k4));
+                st4(cp + 2 * P.mode_floats + 4 * k4, ld4(M.dh + 4 * k4));
+                st4(cp + 3 * P.mode_floats + 4 * k4, ld4(M.dl + 4 * k4));
               }
             }
           }
@@ -420,9 +497,8 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
             for (int g = 0; g < GM; ++g) {
               const int k4 = lane + kWave * g;
               if (g < G && k4 < nc) {
-                const int so = U.state_off + 4 * k4;
-                st4(P.rec_x + ro + 4 * k4, ld4(P.x_hi + so));
-                st4(P.rec_d + ro + 4 * k4, ld4(P.d_hi + so));
+                st4(P.rec_x + ro + 4 * k4, ld4(M.xh + 4 * k4));
+                st4(P.rec_d + ro + 4 * k4, ld4(M.dh + 4 * k4));
               }
             }
           }
@@ -461,15 +537,15 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
         for (int g = 0; g < GM; ++g) {
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc) {
-            const float4 xh = ld4(P.x_hi + U.state_off + 4 * k4);
-            const float4 l = ld4(P.lam + I.mode_off + 4 * k4);
+            const float4 xh = ld4(M.xh + 4 * k4);
+            const float4 l = ld4(M.lam + 4 * k4);
             Fa[g] = make_float4(l.x * xh.x * S, l.y * xh.y * S, l.z * xh.z * S, l.w * xh.w * S);
           }
         }
       }
       if (wave == 0) {
         if (I.nslab == 1) {
-          update_groups<GM>(P, I, U.state_off, Fa, n, G, lane);
+          update_groups<GM>(M, nc, e, Fa, G, lane, P.flags);
         } else {
           float* dst = P.part + I.part_off + ((long long)(n & 1) * I.nslab + U.slab) * I.ntp;
 #pragma unroll
@@ -496,11 +572,17 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
         if (lane == 0) L.flag[0] = ok ? 1 : 0;
       }
       __syncthreads();
-      if (L.flag[0] == 0) return;  // every wave leaves together
+      if (L.flag[0] == 0) {  // every wave leaves together
+        res_copy(false);
+        return;
+      }
       if (wave == 0) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const ModeRefs M = refs(U, I);
         const int nc = I.ntp >> 2;
         const int G = (nc + kWave - 1) / kWave;
+        float e = 0.f;
+        if (n < I.n_exc) e = P.e_ext[I.e_off + n];
         const float* src = P.part + I.part_off + (long long)(n & 1) * I.nslab * I.ntp;
         float4 F[GM];
 #pragma unroll
@@ -511,11 +593,12 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
             for (int t = 0; t < I.nslab; ++t)
               F[g] = add4(F[g], ld4(src + (long long)t * I.ntp + 4 * k4));
         }
-        update_groups<GM>(P, I, U.state_off, F, n, G, lane);
+        update_groups<GM>(M, nc, e, F, G, lane, P.flags);
       }
       __syncthreads();  // flag reused
     }
   }
+  res_copy(false);
 }
 
 __global__ void advance_kernel(long long* step_base, int n_steps) {
@@ -564,15 +647,25 @@ __global__ void check_kernel(const float* H, const InstDev* inst, int* out) {
 // kernels' symbols local to this file).
 namespace modal {
 // gm: float4 column groups per lane needed by the widest instance (1, 2 or
-// 4); nw: waves per workgroup (1 or 4).
+// 4); nw: waves per workgroup (1, 4 or 8); P.res_stride > 0 selects the
+// variant with LDS-resident state (four or eight waves, one unit per
+// workgroup).
 hipError_t launch_step(const StepParams& P, int gm, int nw, int n_wg, size_t lds_bytes, hipStream_t s) {
-#define SL(G, W) hipLaunchKernelGGL((step_kernel<G, W>), dim3(n_wg), dim3(kWave * W), lds_bytes, s, P)
-  if (nw == 1) {
-    if (gm <= 1) SL(1, 1); else if (gm <= 2) SL(2, 1); else SL(4, 1);
+#define SL(G, W, R) hipLaunchKernelGGL((step_kernel<G, W, R>), dim3(n_wg), dim3(kWave * W), lds_bytes, s, P)
+  if (P.res_stride > 0) {
+    if (nw == 8) {
+      if (gm <= 1) SL(1, 8, true); else if (gm <= 2) SL(2, 8, true); else SL(4, 8, true);
+    } else if (nw == 4) {
+      if (gm <= 1) SL(1, 4, true); else if (gm <= 2) SL(2, 4, true); else SL(4, 4, true);
+    } else {
+      return hipErrorInvalidValue;  // resident launches use four or eight waves
+    }
+  } else if (nw == 1) {
+    if (gm <= 1) SL(1, 1, false); else if (gm <= 2) SL(2, 1, false); else SL(4, 1, false);
   } else if (nw == 8) {
-    if (gm <= 1) SL(1, 8); else if (gm <= 2) SL(2, 8); else SL(4, 8);
+    if (gm <= 1) SL(1, 8, false); else if (gm <= 2) SL(2, 8, false); else SL(4, 8, false);
   } else {
-    if (gm <= 1) SL(1, 4); else if (gm <= 2) SL(2, 4); else SL(4, 4);
+    if (gm <= 1) SL(1, 4, false); else if (gm <= 2) SL(2, 4, false); else SL(4, 4, false);
   }
 #undef SL
   return hipGetLastError();
@@ -585,22 +678,36 @@ hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out
   hipLaunchKernelGGL(check_kernel, dim3(64, batch), dim3(256), 0, s, H, inst, out);
   return hipGetLastError();
 }
-hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes) {
-#define SO(G, W) \
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<G, W>, kWave * W, lds_bytes)
+hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes, bool res) {
+#define SO(G, W, R) \
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<G, W, R>, kWave * W, lds_bytes)
+  if (res) {
+    if (nw == 8) {
+      if (gm <= 1) SO(1, 8, true);
+      if (gm <= 2) SO(2, 8, true);
+      SO(4, 8, true);
+    }
+    if (nw == 4) {
+      if (gm <= 1) SO(1, 4, true);
+      if (gm <= 2) SO(2, 4, true);
+      SO(4, 4, true);
+    }
+    *blocks_per_cu = 0;
+    return hipSuccess;
+  }
   if (nw == 1) {
-    if (gm <= 1) SO(1, 1);
-    if (gm <= 2) SO(2, 1);
-    SO(4, 1);
+    if (gm <= 1) SO(1, 1, false);
+    if (gm <= 2) SO(2, 1, false);
+    SO(4, 1, false);
   }
   if (nw == 8) {
-    if (gm <= 1) SO(1, 8);
-    if (gm <= 2) SO(2, 8);
-    SO(4, 8);
+    if (gm <= 1) SO(1, 8, false);
+    if (gm <= 2) SO(2, 8, false);
+    SO(4, 8, false);
   }
-  if (gm <= 1) SO(1, 4);
-  if (gm <= 2) SO(2, 4);
-  SO(4, 4);
+  if (gm <= 1) SO(1, 4, false);
+  if (gm <= 2) SO(2, 4, false);
+  SO(4, 4, false);
 #undef SO
 }
 }  // namespace modal
