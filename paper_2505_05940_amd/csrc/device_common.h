@@ -67,10 +67,26 @@ __device__ __forceinline__ void ff_step(float& xh, float& xl, float& dh, float& 
 }
 
 // ------------------------------------------------------------------ helpers
+// Data-parallel move between lanes of a 16-lane row (DPP control word C).
+template <int C>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), C, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+// Sum over the 64 lanes of a wave (all lanes active), the same on every lane.
+// Within each 16-lane row four DPP exchanges (partner lane ^1, ^2, the mirror
+// within 8 lanes, the mirror within 16) leave the row's sum on all its lanes,
+// identical bits on each since every pairing is symmetric; the four row sums
+// are then read out and added.  No LDS crossbar round trips, unlike a
+// shuffle-based butterfly.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 __device__ __forceinline__ float4 f4(float v) { return make_float4(v, v, v, v); }
 __device__ __forceinline__ float4 fma4(float4 a, float b, float4 c) {
