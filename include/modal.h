@@ -195,10 +195,13 @@ int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
  * and [2], [8], [9] are 0), 2 linear closed form,
  * [11] FP32 operations of the force per step (sum over VK instances of
  * 2 n_in n_t^2 + 4 n_in n_t), [12] instances stored parity-blocked,
- * [13] dense-equivalent tensor bytes per step (sum of 4 n_in n_t^2).
+ * [13] dense-equivalent tensor bytes per step (sum of 4 n_in n_t^2),
+ * [14] floats per LDS-resident array when every workgroup owns one unit and
+ * keeps its state and coefficients in LDS for a whole launch (latency-bound
+ * plans), else 0.
  * [3] counts the entries of the stored representation: for a blocked
  * instance, 4 bytes per entry of its stored blocks without padding. */
-int modal_info(const modal_ctx *c, int64_t info[14]);
+int modal_info(const modal_ctx *c, int64_t info[15]);
 
 void modal_destroy(modal_ctx *c);
 

@@ -2095,7 +2095,7 @@ int modal_get_state(modal_ctx* c, double* x, double* xm1, void* stream_) {
   return MODAL_OK;
 }
 
-int modal_info(const modal_ctx* c, int64_t info[14]) {
+int modal_info(const modal_ctx* c, int64_t info[15]) {
   if (!c || !info) return fail(MODAL_EINVAL, "NULL argument");
   info[0] = c->n_wg;
   info[1] = c->n_units;
@@ -2111,6 +2111,7 @@ int modal_info(const modal_ctx* c, int64_t info[14]) {
   info[11] = c->flops;
   info[12] = c->n_blocked;
   info[13] = c->shared ? c->coupling_bytes : c->dense_bytes;
+  info[14] = c->res_stride;
   return MODAL_OK;
 }
 

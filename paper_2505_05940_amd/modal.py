@@ -317,12 +317,12 @@ class Sim:
         return x, xm
 
     def info(self):
-        v = (C.c_int64 * 14)()
+        v = (C.c_int64 * 15)()
         _check(lib.modal_info(self._ctx, v))
         keys = ("workgroups", "units", "split_instances", "coupling_bytes_per_step",
                 "padded_bytes_per_step", "steps", "lds_bytes", "workgroups_per_cu",
                 "plan_makespan", "plan_mean", "path", "flops_per_step", "blocked_instances",
-                "dense_bytes_per_step")
+                "dense_bytes_per_step", "resident_floats")
         out = dict(zip(keys, list(v)))
         out["shared"] = int(out["path"] == 1)  # 0 recursion, 1 shared tensor, 2 linear closed form
         return out
