@@ -154,7 +154,7 @@ typedef struct {
  * dense tensors under 64 MB per step, waves and max_workgroups 0, no
  * MODAL_FLAG_SPLIT_ANY) keeps its tensors dense, takes 8 waves per
  * workgroup and, in batches of at most 16 instances, cuts each instance
- * into slabs of about 6 in-plane rows, one per workgroup.  Any other batch
+ * into slabs of about 8 in-plane rows, one per workgroup.  Any other batch
  * is packed onto the co-resident workgroups by streamed bytes, with
  * sine-family tensors stored parity-blocked (mode_class given, forward
  * only).

@@ -355,11 +355,13 @@ constexpr double kRecAllBytes = 2.0 * 1073741824.0;
 // instance cut into slabs of about kLatencyRows in-plane rows (at most
 // kLatencyMaxSlabs, no more than CUs / batch, and only in batches of at most
 // kLatencyMaxSplitBatch instances), one slab per workgroup.
-// Measured on single sine-family plates: 100/100 modes step in 12.2 us this
-// way (15 slabs), against 82 us blocked on the byte-balanced plan; 50/50 in
-// 9.2 us against 39.6 us.
+// Measured on single sine-family plates: 100/100 modes step in 11.0 us this
+// way (13 slabs), against 82 us blocked on the byte-balanced plan; 50/50 in
+// 9.1 us against 39.6 us.  About 8 rows, one per wave, was the best slab size
+// of 5, 6, 8 and 10 (100/100: 13.2, 11.8, 11.0, 13.5 us): smaller slabs add
+// workgroups to every step's exchange, larger ones give some waves two rows.
 constexpr double kLatencyBytes = 64.0 * 1048576.0;
-constexpr int kLatencyRows = 6;
+constexpr int kLatencyRows = 8;
 constexpr int kLatencyMaxSlabs = 16;
 constexpr int kLatencyMaxSplitBatch = 16;  // larger latency-bound batches keep instances whole
 
