@@ -11,8 +11,12 @@ eye: modes and eigenvalues (Sec. 3, eigenvalue problem), the in-plane (Airy)
 eigenpairs, the coupling tensor H by quadrature (coupling-coefficient
 equations), the modal ODE coefficients, the Stormer-Verlet and
 transfer-function recursions (Sec. 3.2), the tension-modulated and von Karman
-modal forces (Sec. 3.1), and the reverse-mode gradient of the time loop.
+modal forces (Sec. 3.1), the reverse-mode gradient of the time loop, and the
+spectral loss, its hand-written gradient and the log-mel features (Sec. 4.3).
 
-Functions whose values no test pins independently are marked
-"parity unpinned" in their docstrings.
+Every function is pinned by a CPU test against something other than itself
+(textbook frequencies and decay rates, forces computed in physical space,
+closed forms, brute force, complex-step and difference derivatives, direct
+DFT sums).  A function without such a pin would say "parity unpinned" in its
+docstring; none does.
 """

@@ -107,7 +107,8 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None, full_tensor=False):
     """Gradients of L with dL/dy^n = ybar[n].
 
     Returns dict: m, p, r (per mode), x0, xm1 (per mode), c (per mode),
-    scale (force scale s, the nonlinearity's prefactor), theta (if Hdot),
+    scale (force scale s, the nonlinearity's prefactor), theta (if Hdot;
+    Hdot may also be a list of tangent tensors, one theta per entry),
     and for a von Karman instance row (per in-plane mode n): dL/d log s_n for
     a factor s_n on row n of the scaled tensor.  That factor scales V_n and
     eta_n together, so the force term eta_n V_n goes as s_n^2 and
@@ -122,7 +123,10 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None, full_tensor=False):
     qb = np.zeros(n)
     db_next = np.zeros(n)  # db^{n+2}
     gm, gp, gr, gc = (np.zeros(n) for _ in range(4))
-    gs, gth = 0.0, 0.0
+    gs = 0.0
+    many = isinstance(Hdot, (list, tuple))
+    Hdots = list(Hdot) if many else ([] if Hdot is None else [Hdot])
+    gth = np.zeros(len(Hdots))
     vk = inst["kind"] == "vk"
     grow = np.zeros(inst["Ht"].shape[0]) if vk else None
     gH = np.zeros(inst["Ht"].shape) if (vk and full_tensor) else None
@@ -143,17 +147,18 @@ def reverse(inst, n_steps, fs, ybar, scheme="sv", Hdot=None, full_tensor=False):
                 eta, w = V @ X, V @ u
                 for i in range(n_in):
                     gH[i] -= np.outer(w[i] * X + eta[i] * u, X)
-        if Hdot is not None:
-            n_in = Hdot.shape[0]
+        for j, Hd in enumerate(Hdots):
+            n_in = Hd.shape[0]
             V = (inst["Ht"].reshape(n_in * n, n) @ X).reshape(n_in, n)
-            Vd = (Hdot.reshape(n_in * n, n) @ X).reshape(n_in, n)
+            Vd = (Hd.reshape(n_in * n, n) @ X).reshape(n_in, n)
             eta, etad = V @ X, Vd @ X
             dF = etad @ V + eta @ Vd
-            gth -= u @ dF
+            gth[j] -= u @ dF
         qb = ybar[k] * c + qb + m * db - _jvp(inst, X, u)
         db_next = db
     d0b = -p * db_next  # d^0 only feeds d^1
-    return dict(m=gm, p=gp, r=gr, c=gc, x0=qb + d0b, xm1=-d0b, scale=gs, theta=gth, row=grow, H=gH)
+    theta = list(gth) if many else (float(gth[0]) if Hdots else 0.0)
+    return dict(m=gm, p=gp, r=gr, c=gc, x0=qb + d0b, xm1=-d0b, scale=gs, theta=theta, row=grow, H=gH)
 
 
 def sv_omega_gamma_grads(g, omega, gamma, T):
