@@ -50,3 +50,32 @@ def plate_from_theta(fit, theta):
                                        rr * min(Lx, Ly))
     cw = excitation.plate_output(m, q, Lx, Ly, fit["out"][0] * Lx, fit["out"][1] * Ly)
     return dict(kind="vk", omega=omega, gamma=gamma, lam=lam, Ht=Ht, x0=x0, xm1=x0.copy(), c=cw)
+
+
+def theta_gradient(fit, theta, n_steps, fs, ybar, h_rel=1e-6):
+    """dL/dtheta for a loss with dL/dy^n = ybar[n], by the chain rule: the
+    reverse recursion of the time loop (``adjoint.reverse``) gives the
+    gradients with respect to omega, gamma, q^0, q^-1, c and the tensor
+    directions; the derivatives of those pieces with respect to each theta_j
+    are central differences of ``plate_from_theta`` at a relative step h_rel
+    (smooth maps with no time loop in them).  The tensor's derivative enters
+    as one tangent tensor per parameter."""
+    from . import adjoint
+    theta = np.asarray(theta, dtype=float)
+    inst = plate_from_theta(fit, theta)
+    keys = ("omega", "gamma", "x0", "c", "Ht")
+    dpiece = []
+    for j in range(len(theta)):
+        e = h_rel * theta[j]
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += e
+        tm[j] -= e
+        a, b = plate_from_theta(fit, tp), plate_from_theta(fit, tm)
+        dpiece.append({k: (a[k] - b[k]) / (2.0 * e) for k in keys})
+    g = adjoint.reverse(inst, n_steps, fs, np.asarray(ybar, dtype=float),
+                        Hdot=[d["Ht"] for d in dpiece])
+    g_omega, g_gamma = adjoint.sv_omega_gamma_grads(g, inst["omega"], inst["gamma"], 1.0 / fs)
+    return np.array([
+        np.sum(g_omega * d["omega"]) + np.sum(g_gamma * d["gamma"])
+        + np.sum((g["x0"] + g["xm1"]) * d["x0"]) + np.sum(g["c"] * d["c"]) + g["theta"][j]
+        for j, d in enumerate(dpiece)])

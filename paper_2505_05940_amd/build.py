@@ -46,12 +46,13 @@ def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = []
     srcs = [("step_kernel.hip", True), ("grad_kernel.hip", True), ("shared_kernel.hip", True),
             ("linear_kernel.hip", True), ("tf_kernel.hip", True),
             ("modal_api.cpp", True),
             ("mlp_kernels.hip", True), ("mlp_api.cpp", True), ("coupling_host.cpp", False)]
-    for src, hip in srcs:
+
+    def compile_one(item):
+        src, hip = item
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         path = os.path.join(CSRC, src)
         if hip:
@@ -62,7 +63,12 @@ def build(verbose: bool = False) -> str:
         r = _run(cmd)
         if verbose and (r.stdout or r.stderr):
             sys.stderr.write(r.stdout + r.stderr)
-        objs.append(obj)
+        return obj
+
+    # the translation units compile independently (at most 8 at a time)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-pthread"])
     os.replace(tmp, LIB)

@@ -234,11 +234,17 @@ def from_unconstrained(z):
 
 
 def fit(target: torch.Tensor, theta0, setup: PlateSetup, n_steps: int, iters: int = 100,
-        lr: float = 0.05, tol: float = 0.1, loss_fn=mrstft_loss, callback=None):
+        lr: float = 0.05, tol: float = 0.1, loss_fn=mrstft_loss, callback=None, free=None):
     """Adam with a one-cycle cosine schedule on unconstrained parameters,
     batched over rows of theta0.  A row that reaches tol is frozen there;
-    the loop stops when every row has.  Returns (theta [B,5] and losses [B]
-    of each row's best iterate, iterations, loss history)."""
+    the loop stops when every row has.  ``free``: the indices of the
+    parameters that are fitted (default all five); the others keep their
+    values from theta0 (their gradients are dropped before each step).
+    Returns (theta [B,5] and losses [B] of each row's best iterate,
+    iterations, loss history)."""
+    fixed = np.ones(5, bool)
+    fixed[list(range(5)) if free is None else list(free)] = False
+    fixed_t = torch.from_numpy(fixed)
     z = torch.tensor(np.stack([to_unconstrained(t) for t in np.atleast_2d(theta0)]),
                      dtype=torch.float64, requires_grad=True)
     B = z.shape[0]
@@ -270,6 +276,8 @@ def fit(target: torch.Tensor, theta0, setup: PlateSetup, n_steps: int, iters: in
         if frozen.all():
             return best_th, best_L, it, hist
         L.sum().backward()
+        if fixed.any():
+            z.grad[:, fixed_t] = 0.0
         opt.step()
         with torch.no_grad():  # frozen rows stay where they reached tol
             fz = torch.from_numpy(frozen)

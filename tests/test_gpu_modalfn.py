@@ -1,0 +1,134 @@
+"""The differentiable path end to end: ``fit.ModalFn`` (forward: modal_run;
+backward: modal_grad and the FP64 chain rule to theta = (T0^, D^, a, d1^,
+d3^)) and the fit driver ``fit.fit`` (paper, Sec. 4.3: parameters fitted by
+propagating gradients through the time integrator).
+
+Gradients are compared in log-parameter units, theta_j dL/dtheta_j."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint as OA
+from oracle import params as OP
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _setup(fw):
+    from paper_2505_05940_amd import fit
+    return fit.PlateSetup(n_t=fw["n_t"], n_in=fw["n_in"], area=fw["area"], h=fw["h"], nu=fw["nu"],
+                          base_aspect=fw["base_aspect"], strike=fw["strike"], out=fw["out"],
+                          proj_grid=fw["proj_grid"], fs=fw["fs"])
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def test_modalfn_small_plates_against_oracle(torch_gpu):
+    """Two 16/16-mode plates (the base and the target parameters) over 2000
+    steps, L = sum_n w_b[n] y_b[n] with seeded weights: the theta-gradients of
+    ModalFn.backward against the oracle's reverse recursion and chain rule,
+    to 1e-4 of each gradient's largest component."""
+    torch = torch_gpu
+    from paper_2505_05940_amd import fit
+    fw = W.plate_fit(n_t=16)
+    st = _setup(fw)
+    steps = 2000
+    th = np.stack([fw["theta0"], fw["theta_target"] * np.array([1.0, 1.0, 1.0, 2.0, 1.0])])
+    rng = np.random.default_rng(21)
+    w = rng.normal(size=(2, steps)) / np.abs(OP.plate_from_theta(fw, th[0])["x0"]).max()
+    _say("case: ModalFn, two 16/16 plates, 2000 steps, linear functional of y")
+    theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+    y = fit.ModalFn.apply(theta, st, steps)
+    L = (y.double() * torch.tensor(w, device=y.device)).sum()
+    L.backward()
+    got = theta.grad.numpy() * th
+    for b in range(2):
+        yo = OA.forward(OP.plate_from_theta(fw, th[b]), steps, 44100.0)[0]
+        e = np.linalg.norm(y[b].detach().double().cpu().numpy() - yo) / np.linalg.norm(yo)
+        assert e < 1e-5, e
+        ref = OP.theta_gradient(fw, th[b], steps, 44100.0, w[b]) * th[b]
+        err = np.abs(got[b] - ref) / np.abs(ref).max()
+        _say(f"  plate {b}: theta*grad {got[b]} oracle {ref} max err {err.max():.1e}")
+        assert err.max() < 1e-4, (b, got[b], ref)
+
+
+@pytest.mark.timeout(900)
+def test_config4_mrstft_gradient_against_oracle_and_differences(torch_gpu):
+    """The 200/200-mode fitting plate over 1 s (44 100 steps, checkpoints
+    every 512): the MR-STFT loss against the oracle's target output and its
+    theta-gradient through ModalFn, against the FP64 oracle's reverse
+    recursion + chain rule and against its central differences at the
+    configured relative step 1e-4, stored in tests/golden/gradient_200.json.
+    Bar: 1e-3 per component (relative to the oracle's value)."""
+    torch = torch_gpu
+    from paper_2505_05940_amd import fit
+    from paper_2505_05940_amd.losses import mrstft_loss
+    path = os.path.join(GOLDEN, "gradient_200.json")
+    if not os.path.exists(path):
+        pytest.fail(f"{path} missing: run tests/golden/make_golden.py gradient")
+    rec = json.load(open(path))
+    arr = np.load(os.path.join(GOLDEN, "gradient_200.npz"))
+    fw = W.plate_fit()
+    st = _setup(fw)
+    th0 = np.asarray(rec["theta0"])
+    assert np.allclose(th0, fw["theta0"], rtol=1e-15)
+    steps = int(rec["steps"])
+    target = torch.tensor(arr["target"], device="cuda").reshape(1, -1)
+    _say("case: ModalFn, 200/200 plate, 44100 steps, MR-STFT against the oracle's target")
+    theta = torch.tensor(th0[None], dtype=torch.float64, requires_grad=True)
+    y = fit.ModalFn.apply(theta, st, steps, 512)
+    e = float(np.linalg.norm(y[0].detach().double().cpu().numpy() - arr["y0"].astype(float))
+              / np.linalg.norm(arr["y0"].astype(float)))
+    _say(f"  forward rel L2 against the oracle: {e:.2e}")
+    assert e < 1e-5, e
+    L = mrstft_loss(y, target)
+    _say(f"  loss {L.item():.6f} (oracle {rec['loss']:.6f})")
+    assert abs(L.item() - rec["loss"]) < 1e-5 * abs(rec["loss"])
+    L.backward()
+    got = theta.grad.numpy()[0]
+    for name, key in (("oracle reverse", "grad_reverse"), ("central differences 1e-4", "grad_fd")):
+        ref = np.asarray(rec[key])
+        err = np.abs(got - ref) / np.abs(ref)
+        _say(f"  vs {name}: {got} / {ref}, rel err {err}")
+        assert err.max() < 1e-3, (name, got, ref, err)
+
+
+@pytest.mark.timeout(600)
+def test_fit_bending_stiffness_only(torch_gpu):
+    """fit.fit with only D^ free, from 1.05 times the target on a 16/16
+    plate over 0.25 s, MR-STFT loss: recovers the target's D^ to 1e-4.  (The
+    start lies in the loss's monotone basin around the target, about
+    [0.95, 1.085] times it; further out the spectral loss has local minima.)"""
+    torch = torch_gpu
+    from paper_2505_05940_amd import fit, modal
+    fw = W.plate_fit(n_t=16)
+    st = _setup(fw)
+    steps = 11025
+    tgt = fw["theta_target"].copy()
+    sim = modal.Sim([fit.plate_instance(st, tgt)], 44100.0)
+    target = sim.run(steps).clone()
+    sim.close()
+    th0 = tgt.copy()
+    th0[1] *= 1.05
+    _say("case: fit.fit, D^ only, 16/16 plate, 11025 steps, start 1.05 x target")
+    best, L, its, hist = fit.fit(target, th0, st, steps, iters=400, lr=0.01, tol=0.0, free=[1])
+    rel = abs(best[0][1] / tgt[1] - 1.0)
+    _say(f"  best D^ {best[0][1]:.8g} target {tgt[1]:.8g} rel {rel:.1e} loss {L[0]:.2e} after {its} iterations")
+    assert np.allclose(np.delete(best[0], 1), np.delete(th0, 1), rtol=1e-12, atol=0)
+    assert rel < 1e-4, rel

@@ -57,3 +57,21 @@ def test_logmel_shape_and_slices():
     assert f.shape == (3, 1024) and torch.isfinite(f).all()
     fb = losses.mel_filterbank(128, 2048, 44100.0)
     assert fb.shape == (128, 1025) and (fb >= 0).all() and (fb.sum(1) > 0).all()
+
+
+def test_logmel_matches_oracle():
+    """The product's log-mel features (torch STFT, mel matrix product) against
+    the oracle's direct-DFT, double-loop-filter version of the same
+    definition, at the proposal network's settings (1 s, 128 bands, 8
+    slices, n_fft 2048, hop 512)."""
+    from oracle import losses as OL
+    from paper_2505_05940_amd import losses
+    rng = np.random.default_rng(11)
+    t = np.arange(44100) / 44100.0
+    f = rng.uniform(60.0, 9000.0, size=12)
+    y = sum(np.exp(-rng.uniform(1, 20) * t) * np.sin(2 * np.pi * fk * t + rng.uniform(0, 6)) for fk in f)
+    y = 1e-4 * (y + 0.01 * rng.normal(size=t.size))
+    got = losses.logmel_features(torch.tensor(y[None], dtype=torch.float64)).numpy()[0]
+    ref = OL.logmel(y)
+    assert got.shape == ref.shape == (1024,)
+    assert np.abs(got - ref).max() < 1e-6 * np.abs(ref).max(), np.abs(got - ref).max()
