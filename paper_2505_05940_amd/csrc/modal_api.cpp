@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <queue>
 #include <atomic>
 #include <string>
@@ -20,6 +21,8 @@
 namespace modal {
 hipError_t launch_step(const StepParams& P, int gm, int nw, int n_wg, size_t lds_bytes, hipStream_t s);
 hipError_t launch_advance(long long* step_base, int n, hipStream_t s);
+hipError_t launch_ctr_fill(const InstDev* inst, int batch, const long long* step_base, unsigned int* ctr,
+                           hipStream_t s);
 hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s);
 hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes, bool res = false);
 hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, int n_wg, size_t lds,
@@ -51,9 +54,38 @@ hipError_t launch_lin_conv(const LinForced* forced, int n_forced, const double* 
 
 using namespace modal;
 
+// Device memory of modal_run_noalloc: the arrival counters and partial forces
+// of split instances, which modal_run keeps in memory the context allocated.
+// One copy per GPU, held until the process ends.  In host code the name is
+// only a stand-in; the address of each device's copy comes from
+// hipGetSymbolAddress (modal_init, once per device) and is the one passed to
+// kernels.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Address of the current device's scratch copy, resolved on first use per
+// device (with that device current).
+hipError_t resolve_scratch(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -161,6 +193,7 @@ struct Unit {
 
 struct modal_ctx {
   int batch = 0, scheme = 0, flags = 0, chunk = 0;
+  int device = 0;  // the device current at modal_init
   double fs = 0;
   int n_wg = 0, n_units = 0, n_split = 0, occ = 0, gm = 1, nw = 4;
   int res_stride = 0;  // > 0: LDS-resident state (one unit per workgroup)
@@ -211,6 +244,9 @@ struct modal_ctx {
   long long recall_cap = 0;  // steps the buffer holds
   long long rec_upto = 0;
   bool run_rec = false;
+  // modal_run_noalloc advanced the steps on counters of its own: the
+  // context's counters must be brought up to date before its next launch
+  bool ctr_stale = false;
   bool tangent = false;
   // per-row (in-plane) gradient pools: rows of all VK instances
   int rows_total = 0;
@@ -1167,7 +1203,14 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   if (rc) return rc;
   hipStream_t stream = (hipStream_t)stream_;
   const double T = 1.0 / d->fs;
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  {
+    void* sp = nullptr;  // modal_run_noalloc's scratch, once per device
+    HIP_TRY(resolve_scratch(device, &sp));
+  }
   modal_ctx* c = new modal_ctx();
+  c->device = device;
   c->batch = d->batch;
   c->scheme = d->scheme;
   c->flags = d->flags;
@@ -1629,6 +1672,7 @@ int modal_reset(modal_ctx* c, void* stream_) {
   HIP_TRY(hipMemsetAsync(c->dStep, 0, sizeof(long long), s));
   c->steps = 0;
   c->ckpt_broken = false;  // checkpoints of [0, ckpt_upto) stay valid
+  c->ctr_stale = false;
   return MODAL_OK;
 }
 
@@ -1726,6 +1770,10 @@ int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* s
       c->run_rec = true;
     }
   }
+  if (c->ctr_stale) {
+    HIP_TRY(launch_ctr_fill(c->P.inst, c->batch, c->dStep, c->dCtr, s));
+    c->ctr_stale = false;
+  }
   if (c->flags & MODAL_FLAG_GRAPH) {
     hipGraphExec_t exec = nullptr;
     for (auto& g : c->graphs)
@@ -1760,6 +1808,54 @@ int modal_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* s
   return modal_check(c, stream_);
 }
 
+int modal_run_noalloc(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride, void* stream_) {
+  if (!c) return fail(MODAL_EINVAL, "ctx is NULL");
+  if (n_steps < 0 || n_steps > (1LL << 31) - 1) return fail(MODAL_EINVAL, "n_steps out of range");
+  if (n_steps == 0) return MODAL_OK;
+  if (!y || y_stride < n_steps) return fail(MODAL_EINVAL, "y NULL or y_stride < n_steps");
+  if (c->linear || c->shared)
+    return fail(MODAL_ESTATE, "modal_run_noalloc steps the persistent recursion only; this context "
+                              "runs the linear closed form or the shared-tensor path (use modal_run)");
+  // scratch layout: counters [batch] at 0, partial forces from the next
+  // 256-byte boundary (the layout of the context's own buffers)
+  const size_t ctr_bytes = (sizeof(unsigned int) * (size_t)c->batch + 255) & ~(size_t)255;
+  const size_t need = ctr_bytes + sizeof(float) * (size_t)(c->part_floats + 64);
+  if (need > kScratchBytes)
+    return fail(MODAL_EINVAL, "modal_run_noalloc: the batch's partial forces and counters need " +
+                                  std::to_string(need) + " bytes; the scratch holds " +
+                                  std::to_string(kScratchBytes) + " (use modal_run)");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != c->device) return fail(MODAL_ESTATE, "the current device is not the context's");
+  void* sp = nullptr;
+  HIP_TRY(resolve_scratch(dev, &sp));  // resolved by modal_init: no allocation here
+  unsigned char* base = static_cast<unsigned char*>(sp);
+  unsigned int* ctr = reinterpret_cast<unsigned int*>(base);
+  float* part = reinterpret_cast<float*>(base + ctr_bytes);
+  hipStream_t s = (hipStream_t)stream_;
+  // another call may have left other counters behind: set them to where this
+  // context's steps stand (a fill kernel, so a capturing caller records no
+  // memset node)
+  HIP_TRY(launch_ctr_fill(c->P.inst, c->batch, c->dStep, ctr, s));
+  const int64_t chunk = c->chunk > 0 ? c->chunk : n_steps;
+  for (int64_t done = 0; done < n_steps; done += chunk) {
+    const int64_t k = std::min<int64_t>(chunk, n_steps - done);
+    StepParams P = c->P;
+    P.part = part;
+    P.ctr = ctr;
+    P.y = y + done;
+    P.y_stride = y_stride;
+    P.n_steps = (int)k;
+    HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
+    HIP_TRY(launch_advance(c->dStep, (int)k, s));
+  }
+  // no checkpoints were recorded: a gradient context's recorded checkpoints
+  // stop at ckpt_upto, and a later modal_run past them marks them broken
+  c->steps += n_steps;
+  c->ctr_stale = true;
+  if (c->flags & MODAL_FLAG_ASYNC) return MODAL_OK;
+  return modal_check(c, stream_);
+}
 
 int modal_set_tangent(modal_ctx* c, int32_t b, const float* Hd, void* stream_) {
   if (!c || !Hd) return fail(MODAL_EINVAL, "NULL argument");

@@ -605,6 +605,16 @@ __global__ void advance_kernel(long long* step_base, int n_steps) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += n_steps;
 }
 
+// Arrival counters as they stand after *step_base steps from a reset: every
+// slab of an instance has arrived once per step, ctr[b] = nslab_b * steps
+// (mod 2^32, like the waits' targets).  Lets a launch run on counters that
+// another context left behind.
+__global__ void ctr_fill_kernel(const InstDev* inst, int batch, const long long* step_base,
+                                unsigned int* ctr) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) ctr[b] = (unsigned int)inst[b].nslab * (unsigned int)(unsigned long long)*step_base;
+}
+
 // Symmetry and finiteness of each instance's Ht: out[2b] = max |H - H^T|,
 // out[2b+1] = max |H|, both as float bits (non-negative floats order like
 // their bit patterns); a non-finite entry reports +inf in both.
@@ -672,6 +682,11 @@ hipError_t launch_step(const StepParams& P, int gm, int nw, int n_wg, size_t lds
 }
 hipError_t launch_advance(long long* step_base, int n, hipStream_t s) {
   hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, step_base, n);
+  return hipGetLastError();
+}
+hipError_t launch_ctr_fill(const InstDev* inst, int batch, const long long* step_base, unsigned int* ctr,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(ctr_fill_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, inst, batch, step_base, ctr);
   return hipGetLastError();
 }
 hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s) {

@@ -62,6 +62,7 @@ def _load():
     vp = C.c_void_p
     lib.modal_init.argtypes = [C.POINTER(vp), C.POINTER(modal_desc), vp]
     lib.modal_run.argtypes = [vp, C.c_int64, _fp, C.c_int64, vp]
+    lib.modal_run_noalloc.argtypes = [vp, C.c_int64, _fp, C.c_int64, vp]
     lib.modal_check.argtypes = [vp, vp]
     lib.modal_reset.argtypes = [vp, vp]
     lib.modal_get_state.argtypes = [vp, _dp, _dp, vp]
@@ -83,7 +84,7 @@ def _load():
                                            _dp, _fp, C.c_int32]
     lib.modal_tf_response.argtypes = [vp, vp, C.c_int32, vp, C.c_int32, vp, vp]
     lib.modal_tf_grad.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, C.c_int32, vp, vp, vp]
-    for f in ("modal_init", "modal_run", "modal_check", "modal_reset", "modal_get_state",
+    for f in ("modal_init", "modal_run", "modal_run_noalloc", "modal_check", "modal_reset", "modal_get_state",
               "modal_info", "modal_vk_coupling_sine", "modal_tf_response", "modal_tf_grad"):
         getattr(lib, f).restype = C.c_int
     return lib
@@ -238,6 +239,16 @@ class Sim:
         assert out.stride(1) == 1 and out.shape[1] >= n_steps
         _check(lib.modal_run(self._ctx, n_steps, C.cast(C.c_void_p(out.data_ptr()), _fp),
                              out.stride(0), _stream_handle(self._stream)))
+        return out
+
+    def run_noalloc(self, n_steps, out):
+        """``modal_run_noalloc``: like ``run`` into a caller-given buffer, with
+        no device allocation in the call."""
+        import torch
+        assert out.dtype == torch.float32 and out.is_cuda and out.shape[0] == self.batch
+        assert out.stride(1) == 1 and out.shape[1] >= n_steps
+        _check(lib.modal_run_noalloc(self._ctx, n_steps, C.cast(C.c_void_p(out.data_ptr()), _fp),
+                                     out.stride(0), _stream_handle(self._stream)))
         return out
 
     def check(self):
