@@ -128,6 +128,11 @@ typedef struct {
                                    reduction space fits the LDS; else 4).
                                    The reverse kernel takes fewer waves when
                                    its larger reduction space does not fit.  */
+  int32_t barrier_us;           /* limit of each wait for the other slabs of
+                                   a split instance, in microseconds (0 =
+                                   4 s); past it the run is abandoned, every
+                                   workgroup leaves, and modal_run or
+                                   modal_grad returns MODAL_EHANG           */
 } modal_desc;
 
 /* Validates the description (before any device work), computes the per-mode
@@ -175,19 +180,19 @@ int modal_run(modal_ctx *c, int64_t n_steps, float *y, int64_t y_stride,
 /* modal_run for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same launches and results as modal_run (bit for bit), with the arrival
- * counters and partial forces of split instances taken from a scratch
+ * words and partial forces of split instances taken from a scratch
  * array of 16 MiB that the library holds on each GPU until the process ends
  * (its address resolved once per device by modal_init), and no hipMalloc,
  * hipFree, graph creation or checkpoint recording.  A small kernel first sets
- * the scratch counters to this context's step count, so calls of different
+ * the scratch arrival words to this context's step count, so calls of different
  * contexts may follow each other in any order; calls that overlap on one GPU
  * (two streams at once) race on the scratch and must not be issued.
  * y, y_stride and the return values as modal_run; the launches go straight
  * to `stream` (MODAL_FLAG_GRAPH is not used here; a caller may capture them
  * itself, with MODAL_FLAG_ASYNC so that no status read-back is made).
- * Errors: EINVAL when the batch's counters (4 bytes per instance, rounded up
- * to 256) and partial forces (4 bytes per float of 2 x slabs x padded modes
- * per split instance) need more than the 16 MiB; ESTATE on the linear
+ * Errors: EINVAL when the batch's arrival words (4 bytes per slab, rounded
+ * up to 256) and partial forces (4 bytes per float of 2 x slabs x padded
+ * modes per split instance) need more than the 16 MiB; ESTATE on the linear
  * closed-form and shared-tensor paths, or when the current device is not the
  * context's. */
 int modal_run_noalloc(modal_ctx *c, int64_t n_steps, float *y, int64_t y_stride,

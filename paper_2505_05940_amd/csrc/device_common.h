@@ -115,6 +115,24 @@ __device__ __forceinline__ float4 sum_strided4(const float* p, int n, int stride
   return add4(add4(s0, s1), add4(s2, s3));
 }
 
+// Sum over t = t0, t0 + dt, ... (t < n) of the float4 at p + t * stride
+// (global memory written by other workgroups), with eight loads issued
+// before the first add so that their latencies overlap; a fixed order, so
+// every caller gets the same bits.
+__device__ __forceinline__ float4 sum_slabs4(const float* p, int t0, int dt, int n, long long stride) {
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  int t = t0;
+  for (; t + 7 * dt < n; t += 8 * dt) {
+    float4 a[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = *reinterpret_cast<const float4*>(p + (long long)(t + i * dt) * stride);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s = add4(s, a[i]);
+  }
+  for (; t < n; t += dt) s = add4(s, *reinterpret_cast<const float4*>(p + (long long)t * stride));
+  return s;
+}
+
 // sum of n consecutive floats (LDS), four partial sums
 __device__ __forceinline__ float sum_run(const float* p, int n) {
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
@@ -175,21 +193,25 @@ __device__ __forceinline__ void block_lds_sync() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Timeout of a per-instance barrier in ticks of the 100 MHz wall clock.
-constexpr unsigned long long kBarrierTimeout = 400000000ull;  // 4 s
 
-// Waits until the instance's arrival counter reaches `target` (wrap-safe).
-// Returns false if the wait was abandoned (timeout here or elsewhere).
-__device__ inline bool wait_counter(unsigned int* ctr, unsigned int target, int* flags) {
+// Waits until every slab's arrival word f[t] (t < nslab) has reached
+// `target` (wrap-safe); called by a whole wave, whose lanes poll the words
+// together, so that no slab's arrival waits on another's (each slab stores
+// its own word; nothing is read-modify-written).  Returns false if the wait
+// was abandoned (after `timeout` ticks here, or elsewhere).
+__device__ inline bool wait_slabs(const unsigned int* f, int nslab, unsigned int target, int* flags,
+                                  unsigned long long timeout) {
+  const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long t0 = wall_clock64();
   while (true) {
-    // relaxed polling: the caller's acquire fence after a successful wait
-    // orders the reads of the published partials, so the loop itself does no
-    // cache invalidation per poll
-    unsigned int v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((int)(v - target) >= 0) return true;
+    bool ok = true;
+    for (int t = lane; t < nslab; t += kWave) {
+      const unsigned int v = __hip_atomic_load(f + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ok = ok && (int)(v - target) >= 0;
+    }
+    if (__all(ok)) return true;
     if (__hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    if (wall_clock64() - t0 > kBarrierTimeout) {
+    if (wall_clock64() - t0 > timeout) {
       __hip_atomic_store(&flags[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }

@@ -146,6 +146,212 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
   }
 }
 
+// vk_rows2 over a range of row blocks [t0, t1) of the unit whose rows start
+// at row0 (block t is block t % nblk of row row0 + t / nblk), for one-unit
+// workgroups whose waves share the unit's blocks evenly.  Rows wholly in the
+// range are finished here.  For a row the range cuts, the partial V, W (and
+// Vd) are parked in `defer` (slot s at s NR ntp) and the partial eta, V.u,
+// Vd.q and Vd.u with the row index in the wave's exchange words (slot 0: a
+// row entered mid-row, slot 1: a row left mid-row), for vk_rows2_finish.
+template <int GM, bool TAN, int DEPTH>
+__device__ void vk_rows2_range(const float* __restrict__ Hb, const float* __restrict__ Hdb, int nt,
+                               int ntp, int qs, int row0, int t0, int t1, const float* Xs,
+                               const float* Us, float* red, float4 (&Ju)[GM], float4 (&Fa)[GM],
+                               float& tsum, int G, int lane, float* rrow, float* teta, float* tw,
+                               float* defer, float* xv, int* xr) {
+  constexpr int J = kSweepLoads;
+  constexpr int NR = TAN ? 3 : 2;
+  if (lane == 0) {
+    xr[0] = -1;
+    xr[1] = -1;
+  }
+  if (t1 <= t0) return;
+  const int nc = ntp >> 2;
+  const int qsnc = qs * nc;
+  int voff[J], sub[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int v = lane + kWave * j;
+    voff[j] = 16 * v;
+    sub[j] = v < qsnc ? v / nc : 0;
+  }
+  const int nblk = (nt + qs - 1) / qs;
+  const long long blk_floats = (long long)qs * ntp;
+  const long long row_floats = (long long)nt * ntp;
+  const int blk_bytes = 4 * qs * ntp;
+  const int last_bytes = 4 * (nt - (nblk - 1) * qs) * ntp;
+  const int slab = qs * ntp;
+  int lt = t0, ln = row0 + t0 / nblk, lb = t0 % nblk;
+  auto load = [&](float4 (&h)[J], float4 (&hd)[J]) {
+    const bool live = lt < t1;
+    const long long o = live ? (long long)ln * row_floats + (long long)lb * blk_floats : 0;
+    const int bytes = live ? (lb == nblk - 1 ? last_bytes : blk_bytes) : 0;
+    const v4i r = buf_rsrc(Hb + o, bytes);
+#pragma unroll
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+    if (TAN) {
+      const v4i rd = buf_rsrc(Hdb + o, bytes);
+#pragma unroll
+      for (int j = 0; j < J; ++j) hd[j] = buf_ld4(rd, voff[j]);
+    }
+    ++lt;
+    if (++lb == nblk) {
+      lb = 0;
+      ++ln;
+    }
+  };
+  float4 ha[J], hb[J], hda[J], hdb[J], aV[J], aW[J], aD[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) aV[j] = aW[j] = aD[j] = f4(0.f);
+  int t = t0, n = row0 + t0 / nblk, b = t0 % nblk, bfirst = b;
+  auto step = [&](float4 (&hc)[J], float4 (&hdc)[J], float4 (&hn)[J], float4 (&hdn)[J]) -> bool {
+    load(hn, hdn);
+    const int q0 = b * qs;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int qi = min(q0 + sub[j], nt - 1);
+      const float x = Xs[qi], u = Us[qi];
+      aV[j] = fma4(hc[j], x, aV[j]);
+      aW[j] = fma4(hc[j], u, aW[j]);
+      if (TAN) aD[j] = fma4(hdc[j], x, aD[j]);
+    }
+    ++t;
+    if (++b < nblk && t < t1) return true;
+    float* rb = red + (n & 1) * NR * slab;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (voff[j] < blk_bytes) {
+        const int o = voff[j] >> 2;
+        st4(rb + o, aV[j]);
+        st4(rb + slab + o, aW[j]);
+        if (TAN) st4(rb + 2 * slab + o, aD[j]);
+      }
+    }
+    wave_lds_sync();
+    float eta = 0.f, w = 0.f, etad = 0.f, vdu = 0.f;
+    float4 V[GM], W[GM], D[GM];
+#pragma unroll
+    for (int g = 0; g < GM; ++g) {
+      V[g] = W[g] = D[g] = f4(0.f);
+      const int k4 = lane + kWave * g;
+      if (g < G && k4 < nc) {
+        const float4 sv = sum_strided4(rb + 4 * k4, qs, ntp);
+        const float4 sw = sum_strided4(rb + slab + 4 * k4, qs, ntp);
+        const float4 sd = TAN ? sum_strided4(rb + 2 * slab + 4 * k4, qs, ntp) : f4(0.f);
+        V[g] = sv;
+        W[g] = sw;
+        D[g] = sd;
+        const float4 x = ld4(Xs + 4 * k4), u = ld4(Us + 4 * k4);
+        eta += dot4(sv, x);
+        w += dot4(sv, u);
+        if (TAN) {
+          etad += dot4(sd, x);
+          vdu += dot4(sd, u);
+        }
+      }
+    }
+    eta = wave_sum(eta);
+    w = wave_sum(w);
+    if (TAN) {
+      etad = wave_sum(etad);
+      vdu = wave_sum(vdu);
+    }
+    if (bfirst == 0 && b == nblk) {
+      if (rrow && lane == 0) rrow[n] = -2.f * eta * w;
+      if (teta && lane == 0) {
+        teta[n] = eta;
+        tw[n] = w;
+      }
+      if (TAN) tsum -= etad * w + eta * vdu;
+#pragma unroll
+      for (int g = 0; g < GM; ++g) {
+        Ju[g] = fma4(V[g], 2.f * w, fma4(W[g], eta, Ju[g]));
+        Fa[g] = fma4(V[g], eta, Fa[g]);
+      }
+    } else {
+      const int slot = bfirst > 0 ? 0 : 1;
+      float* dp = defer + slot * NR * ntp;
+#pragma unroll
+      for (int g = 0; g < GM; ++g) {
+        const int k4 = lane + kWave * g;
+        if (g < G && k4 < nc) {
+          st4(dp + 4 * k4, V[g]);
+          st4(dp + ntp + 4 * k4, W[g]);
+          if (TAN) st4(dp + 2 * ntp + 4 * k4, D[g]);
+        }
+      }
+      if (lane == 0) {
+        xv[slot * kXchVals] = eta;
+        xv[slot * kXchVals + 1] = w;
+        xv[slot * kXchVals + 2] = etad;
+        xv[slot * kXchVals + 3] = vdu;
+        xr[slot] = n;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) aV[j] = aW[j] = aD[j] = f4(0.f);
+    b = 0;
+    bfirst = 0;
+    ++n;
+    return t < t1;
+  };
+  load(ha, hda);
+  if (DEPTH == 2) {
+    while (step(ha, hda, hb, hdb) && step(hb, hdb, ha, hda)) {
+    }
+  } else {
+    float4 hx[J], hdx[J];
+    load(hb, hdb);
+    while (step(ha, hda, hx, hdx) && step(hb, hdb, ha, hda) && step(hx, hdx, hb, hdb)) {
+    }
+  }
+}
+
+// Completes the rows vk_rows2_range left to several waves, after a workgroup
+// barrier: the row's eta, V.u, Vd.q and Vd.u are the sums of every sharing
+// wave's partials (in wave order); each sharing wave adds its partial vectors
+// times them, and the wave that holds the row's first block (slot 1) writes
+// the row's records and its tangent term.  xv, xr: exchange words of all nw
+// waves (this wave's at 2 wave).
+template <int GM, bool TAN>
+__device__ void vk_rows2_finish(const float* xv, const int* xr, int nw, int wave, int ntp,
+                                const float* defer, float4 (&Ju)[GM], float4 (&Fa)[GM], float& tsum,
+                                int G, int lane, float* rrow, float* teta, float* tw) {
+  constexpr int NR = TAN ? 3 : 2;
+  const int nc = ntp >> 2;
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot) {
+    const int n = xr[2 * wave + slot];
+    if (n < 0) continue;
+    float eta = 0.f, w = 0.f, etad = 0.f, vdu = 0.f;
+    for (int i = 0; i < 2 * nw; ++i)
+      if (xr[i] == n) {
+        eta += xv[i * kXchVals];
+        w += xv[i * kXchVals + 1];
+        etad += xv[i * kXchVals + 2];
+        vdu += xv[i * kXchVals + 3];
+      }
+    const float* dp = defer + slot * NR * ntp;
+#pragma unroll
+    for (int g = 0; g < GM; ++g) {
+      const int k4 = lane + kWave * g;
+      if (g < G && k4 < nc) {
+        const float4 V = ld4(dp + 4 * k4), W = ld4(dp + ntp + 4 * k4);
+        Ju[g] = fma4(V, 2.f * w, fma4(W, eta, Ju[g]));
+        Fa[g] = fma4(V, eta, Fa[g]);
+      }
+    }
+    if (slot == 1) {
+      if (rrow && lane == 0) rrow[n] = -2.f * eta * w;
+      if (teta && lane == 0) {
+        teta[n] = eta;
+        tw[n] = w;
+      }
+      if (TAN) tsum -= etad * w + eta * vdu;
+    }
+  }
+}
+
 __device__ __forceinline__ void acc_add(float* acc, int k, int sf, int i, ff v) {
   ff a{acc[(2 * k) * (long long)sf + i], acc[(2 * k + 1) * (long long)sf + i]};
   a = ff_add(a, v);
@@ -267,7 +473,7 @@ __device__ void adj_post(const GradParams& P, const InstDev& I, const UnitDev& U
 // per workgroup.  As in the forward kernel, the waves of a workgroup divide a
 // unit's rows among themselves and wave 0 sums their partial J u, F and
 // tangent sums, finishes the step or publishes the unit's share.
-template <int GM, bool TAN, int NW>
+template <int GM, bool TAN, int NW, bool SPLIT>
 __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
   extern __shared__ float4 lds4[];
   const GradLds L = grad_lds(reinterpret_cast<float*>(lds4));
@@ -317,8 +523,30 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
         float* rrow = P.rrec ? P.rrec + (long long)s * P.rows_total + I.row_off : nullptr;
         float* teta = P.trec ? P.trec + (n - P.seg_base) * 2LL * P.rows_total + I.row_off : nullptr;
         float* tw = teta ? teta + P.rows_total : nullptr;
-        vk_rows2<GM, TAN, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs, r0, r1,
-                          Xs, Us, red, Ju, Fa, tsum, G, lane, rrow, teta, tw);
+        if (SPLIT && NW > 1 && R < NW) {
+          // one unit per workgroup with fewer rows than waves: the waves
+          // share its row blocks evenly
+          const int nblk = (I.nt + U.qs - 1) / U.qs;
+          const int T = R * nblk;
+          constexpr int NR = TAN ? 3 : 2;
+          float* xv = L.xch;
+          int* xr = reinterpret_cast<int*>(L.xch + 2 * NW * kXchVals);
+          float* defer = red + 2 * NR * U.qs * I.ntp;
+          vk_rows2_range<GM, TAN, (NW == 8 && GM <= 2) ? 3 : 2>(
+              P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs, U.row0, (T * wave) / NW,
+              (T * (wave + 1)) / NW, Xs, Us, red, Ju, Fa, tsum, G, lane, rrow, teta, tw, defer,
+              xv + 2 * wave * kXchVals, xr + 2 * wave);
+          bool cut = false;  // a wave boundary inside a row
+          for (int w = 1; w < NW; ++w) cut |= ((T * w) / NW) % nblk != 0;
+          if (cut) {
+            __syncthreads();  // every wave's partials of the rows it shares
+            vk_rows2_finish<GM, TAN>(xv, xr, NW, wave, I.ntp, defer, Ju, Fa, tsum, G, lane, rrow, teta, tw);
+          }
+        } else {
+          vk_rows2<GM, TAN, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt,
+                                                          I.ntp, U.qs, r0, r1, Xs, Us, red, Ju, Fa, tsum, G,
+                                                          lane, rrow, teta, tw);
+        }
         if (NW > 1) {
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
@@ -383,7 +611,8 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           __builtin_amdgcn_wave_barrier();
           if (lane == 0)
-            __hip_atomic_fetch_add(&P.ctr[U.inst], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&P.ctr[I.ctr_off + U.slab], (unsigned int)(rstep + 1), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       __syncthreads();  // LDS reused by the next unit
@@ -393,17 +622,46 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
       const InstDev I = P.inst[U.inst];
       if (I.nslab == 1) continue;
       if (wave == 0) {
-        const unsigned int target = (unsigned int)I.nslab * (unsigned int)(rstep + 1);
-        const bool ok = wait_counter(&P.ctr[U.inst], target, P.flags);
+        const bool ok = wait_slabs(P.ctr + I.ctr_off, I.nslab, (unsigned int)(rstep + 1), P.flags, P.timeout_ticks);
         if (lane == 0) L.flag[0] = ok ? 1 : 0;
       }
       __syncthreads();
       if (L.flag[0] == 0) return;  // every wave leaves together
-      if (wave == 0) {
+      const int nc = I.ntp >> 2;
+      const int G = (nc + kWave - 1) / kWave;
+      const float* src = P.part + 2 * I.part_off + (long long)(rstep & 1) * I.nslab * 2 * I.ntp;
+      if (SPLIT && NW > 1 && I.nslab >= 2 * NW) {
+        // many slabs: every wave sums every NW-th partial, wave 0 adds the
+        // waves' sums
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int nc = I.ntp >> 2;
-        const int G = (nc + kWave - 1) / kWave;
-        const float* src = P.part + 2 * I.part_off + (long long)(rstep & 1) * I.nslab * 2 * I.ntp;
+        float4 Ju[GM], F[GM];
+#pragma unroll
+        for (int g = 0; g < GM; ++g) {
+          Ju[g] = F[g] = f4(0.f);
+          const int k4 = lane + kWave * g;
+          if (g < G && k4 < nc) {
+            Ju[g] = sum_slabs4(src + 4 * k4, wave, NW, I.nslab, 2LL * I.ntp);
+            F[g] = sum_slabs4(src + I.ntp + 4 * k4, wave, NW, I.nslab, 2LL * I.ntp);
+            st4(red + 4 * k4, Ju[g]);
+            st4(red + I.ntp + 4 * k4, F[g]);
+          }
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+          for (int g = 0; g < GM; ++g) {
+            const int k4 = lane + kWave * g;
+            if (g < G && k4 < nc)
+              for (int w = 1; w < NW; ++w) {
+                const float* o = L.red + w * P.red_floats;
+                Ju[g] = add4(Ju[g], ld4(o + 4 * k4));
+                F[g] = add4(F[g], ld4(o + I.ntp + 4 * k4));
+              }
+          }
+          adj_post<GM>(P, I, U, n, Ju, F, G, lane);
+        }
+      } else if (wave == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         float4 Ju[GM], F[GM];
 #pragma unroll
         for (int g = 0; g < GM; ++g) {
@@ -528,7 +786,7 @@ __global__ void row_sum_kernel(const float* rrec, int seg_len, int rows, float* 
 }
 
 // Copies checkpoint `slot` ([4][mode_floats]) into every unit's state and
-// rewinds the step counter and the forward arrival counters to `step`.
+// rewinds the step counter and the forward arrival words to `step`.
 __global__ void restore_kernel(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
                                const UnitDev* unit, int n_units, float* state, int state_floats,
                                long long* step_base, long long step, unsigned int* ctr) {
@@ -536,7 +794,7 @@ __global__ void restore_kernel(const float* ckpt, long long slot, int mode_float
   if (u >= n_units) return;
   const UnitDev U = unit[u];
   const InstDev I = inst[U.inst];
-  if (U.slab == 0 && threadIdx.x == 0) ctr[U.inst] = (unsigned int)I.nslab * (unsigned int)step;
+  if (threadIdx.x == 0) ctr[I.ctr_off + U.slab] = (unsigned int)step;
   const float* src = ckpt + slot * 4LL * mode_floats + I.mode_off;
   for (int k = threadIdx.x; k < I.ntp; k += blockDim.x)
     for (int a = 0; a < 4; ++a)
@@ -545,11 +803,15 @@ __global__ void restore_kernel(const float* ckpt, long long slot, int mode_float
 }
 
 // gm: float4 column groups per lane (1, 2 or 4); nw: waves per workgroup (1 or 4).
-hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, int n_wg, size_t lds,
+// split: the launch's workgroups own one unit each and their waves share the
+// unit's row blocks (latency-bound plans); only with four or eight waves.
+hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, bool split, int n_wg, size_t lds,
                        hipStream_t s) {
-#define GL(G, T, W) hipLaunchKernelGGL((grad_kernel<G, T, W>), dim3(n_wg), dim3(kWave * W), lds, s, P)
-#define GL_NW(G, T) \
-  if (nw == 1) GL(G, T, 1); else if (nw == 8) GL(G, T, 8); else GL(G, T, 4);
+#define GL(G, T, W, S) hipLaunchKernelGGL((grad_kernel<G, T, W, S>), dim3(n_wg), dim3(kWave * W), lds, s, P)
+#define GL_NW(G, T)                                        \
+  if (nw == 1) GL(G, T, 1, false);                         \
+  else if (nw == 8) { if (split) GL(G, T, 8, true); else GL(G, T, 8, false); } \
+  else { if (split) GL(G, T, 4, true); else GL(G, T, 4, false); }
 #define GL_T(G) \
   if (tangent) { GL_NW(G, true) } else { GL_NW(G, false) }
   if (gm <= 1) {
@@ -565,11 +827,15 @@ hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, int n_
   return hipGetLastError();
 }
 
-hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, size_t lds) {
-#define GO(G, T, W) \
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<G, T, W>, kWave * W, lds)
-#define GO_NW(G, T) \
-  { if (nw == 1) { GO(G, T, 1); } else if (nw == 8) { GO(G, T, 8); } else { GO(G, T, 4); } }
+hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, bool split, size_t lds) {
+#define GO(G, T, W, S) \
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, grad_kernel<G, T, W, S>, kWave * W, lds)
+#define GO_NW(G, T)                                                         \
+  {                                                                         \
+    if (nw == 1) { GO(G, T, 1, false); }                                    \
+    else if (nw == 8) { if (split) { GO(G, T, 8, true); } else { GO(G, T, 8, false); } } \
+    else { if (split) { GO(G, T, 4, true); } else { GO(G, T, 4, false); } } \
+  }
 #define GO_T(G) \
   { if (tangent) { GO_NW(G, true) } else { GO_NW(G, false) } }
   if (gm <= 1) GO_T(1)

@@ -20,6 +20,8 @@ struct InstDev {
   long long h_off;     // float offset of Ht[nin][nt][ntp] in the tensor pool
   int mode_off;        // offset into the per-mode arrays (multiple of 4)
   int nslab;           // number of work units (workgroups) sharing it
+  int ctr_off;         // first of its nslab arrival words (one per slab: the
+                       // number of steps that slab has published)
   long long part_off;  // float offset of its partial forces [2][nslab][ntp]
   float kappa;         // TENSION
   int out_row;         // row of y
@@ -61,18 +63,26 @@ struct UnitDev {
 // arrays of res_stride floats after the reduction regions (X hi, X lo, d hi,
 // d lo, m hi, m lo, p hi, p lo, r hi, r lo, b, c, lambda).
 constexpr int kResArrays = 13;
+// Exchange words of the waves that share an in-plane row (one-unit
+// workgroups, whose waves divide the unit's row blocks rather than its rows):
+// per wave two row slots, each with kXchVals partial scalars and the row
+// index (an int stored in a float slot's bits), for at most 8 waves.
+constexpr int kXchVals = 4;
+constexpr int kXchWords = 8 * 2 * (kXchVals + 1);
 struct StepLds {
-  float *xs, *red, *res;
+  float *xs, *red, *res, *xch;
   int* flag;
 };
 __host__ __device__ inline size_t step_lds_bytes(int nw, int red_floats, int res_stride = 0) {
-  return sizeof(float) * ((size_t)kMaxModes + 4 + (size_t)nw * red_floats + (size_t)kResArrays * res_stride);
+  return sizeof(float) * ((size_t)kMaxModes + 4 + kXchWords + (size_t)nw * red_floats +
+                          (size_t)kResArrays * res_stride);
 }
 __host__ __device__ inline StepLds step_lds(float* base, int nw, int red_floats) {
   StepLds L;
   L.xs = base;
   L.flag = reinterpret_cast<int*>(base + kMaxModes);
-  L.red = reinterpret_cast<float*>(L.flag + 4);
+  L.xch = reinterpret_cast<float*>(L.flag + 4);
+  L.red = L.xch + kXchWords;
   L.res = L.red + (size_t)nw * red_floats;
   return L;
 }
@@ -82,18 +92,19 @@ __host__ __device__ inline StepLds step_lds(float* base, int nw, int red_floats)
 // per row, double-buffered); a finished wave parks J u, F and its tangent
 // sum in the first 2 ntp + 1 floats of its region.
 struct GradLds {
-  float *xs, *us, *red;
+  float *xs, *us, *red, *xch;
   int* flag;
 };
 __host__ __device__ inline size_t grad_lds_bytes(int nw, int red_floats) {
-  return sizeof(float) * (2 * (size_t)kMaxModes + 4 + (size_t)nw * red_floats);
+  return sizeof(float) * (2 * (size_t)kMaxModes + 4 + kXchWords + (size_t)nw * red_floats);
 }
 __host__ __device__ inline GradLds grad_lds(float* base) {
   GradLds L;
   L.xs = base;
   L.us = base + kMaxModes;
   L.flag = reinterpret_cast<int*>(base + 2 * kMaxModes);
-  L.red = reinterpret_cast<float*>(L.flag + 4);
+  L.xch = reinterpret_cast<float*>(L.flag + 4);
+  L.red = L.xch + kXchWords;
   return L;
 }
 
@@ -110,8 +121,9 @@ struct StepParams {
   // per-unit state (float-float X = q^n and d = q^n - q^{n-1})
   float *x_hi, *x_lo, *d_hi, *d_lo;
   float* part;              // partial forces of split instances
-  unsigned int* ctr;        // arrival counters of split instances
+  unsigned int* ctr;        // arrival words of split instances' slabs (InstDev.ctr_off)
   int* flags;               // [0] barrier timeout, [1] non-finite state
+  unsigned long long timeout_ticks;  // limit of a slab wait (100 MHz clock ticks)
   long long* step_base;     // absolute index of the next step (device)
   float* y;                 // output, y[row * y_stride + s]; NULL = none
   long long y_stride;
@@ -156,6 +168,7 @@ struct GradParams {
   float* part;           // partial (J u, F) of split instances, [2][nslab][2 ntp] at 2 part_off
   unsigned int* ctr;
   int* flags;
+  unsigned long long timeout_ticks;  // limit of a slab wait (100 MHz clock ticks)
   long long done_before;  // reverse steps completed before this launch
   int red_floats;
   // per-row record of -2 eta_n (V_n . u) for every reverse step of the

@@ -25,9 +25,9 @@ hipError_t launch_ctr_fill(const InstDev* inst, int batch, const long long* step
                            hipStream_t s);
 hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s);
 hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes, bool res = false);
-hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, int n_wg, size_t lds,
+hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, bool split, int n_wg, size_t lds,
                        hipStream_t s);
-hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, size_t lds);
+hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, bool split, size_t lds);
 hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, const InstDev* inst,
                           const UnitDev* unit, int n_units, float* state, int state_floats,
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
@@ -54,7 +54,7 @@ hipError_t launch_lin_conv(const LinForced* forced, int n_forced, const double* 
 
 using namespace modal;
 
-// Device memory of modal_run_noalloc: the arrival counters and partial forces
+// Device memory of modal_run_noalloc: the arrival words and partial forces
 // of split instances, which modal_run keeps in memory the context allocated.
 // One copy per GPU, held until the process ends.  In host code the name is
 // only a stand-in; the address of each device's copy comes from
@@ -213,7 +213,8 @@ struct modal_ctx {
   float* dCoef = nullptr;    // 9 per-mode arrays
   float* dState = nullptr;   // 4 per-unit arrays
   float* dPart = nullptr;
-  unsigned int* dCtr = nullptr;
+  unsigned int* dCtr = nullptr;  // arrival words, n_ctr of them (one per slab)
+  int n_ctr = 0;
   int* dFlags = nullptr;
   long long* dStep = nullptr;
   float* dE = nullptr;
@@ -244,8 +245,8 @@ struct modal_ctx {
   long long recall_cap = 0;  // steps the buffer holds
   long long rec_upto = 0;
   bool run_rec = false;
-  // modal_run_noalloc advanced the steps on counters of its own: the
-  // context's counters must be brought up to date before its next launch
+  // modal_run_noalloc advanced the steps on arrival words of its own: the
+  // context's words must be brought up to date before its next launch
   bool ctr_stale = false;
   bool tangent = false;
   // per-row (in-plane) gradient pools: rows of all VK instances
@@ -334,8 +335,8 @@ int validate(const modal_desc* d) {
   if (d->scheme != MODAL_SCHEME_SV && d->scheme != MODAL_SCHEME_TF)
     return fail(MODAL_EINVAL, "unknown scheme");
   if ((d->waves != 0 && d->waves != 1 && d->waves != 4 && d->waves != 8) || d->max_workgroups < 0 ||
-      d->chunk_steps < 0)
-    return fail(MODAL_EINVAL, "waves (0, 1, 4 or 8), max_workgroups or chunk_steps");
+      d->chunk_steps < 0 || d->barrier_us < 0)
+    return fail(MODAL_EINVAL, "waves (0, 1, 4 or 8), max_workgroups, chunk_steps or barrier_us");
   const double T = 1.0 / d->fs;
   for (int b = 0; b < d->batch; ++b) {
     const modal_instance& I = d->inst[b];
@@ -389,17 +390,27 @@ constexpr double kRecAllBytes = 2.0 * 1073741824.0;
 // below this many bytes per step is bound by each step's latency, not by
 // HBM: it runs dense (no parity blocks), with 8 waves per workgroup, each
 // instance cut into slabs of about kLatencyRows in-plane rows (at most
-// kLatencyMaxSlabs, no more than CUs / batch, and only in batches of at most
+// no more than CUs / batch, and only in batches of at most
 // kLatencyMaxSplitBatch instances), one slab per workgroup.
 // Measured on single sine-family plates: 100/100 modes step in 11.0 us this
 // way (13 slabs), against 82 us blocked on the byte-balanced plan; 50/50 in
 // 9.1 us against 39.6 us.  About 8 rows, one per wave, was the best slab size
 // of 5, 6, 8 and 10 (100/100: 13.2, 11.8, 11.0, 13.5 us): smaller slabs add
 // workgroups to every step's exchange, larger ones give some waves two rows.
+// Default limit of a wait for the other slabs of a split instance, in ticks
+// of the device's 100 MHz clock (4 s).
+constexpr unsigned long long kBarrierTicks = 400000000ull;
 constexpr double kLatencyBytes = 64.0 * 1048576.0;
 constexpr int kLatencyRows = 8;
-constexpr int kLatencyMaxSlabs = 16;
 constexpr int kLatencyMaxSplitBatch = 16;  // larger latency-bound batches keep instances whole
+// A large instance of such a batch is also cut so that no slab streams more
+// than about this many tensor bytes per step (the waves of a one-unit
+// workgroup share its row blocks, so slabs of fewer rows than waves keep
+// every wave busy).
+#ifndef MODAL_LATENCY_SLAB_KB
+#define MODAL_LATENCY_SLAB_KB 512
+#endif
+constexpr double kLatencySlabBytes = 1024.0 * MODAL_LATENCY_SLAB_KB;
 
 // Per-step cost of the exchange and barrier of one slab of a split instance,
 // in streamed-byte units (release fence, arrival, wait, acquire and reading
@@ -625,7 +636,10 @@ int pack(const modal_desc* d, const std::vector<double>& row_cost,
 }
 
 // Smallest capacity (binary search) at which the batch packs into n_bins
-// workgroups, and that packing.
+// workgroups, and that packing.  (Filling workgroups in turn with slabs of
+// unequal sizes instead brings the planned heaviest workgroup within 3 % of
+// the mean on the 256-plate batch, against 14 % here, but measured 10 %
+// slower: more units per workgroup and more exchanges.)
 bool plan_batch(const modal_desc* d, const std::vector<double>& row_cost,
                 const std::vector<double>& fixed_cost, double total, int n_bins,
                 std::vector<Unit>& units, std::vector<int>& bin_of, std::vector<double>& load) {
@@ -1148,6 +1162,7 @@ int init_shared(modal_ctx* c, const modal_desc* d, std::vector<SharedGroup>& gro
   if (!r) r = dalloc(&c->dShS2, sizeof(float) * s2.size());
   if (!r) r = dalloc(&c->dCoef, sizeof(float) * coef.size());
   if (!r) r = dalloc(&c->dState, sizeof(float) * c->state0.size());
+  c->n_ctr = d->batch;
   if (!r) r = dalloc(&c->dCtr, sizeof(unsigned int) * d->batch);
   if (!r) r = dalloc(&c->dFlags, sizeof(int) * 2);
   if (!r) r = dalloc(&c->dStep, sizeof(long long));
@@ -1329,7 +1344,9 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
         c->coupling_bytes += 4LL * D.nin * D.nt * D.nt;
         c->padded_bytes += 4 * f;
         choose_sweep(D.nt, D.ntp / 4, qs_of[b], J_of[b]);
-        red_floats = std::max(red_floats, 2 * qs_of[b] * D.ntp);
+        // row double buffer; in latency-bound plans also two parked partial
+        // rows (a row shared by several waves of a one-unit workgroup)
+        red_floats = std::max(red_floats, 2 * qs_of[b] * D.ntp + (latency ? 2 * D.ntp : 0));
       }
     }
     unit_costs(I, row_cost[b], fixed_cost[b], &plans[b]);
@@ -1374,7 +1391,13 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
       c->nw_grad[tan] = c->nw;
       for (;;) {
         c->grad_lds_v[tan] = grad_lds_bytes(c->nw_grad[tan], (tan ? 3 : 2) * red_floats);
-        HIP_TRY(grad_occupancy(&o, c->gm, tan == 1, c->nw_grad[tan], c->grad_lds_v[tan]));
+        HIP_TRY(grad_occupancy(&o, c->gm, tan == 1, c->nw_grad[tan], false, c->grad_lds_v[tan]));
+        if (latency && o >= 1 && c->nw_grad[tan] > 1) {
+          // the variant whose waves share a one-unit workgroup's row blocks
+          int o2 = 0;
+          HIP_TRY(grad_occupancy(&o2, c->gm, tan == 1, c->nw_grad[tan], true, c->grad_lds_v[tan]));
+          o = std::min(o, o2);
+        }
         if (o >= 1 || c->nw_grad[tan] == 1) break;
         c->nw_grad[tan] = c->nw_grad[tan] == 8 ? 4 : 1;
       }
@@ -1409,11 +1432,14 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
     // 40/40 in 4 slabs each step in 16 us instead of 12)
     const int cap_slabs = d->batch > kLatencyMaxSplitBatch
                               ? 1
-                              : std::max(1, std::min(kLatencyMaxSlabs, prop.multiProcessorCount / d->batch));
+                              : std::max(1, prop.multiProcessorCount / d->batch);
     for (int b = 0; b < d->batch; ++b) {
       const int rows = inst[b].kind == KIND_VK ? inst[b].nin : 1;
+      const double bytes = inst[b].kind == KIND_VK ? 4.0 * inst[b].nin * (double)inst[b].nt * inst[b].nt : 0.0;
+      const int by_rows = (rows + kLatencyRows / 2) / kLatencyRows;
+      const int by_bytes = (int)std::ceil(bytes / kLatencySlabBytes);
       const int S = inst[b].kind == KIND_VK
-                        ? std::max(1, std::min(cap_slabs, (rows + kLatencyRows / 2) / kLatencyRows))
+                        ? std::max(1, std::min({cap_slabs, rows, std::max(by_rows, by_bytes)}))
                         : 1;
       for (int sl = 0; sl < S; ++sl) {
         const int r0 = (int)((long long)rows * sl / S), r1 = (int)((long long)rows * (sl + 1) / S);
@@ -1474,8 +1500,11 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   }
   for (int w = 1; w <= n_wg; ++w) wg_begin[w] = std::max(wg_begin[w], wg_begin[w - 1]);
   long long part_floats = 0;
+  int n_ctr = 0;
   for (int b = 0; b < d->batch; ++b) {
     inst[b].nslab = nslab[b];
+    inst[b].ctr_off = n_ctr;
+    n_ctr += std::max(1, nslab[b]);
     inst[b].part_off = part_floats;
     if (nslab[b] > 1) {
       part_floats += 2LL * nslab[b] * inst[b].ntp;
@@ -1484,6 +1513,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   }
   c->n_wg = n_wg;
   c->n_units = (int)udev.size();
+  c->n_ctr = n_ctr;
   // A latency-bound plan gives every workgroup one unit; its state and
   // coefficients then stay in LDS for the whole launch, which takes the
   // global round trips of the output and the update out of every step (a
@@ -1566,7 +1596,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   ALLOC(c->dCoef, sizeof(float) * coef.size());
   ALLOC(c->dState, sizeof(float) * c->state0.size());
   ALLOC(c->dPart, sizeof(float) * (size_t)(part_floats + 64));
-  ALLOC(c->dCtr, sizeof(unsigned int) * d->batch);
+  ALLOC(c->dCtr, sizeof(unsigned int) * n_ctr);
   ALLOC(c->dFlags, sizeof(int) * (2 + 2 * d->batch));
   ALLOC(c->dStep, sizeof(long long));
   ALLOC(c->dE, sizeof(float) * (size_t)(e_floats + 1));
@@ -1645,6 +1675,7 @@ int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
   P.part = c->dPart;
   P.ctr = c->dCtr;
   P.flags = c->dFlags;
+  P.timeout_ticks = d->barrier_us > 0 ? 100ull * (unsigned long long)d->barrier_us : kBarrierTicks;
   P.step_base = c->dStep;
   P.red_floats = red_floats;
   P.mode_floats = mode_floats;
@@ -1667,7 +1698,7 @@ int modal_reset(modal_ctx* c, void* stream_) {
   }
   HIP_TRY(hipMemcpyAsync(c->dState, c->state0.data(), sizeof(float) * c->state0.size(),
                          hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(c->dCtr, 0, sizeof(unsigned int) * c->batch, s));
+  HIP_TRY(hipMemsetAsync(c->dCtr, 0, sizeof(unsigned int) * c->n_ctr, s));
   HIP_TRY(hipMemsetAsync(c->dFlags, 0, sizeof(int) * 2, s));
   HIP_TRY(hipMemsetAsync(c->dStep, 0, sizeof(long long), s));
   c->steps = 0;
@@ -1816,12 +1847,12 @@ int modal_run_noalloc(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride,
   if (c->linear || c->shared)
     return fail(MODAL_ESTATE, "modal_run_noalloc steps the persistent recursion only; this context "
                               "runs the linear closed form or the shared-tensor path (use modal_run)");
-  // scratch layout: counters [batch] at 0, partial forces from the next
+  // scratch layout: arrival words [n_ctr] at 0, partial forces from the next
   // 256-byte boundary (the layout of the context's own buffers)
-  const size_t ctr_bytes = (sizeof(unsigned int) * (size_t)c->batch + 255) & ~(size_t)255;
+  const size_t ctr_bytes = (sizeof(unsigned int) * (size_t)c->n_ctr + 255) & ~(size_t)255;
   const size_t need = ctr_bytes + sizeof(float) * (size_t)(c->part_floats + 64);
   if (need > kScratchBytes)
-    return fail(MODAL_EINVAL, "modal_run_noalloc: the batch's partial forces and counters need " +
+    return fail(MODAL_EINVAL, "modal_run_noalloc: the batch's partial forces and arrival words need " +
                                   std::to_string(need) + " bytes; the scratch holds " +
                                   std::to_string(kScratchBytes) + " (use modal_run)");
   int dev = -1;
@@ -1833,7 +1864,7 @@ int modal_run_noalloc(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride,
   unsigned int* ctr = reinterpret_cast<unsigned int*>(base);
   float* part = reinterpret_cast<float*>(base + ctr_bytes);
   hipStream_t s = (hipStream_t)stream_;
-  // another call may have left other counters behind: set them to where this
+  // another call may have left other words behind: set them to where this
   // context's steps stand (a fill kernel, so a capturing caller records no
   // memset node)
   HIP_TRY(launch_ctr_fill(c->P.inst, c->batch, c->dStep, ctr, s));
@@ -2025,7 +2056,7 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     int r = dalloc(&c->dAdj, sizeof(float) * 4 * (size_t)sf);
     if (!r) r = dalloc(&c->dAcc, sizeof(float) * 12 * (size_t)sf);
     if (!r) r = dalloc(&c->dGPart, sizeof(float) * (size_t)(2 * c->part_floats + 64));
-    if (!r) r = dalloc(&c->dGCtr, sizeof(unsigned int) * c->batch);
+    if (!r) r = dalloc(&c->dGCtr, sizeof(unsigned int) * c->n_ctr);
     if (r) return r;
   }
   // forward from the initial state with checkpoints (unless the last runs
@@ -2044,7 +2075,7 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   }
   HIP_TRY(hipMemsetAsync(c->dAdj, 0, sizeof(float) * 4 * (size_t)sf, s));
   HIP_TRY(hipMemsetAsync(c->dAcc, 0, sizeof(float) * 12 * (size_t)sf, s));
-  HIP_TRY(hipMemsetAsync(c->dGCtr, 0, sizeof(unsigned int) * c->batch, s));
+  HIP_TRY(hipMemsetAsync(c->dGCtr, 0, sizeof(unsigned int) * c->n_ctr, s));
   const bool rows_on = g_row && c->rows_total > 0;
   if (rows_on) HIP_TRY(hipMemsetAsync(c->dRacc, 0, sizeof(float) * 2 * (size_t)c->rows_total, s));
   GradParams G{};
@@ -2069,6 +2100,7 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   G.part = c->dGPart;
   G.ctr = c->dGCtr;
   G.flags = F.flags;
+  G.timeout_ticks = F.timeout_ticks;
   G.red_floats = (c->tangent ? 3 : 2) * c->red_floats;
   G.rrec = rows_on ? c->dRrec : nullptr;
   G.rows_total = c->rows_total;
@@ -2096,7 +2128,8 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
     G.seg_base = s0;
     G.seg_len = len;
     G.done_before = n_steps - s0 - len;
-    HIP_TRY(launch_grad(G, c->gm, c->tangent, c->nw_grad[c->tangent], c->n_wg, c->grad_lds_v[c->tangent], s));
+    HIP_TRY(launch_grad(G, c->gm, c->tangent, c->nw_grad[c->tangent], c->res_stride > 0 && c->nw_grad[c->tangent] > 1,
+                        c->n_wg, c->grad_lds_v[c->tangent], s));
     if (rows_on) HIP_TRY(launch_row_sum(c->dRrec, len, c->rows_total, c->dRacc, s));
     if (tens_on)
       HIP_TRY(launch_tensor_grad(c->dTJobs, (int)tjobs.size(), tj_nin, tj_nt, G.rec_x, c->dUrec, c->dTrec, mf,

@@ -16,7 +16,8 @@
 //        d^{n+1} = m q^n - p d^n + r (f_ext^n - F^n),  q^{n+1} = q^n + d^{n+1}
 //      (m = g + p - 1 = -r omega^2 for Stormer-Verlet), where instances split
 //      over several workgroups first exchange their partial forces through
-//      global memory and wait on a per-instance arrival counter.
+//      global memory and wait until every slab of the instance has stored
+//      its arrival word for the step.
 // The coupling tensor is streamed from HBM once per step with 16-byte
 // non-temporal loads; each element is used once, so it goes straight to
 // registers.  LDS holds q^n and the cross-lane reduction of V.
@@ -131,6 +132,144 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
   }
 }
 
+// The dense sweep over a range of row blocks instead of whole rows: blocks
+// [t0, t1) of the unit whose rows start at row0, block t being block t % nblk
+// of row row0 + t / nblk.  Used when a workgroup owns a single unit and its
+// waves share the unit's blocks evenly, so that a unit of fewer rows than
+// waves keeps every wave busy.  A row that lies wholly in the range is
+// finished here (eta_n V_n added to the force).  A row that the range cuts
+// (at most its first and its last) gives only partial V and eta_n, which
+// are linear in the blocks summed: the partial V is parked in `defer` (two
+// slots of ntp floats) and the partial eta_n and the row index in the
+// wave's exchange words (slot 0: a row the range enters mid-row, slot 1: a
+// row it leaves mid-row; row -1 = unused), for vk_rows_finish.
+template <int GM, int DEPTH>
+__device__ void vk_rows_range(const float* __restrict__ Hb, int nt, int ntp, int qs, int row0, int t0,
+                              int t1, const float* Xs, float* red, float4 (&Fa)[GM], int G, int lane,
+                              float* defer, float* xv, int* xr) {
+  constexpr int J = kSweepLoads;
+  if (lane == 0) {
+    xr[0] = -1;
+    xr[1] = -1;
+  }
+  if (t1 <= t0) return;
+  const int nc = ntp >> 2;
+  const int qsnc = qs * nc;
+  int voff[J], sub[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int v = lane + kWave * j;
+    voff[j] = 16 * v;
+    sub[j] = v < qsnc ? v / nc : 0;
+  }
+  const int nblk = (nt + qs - 1) / qs;
+  const long long blk_floats = (long long)qs * ntp;
+  const long long row_floats = (long long)nt * ntp;
+  const int blk_bytes = 4 * qs * ntp;
+  const int last_bytes = 4 * (nt - (nblk - 1) * qs) * ntp;
+  // loader: block lt (flattened), row ln, block lb of that row
+  int lt = t0, ln = row0 + t0 / nblk, lb = t0 % nblk;
+  auto load = [&](float4 (&h)[J]) {
+    const bool live = lt < t1;
+    const float* bp = Hb + (live ? (long long)ln * row_floats + (long long)lb * blk_floats : 0);
+    const int bytes = live ? (lb == nblk - 1 ? last_bytes : blk_bytes) : 0;
+    const v4i r = buf_rsrc(bp, bytes);
+#pragma unroll
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+    ++lt;
+    if (++lb == nblk) {
+      lb = 0;
+      ++ln;
+    }
+  };
+  float4 ha[J], hb[J], acc[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
+  int t = t0, n = row0 + t0 / nblk, b = t0 % nblk, bfirst = b;
+  auto step = [&](float4 (&hc)[J], float4 (&hn)[J]) -> bool {
+    load(hn);
+    const int q0 = b * qs;
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = fma4(hc[j], Xs[min(q0 + sub[j], nt - 1)], acc[j]);
+    ++t;
+    if (++b < nblk && t < t1) return true;
+    // the row, or the range's share of it, is summed
+    float* rb = red + (n & 1) * qs * ntp;
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      if (voff[j] < blk_bytes) st4(rb + (voff[j] >> 2), acc[j]);
+    wave_lds_sync();
+    float eta = 0.f;
+    float4 V[GM];
+#pragma unroll
+    for (int g = 0; g < GM; ++g) {
+      V[g] = f4(0.f);
+      const int k4 = lane + kWave * g;
+      if (g < G && k4 < nc) {
+        const float4 sv = sum_strided4(rb + 4 * k4, qs, ntp);
+        V[g] = sv;
+        eta += dot4(sv, ld4(Xs + 4 * k4));
+      }
+    }
+    eta = wave_sum(eta);
+    if (bfirst == 0 && b == nblk) {
+#pragma unroll
+      for (int g = 0; g < GM; ++g) Fa[g] = fma4(V[g], eta, Fa[g]);
+    } else {
+      const int slot = bfirst > 0 ? 0 : 1;
+#pragma unroll
+      for (int g = 0; g < GM; ++g) {
+        const int k4 = lane + kWave * g;
+        if (g < G && k4 < nc) st4(defer + slot * ntp + 4 * k4, V[g]);
+      }
+      if (lane == 0) {
+        xv[slot] = eta;
+        xr[slot] = n;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
+    b = 0;
+    bfirst = 0;
+    ++n;
+    return t < t1;
+  };
+  load(ha);
+  if (DEPTH == 2) {
+    while (step(ha, hb) && step(hb, ha)) {
+    }
+  } else {
+    float4 hx[J];
+    load(hb);
+    while (step(ha, hx) && step(hb, ha) && step(hx, hb)) {
+    }
+  }
+}
+
+// Completes the rows that vk_rows_range left to several waves, after a
+// workgroup barrier: eta_n is the sum of the partials of every wave that
+// holds row n (in wave order), and each of those waves adds eta_n times its
+// partial V_n.  xv, xr: the exchange words of all nw waves (this wave's at
+// 2 wave).
+template <int GM>
+__device__ void vk_rows_finish(const float* xv, const int* xr, int nw, int wave, int ntp,
+                               const float* defer, float4 (&Fa)[GM], int G, int lane) {
+  const int nc = ntp >> 2;
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot) {
+    const int n = xr[2 * wave + slot];
+    if (n < 0) continue;
+    float eta = 0.f;
+    for (int i = 0; i < 2 * nw; ++i)
+      if (xr[i] == n) eta += xv[i];
+#pragma unroll
+    for (int g = 0; g < GM; ++g) {
+      const int k4 = lane + kWave * g;
+      if (g < G && k4 < nc) Fa[g] = fma4(ld4(defer + slot * ntp + 4 * k4), eta, Fa[g]);
+    }
+  }
+}
+
 // ---------------------------------------------- parity-blocked von Karman rows
 // Rows [row0, row1) of an instance stored parity-blocked: modes are grouped
 // by class (class i on internal modes [cls[i], cls[i+1])), and in-plane row
@@ -177,9 +316,12 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
   if (row1 <= row0) return;
   const int ntp = I.ntp;
   const int nc_modes = ntp >> 2;
-  int co[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) co[i] = I.cls[i];
+  // class boundaries, read with selects (a runtime index into a private
+  // array would put it in scratch memory)
+  const int c0 = I.cls[0], c1 = I.cls[1], c2 = I.cls[2], c3 = I.cls[3], c4 = I.cls[4];
+  auto co = [&](int i) {
+    return i <= 0 ? c0 : (i == 1 ? c1 : (i == 2 ? c2 : (i == 3 ? c3 : c4)));
+  };
   float* rd = red + 2 * kSlotFloats;  // [kSweepLoads * 64] per-slot row dot partials
   float* vrow = rd + J * kWave;       // [ntp] row-dot part of V for the current row
   for (int k = lane; k < ntp; k += kWave) vrow[k] = 0.f;
@@ -187,7 +329,7 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
   // block offsets of row ln
   int ln = row0, li = 0, lb = 0;
   int4 jv = jm[2 * row0], jo = jm[2 * row0 + 1];
-  auto has_block = [&](int i) { return co[i + 1] > co[i] && sel4(jv, i) >= 0; };
+  auto has_block = [&](int i) { return co(i + 1) > co(i) && sel4(jv, i) >= 0; };
   // a paired block's partner (-1) is skipped like an empty one
   auto next_row = [&]() {
     if (++ln < row1) {
@@ -211,14 +353,14 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
     int bytes = 0;
     m = BlkMeta{0, 0, 0, 0, 0, 1};
     if (live) {
-      const int R = co[li + 1] - co[li];
+      const int R = co(li + 1) - co(li);
       const int je = sel4(jv, li);
       const int tj = je & 7;
-      m.tc = co[tj] >> 2;
-      m.tlen = (co[tj + 1] - co[tj]) >> 2;
+      m.tc = co(tj) >> 2;
+      m.tlen = (co(tj + 1) - co(tj)) >> 2;
       m.qs = (je >> 4) & 511;  // min(R, 256 / tlen), from the map entry
       const int nb = je >> 13;  // pieces of the block
-      m.q0 = co[li] + lb * m.qs;
+      m.q0 = co(li) + lb * m.qs;
       m.rows = min(m.qs, R - lb * m.qs);
       bp = Hb + sel4(jo, li) + (long long)lb * m.qs * 4 * m.tlen;
       bytes = 16 * m.rows * m.tlen;
@@ -510,11 +652,32 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
       if (I.kind == KIND_VK) {
         __syncthreads();  // q^n in LDS
         const int R = U.row1 - U.row0;
-        const int r0 = U.row0 + (R * wave) / NW, r1 = U.row0 + (R * (wave + 1)) / NW;
-        if (I.blk)
-          vk_rows_blk<GM>(P.H + I.h_off, P.jmap + I.jmap_off, I, r0, r1, Xs, red, Fa, G, lane);
-        else
-          vk_rows<GM, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa, G, lane);
+        if (RES && NW > 1 && !I.blk && R < NW) {
+          // one unit per workgroup with fewer rows than waves: the waves
+          // share its row blocks evenly (with whole rows per wave, measured
+          // faster otherwise: 50/50 plates 9.1 us per step against 11.8)
+          const int nblk = (I.nt + U.qs - 1) / U.qs;
+          const int T = R * nblk;
+          float* xv = L.xch;
+          int* xr = reinterpret_cast<int*>(L.xch + 2 * NW);
+          float* defer = red + 2 * U.qs * I.ntp;
+          vk_rows_range<GM, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, I.nt, I.ntp, U.qs, U.row0,
+                                                          (T * wave) / NW, (T * (wave + 1)) / NW, Xs, red,
+                                                          Fa, G, lane, defer, xv + 2 * wave, xr + 2 * wave);
+          bool cut = false;  // a wave boundary inside a row
+          for (int w = 1; w < NW; ++w) cut |= ((T * w) / NW) % nblk != 0;
+          if (cut) {
+            __syncthreads();  // every wave's partial eta_n of the rows it shares
+            vk_rows_finish<GM>(xv, xr, NW, wave, I.ntp, defer, Fa, G, lane);
+          }
+        } else {
+          const int r0 = U.row0 + (R * wave) / NW, r1 = U.row0 + (R * (wave + 1)) / NW;
+          if (I.blk)
+            vk_rows_blk<GM>(P.H + I.h_off, P.jmap + I.jmap_off, I, r0, r1, Xs, red, Fa, G, lane);
+          else
+            vk_rows<GM, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa,
+                                                      G, lane);
+        }
         if (NW > 1) {
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
@@ -556,7 +719,8 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           __builtin_amdgcn_wave_barrier();
           if (lane == 0)
-            __hip_atomic_fetch_add(&P.ctr[U.inst], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&P.ctr[I.ctr_off + U.slab], (unsigned int)(n + 1), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
       }
       __syncthreads();  // LDS reused by the next unit
@@ -567,8 +731,7 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
       const InstDev I = P.inst[U.inst];
       if (I.nslab == 1) continue;
       if (wave == 0) {
-        const unsigned int target = (unsigned int)I.nslab * (unsigned int)(n + 1);
-        const bool ok = wait_counter(&P.ctr[U.inst], target, P.flags);
+        const bool ok = wait_slabs(P.ctr + I.ctr_off, I.nslab, (unsigned int)(n + 1), P.flags, P.timeout_ticks);
         if (lane == 0) L.flag[0] = ok ? 1 : 0;
       }
       __syncthreads();
@@ -576,14 +739,41 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
         res_copy(false);
         return;
       }
-      if (wave == 0) {
+      const int nc = I.ntp >> 2;
+      const int G = (nc + kWave - 1) / kWave;
+      const float* src = P.part + I.part_off + (long long)(n & 1) * I.nslab * I.ntp;
+      if (RES && NW > 1 && I.nslab >= 2 * NW) {
+        // one unit per workgroup and many slabs: every wave sums every NW-th
+        // partial force, and wave 0 adds the waves' sums
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        float4 F[GM];
+#pragma unroll
+        for (int g = 0; g < GM; ++g) {
+          F[g] = f4(0.f);
+          const int k4 = lane + kWave * g;
+          if (g < G && k4 < nc) {
+            F[g] = sum_slabs4(src + 4 * k4, wave, NW, I.nslab, I.ntp);
+            st4(red + 4 * k4, F[g]);
+          }
+        }
+        __syncthreads();
+        if (wave == 0) {
+          const ModeRefs M = refs(U, I);
+          float e = 0.f;
+          if (n < I.n_exc) e = P.e_ext[I.e_off + n];
+#pragma unroll
+          for (int g = 0; g < GM; ++g) {
+            const int k4 = lane + kWave * g;
+            if (g < G && k4 < nc)
+              for (int w = 1; w < NW; ++w) F[g] = add4(F[g], ld4(L.red + w * P.red_floats + 4 * k4));
+          }
+          update_groups<GM>(M, nc, e, F, G, lane, P.flags);
+        }
+      } else if (wave == 0) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const ModeRefs M = refs(U, I);
-        const int nc = I.ntp >> 2;
-        const int G = (nc + kWave - 1) / kWave;
         float e = 0.f;
         if (n < I.n_exc) e = P.e_ext[I.e_off + n];
-        const float* src = P.part + I.part_off + (long long)(n & 1) * I.nslab * I.ntp;
         float4 F[GM];
 #pragma unroll
         for (int g = 0; g < GM; ++g) {
@@ -605,14 +795,15 @@ __global__ void advance_kernel(long long* step_base, int n_steps) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step_base += n_steps;
 }
 
-// Arrival counters as they stand after *step_base steps from a reset: every
-// slab of an instance has arrived once per step, ctr[b] = nslab_b * steps
-// (mod 2^32, like the waits' targets).  Lets a launch run on counters that
-// another context left behind.
+// Arrival words as they stand after *step_base steps from a reset: every
+// slab has published every step (mod 2^32, like the waits' targets).  Lets
+// a launch run on words that another context left behind.
 __global__ void ctr_fill_kernel(const InstDev* inst, int batch, const long long* step_base,
                                 unsigned int* ctr) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < batch) ctr[b] = (unsigned int)inst[b].nslab * (unsigned int)(unsigned long long)*step_base;
+  if (b >= batch) return;
+  const unsigned int v = (unsigned int)(unsigned long long)*step_base;
+  for (int t = 0; t < inst[b].nslab; ++t) ctr[inst[b].ctr_off + t] = v;
 }
 
 // Symmetry and finiteness of each instance's Ht: out[2b] = max |H - H^T|,

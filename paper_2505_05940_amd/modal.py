@@ -45,7 +45,7 @@ class modal_desc(C.Structure):
     _fields_ = [("batch", C.c_int32), ("scheme", C.c_int32),
                 ("inst", C.POINTER(modal_instance)), ("fs", C.c_double),
                 ("flags", C.c_int32), ("max_workgroups", C.c_int32),
-                ("chunk_steps", C.c_int32), ("waves", C.c_int32)]
+                ("chunk_steps", C.c_int32), ("waves", C.c_int32), ("barrier_us", C.c_int32)]
 
 
 class ModalError(RuntimeError):
@@ -130,7 +130,7 @@ def vk_coupling_sine(Lx, Ly, m, q, a, b, scale_n, grid=None, threads=0):
 
 
 def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_steps=0,
-                shapes_only=False, waves=0):
+                shapes_only=False, waves=0, barrier_us=0):
     """modal_desc for a list of instance dicts; returns (desc, keep-alive list, n_t list).
     With shapes_only (planning previews, which never read tensors) a vk
     instance may give "n_in" instead of "Ht"."""
@@ -192,7 +192,8 @@ def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_ste
             s.e_ext = e.ctypes.data_as(_fp)
             s.n_exc = len(e)
     desc = modal_desc(batch=batch, scheme=SCHEME[scheme], inst=arr, fs=float(fs), flags=flags,
-                      max_workgroups=max_workgroups, chunk_steps=chunk_steps, waves=waves)
+                      max_workgroups=max_workgroups, chunk_steps=chunk_steps, waves=waves,
+                      barrier_us=barrier_us)
     return desc, keep, n_t
 
 
@@ -217,11 +218,11 @@ class Sim:
     """
 
     def __init__(self, instances, fs, scheme="sv", flags=0, max_workgroups=0,
-                 chunk_steps=0, stream=None, waves=0):
+                 chunk_steps=0, stream=None, waves=0, barrier_us=0):
         self._ctx = C.c_void_p()
         self.batch = len(instances)
         desc, keep, self.n_t = _build_desc(instances, fs, scheme, flags, max_workgroups, chunk_steps,
-                                           waves=waves)
+                                           waves=waves, barrier_us=barrier_us)
         self._stream = stream
         _check(lib.modal_init(C.byref(self._ctx), C.byref(desc), _stream_handle(stream)))
         self.modes_total = sum(self.n_t)
