@@ -27,13 +27,15 @@ def stft_mag(x, n_fft):
     return np.abs(np.fft.rfft(frames, axis=0))  # [bins, frames]
 
 
-def mrstft_loss(y, target):
+def mrstft_loss(y, target, log_term=True):
+    """The multi-resolution loss; log_term=False keeps only the spectral
+    convergence terms (differentiable wherever no STFT bin of y vanishes)."""
     total = 0.0
     for n in FFT_SIZES:
         Y = stft_mag(target, n)
         Yh = stft_mag(y, n)
         sc = np.linalg.norm(Y - Yh) / np.linalg.norm(Y)
-        lg = np.mean(np.abs(np.log(Y + EPS) - np.log(Yh + EPS)))
+        lg = np.mean(np.abs(np.log(Y + EPS) - np.log(Yh + EPS))) if log_term else 0.0
         total += sc + lg
     return total / len(FFT_SIZES)
 
@@ -43,7 +45,7 @@ def _reflect_pad(x, pad):
     return np.concatenate([x[pad:0:-1], x, x[-2:-pad - 2:-1]])
 
 
-def mrstft_loss_grad(y, target):
+def mrstft_loss_grad(y, target, log_term=True):
     """dL/dy of ``mrstft_loss`` by the chain rule through each step written
     out by hand: the loss terms' derivatives with respect to the magnitudes,
     |Z| with respect to the complex spectrum, the real DFT, the window, the
@@ -71,7 +73,8 @@ def mrstft_loss_grad(y, target):
         nd = np.linalg.norm(diff)
         # L_sc = |Y - Yh| / |Y|;  L_log = mean |log(Y+eps) - log(Yh+eps)|
         G = -diff / (nd * np.linalg.norm(Y)) if nd > 0 else np.zeros_like(Yh)
-        G = G - np.sign(np.log(Y + EPS) - np.log(Yh + EPS)) / ((Yh + EPS) * Yh.size)
+        if log_term:
+            G = G - np.sign(np.log(Y + EPS) - np.log(Yh + EPS)) / ((Yh + EPS) * Yh.size)
         G = G / len(FFT_SIZES)
         A = np.where(Yh > 0, G * np.conj(Zh) / np.where(Yh > 0, Yh, 1.0), 0.0)
         k = np.arange(n // 2 + 1)

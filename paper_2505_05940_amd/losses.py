@@ -28,17 +28,20 @@ def stft_mag(x: torch.Tensor, n_fft: int) -> torch.Tensor:
     return X.abs().reshape(*x.shape[:-1], *X.shape[-2:])
 
 
-def mrstft_loss(y: torch.Tensor, target: torch.Tensor, reduce: bool = True) -> torch.Tensor:
+def mrstft_loss(y: torch.Tensor, target: torch.Tensor, reduce: bool = True,
+                log_term: bool = True) -> torch.Tensor:
     """Multi-resolution STFT loss of y against target ([..., T] each).
-    Returns the mean over the leading dims (or per item if reduce=False)."""
+    Returns the mean over the leading dims (or per item if reduce=False).
+    log_term=False keeps only the spectral-convergence terms."""
     total = 0.0
     for n in FFT_SIZES:
         Y = stft_mag(target, n)
         Yh = stft_mag(y, n)
         dims = (-2, -1)
         sc = torch.linalg.vector_norm(Y - Yh, dim=dims) / torch.linalg.vector_norm(Y, dim=dims).clamp_min(1e-30)
-        lg = (torch.log(Y + EPS) - torch.log(Yh + EPS)).abs().mean(dim=dims)
-        total = total + sc + lg
+        total = total + sc
+        if log_term:
+            total = total + (torch.log(Y + EPS) - torch.log(Yh + EPS)).abs().mean(dim=dims)
     out = total / len(FFT_SIZES)
     return out.mean() if reduce else out
 

@@ -71,42 +71,52 @@ def test_modalfn_small_plates_against_oracle(torch_gpu):
 @pytest.mark.timeout(900)
 def test_config4_mrstft_gradient_against_oracle_and_differences(torch_gpu):
     """The 200/200-mode fitting plate over 1 s (44 100 steps, checkpoints
-    every 512): the MR-STFT loss against the oracle's target output and its
-    theta-gradient through ModalFn, against the FP64 oracle's reverse
-    recursion + chain rule and against its central differences at the
-    configured relative step 1e-4, stored in tests/golden/gradient_200.json.
-    Bar: 1e-3 per component (relative to the oracle's value)."""
+    every 512), the configured gradient: the theta-gradient through ModalFn of
+    the MR-STFT loss against the oracle's target output, compared with the
+    FP64 oracle's reverse recursion + chain rule (tests/golden/
+    gradient_200.json) to 1e-3 per component.  The same for the loss's
+    spectral-convergence terms alone (gradient_200_sc.json), also against
+    the oracle's central differences at the configured relative step 1e-4,
+    to 1e-3 per component.  (The log-magnitude term is an absolute value per
+    STFT bin; at a step of 1e-4 the differences of the full loss cross its
+    kinks and miss the derivative by up to tens of per cent for D^ and a, so
+    that check is made on the smooth part of the loss.)"""
     torch = torch_gpu
     from paper_2505_05940_amd import fit
     from paper_2505_05940_amd.losses import mrstft_loss
-    path = os.path.join(GOLDEN, "gradient_200.json")
-    if not os.path.exists(path):
-        pytest.fail(f"{path} missing: run tests/golden/make_golden.py gradient")
-    rec = json.load(open(path))
+    recs = {}
+    for name in ("gradient_200", "gradient_200_sc"):
+        path = os.path.join(GOLDEN, name + ".json")
+        if not os.path.exists(path):
+            pytest.fail(f"{path} missing: run tests/golden/make_golden.py")
+        recs[name] = json.load(open(path))
     arr = np.load(os.path.join(GOLDEN, "gradient_200.npz"))
     fw = W.plate_fit()
     st = _setup(fw)
-    th0 = np.asarray(rec["theta0"])
+    th0 = np.asarray(recs["gradient_200"]["theta0"])
     assert np.allclose(th0, fw["theta0"], rtol=1e-15)
-    steps = int(rec["steps"])
+    steps = int(recs["gradient_200"]["steps"])
     target = torch.tensor(arr["target"], device="cuda").reshape(1, -1)
-    _say("case: ModalFn, 200/200 plate, 44100 steps, MR-STFT against the oracle's target")
-    theta = torch.tensor(th0[None], dtype=torch.float64, requires_grad=True)
-    y = fit.ModalFn.apply(theta, st, steps, 512)
-    e = float(np.linalg.norm(y[0].detach().double().cpu().numpy() - arr["y0"].astype(float))
-              / np.linalg.norm(arr["y0"].astype(float)))
-    _say(f"  forward rel L2 against the oracle: {e:.2e}")
-    assert e < 1e-5, e
-    L = mrstft_loss(y, target)
-    _say(f"  loss {L.item():.6f} (oracle {rec['loss']:.6f})")
-    assert abs(L.item() - rec["loss"]) < 1e-5 * abs(rec["loss"])
-    L.backward()
-    got = theta.grad.numpy()[0]
-    for name, key in (("oracle reverse", "grad_reverse"), ("central differences 1e-4", "grad_fd")):
-        ref = np.asarray(rec[key])
-        err = np.abs(got - ref) / np.abs(ref)
-        _say(f"  vs {name}: {got} / {ref}, rel err {err}")
-        assert err.max() < 1e-3, (name, got, ref, err)
+    for name, log_term in (("gradient_200", True), ("gradient_200_sc", False)):
+        rec = recs[name]
+        _say(f"case: ModalFn, 200/200 plate, {steps} steps, {rec['loss_terms'] if 'loss_terms' in rec else 'MR-STFT'}")
+        theta = torch.tensor(th0[None], dtype=torch.float64, requires_grad=True)
+        y = fit.ModalFn.apply(theta, st, steps, 512)
+        e = float(np.linalg.norm(y[0].detach().double().cpu().numpy() - arr["y0"].astype(float))
+                  / np.linalg.norm(arr["y0"].astype(float)))
+        _say(f"  forward rel L2 against the oracle: {e:.2e}")
+        assert e < 1e-5, e
+        L = mrstft_loss(y, target, log_term=log_term)
+        _say(f"  loss {L.item():.8f} (oracle {rec['loss']:.8f})")
+        assert abs(L.item() - rec["loss"]) < 1e-5 * abs(rec["loss"])
+        L.backward()
+        got = theta.grad.numpy()[0]
+        refs = [("oracle reverse", "grad_reverse")] + ([] if log_term else [("differences 1e-4", "grad_fd")])
+        for what, key in refs:
+            ref = np.asarray(rec[key])
+            err = np.abs(got - ref) / np.abs(ref)
+            _say(f"  vs {what}: {got} / {ref}, rel err {err}")
+            assert err.max() < 1e-3, (name, what, got, ref, err)
 
 
 @pytest.mark.timeout(600)
