@@ -146,16 +146,17 @@ def dense_path(batch, n_modes, samples, launches, seed):
     }
 
 
-FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def linear_path(batch, n_modes, seed):
     """Linear strings (closed-form path) for one second at 44.1 kHz, with the
-    step-by-step recursion of the same batch timed beside it.  FP64
-    operations per (mode, sample) counted as 4: the three-term recurrence
-    that advances each mode's output (a multiply and a fused multiply-add)
-    and the add into the sample; the direct powers each lane takes every 32
-    samples are not counted."""
+    step-by-step recursion of the same batch timed beside it.  The closed
+    form runs in float-float arithmetic; FP32 operations per (mode, sample)
+    counted as 60 (an FMA as two): the three-term recurrence that advances
+    each mode's output (two float-float products of 10 and a float-float sum
+    of 20) and the float-float add into the sample (20); the powers each lane
+    takes every 32 samples are not counted."""
     import torch
     import workloads as W
     from paper_2505_05940_amd import modal
@@ -177,16 +178,16 @@ def linear_path(batch, n_modes, seed):
         res[name] = a.elapsed_time(b) * 1e-3
         sim.close()
     t = res["closed_form"]
-    achieved = 4.0 * modes * 44100 / t / 1e12
+    achieved = 60.0 * modes * 44100 / t / 1e12
     return {
         "workload": f"{batch} linear stiff strings, {modes} modes in all, 44100 samples, "
                     f"{batch // 8} with a 1000-sample forcing",
         "value": modes * 44100 / t, "unit": "instance*mode*samples/s",
         "seconds": t, "recursion_seconds": res["recursion"],
         "time_basis": "whole closed-form run (sum and convolution kernels, segment upload)",
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "modal::lin_sum_kernel (FP64)"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "modal::lin_sum_kernel (float-float)"},
     }
 
 
@@ -269,57 +270,67 @@ def single_instance_rates():
 
 
 def fit_wall_time():
-    """Wall time to the target spectral loss: a proposal network is trained
-    on 200 000 plates simulated by the dense path (60 epochs), then 64
-    held-out seeded targets (40/40 modes, 0.25 s) are fitted by gradients
-    through the time loop from the network's guesses, with Adam (one-cycle
-    cosine, 60 iterations at most).  The figure is the wall time, from the
-    start of the fit (inference included), until half of the targets have an
-    MR-STFT loss below 0.1 (None if fewer than half get there)."""
+    """Wall time to the target spectral loss, proposal-initialised against
+    plain fitting: a proposal network is trained on 200 000 plates simulated
+    by the dense path (60 epochs); then 64 held-out seeded targets (40/40
+    modes, 0.25 s) are fitted by gradients through the time loop with Adam
+    (one-cycle cosine, 60 iterations at most), once from the network's
+    guesses (inference included in the wall time) and once from the prior
+    centre, on the same targets and budget.  The headline figure is the
+    proposal arm's wall time, from the start of its fit, until half of the
+    targets have an MR-STFT loss below 0.1 (None if fewer than half get
+    there)."""
     from paper_2505_05940_amd import proposal
-    res = proposal.run(proposal.bench_args(), stream=sys.stderr)
-    arm = res["arms"]["proposal"]
-    return arm["time_to_half_s"], {
-        "workload": "64 held-out plates (40/40 modes, 11025 steps), proposal-initialised fits, "
-                    "target MR-STFT < 0.1",
-        "time_to_half_s": arm["time_to_half_s"], "success_rate": arm["success_rate"],
-        "time_to_target_median_s": arm["time_to_target_median_s"],
-        "final_loss_median": arm["final_loss_median"], "iterations": arm["iterations"],
+    args = proposal.bench_args()
+    res = proposal.run(args, stream=sys.stderr)
+    keys = ("time_to_half_s", "success_rate", "time_to_target_median_s", "final_loss_median",
+            "iterations", "wall_s", "param_error_start", "param_error_end")
+    arms = {name: {k: arm[k] for k in keys} for name, arm in res["arms"].items()}
+    return res["arms"]["proposal"]["time_to_half_s"], {
+        "workload": f"{args.test} held-out plates ({args.modes}/{args.modes} modes, {args.steps} steps), "
+                    f"fits from the proposal and from the prior centre, target MR-STFT < {args.tol}",
+        "arms": arms,
+        "reduced_from_config": {"audio_s": [args.steps / 44100.0, 1.0], "targets": [args.test, 512],
+                                "max_iterations": [args.iters, 1000], "families": [["plate"], ["string", "plate"]]},
         "dataset_s": res["gen_s"], "train_s": res["train_s"], "proposal_z_err": res["proposal_z_err"],
+        "training_sims": args.train, "epochs": args.epochs,
     }
 
 
-def cpu_baseline(wls, n_inst, seconds, seed):
-    """The FP64 oracle's time loop on a seeded sample of the batch (its
-    coupling tensors built beforehand, untimed).  Each sampled instance runs
-    for about ``seconds / n_inst`` seconds from its initial state (the step
-    count set from a 5-step probe).  Rate = sum N x steps / time over the
-    sample, a ratio estimator of the whole batch's rate."""
-    from oracle import instances as OI
-    from oracle import simulate as OS
+def _cpu_info():
+    """nproc and the lscpu model and sockets of this host."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core"):
+                info[k.strip()] = v.strip()
     except Exception:
-        cores = os.cpu_count()
-    rng = np.random.default_rng(seed)
-    pick = sorted(rng.choice(len(wls), size=n_inst, replace=False).tolist())
-    work, secs, steps_used = 0, 0.0, []
-    for i in pick:
-        inst = OI.plate_instance(wls[i])
-        t0 = time.perf_counter()
-        OS.run(inst, 5, wls[i]["fs"])
-        per = (time.perf_counter() - t0) / 5
-        n_steps = int(max(20, min(44100, seconds / n_inst / per)))
-        t0 = time.perf_counter()
-        OS.run(inst, n_steps, wls[i]["fs"])
-        secs += time.perf_counter() - t0
-        work += wls[i]["n_t"] * n_steps
-        steps_used.append(n_steps)
-    return dict(value=work / secs, unit="instance*mode*samples/s", cores=int(cores),
+        pass
+    return info
+
+
+def cpu_baseline(wls, n_steps):
+    """The oracle's C++ FP64 time loop (oracle/cpp, compiled here with
+    -O3 -march=native -fopenmp) on all plates of the batch, on all host
+    threads, largest plates first: every plate built (untimed), then run for
+    n_steps steps from rest (timed).  Rate = sum N x n_steps / loop time; the
+    per-step cost does not change over a run, so the rate extrapolates
+    linearly to the full second."""
+    import tempfile
+    from oracle import cpu_batch as CB
+    d = tempfile.mkdtemp(prefix="vk_oracle_")
+    lib = CB.load(CB.compile_lib(os.path.join(d, "libvk_batch_oracle.so")))
+    _, t_build, t_loop, used = CB.run_batch(wls, n_steps, lib=lib)
+    modes = sum(w["n_t"] for w in wls)
+    return dict(value=modes * n_steps / t_loop, unit="instance*mode*samples/s", cores=used,
                 kind="oracle",
-                sample=f"instances {pick} (N={[wls[i]['n_t'] for i in pick]}) of the batch, "
-                       f"{steps_used} steps each from rest, FP64 numpy time loop, {secs:.1f} s")
+                sample=f"all {len(wls)} plates of the batch, {n_steps} steps each from rest "
+                       f"(of 44100; extrapolated linearly), C++ FP64 loop on {used} threads, "
+                       f"loop {t_loop:.1f} s, tensor build {t_build:.1f} s (untimed)",
+                host=_cpu_info())
 
 
 def main():
@@ -348,8 +359,8 @@ def main():
     ap.add_argument("--no-fit", action="store_true",
                     help="skip the fit wall-time measurement (proposal + gradient fitting)")
     ap.add_argument("--dense-modes", type=int, default=40)
-    ap.add_argument("--cpu-instances", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="steps of every batch plate in the CPU oracle baseline")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -478,7 +489,7 @@ def main():
         out["config"]["fit_wall_time_s"], out["fit"] = fit_wall_time()
         print(f"[bench] fit: {out['fit']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wls, args.cpu_instances, args.cpu_seconds, args.seed)
+        out["cpu_baseline"] = cpu_baseline(wls, args.cpu_steps)
     print(json.dumps(out))
 
 

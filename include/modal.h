@@ -150,11 +150,11 @@ typedef struct {
  * rounding inside the force (order of sums, where the row scale is applied).
  * Linear path: when every instance is MODAL_KIND_LINEAR (and neither
  * MODAL_FLAG_GRAD nor MODAL_FLAG_RECURSE is set), each mode's recursion is
- * solved in closed form from the roots of its characteristic polynomial and
- * modal_run evaluates the outputs of all requested steps in parallel in
- * FP64 (free response plus the excitation convolved with the impulse
- * response); MODAL_FLAG_GRAPH has no effect there.  A mode with a double
- * root keeps the batch on the recursion.
+ * solved in closed form from the roots of its characteristic polynomial
+ * (FP64 on the host) and modal_run evaluates the outputs of all requested
+ * steps in parallel in float-float arithmetic (free response plus the
+ * excitation convolved with the impulse response); MODAL_FLAG_GRAPH has no
+ * effect there.  A mode with a double root keeps the batch on the recursion.
  * Streaming path plans: a latency-bound batch (at most one instance per CU,
  * dense tensors under 64 MB per step, waves and max_workgroups 0, no
  * MODAL_FLAG_SPLIT_ANY) keeps its tensors dense, takes 8 waves per
@@ -296,20 +296,24 @@ int modal_set_tensor(modal_ctx *c, int32_t inst, const float *H, void *stream);
  * free output weights per mode):
  *   H[b][k] = sum over modes mu of instance b of
  *             w_mu (b1_mu z + b2_mu) / (z^2 + a1_mu z + a2_mu),  z = e^{i omega[k]}.
- * All pointers are device memory: coef [modes][5] = (a1, a2, b1, b2, w) in
- * FP64, modes of instance b at [mode_off[b], mode_off[b+1]) (int32
- * [batch + 1]); omega [n_freq] in radians per sample; H [batch][n_freq][2]
- * (real, imaginary) written.  Asynchronous on `stream`.  EINVAL for NULL
- * pointers, batch outside [1, 65535] or n_freq < 1. */
+ * All pointers are host memory, FP64: coef [modes][5] = (a1, a2, b1, b2, w),
+ * modes of instance b at [mode_off[b], mode_off[b+1]) (int32 [batch + 1],
+ * non-decreasing); omega [n_freq] in radians per sample; H [batch][n_freq][2]
+ * (real, imaginary) written.  The device evaluates the sums in float-float
+ * arithmetic (FP32 pairs, about 48 bits) from the split inputs, and the host
+ * adds the pairs back into FP64; near a lightly damped pole the relative
+ * error grows like 2^-48 / (gamma T).  Synchronous on `stream` (device
+ * buffers are allocated and freed within the call).  EINVAL for NULL
+ * pointers, batch outside [1, 65535], n_freq < 1 or a decreasing mode_off. */
 int modal_tf_response(const double *coef, const int32_t *mode_off, int32_t batch,
                       const double *omega, int32_t n_freq, double *H, void *stream);
 
 /* Gradient of L = sum_{b,k} Re(conj(g[b][k]) H[b][k]) with g = dL_dH
- * [batch][n_freq][2] (dL/dRe H, dL/dIm H), device memory, with respect to
- * every mode's (a1, a2, b1, b2, w): g_coef [modes][5] (device, written; modes
- * outside every instance's range are left as they are).  max_modes: the
- * largest mode count of an instance.  Same layout and errors as
- * modal_tf_response. */
+ * [batch][n_freq][2] (dL/dRe H, dL/dIm H), host memory, with respect to
+ * every mode's (a1, a2, b1, b2, w): g_coef [modes][5] (host, written; modes
+ * outside every instance's range are left as they are).  max_modes: at
+ * least the largest mode count of an instance.  Same layout, arithmetic and
+ * errors as modal_tf_response. */
 int modal_tf_grad(const double *coef, const int32_t *mode_off, int32_t batch, int32_t max_modes,
                   const double *omega, int32_t n_freq, const double *dL_dH, double *g_coef,
                   void *stream);

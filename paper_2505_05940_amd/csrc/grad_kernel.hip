@@ -523,9 +523,9 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
         float* rrow = P.rrec ? P.rrec + (long long)s * P.rows_total + I.row_off : nullptr;
         float* teta = P.trec ? P.trec + (n - P.seg_base) * 2LL * P.rows_total + I.row_off : nullptr;
         float* tw = teta ? teta + P.rows_total : nullptr;
-        if (SPLIT && NW > 1 && R < NW) {
-          // one unit per workgroup with fewer rows than waves: the waves
-          // share its row blocks evenly
+        if (SPLIT && NW > 1 && 2 * R <= NW) {
+          // one unit per workgroup with at most half as many rows as waves:
+          // the waves share its row blocks evenly
           const int nblk = (I.nt + U.qs - 1) / U.qs;
           const int T = R * nblk;
           constexpr int NR = TAN ? 3 : 2;

@@ -247,15 +247,21 @@ __host__ __device__ inline size_t shared_lds_bytes(int kt, int kc, int jt, int n
 constexpr int kLinWaves = 2;  // waves per closed-form workgroup
 constexpr int kLinRun = 32;   // steps per lane (strided by 64)
 
-// One mode: both roots of z^2 - g z - p as (log|z|, arg(z)/pi), their 64th
-// powers, and the recurrence y(n + 64) = a y(n) - b y(n - 64) that every
-// combination of the two root terms satisfies.  conj: z2 = conj(z1), only
-// root 1 is evaluated (its amplitude carries the factor 2).
+// A float-float complex number: real and imaginary parts as (high, low)
+// FP32 pairs whose sum carries about 48 bits.
+struct FFc {
+  float rh, rl, ih, il;
+};
+
+// One mode: both roots of z^2 - g z - p, their 64th powers, and the
+// recurrence y(n + 64) = a y(n) - b y(n - 64) that every combination of the
+// two root terms satisfies (a = Re(z1^64 + z2^64), b = Re((z1 z2)^64)), all
+// float-float, rounded from the host's FP64 values.  conj: z2 = conj(z1),
+// only root 1 is evaluated (its amplitude carries the factor 2).
 struct LinMode {
-  double2 s1, s2;
-  double a, b;
-  double lm1, f1, lm2, f2;
-  int conj, pad;
+  FFc z1, z2, s1, s2;
+  float ah, al, bh, bl;
+  int conj, pad[3];
 };
 
 // A run of output samples of one instance from one amplitude set: sample i
@@ -269,12 +275,12 @@ struct LinSeg {
   long long len;
 };
 
-// Per mode, what the amplitude sets are built from.
+// Per mode, what the amplitude sets are built from (float-float).
 struct LinInit {
-  double2 z1, z2, A, B, C;
-  double c, b;
+  FFc z1, z2, A, B, C;
+  float ch, cl, bh, bl;  // output weight c and force weight b
   long long e_off, n_exc;
-  int conj, pad;
+  int conj, pad[3];
 };
 
 struct LinForced {

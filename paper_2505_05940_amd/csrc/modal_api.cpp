@@ -33,21 +33,21 @@ hipError_t launch_restore(const float* ckpt, long long slot, int mode_floats, co
                           long long* step_base, long long step, unsigned int* ctr, hipStream_t s);
 hipError_t launch_shared(const SharedParams& P, int kt, int kc, int jt, int n_wg, hipStream_t s);
 hipError_t launch_row_sum(const float* rrec, int seg_len, int rows, float* acc, hipStream_t s);
-hipError_t launch_tf_response(const double* coef, const int* mode_off, int batch, const double* omega,
-                              int n_freq, double* H, hipStream_t s);
-hipError_t launch_tf_grad(const double* coef, const int* mode_off, int batch, int max_modes, const double* omega,
-                          int n_freq, const double* gH, double* g_coef, hipStream_t s);
+hipError_t launch_tf_response(const float2* coef, const int* mode_off, int batch, const FFc* z, int n_freq,
+                              FFc* H, hipStream_t s);
+hipError_t launch_tf_grad(const float2* coef, const int* mode_off, int batch, int max_modes, const FFc* z,
+                          int n_freq, const FFc* gH, float2* g_coef, hipStream_t s);
 hipError_t launch_sym_check(const float* H, int nin, int nt, int* bad, hipStream_t s);
 hipError_t launch_tensor_grad(const TGradJob* jobs, int n_jobs, int max_nin, int max_nt, const float* rec_x,
                               const float* urec, const float* trec, int mode_floats, int rows_total,
                               int seg_len, hipStream_t s);
-hipError_t launch_lin_sum(const LinMode* modes, const double4* amp, const double2* ztab, const LinSeg* segs,
+hipError_t launch_lin_sum(const LinMode* modes, const FFc* amp, const FFc* ztab, const LinSeg* segs,
                           int n_segs, long long max_len, float* out, hipStream_t s);
-hipError_t launch_lin_sum_f64(const LinMode* modes, const double4* amp, const double2* ztab,
-                              const LinSeg* segs, int n_segs, long long max_len, double* out, hipStream_t s);
-hipError_t launch_lin_amp(const LinInit* init, const LinMode* modes, int M, const float* e_ext, double4* amp,
-                          double2* ztab, hipStream_t s);
-hipError_t launch_lin_conv(const LinForced* forced, int n_forced, const double* h, long long h_stride,
+hipError_t launch_lin_sum_ff(const LinMode* modes, const FFc* amp, const FFc* ztab, const LinSeg* segs,
+                             int n_segs, long long max_len, float2* out, hipStream_t s);
+hipError_t launch_lin_amp(const LinInit* init, const LinMode* modes, int M, const float* e_ext, FFc* amp,
+                          FFc* ztab, hipStream_t s);
+hipError_t launch_lin_conv(const LinForced* forced, int n_forced, const float2* h, long long h_stride,
                            const float* e_ext, long long base, long long n_steps, long long window,
                            float* y, long long y_stride, hipStream_t s);
 }  // namespace modal
@@ -111,6 +111,14 @@ int round4(int n) { return (n + 3) & ~3; }
 void split(double v, float& hi, float& lo) {
   hi = (float)v;
   lo = (float)(v - (double)hi);
+}
+
+// FP64 complex -> float-float complex
+FFc ffc(std::complex<double> v) {
+  FFc r;
+  split(v.real(), r.rh, r.rl);
+  split(v.imag(), r.ih, r.il);
+  return r;
 }
 
 struct Coef {
@@ -274,11 +282,11 @@ struct modal_ctx {
   std::vector<int> lin_moff, lin_mc;  // device mode ranges; [moff, mc) conjugate pairs
   LinMode* dLinModes = nullptr;
   LinInit* dLinInit = nullptr;
-  double4* dLinAmp = nullptr;
-  double2* dLinTab = nullptr;  // z1^l, l < 64, per mode
+  FFc* dLinAmp = nullptr;      // [3 sets][modes][2 roots]
+  FFc* dLinTab = nullptr;      // z1^l, l < 64, per mode
   LinSeg* dLinSeg = nullptr;
   LinForced* dLinForced = nullptr;
-  double* dLinH = nullptr;
+  float2* dLinH = nullptr;     // float-float impulse responses of forced instances
   int n_forced = 0;
   long long lin_h_stride = 1, lin_max_exc = 0;
   // shared-tensor path
@@ -897,29 +905,26 @@ int init_linear(modal_ctx* c, const modal_desc* d, hipStream_t stream) {
       const cd s1 = std::polar(std::exp(64.0 * lm1), 64.0 * std::arg(z1));
       const cd s2 = std::polar(std::exp(64.0 * lm2), 64.0 * std::arg(z2));
       LinMode& m = modes[slot];
-      m.s1 = make_double2(s1.real(), s1.imag());
-      m.s2 = make_double2(s2.real(), s2.imag());
-      m.a = (s1 + s2).real();
-      m.b = (s1 * s2).real();
-      m.lm1 = lm1;
-      m.f1 = std::arg(z1) / M_PI;
-      m.lm2 = lm2;
-      m.f2 = std::arg(z2) / M_PI;
+      m.z1 = ffc(z1);
+      m.z2 = ffc(z2);
+      m.s1 = ffc(s1);
+      m.s2 = ffc(s2);
+      split((s1 + s2).real(), m.ah, m.al);
+      split((s1 * s2).real(), m.bh, m.bl);
       m.conj = c->lconj[k];
-      m.pad = 0;
+      m.pad[0] = m.pad[1] = m.pad[2] = 0;
       LinInit& I = init[slot];
-      auto d2 = [](cd v) { return make_double2(v.real(), v.imag()); };
-      I.z1 = d2(z1);
-      I.z2 = d2(z2);
-      I.A = d2(c->lA[k]);
-      I.B = d2(c->lB[k]);
-      I.C = d2(c->lC[k]);
-      I.c = c->lc[k];
-      I.b = c->lb[k];
+      I.z1 = ffc(z1);
+      I.z2 = ffc(z2);
+      I.A = ffc(c->lA[k]);
+      I.B = ffc(c->lB[k]);
+      I.C = ffc(c->lC[k]);
+      split(c->lc[k], I.ch, I.cl);
+      split(c->lb[k], I.bh, I.bl);
       I.e_off = eoff[b];
       I.n_exc = (long long)c->le[b].size();
       I.conj = c->lconj[k];
-      I.pad = 0;
+      I.pad[0] = I.pad[1] = I.pad[2] = 0;
     }
   c->n_forced = (int)forced.size();
   c->lin_h_stride = std::max<long long>(1, c->lin_max_exc);
@@ -931,11 +936,11 @@ int init_linear(modal_ctx* c, const modal_desc* d, hipStream_t stream) {
   }
   int r = dalloc(&c->dLinModes, sizeof(LinMode) * std::max<size_t>(M, 1));
   if (!r) r = dalloc(&c->dLinInit, sizeof(LinInit) * std::max<size_t>(M, 1));
-  if (!r) r = dalloc(&c->dLinAmp, sizeof(double4) * 3 * std::max<size_t>(M, 1));
-  if (!r) r = dalloc(&c->dLinTab, sizeof(double2) * 64 * std::max<size_t>(M, 1));
+  if (!r) r = dalloc(&c->dLinAmp, sizeof(FFc) * 2 * 3 * std::max<size_t>(M, 1));
+  if (!r) r = dalloc(&c->dLinTab, sizeof(FFc) * 64 * std::max<size_t>(M, 1));
   if (!r) r = dalloc(&c->dLinSeg, sizeof(LinSeg) * std::max<size_t>(2 * (size_t)B, hseg.size()));
   if (!r) r = dalloc(&c->dLinForced, sizeof(LinForced) * std::max<size_t>(forced.size(), 1));
-  if (!r) r = dalloc(&c->dLinH, sizeof(double) * std::max<size_t>(1, forced.size() * c->lin_h_stride));
+  if (!r) r = dalloc(&c->dLinH, sizeof(float2) * std::max<size_t>(1, forced.size() * c->lin_h_stride));
   if (!r) r = dalloc(&c->dE, sizeof(float) * epool.size());
   if (!r) r = dalloc(&c->dFlags, sizeof(int) * 2);
   if (r) return r;
@@ -949,8 +954,8 @@ int init_linear(modal_ctx* c, const modal_desc* d, hipStream_t stream) {
     HIP_TRY(hipMemcpyAsync(c->dLinSeg, hseg.data(), sizeof(LinSeg) * hseg.size(), hipMemcpyHostToDevice,
                            stream));
   HIP_TRY(launch_lin_amp(c->dLinInit, c->dLinModes, (int)M, c->dE, c->dLinAmp, c->dLinTab, stream));
-  HIP_TRY(launch_lin_sum_f64(c->dLinModes, c->dLinAmp, c->dLinTab, c->dLinSeg, (int)hseg.size(), c->lin_max_exc - 1,
-                             c->dLinH, stream));
+  HIP_TRY(launch_lin_sum_ff(c->dLinModes, c->dLinAmp, c->dLinTab, c->dLinSeg, (int)hseg.size(), c->lin_max_exc - 1,
+                            c->dLinH, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   for (int b = 0; b < B; ++b) {
     c->kind.push_back(d->inst[b].kind);
@@ -1907,19 +1912,100 @@ int modal_set_tangent(modal_ctx* c, int32_t b, const float* Hd, void* stream_) {
   return MODAL_OK;
 }
 
+namespace {
+
+// Device copies of a transfer-function call's inputs as float-float pairs
+// (split from the host's FP64 values) and room for its outputs; freed when
+// the call returns.
+struct TfCall {
+  float2* coef = nullptr;
+  int* off = nullptr;
+  FFc* z = nullptr;
+  FFc* out = nullptr;  // H, or dL/dH for the gradient
+  float2* g = nullptr;
+  ~TfCall() {
+    for (void* p : {(void*)coef, (void*)off, (void*)z, (void*)out, (void*)g})
+      if (p) (void)hipFree(p);
+  }
+};
+
+int tf_check(const int32_t* mode_off, int32_t batch, int32_t n_freq, int& modes) {
+  if (batch < 1 || batch > 65535 || n_freq < 1) return fail(MODAL_EINVAL, "batch or n_freq");
+  for (int b = 0; b < batch; ++b)
+    if (mode_off[b] < 0 || mode_off[b + 1] < mode_off[b]) return fail(MODAL_EINVAL, "mode_off not increasing");
+  modes = mode_off[batch];
+  return MODAL_OK;
+}
+
+int tf_upload(TfCall& t, const double* coef, const int32_t* mode_off, int32_t batch, const double* omega,
+              int32_t n_freq, int modes, hipStream_t s) {
+  std::vector<float2> cf(5 * (size_t)std::max(modes, 1));
+  for (size_t i = 0; i < 5 * (size_t)modes; ++i) split(coef[i], cf[i].x, cf[i].y);
+  std::vector<FFc> zf(n_freq);
+  for (int k = 0; k < n_freq; ++k) zf[k] = ffc(std::polar(1.0, omega[k]));
+  int r = dalloc(&t.coef, sizeof(float2) * cf.size());
+  if (!r) r = dalloc(&t.off, sizeof(int) * (batch + 1));
+  if (!r) r = dalloc(&t.z, sizeof(FFc) * n_freq);
+  if (!r) r = dalloc(&t.out, sizeof(FFc) * (size_t)batch * n_freq);
+  if (r) return r;
+  HIP_TRY(hipMemcpyAsync(t.coef, cf.data(), sizeof(float2) * cf.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(t.off, mode_off, sizeof(int) * (batch + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(t.z, zf.data(), sizeof(FFc) * n_freq, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // the host vectors go out of scope
+  return MODAL_OK;
+}
+
+}  // namespace
+
 int modal_tf_response(const double* coef, const int32_t* mode_off, int32_t batch, const double* omega,
                       int32_t n_freq, double* H, void* stream_) {
   if (!coef || !mode_off || !omega || !H) return fail(MODAL_EINVAL, "NULL argument");
-  if (batch < 1 || batch > 65535 || n_freq < 1) return fail(MODAL_EINVAL, "batch or n_freq");
-  HIP_TRY(launch_tf_response(coef, mode_off, batch, omega, n_freq, H, (hipStream_t)stream_));
+  int modes = 0;
+  int r = tf_check(mode_off, batch, n_freq, modes);
+  if (r) return r;
+  hipStream_t s = (hipStream_t)stream_;
+  TfCall t;
+  r = tf_upload(t, coef, mode_off, batch, omega, n_freq, modes, s);
+  if (r) return r;
+  HIP_TRY(launch_tf_response(t.coef, t.off, batch, t.z, n_freq, t.out, s));
+  std::vector<FFc> h((size_t)batch * n_freq);
+  HIP_TRY(hipMemcpyAsync(h.data(), t.out, sizeof(FFc) * h.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (size_t i = 0; i < h.size(); ++i) {
+    H[2 * i] = (double)h[i].rh + (double)h[i].rl;
+    H[2 * i + 1] = (double)h[i].ih + (double)h[i].il;
+  }
   return MODAL_OK;
 }
 
 int modal_tf_grad(const double* coef, const int32_t* mode_off, int32_t batch, int32_t max_modes,
                   const double* omega, int32_t n_freq, const double* dL_dH, double* g_coef, void* stream_) {
   if (!coef || !mode_off || !omega || !dL_dH || !g_coef) return fail(MODAL_EINVAL, "NULL argument");
-  if (batch < 1 || batch > 65535 || n_freq < 1 || max_modes < 0) return fail(MODAL_EINVAL, "batch, n_freq or max_modes");
-  HIP_TRY(launch_tf_grad(coef, mode_off, batch, max_modes, omega, n_freq, dL_dH, g_coef, (hipStream_t)stream_));
+  int modes = 0;
+  int r = tf_check(mode_off, batch, n_freq, modes);
+  if (r) return r;
+  if (max_modes < 0) return fail(MODAL_EINVAL, "max_modes");
+  for (int b = 0; b < batch; ++b)
+    if (mode_off[b + 1] - mode_off[b] > max_modes) return fail(MODAL_EINVAL, "an instance has more than max_modes modes");
+  hipStream_t s = (hipStream_t)stream_;
+  TfCall t;
+  r = tf_upload(t, coef, mode_off, batch, omega, n_freq, modes, s);
+  if (r) return r;
+  std::vector<FFc> gh((size_t)batch * n_freq);
+  for (size_t i = 0; i < gh.size(); ++i) {
+    split(dL_dH[2 * i], gh[i].rh, gh[i].rl);
+    split(dL_dH[2 * i + 1], gh[i].ih, gh[i].il);
+  }
+  r = dalloc(&t.g, sizeof(float2) * 5 * (size_t)std::max(modes, 1));
+  if (r) return r;
+  HIP_TRY(hipMemcpyAsync(t.out, gh.data(), sizeof(FFc) * gh.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_tf_grad(t.coef, t.off, batch, max_modes, t.z, n_freq, t.out, t.g, s));
+  std::vector<float2> g(5 * (size_t)std::max(modes, 1));
+  HIP_TRY(hipMemcpyAsync(g.data(), t.g, sizeof(float2) * g.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int b = 0; b < batch; ++b)
+    for (int m = mode_off[b]; m < mode_off[b + 1]; ++m)
+      for (int j = 0; j < 5; ++j) g_coef[5 * (size_t)m + j] = (double)g[5 * (size_t)m + j].x + (double)g[5 * (size_t)m + j].y;
   return MODAL_OK;
 }
 

@@ -316,12 +316,12 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
   if (row1 <= row0) return;
   const int ntp = I.ntp;
   const int nc_modes = ntp >> 2;
-  // class boundaries, read with selects (a runtime index into a private
-  // array would put it in scratch memory)
-  const int c0 = I.cls[0], c1 = I.cls[1], c2 = I.cls[2], c3 = I.cls[3], c4 = I.cls[4];
-  auto co = [&](int i) {
-    return i <= 0 ? c0 : (i == 1 ? c1 : (i == 2 ? c2 : (i == 3 ? c3 : c4)));
-  };
+  // class boundaries (a private array; read through selects instead, it left
+  // scratch but measured 9 % slower on the 256-plate batch)
+  int cb[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) cb[i] = I.cls[i];
+  auto co = [&](int i) { return cb[i]; };
   float* rd = red + 2 * kSlotFloats;  // [kSweepLoads * 64] per-slot row dot partials
   float* vrow = rd + J * kWave;       // [ntp] row-dot part of V for the current row
   for (int k = lane; k < ntp; k += kWave) vrow[k] = 0.f;
@@ -652,10 +652,11 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
       if (I.kind == KIND_VK) {
         __syncthreads();  // q^n in LDS
         const int R = U.row1 - U.row0;
-        if (RES && NW > 1 && !I.blk && R < NW) {
-          // one unit per workgroup with fewer rows than waves: the waves
-          // share its row blocks evenly (with whole rows per wave, measured
-          // faster otherwise: 50/50 plates 9.1 us per step against 11.8)
+        if (RES && NW > 1 && !I.blk && 2 * R <= NW) {
+          // one unit per workgroup with at most half as many rows as waves:
+          // the waves share its row blocks evenly (with whole rows per wave
+          // otherwise, measured faster there: 50/50 plates 9.1 us per step
+          // against 11.8, 100/100 in 7-row slabs 11.7 against 14.6)
           const int nblk = (I.nt + U.qs - 1) / U.qs;
           const int T = R * nblk;
           float* xv = L.xch;

@@ -16,9 +16,10 @@ absolute log difference (the loss of Sec. 4.3 with the STFT magnitude
 replaced by the Bark-sampled magnitude).  No time-domain simulation runs.
 
 The response and its gradient run in the library's HIP kernels
-(modal_tf_response, modal_tf_grad); the chain from (T0^, D^, d1^, d3^, w,
-beta) to the coefficients and the loss are torch on the device.  The
-envelope of the target (linear prediction) is host preprocessing done once.
+(modal_tf_response, modal_tf_grad), in float-float arithmetic; the FP64 chain
+from (T0^, D^, d1^, d3^, w, beta) to the coefficients and the loss is torch
+on the host (a few hundred modes and frequencies).  The envelope of the
+target (linear prediction) is host preprocessing done once.
 """
 from __future__ import annotations
 
@@ -76,19 +77,20 @@ def lpc_envelope(a, err, Omega) -> np.ndarray:
 
 class TfResponse(torch.autograd.Function):
     """H [batch, n_freq, 2] (real, imaginary) from coef [modes, 5] =
-    (a1, a2, b1, b2, w), all FP64 on the device; backward through
-    modal_tf_grad."""
+    (a1, a2, b1, b2, w); host FP64 tensors in and out, evaluated by the
+    library's float-float kernels; backward through modal_tf_grad."""
 
     @staticmethod
     def forward(ctx, coef, mode_off, omega, max_modes):
-        assert coef.is_cuda and coef.dtype == torch.float64 and coef.is_contiguous() and coef.shape[1] == 5
-        assert mode_off.dtype == torch.int32 and omega.dtype == torch.float64
+        assert not coef.is_cuda and coef.dtype == torch.float64 and coef.is_contiguous() and coef.shape[1] == 5
+        assert mode_off.dtype == torch.int32 and omega.dtype == torch.float64 and not omega.is_cuda
         B, K = mode_off.numel() - 1, omega.numel()
-        H = torch.empty((B, K, 2), dtype=torch.float64, device=coef.device)
-        _check(_lib.modal_tf_response(C.c_void_p(coef.data_ptr()), C.c_void_p(mode_off.data_ptr()), B,
+        H = torch.empty((B, K, 2), dtype=torch.float64)
+        cf = coef.detach()
+        _check(_lib.modal_tf_response(C.c_void_p(cf.data_ptr()), C.c_void_p(mode_off.data_ptr()), B,
                                       C.c_void_p(omega.data_ptr()), K, C.c_void_p(H.data_ptr()),
                                       _stream_handle(None)))
-        ctx.save_for_backward(coef, mode_off, omega)
+        ctx.save_for_backward(cf, mode_off, omega)
         ctx.max_modes = int(max_modes)
         return H
 
@@ -131,7 +133,7 @@ def fit_tf(target, fs: float, n_modes: int, theta0, iters: int = 600, lr: float 
     coefficients of a string's transfer function to the target's
     Bark-sampled LPC envelope with Adam (logs of the physical parameters).
     Returns (theta, weights, beta, loss history)."""
-    dev = torch.device("cuda")
+    dev = torch.device("cpu")  # the chain and the loss; the sums run on the GPU
     Om = bark_grid(n_freq, f_lo, f_hi, fs)
     a, err = lpc(np.asarray(target, dtype=np.float64), order)
     E = torch.tensor(lpc_envelope(a, err, Om), device=dev)

@@ -1,7 +1,11 @@
 """Transfer-function response and gradient kernels (modal_tf_response,
 modal_tf_grad, through the C ABI) against the FP64 oracle, and the
-transfer-function fit of a synthetic linear string.  Both sides compute in
-FP64: bar 1e-11 relative."""
+transfer-function fit of a synthetic linear string.  The kernels compute in
+float-float arithmetic (FP32 pairs, relative precision about 2^-48 = 3.6e-15)
+from FP64 inputs split on the host; at a pole the denominator z^2 + a1 z + a2
+cancels down to about gamma T of its terms (gamma T >= 1.1e-5 here), so the
+relative error near the largest values is bounded by about 3.6e-15 / 1.1e-5 =
+3.2e-10: bar 1e-9 relative to the largest value."""
 import math
 
 import numpy as np
@@ -38,22 +42,21 @@ def test_response_and_gradient_match_the_oracle(gpu):
     coefs = [_coef(n, rng) for n in sizes]
     Om = OT.bark_grid(300, 40, 16000, FS)
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
-    dev = "cuda"
-    coef = torch.tensor(np.concatenate(coefs), device=dev, requires_grad=True)
+    coef = torch.tensor(np.concatenate(coefs), requires_grad=True)
     print("case: tf response and gradient, modes 5/70/1, 300 frequencies", flush=True)
-    H = transfer.TfResponse.apply(coef, torch.tensor(off, device=dev), torch.tensor(Om, device=dev), 70)
+    H = transfer.TfResponse.apply(coef, torch.tensor(off), torch.tensor(Om), 70)
     g = rng.normal(size=(3, 300, 2))
-    (H * torch.tensor(g, device=dev)).sum().backward()
+    (H * torch.tensor(g)).sum().backward()
     Hc = H.detach().cpu().numpy()
     Gc = coef.grad.cpu().numpy()
     for b in range(3):
         ref = OT.response(*coefs[b].T, Om)
         got = Hc[b, :, 0] + 1j * Hc[b, :, 1]
-        assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max(), b
+        assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max(), b
         gref = OT.response_grad(*coefs[b].T, Om, g[b, :, 0] + 1j * g[b, :, 1])
         gg = Gc[off[b]:off[b + 1]]
         for j in range(5):
-            assert np.abs(gg[:, j] - gref[:, j]).max() <= 1e-11 * np.abs(gref[:, j]).max(), (b, j)
+            assert np.abs(gg[:, j] - gref[:, j]).max() <= 1e-9 * np.abs(gref[:, j]).max(), (b, j)
 
 
 def test_fit_recovers_pitch_and_inharmonicity(gpu):
