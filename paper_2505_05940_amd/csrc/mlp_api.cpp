@@ -11,10 +11,12 @@
 #include "../../include/modal.h"
 
 namespace modal {
-hipError_t launch_gemm(const float* A, long long sam, long long sak, const float* B, long long sbk,
-                       long long sbn, float* C, long long scm, int M, int N, int K, int epi,
-                       const float* bias, const float* mask, hipStream_t s);
-hipError_t launch_colsum(const float* G, int M, int N, float* db, hipStream_t s);
+hipError_t launch_gemm(const float* A, long long lda, int a_kc, const float* B, long long ldb, int b_kc, float* C,
+                       long long ldc, int M, int N, int K, int epi, const float* bias, const float* mask,
+                       float* part, hipStream_t s);
+constexpr int kMaxSplit = 8;
+hipError_t launch_colsum(const float* G, int M, int N, float* part, float* db, hipStream_t s);
+constexpr int kColSlices = 16;
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
                        float b2, float eps, int t, hipStream_t s);
 }  // namespace modal
@@ -42,7 +44,8 @@ struct mlp_ctx {
   std::vector<long long> w_off, b_off, act_off;
   long long n_params = 0, act_floats = 0;
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *act = nullptr, *d0 = nullptr,
-        *d1 = nullptr;
+        *d1 = nullptr, *part = nullptr,  // part: column-sum partials
+        *kpart = nullptr;                 // split-K partial tiles
 };
 
 extern "C" {
@@ -51,7 +54,7 @@ const char* mlp_last_error(void) { return g_mlp_err.c_str(); }
 
 void mlp_destroy(mlp_ctx* c) {
   if (!c) return;
-  for (float* q : {c->p, c->g, c->m, c->v, c->act, c->d0, c->d1})
+  for (float* q : {c->p, c->g, c->m, c->v, c->act, c->d0, c->d1, c->part, c->kpart})
     if (q) (void)hipFree(q);
   delete c;
 }
@@ -91,7 +94,10 @@ int mlp_init(mlp_ctx** out, int32_t n_layers, const int32_t* dims, int32_t max_b
   }
   if (hipMalloc((void**)&c->act, sizeof(float) * (size_t)c->act_floats) != hipSuccess ||
       hipMalloc((void**)&c->d0, sizeof(float) * (size_t)max_batch * c->max_d) != hipSuccess ||
-      hipMalloc((void**)&c->d1, sizeof(float) * (size_t)max_batch * c->max_d) != hipSuccess) {
+      hipMalloc((void**)&c->d1, sizeof(float) * (size_t)max_batch * c->max_d) != hipSuccess ||
+      hipMalloc((void**)&c->part, sizeof(float) * (size_t)kColSlices * c->max_d) != hipSuccess ||
+      hipMalloc((void**)&c->kpart, sizeof(float) * (size_t)kMaxSplit * std::max(max_batch, c->max_d) *
+                                       c->max_d) != hipSuccess) {
     mlp_destroy(c);
     return mfail(MODAL_ENOMEM, "hipMalloc activations");
   }
@@ -132,8 +138,9 @@ int mlp_forward(mlp_ctx* c, const float* x, int32_t B, float* y, void* stream) {
     const int in = c->dims[l], out = c->dims[l + 1];
     const float* a = c->act + c->act_off[l];
     float* z = c->act + c->act_off[l + 1];
-    MHIP(launch_gemm(a, in, 1, c->p + c->w_off[l], 1, in, z, out, B, out, in,
-                     l + 1 < c->L ? EPI_BIAS_RELU : EPI_BIAS, c->p + c->b_off[l], nullptr, s));
+    // Z[b, o] = sum_i a[b, i] W[o, i]: A(b, i) = a[b in + i], B(i, o) = W[o in + i]
+    MHIP(launch_gemm(a, in, 1, c->p + c->w_off[l], in, 1, z, out, B, out, in,
+                     l + 1 < c->L ? EPI_BIAS_RELU : EPI_BIAS, c->p + c->b_off[l], nullptr, c->kpart, s));
   }
   MHIP(hipMemcpyAsync(y, c->act + c->act_off[c->L], sizeof(float) * (size_t)B * c->dims[c->L],
                       hipMemcpyDeviceToDevice, s));
@@ -151,14 +158,16 @@ int mlp_backward(mlp_ctx* c, const float* dy, void* stream) {
   for (int l = c->L - 1; l >= 0; --l) {
     const int in = c->dims[l], out = c->dims[l + 1];
     const float* a = c->act + c->act_off[l];
-    // dW[o, i] = sum_b g[b, o] a[b, i]
-    MHIP(launch_gemm(gcur, 1, out, a, in, 1, c->g + c->w_off[l], in, out, in, B, EPI_STORE, nullptr,
-                     nullptr, s));
-    MHIP(launch_colsum(gcur, B, out, c->g + c->b_off[l], s));
+    // dW[o, i] = sum_b g[b, o] a[b, i]: A(o, b) = g[b out + o] (o contiguous),
+    // B(b, i) = a[b in + i] (i contiguous)
+    MHIP(launch_gemm(gcur, out, 0, a, in, 0, c->g + c->w_off[l], in, out, in, B, EPI_STORE, nullptr,
+                     nullptr, c->kpart, s));
+    MHIP(launch_colsum(gcur, B, out, c->part, c->g + c->b_off[l], s));
     if (l > 0) {
-      // g_prev[b, i] = (sum_o g[b, o] W[o, i]) * [a[b, i] > 0]
-      MHIP(launch_gemm(gcur, out, 1, c->p + c->w_off[l], in, 1, gnext, in, B, in, out, EPI_MASK,
-                       nullptr, a, s));
+      // g_prev[b, i] = (sum_o g[b, o] W[o, i]) * [a[b, i] > 0]: A(b, o) =
+      // g[b out + o] (o contiguous), B(o, i) = W[o in + i] (i contiguous)
+      MHIP(launch_gemm(gcur, out, 1, c->p + c->w_off[l], in, 0, gnext, in, B, in, out, EPI_MASK,
+                       nullptr, a, c->kpart, s));
       std::swap(gcur, gnext);
     }
   }

@@ -2,94 +2,212 @@
 // GEMM with FP32 accumulation and fused epilogues, the bias-gradient column
 // sum, and the Adam update on FP32 master weights (gfx950).
 //
-// GEMM: C[m, n] = sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak] and
-// B(k, n) = B[k sbk + n sbn] (FP32 in memory, rounded to BF16 when staged in
-// LDS), so one kernel serves Y = X W^T, dX = dY W and dW = dY^T X.
-// A 256-thread workgroup computes a 64 x 64 tile; each of its four waves owns
-// a 32 x 32 quadrant accumulated by v_mfma_f32_32x32x8 bf16 over K tiles of
-// 32.  Operand layout of that instruction: lane l supplies A[l % 32][4 (l/32)
-// + i] and B[4 (l/32) + i][l % 32], i < 4; it receives D[8 (r/4) + 4 (l/32)
-// + r % 4][l % 32] in accumulator r < 16.
+// GEMM: C[m, n] = sum_k A(m, k) B(k, n), FP32 in memory and rounded to BF16
+// when staged in LDS.  Each operand is read along whichever of its two
+// indices is contiguous in memory, with 16-byte loads: A(m, k) = A[m lda + k]
+// (k contiguous) or A[k lda + m] (m contiguous), B(k, n) = B[n ldb + k] or
+// B[k ldb + n]; so one kernel serves Y = X W^T, dX = dY W and dW = dY^T X.
+// A 128-thread workgroup computes a 32 x 64 tile of C (two waves, one 32 x 32
+// quadrant each) over K tiles of 64 with gfx950's v_mfma_f32_32x32x16_bf16;
+// the next K tile's global loads are issued before the current tile's MFMAs
+// and written to the second of two LDS buffers afterwards.  Operand layout of
+// the instruction: lane l supplies A[l % 32][8 (l/32) + i] and
+// B[8 (l/32) + i][l % 32], i < 8 (the same k for both); it receives
+// D[8 (r/4) + 4 (l/32) + r % 4][l % 32] in accumulator r < 16.  The LDS
+// tiles are [m][k] and [n][k] with k contiguous (rows padded by 8), so each
+// fragment is one 16-byte LDS read.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 namespace modal {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 enum : int { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_MASK = 3 };
 
 // round-to-nearest-even FP32 -> BF16 bits
-__device__ __forceinline__ short to_bf16(float f) {
+__device__ __forceinline__ unsigned short to_bf16(float f) {
   unsigned int u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (short)(u >> 16);  // inf / nan
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan
   u += 0x7fffu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
+  return (unsigned short)(u >> 16);
 }
 
-constexpr int TM = 64, TN = 64, TK = 32;
+constexpr int TM = 32, TN = 64, TK = 64, TKP = TK + 8;
+constexpr int kGemmThreads = 128;
 
-__global__ void __launch_bounds__(256) gemm_bf16(const float* __restrict__ A, long long sam,
-                                                 long long sak, const float* __restrict__ B,
-                                                 long long sbk, long long sbn, float* __restrict__ C,
-                                                 long long scm, int M, int N, int K, int epi,
-                                                 const float* __restrict__ bias,
-                                                 const float* __restrict__ mask) {
-  __shared__ short As[TM][TK + 4];  // [m][k]
-  __shared__ short Bs[TN][TK + 4];  // [n][k]
+// Four consecutive elements of a row of a row-major matrix (ld elements per
+// row) starting at column c, zero outside [0, rows) x [0, cols); a 16-byte
+// load when the whole group is inside and aligned.
+__device__ __forceinline__ float4 ld_group(const float* __restrict__ X, long long ld, int r, int c, int rows,
+                                           int cols, bool vec) {
+  if (r >= rows) return make_float4(0.f, 0.f, 0.f, 0.f);
+  const float* p = X + (long long)r * ld + c;
+  if (vec && c + 3 < cols) return *reinterpret_cast<const float4*>(p);
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = c + i < cols ? p[i] : 0.f;
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// Stages one operand tile of R rows (m or n) by TK k into registers: R * TK
+// / 4 float4 groups over the 128 threads.  kc: the operand's k index is
+// contiguous in memory (groups run along k), else its m / n index is.
+template <int R>
+struct Stage {
+  static constexpr int G = R * TK / 4 / kGemmThreads;  // groups per thread
+  float4 v[G];
+  __device__ __forceinline__ void load(const float* __restrict__ X, long long ld, bool kc, int r0, int k0,
+                                       int rows, int K, bool vec, int tid) {
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int q = tid + kGemmThreads * j;
+      if (kc) {  // group q: row q / (TK/4), k = 4 (q % (TK/4))
+        const int r = q / (TK / 4), k = 4 * (q % (TK / 4));
+        v[j] = ld_group(X, ld, r0 + r, k0 + k, rows, K, vec);
+      } else {  // group q: k row q / (R/4), rows 4 (q % (R/4)) .. +3
+        const int k = q / (R / 4), r = 4 * (q % (R / 4));
+        v[j] = ld_group(X, ld, k0 + k, r0 + r, K, rows, vec);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(unsigned short (*T)[TKP], bool kc, int tid) const {
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int q = tid + kGemmThreads * j;
+      const unsigned short b0 = to_bf16(v[j].x), b1 = to_bf16(v[j].y), b2 = to_bf16(v[j].z),
+                           b3 = to_bf16(v[j].w);
+      if (kc) {
+        const int r = q / (TK / 4), k = 4 * (q % (TK / 4));
+        uint2 w;
+        w.x = (unsigned int)b0 | ((unsigned int)b1 << 16);
+        w.y = (unsigned int)b2 | ((unsigned int)b3 << 16);
+        *reinterpret_cast<uint2*>(&T[r][k]) = w;
+      } else {
+        const int k = q / (R / 4), r = 4 * (q % (R / 4));
+        T[r][k] = b0;
+        T[r + 1][k] = b1;
+        T[r + 2][k] = b2;
+        T[r + 3][k] = b3;
+      }
+    }
+  }
+};
+
+// blockIdx.z selects a slice [k0, k0 + kc) of K (split K); with several
+// slices (gridDim.z > 1) each writes its raw partial tile to
+// part[z][M][N] and gemm_reduce adds the slices and applies the epilogue.
+__global__ void __launch_bounds__(kGemmThreads) gemm_bf16(const float* __restrict__ A, long long lda, int a_kc,
+                                                          const float* __restrict__ B, long long ldb, int b_kc,
+                                                          float* __restrict__ C, long long ldc, int M, int N,
+                                                          int K, int kc, int epi, const float* __restrict__ bias,
+                                                          const float* __restrict__ mask, float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][TM][TKP];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][TN][TKP];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int qm = wave >> 1, qn = wave & 1;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  // 16-byte loads need rows that start on 16-byte boundaries
+  const bool va = (lda & 3) == 0 && ((reinterpret_cast<unsigned long long>(A) & 15) == 0);
+  const bool vb = (ldb & 3) == 0 && ((reinterpret_cast<unsigned long long>(B) & 15) == 0);
+  Stage<TM> sa;
+  Stage<TN> sb;
   v16f acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    // stage A and B tiles (2048 elements each, 8 per thread), zero-padded
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int idx = tid + 256 * e;
-      const int i = idx / TK, k = idx % TK;
-      const int gm = m0 + i, gk = k0 + k;
-      As[i][k] = to_bf16(gm < M && gk < K ? A[gm * sam + gk * sak] : 0.f);
-      const int gn = n0 + i;
-      Bs[i][k] = to_bf16(gn < N && gk < K ? B[gk * sbk + gn * sbn] : 0.f);
+  // this slice's K range, in whole tiles: [kb0, kb0 + kc) clipped to K
+  const int kb0 = blockIdx.z * kc;
+  const int kend = min(K, kb0 + kc);
+  const int nk = (kend - kb0 + TK - 1) / TK;
+  // operands are read as if K ended at kend (zeros past it)
+  sa.load(A, lda, a_kc, m0, kb0, M, kend, va, tid);
+  sb.load(B, ldb, b_kc, n0, kb0, N, kend, vb, tid);
+  sa.store(As[0], a_kc, tid);
+  sb.store(Bs[0], b_kc, tid);
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nk) {  // next tile's loads in flight during this tile's MFMAs
+      sa.load(A, lda, a_kc, m0, kb0 + (t + 1) * TK, M, kend, va, tid);
+      sb.load(B, ldb, b_kc, n0, kb0 + (t + 1) * TK, N, kend, vb, tid);
     }
-    __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 8) {
-      v4s a, b;
-      const int kb = kk + 4 * (lane >> 5);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = As[qm * 32 + (lane & 31)][kb + i];
-        b[i] = Bs[qn * 32 + (lane & 31)][kb + i];
-      }
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    for (int kk = 0; kk < TK; kk += 16) {
+      const int kb = kk + 8 * (lane >> 5);
+      const v8bf a = *reinterpret_cast<const v8bf*>(&As[cur][lane & 31][kb]);
+      const v8bf b = *reinterpret_cast<const v8bf*>(&Bs[cur][32 * wave + (lane & 31)][kb]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    if (t + 1 < nk) {
+      sa.store(As[cur ^ 1], a_kc, tid);
+      sb.store(Bs[cur ^ 1], b_kc, tid);
     }
     __syncthreads();
   }
-  const int col = n0 + qn * 32 + (lane & 31);
+  const int col = n0 + 32 * wave + (lane & 31);
+  if (gridDim.z > 1) {
+    float* P = part + (long long)blockIdx.z * M * N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (row < M && col < N) P[(long long)row * N + col] = acc[r];
+    }
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int row = m0 + qm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int row = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     if (row < M && col < N) {
       float v = acc[r];
       if (epi == EPI_BIAS || epi == EPI_BIAS_RELU) v += bias[col];
       if (epi == EPI_BIAS_RELU) v = fmaxf(v, 0.f);
-      if (epi == EPI_MASK) v = mask[row * scm + col] > 0.f ? v : 0.f;
-      C[row * scm + col] = v;
+      if (epi == EPI_MASK) v = mask[row * ldc + col] > 0.f ? v : 0.f;
+      C[row * ldc + col] = v;
     }
   }
 }
 
-// db[n] = sum_m G[m, n]  (G row-major [M, N])
-__global__ void colsum(const float* __restrict__ G, int M, int N, float* __restrict__ db) {
+// C[m, n] = epilogue(sum over the S slices of part[z][m][n]), slices added in
+// order (deterministic)
+__global__ void gemm_reduce(const float* __restrict__ part, int S, float* __restrict__ C, long long ldc, int M,
+                            int N, int epi, const float* __restrict__ bias, const float* __restrict__ mask) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)M * N) return;
+  const int row = (int)(i / N), col = (int)(i % N);
+  float v = 0.f;
+  for (int z = 0; z < S; ++z) v += part[(long long)z * M * N + i];
+  if (epi == EPI_BIAS || epi == EPI_BIAS_RELU) v += bias[col];
+  if (epi == EPI_BIAS_RELU) v = fmaxf(v, 0.f);
+  if (epi == EPI_MASK) v = mask[row * ldc + col] > 0.f ? v : 0.f;
+  C[row * ldc + col] = v;
+}
+
+// db[n] = sum_m G[m, n]  (G row-major [M, N]) in two deterministic stages:
+// partial sums over kColSlices row slices (64 columns x 4 row phases per
+// workgroup, phases added through LDS), then the slices added in order.
+constexpr int kColSlices = 16;
+__global__ void __launch_bounds__(256) colsum_part(const float* __restrict__ G, int M, int N,
+                                                  float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
+  const int rows = (M + kColSlices - 1) / kColSlices;
+  const int r0 = blockIdx.y * rows, r1 = min(M, r0 + rows);
+  float s = 0.f;
+  if (n < N)
+    for (int m = r0 + ph; m < r1; m += 4) s += G[(long long)m * N + n];
+  red[ph][c] = s;
+  __syncthreads();
+  if (ph == 0 && n < N) part[(long long)blockIdx.y * N + n] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+__global__ void colsum_final(const float* __restrict__ part, int N, float* __restrict__ db) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   float s = 0.f;
-  for (int m = 0; m < M; ++m) s += G[(long long)m * N + n];
+  for (int t = 0; t < kColSlices; ++t) s += part[(long long)t * N + n];
   db[n] = s;
 }
 
@@ -109,17 +227,34 @@ __global__ void adam(float* __restrict__ p, const float* __restrict__ g, float* 
   }
 }
 
-hipError_t launch_gemm(const float* A, long long sam, long long sak, const float* B, long long sbk,
-                       long long sbn, float* C, long long scm, int M, int N, int K, int epi,
-                       const float* bias, const float* mask, hipStream_t s) {
-  dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM);
-  hipLaunchKernelGGL(gemm_bf16, grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, scm, M, N, K,
-                     epi, bias, mask);
+// Split K so that a launch has at least about 1024 workgroups (K slices of
+// whole 64-wide tiles, at most kMaxSplit); part: scratch of kMaxSplit * M * N
+// floats for the slices' partial tiles.
+constexpr int kMaxSplit = 8;
+hipError_t launch_gemm(const float* A, long long lda, int a_kc, const float* B, long long ldb, int b_kc, float* C,
+                       long long ldc, int M, int N, int K, int epi, const float* bias, const float* mask,
+                       float* part, hipStream_t s) {
+  const int tiles = ((N + TN - 1) / TN) * ((M + TM - 1) / TM);
+  const int ktiles = (K + TK - 1) / TK;
+  int S = std::max(1, std::min({kMaxSplit, ktiles, (1024 + tiles - 1) / tiles}));
+  if (!part) S = 1;
+  const int kc = ((ktiles + S - 1) / S) * TK;
+  S = (K + kc - 1) / kc;
+  dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, S);
+  hipLaunchKernelGGL(gemm_bf16, grid, dim3(kGemmThreads), 0, s, A, lda, a_kc, B, ldb, b_kc, C, ldc, M, N, K, kc,
+                     epi, bias, mask, part);
+  if (S > 1) {
+    const long long n = (long long)M * N;
+    hipLaunchKernelGGL(gemm_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, S, C, ldc, M, N, epi,
+                       bias, mask);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float* G, int M, int N, float* db, hipStream_t s) {
-  hipLaunchKernelGGL(colsum, dim3((N + 255) / 256), dim3(256), 0, s, G, M, N, db);
+// part: scratch of kColSlices * N floats
+hipError_t launch_colsum(const float* G, int M, int N, float* part, float* db, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_part, dim3((N + 63) / 64, kColSlices), dim3(256), 0, s, G, M, N, part);
+  hipLaunchKernelGGL(colsum_final, dim3((N + 255) / 256), dim3(256), 0, s, part, N, db);
   return hipGetLastError();
 }
 
