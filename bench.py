@@ -397,18 +397,22 @@ def main():
         del a, b
     S = args.samples_per_step
     mw, waves = args.max_workgroups, args.waves
+    tune_cache = None
     if args.autotune:
-        from paper_2505_05940_amd.tune import autotune
+        from paper_2505_05940_amd import tune
         t0 = time.time()
-        waves, mw = autotune(insts, 44100.0, cache=None,
-                             log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
-        print(f"[bench] autotuned waves={waves} max_workgroups={mw} in {time.time() - t0:.1f} s",
-              file=sys.stderr, flush=True)
+        tune_cache = tune.CACHE
+        waves_t, mw_t = tune.autotune(insts, 44100.0, cache=tune_cache,
+                                      log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        print(f"[bench] autotuned waves={waves_t} max_workgroups={mw_t} in {time.time() - t0:.1f} s "
+              f"(cache {tune_cache})", file=sys.stderr, flush=True)
     t0 = time.time()
     sim = modal.Sim(insts, 44100.0, flags=modal.FLAG_GRAPH | modal.FLAG_ASYNC,
-                    chunk_steps=S, max_workgroups=mw, waves=waves)
+                    chunk_steps=S, max_workgroups=mw, waves=waves, tune_cache=tune_cache)
     info = sim.info()
     del insts
+    if args.autotune:  # the shape modal_init took from the cache
+        waves, mw = waves_t, mw_t
     print(f"[bench] modal_init {time.time() - t0:.1f} s, plan {info}", file=sys.stderr, flush=True)
     modes = int(sum(w["n_t"] for w in wls))
     y = torch.empty((args.batch, S), device="cuda")

@@ -133,6 +133,14 @@ typedef struct {
                                    4 s); past it the run is abandoned, every
                                    workgroup leaves, and modal_run or
                                    modal_grad returns MODAL_EHANG           */
+  const char *tune_cache;       /* optional path of a JSON file written by
+                                   the autotuner (paper_2505_05940_amd/
+                                   tune.py): {"<key>": {"waves": W,
+                                   "max_workgroups": M, ...}, ...}.  With
+                                   waves and max_workgroups 0, a batch whose
+                                   key (modal_tune_key) is listed takes that
+                                   launch shape; a missing file or key
+                                   leaves the defaults.  NULL = none.       */
 } modal_desc;
 
 /* Validates the description (before any device work), computes the per-mode
@@ -328,6 +336,13 @@ int modal_tf_grad(const double *coef, const int32_t *mode_off, int32_t batch, in
  * workgroup instead, which this preview does not show.  EINVAL if the batch
  * cannot be partitioned. */
 int modal_plan(const modal_desc *d, int32_t n_workgroups, int64_t out[4]);
+
+/* The autotuner's key of a batch: 16 hexadecimal digits of a hash of the
+ * device name, the scheme, the planning flags and every instance's kind,
+ * mode counts and block-structure hint (no tensor values).  out: host
+ * memory of at least 17 chars.  EINVAL for a description modal_init would
+ * reject, or len < 17. */
+int modal_tune_key(const modal_desc *d, char *out, int32_t len);
 
 /* Message for the last failure on the calling thread ("" if none). */
 const char *modal_last_error(void);

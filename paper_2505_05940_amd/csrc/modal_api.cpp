@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -1215,12 +1217,105 @@ extern "C" {
 
 const char* modal_last_error(void) { return g_err.c_str(); }
 
-int modal_init(modal_ctx** out, const modal_desc* d, void* stream_) {
+namespace {
+
+// FNV-1a, 64 bits
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  }
+  void add_int(int32_t v) { add(&v, sizeof v); }
+};
+
+int tune_key(const modal_desc* d, std::string& key) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  Fnv f;
+  f.add(prop.name, strnlen(prop.name, sizeof(prop.name)));
+  f.add_int(d->batch);
+  f.add_int(d->scheme);
+  f.add_int(d->flags & ~(MODAL_FLAG_ASYNC | MODAL_FLAG_GRAPH));
+  for (int b = 0; b < d->batch; ++b) {
+    const modal_instance& I = d->inst[b];
+    f.add_int(I.kind);
+    f.add_int(I.n_t);
+    f.add_int(I.n_in);
+    f.add_int(I.mode_class != nullptr);
+    f.add_int(I.h_row_scale != nullptr);
+  }
+  char buf[17];
+  snprintf(buf, sizeof buf, "%016llx", (unsigned long long)f.h);
+  key = buf;
+  return MODAL_OK;
+}
+
+// The integer after "name": in the JSON object text that follows `from`.
+bool json_int(const std::string& text, size_t from, size_t to, const char* name, int& v) {
+  const std::string pat = std::string("\"") + name + "\"";
+  const size_t p = text.find(pat, from);
+  if (p == std::string::npos || p >= to) return false;
+  const size_t c = text.find(':', p + pat.size());
+  if (c == std::string::npos || c >= to) return false;
+  char* end = nullptr;
+  const long x = std::strtol(text.c_str() + c + 1, &end, 10);
+  if (end == text.c_str() + c + 1) return false;
+  v = (int)x;
+  return true;
+}
+
+// Launch shape for `d` from the autotuner's cache, if listed.
+bool tuned_shape(const modal_desc* d, int& waves, int& max_wg) {
+  FILE* fp = std::fopen(d->tune_cache, "rb");
+  if (!fp) return false;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, fp)) > 0) text.append(buf, n);
+  std::fclose(fp);
+  std::string key;
+  if (tune_key(d, key)) return false;
+  const size_t k = text.find("\"" + key + "\"");
+  if (k == std::string::npos) return false;
+  const size_t end = text.find('}', k);
+  int w = 0, m = 0;
+  if (!json_int(text, k, end, "waves", w) || !json_int(text, k, end, "max_workgroups", m)) return false;
+  if ((w != 1 && w != 4 && w != 8) || m < 1) return false;
+  waves = w;
+  max_wg = m;
+  return true;
+}
+
+}  // namespace
+
+int modal_tune_key(const modal_desc* d, char* out, int32_t len) {
+  if (!out || len < 17) return fail(MODAL_EINVAL, "out NULL or len < 17");
+  int rc = validate(d);
+  if (rc) return rc;
+  std::string key;
+  rc = tune_key(d, key);
+  if (rc) return rc;
+  std::memcpy(out, key.c_str(), 17);
+  return MODAL_OK;
+}
+
+int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
   if (!out) return fail(MODAL_EINVAL, "out is NULL");
   *out = nullptr;
   g_err.clear();
-  int rc = validate(d);
+  int rc = validate(d_in);
   if (rc) return rc;
+  // the autotuner's launch shape for this batch, if cached
+  modal_desc tuned = *d_in;
+  if (d_in->tune_cache && d_in->waves == 0 && d_in->max_workgroups == 0)
+    (void)tuned_shape(d_in, tuned.waves, tuned.max_workgroups);
+  const modal_desc* d = &tuned;
   hipStream_t stream = (hipStream_t)stream_;
   const double T = 1.0 / d->fs;
   int device = 0;

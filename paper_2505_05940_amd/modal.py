@@ -45,7 +45,8 @@ class modal_desc(C.Structure):
     _fields_ = [("batch", C.c_int32), ("scheme", C.c_int32),
                 ("inst", C.POINTER(modal_instance)), ("fs", C.c_double),
                 ("flags", C.c_int32), ("max_workgroups", C.c_int32),
-                ("chunk_steps", C.c_int32), ("waves", C.c_int32), ("barrier_us", C.c_int32)]
+                ("chunk_steps", C.c_int32), ("waves", C.c_int32), ("barrier_us", C.c_int32),
+                ("tune_cache", C.c_char_p)]
 
 
 class ModalError(RuntimeError):
@@ -79,6 +80,8 @@ def _load():
     lib.modal_set_tensor.restype = C.c_int
     lib.modal_plan.argtypes = [C.POINTER(modal_desc), C.c_int32, C.POINTER(C.c_int64)]
     lib.modal_plan.restype = C.c_int
+    lib.modal_tune_key.argtypes = [C.POINTER(modal_desc), C.c_char_p, C.c_int32]
+    lib.modal_tune_key.restype = C.c_int
     lib.modal_vk_coupling_sine.argtypes = [C.c_double, C.c_double, C.c_int32, _ip, _ip,
                                            C.c_int32, _ip, _ip, C.c_int32, C.c_int32,
                                            _dp, _fp, C.c_int32]
@@ -130,7 +133,7 @@ def vk_coupling_sine(Lx, Ly, m, q, a, b, scale_n, grid=None, threads=0):
 
 
 def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_steps=0,
-                shapes_only=False, waves=0, barrier_us=0):
+                shapes_only=False, waves=0, barrier_us=0, tune_cache=None):
     """modal_desc for a list of instance dicts; returns (desc, keep-alive list, n_t list).
     With shapes_only (planning previews, which never read tensors) a vk
     instance may give "n_in" instead of "Ht"."""
@@ -191,10 +194,20 @@ def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_ste
             s.b_ext = b.ctypes.data_as(_dp)
             s.e_ext = e.ctypes.data_as(_fp)
             s.n_exc = len(e)
+    tc = None if tune_cache is None else os.fsencode(tune_cache)
+    keep.append(tc)
     desc = modal_desc(batch=batch, scheme=SCHEME[scheme], inst=arr, fs=float(fs), flags=flags,
                       max_workgroups=max_workgroups, chunk_steps=chunk_steps, waves=waves,
-                      barrier_us=barrier_us)
+                      barrier_us=barrier_us, tune_cache=tc)
     return desc, keep, n_t
+
+
+def tune_key(instances, fs=44100.0, scheme="sv", flags=0):
+    """The autotuner's cache key of a batch (``modal_tune_key``)."""
+    desc, keep, _ = _build_desc(instances, fs, scheme, flags=flags, shapes_only=True)
+    out = C.create_string_buffer(17)
+    _check(lib.modal_tune_key(C.byref(desc), out, 17))
+    return out.value.decode()
 
 
 def plan(instances, n_workgroups, fs=44100.0, scheme="sv", flags=0):
@@ -218,11 +231,11 @@ class Sim:
     """
 
     def __init__(self, instances, fs, scheme="sv", flags=0, max_workgroups=0,
-                 chunk_steps=0, stream=None, waves=0, barrier_us=0):
+                 chunk_steps=0, stream=None, waves=0, barrier_us=0, tune_cache=None):
         self._ctx = C.c_void_p()
         self.batch = len(instances)
         desc, keep, self.n_t = _build_desc(instances, fs, scheme, flags, max_workgroups, chunk_steps,
-                                           waves=waves, barrier_us=barrier_us)
+                                           waves=waves, barrier_us=barrier_us, tune_cache=tune_cache)
         self._stream = stream
         _check(lib.modal_init(C.byref(self._ctx), C.byref(desc), _stream_handle(stream)))
         self.modes_total = sum(self.n_t)
