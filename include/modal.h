@@ -163,6 +163,14 @@ typedef struct {
  * steps in parallel in float-float arithmetic (free response plus the
  * excitation convolved with the impulse response); MODAL_FLAG_GRAPH has no
  * effect there.  A mode with a double root keeps the batch on the recursion.
+ * On-chip path (paper: Sec. 4.2, the single small plate stepped in real
+ * time): a latency-bound batch (below) without MODAL_FLAG_GRAD whose
+ * instances all have n_t <= 64 and whose widest tensor fits one workgroup's
+ * registers (ceil(n_in / 8) rows per wave times the column width, n_t
+ * rounded up to 16, 32, 40, 48 or 64, at most 200: 40/40 and 64/24 fit)
+ * steps each instance in one workgroup of 8 waves that loads its tensor
+ * into registers at the start of each launch; no memory traffic between
+ * workgroups, two workgroup barriers per step.
  * Streaming path plans: a latency-bound batch (at most one instance per CU,
  * dense tensors under 64 MB per step, waves and max_workgroups 0, no
  * MODAL_FLAG_SPLIT_ANY) keeps its tensors dense, takes 8 waves per
@@ -226,7 +234,8 @@ int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
  * the most loaded workgroup and [9] the mean planned cost per co-resident
  * workgroup (both in streamed-byte units), [10] the path: 0 persistent
  * recursion, 1 shared tensor (then [1] is the number of instance columns
- * and [2], [8], [9] are 0), 2 linear closed form,
+ * and [2], [8], [9] are 0), 2 linear closed form, 3 on-chip recursion
+ * (one workgroup per instance, [6] 0),
  * [11] FP32 operations of the force per step (sum over VK instances of
  * 2 n_in n_t^2 + 4 n_in n_t), [12] instances stored parity-blocked,
  * [13] dense-equivalent tensor bytes per step (sum of 4 n_in n_t^2),

@@ -47,7 +47,7 @@ def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     srcs = [("step_kernel.hip", True), ("grad_kernel.hip", True), ("shared_kernel.hip", True),
-            ("linear_kernel.hip", True), ("tf_kernel.hip", True),
+            ("linear_kernel.hip", True), ("tf_kernel.hip", True), ("chip_kernel.hip", True),
             ("modal_api.cpp", True),
             ("mlp_kernels.hip", True), ("mlp_api.cpp", True), ("coupling_host.cpp", False)]
 

@@ -10,6 +10,7 @@ constexpr int kWave = 64;        // CDNA wavefront width; one wave per workgroup
 constexpr int kMaxModes = 1024;  // per instance
 constexpr int kMaxGroups = kMaxModes / 4 / kWave;  // float4 groups per lane
 constexpr int kSweepLoads = 4;  // float4 loads per lane per sweep of Ht rows
+constexpr int kChipWaves = 8;   // waves of an on-chip (register-resident) workgroup
 
 enum : int { KIND_LINEAR = 0, KIND_TENSION = 1, KIND_VK = 2 };
 

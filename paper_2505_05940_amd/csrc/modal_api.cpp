@@ -27,6 +27,8 @@ hipError_t launch_ctr_fill(const InstDev* inst, int batch, const long long* step
                            hipStream_t s);
 hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s);
 hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes, bool res = false);
+hipError_t launch_chip(const StepParams& P, int nt_tile, int rows, int n_wg, hipStream_t s);
+bool chip_shape(int max_nt, int max_rows, int& nt_tile, int& rows);
 hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, bool split, int n_wg, size_t lds,
                        hipStream_t s);
 hipError_t grad_occupancy(int* blocks, int gm, bool tangent, int nw, bool split, size_t lds);
@@ -207,6 +209,9 @@ struct modal_ctx {
   double fs = 0;
   int n_wg = 0, n_units = 0, n_split = 0, occ = 0, gm = 1, nw = 4;
   int res_stride = 0;  // > 0: LDS-resident state (one unit per workgroup)
+  // > 0: the on-chip kernel (one workgroup per instance, tensor in
+  // registers), with chip_nt tensor columns and chip_rows rows per wave
+  int chip_nt = 0, chip_rows = 0;
   // waves of the reverse kernel without and with a tangent tensor (its
   // reduction space per wave holds two or three reduced vectors per row)
   int nw_grad[2] = {4, 4};
@@ -1380,6 +1385,23 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
       if (d->inst[b].kind == MODAL_KIND_VK) dense += 4.0 * d->inst[b].n_in * (double)d->inst[b].n_t * d->inst[b].n_t;
     latency = dense <= kLatencyBytes;
   }
+  // On-chip plan: a forward-only latency-bound batch whose instances each
+  // fit one workgroup's registers (at most 64 modes; a von Karman tensor of
+  // at most kChipWaves * rows in-plane rows) steps every instance in one
+  // workgroup that holds its tensor for the launch, with no exchange
+  // between workgroups.
+  int chip_nt = 0, chip_rows = 0;
+  if (latency && !(d->flags & MODAL_FLAG_GRAD)) {
+    int max_nt = 0, max_rows = 0;
+    bool ok = true;
+    for (int b = 0; b < d->batch && ok; ++b) {
+      const modal_instance& I = d->inst[b];
+      max_nt = std::max(max_nt, I.n_t);
+      if (I.kind == MODAL_KIND_VK) max_rows = std::max(max_rows, (I.n_in + kChipWaves - 1) / kChipWaves);
+    }
+    ok = max_nt <= kWave && chip_shape(max_nt, max_rows, chip_nt, chip_rows);
+    if (!ok) chip_nt = chip_rows = 0;
+  }
   std::vector<BlockPlan> plans;
   if (!latency) plan_blocks(d, plans);
   else plans.assign(d->batch, BlockPlan{});
@@ -1538,7 +1560,7 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
       const double bytes = inst[b].kind == KIND_VK ? 4.0 * inst[b].nin * (double)inst[b].nt * inst[b].nt : 0.0;
       const int by_rows = (rows + kLatencyRows / 2) / kLatencyRows;
       const int by_bytes = (int)std::ceil(bytes / kLatencySlabBytes);
-      const int S = inst[b].kind == KIND_VK
+      const int S = inst[b].kind == KIND_VK && !chip_nt
                         ? std::max(1, std::min({cap_slabs, rows, std::max(by_rows, by_bytes)}))
                         : 1;
       for (int sl = 0; sl < S; ++sl) {
@@ -1621,7 +1643,12 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
   // Berger plate in 2.4 us instead of 2.9).  Only
   // when the variant still fits every planned workgroup on the chip at once.
   c->res_stride = 0;
-  if (latency && n_wg == (int)udev.size() && (c->nw == 4 || c->nw == 8)) {
+  if (latency && chip_nt && n_wg == d->batch) {
+    c->chip_nt = chip_nt;
+    c->chip_rows = chip_rows;
+    c->nw = kChipWaves;
+    c->lds_bytes = 0;
+  } else if (latency && n_wg == (int)udev.size() && (c->nw == 4 || c->nw == 8)) {
     int S = 0;
     for (int b = 0; b < d->batch; ++b) S = std::max(S, inst[b].ntp);
     const size_t lb = step_lds_bytes(c->nw, red_floats, S);
@@ -1831,7 +1858,10 @@ static int enqueue_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride
         P.rec_d = c->dRecAll + (size_t)c->recall_cap * c->mode_floats;
         P.rec_base = 0;
       }
-      HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
+      if (c->chip_nt)
+        HIP_TRY(launch_chip(P, c->chip_nt, c->chip_rows, c->n_wg, s));
+      else
+        HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
     }
     HIP_TRY(launch_advance(c->dStep, (int)k, s));
   }
@@ -1977,7 +2007,10 @@ int modal_run_noalloc(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride,
     P.y = y + done;
     P.y_stride = y_stride;
     P.n_steps = (int)k;
-    HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
+    if (c->chip_nt)
+      HIP_TRY(launch_chip(P, c->chip_nt, c->chip_rows, c->n_wg, s));
+    else
+      HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
     HIP_TRY(launch_advance(c->dStep, (int)k, s));
   }
   // no checkpoints were recorded: a gradient context's recorded checkpoints
@@ -2419,7 +2452,7 @@ int modal_info(const modal_ctx* c, int64_t info[15]) {
   info[7] = c->occ;
   info[8] = (int64_t)c->makespan;
   info[9] = (int64_t)c->mean_load;
-  info[10] = c->shared ? 1 : (c->linear ? 2 : 0);
+  info[10] = c->shared ? 1 : (c->linear ? 2 : (c->chip_nt ? 3 : 0));
   info[11] = c->flops;
   info[12] = c->n_blocked;
   info[13] = c->shared ? c->coupling_bytes : c->dense_bytes;

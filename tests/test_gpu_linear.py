@@ -39,7 +39,7 @@ def test_linear_batch_full_second(gpu, scheme):
         ref = OS.run(dict(insts[b]), 44100, wl["fs"], scheme=scheme)
         assert rel_l2(y[b], ref) < TOL, (b, rel_l2(y[b], ref))
     yr = modal.Sim(insts, wl["fs"], scheme=scheme, flags=modal.FLAG_RECURSE)
-    assert yr.info()["path"] == 0
+    assert yr.info()["path"] in (0, 3)  # the recursion (streaming or on-chip)
     y2 = yr.run(44100).double().cpu().numpy()
     assert max(rel_l2(y[b], y2[b]) for b in range(24)) < 2 * TOL
 
@@ -77,7 +77,7 @@ def test_double_root_keeps_the_recursion(gpu):
     inst = dict(kind="linear", omega=np.array([w, 2 * w]), gamma=np.array([gam, gam]),
                 x0=np.array([1e-3, 1e-3]), xm1=np.array([1e-3, 1e-3]), c=np.array([1.0, 1.0]))
     sim = modal.Sim([inst], fs)
-    assert sim.info()["path"] == 0
+    assert sim.info()["path"] in (0, 3)  # the recursion (streaming or on-chip)
     y = sim.run(500).double().cpu().numpy()[0]
     assert rel_l2(y, OS.run(dict(inst), 500, fs)) < TOL
 

@@ -196,24 +196,26 @@ def test_asymmetric_tensor_rejected(gpu):
 
 def test_latency_plan_single_and_small_batches(gpu):
     """Latency-bound batches (at most one instance per CU, small dense
-    tensors, default shape): a lone plate runs dense in slabs of about eight
-    in-plane rows on their own workgroups; a batch of more than 16 keeps
-    each plate whole on one workgroup.  Both match the FP64 oracle."""
+    tensors, default shape) beyond the on-chip limits (more than 64 modes):
+    a lone plate runs dense in slabs of about eight in-plane rows on their
+    own workgroups; a batch of more than 16 keeps each plate whole on one
+    workgroup.  Both match the FP64 oracle."""
     modal, physics = gpu
-    wl = W.plate_vk(seed=31, n_t=40, family="sine", grid=None, n_steps=1500)
+    wl = W.plate_vk(seed=31, n_t=72, family="sine", grid=None, n_steps=1500)
     p = physics.plate_instance(wl)
     o = OI.plate_instance(wl)
-    _say("case: latency plan, one 40/40 plate")
+    _say("case: latency plan, one 72/72 plate")
     sim = modal.Sim([p], 44100.0)
     info = sim.info()
-    assert info["blocked_instances"] == 0 and info["workgroups"] == 5 and info["split_instances"] == 1, info
+    assert info["path"] == 0 and info["blocked_instances"] == 0, info
+    assert info["workgroups"] == 9 and info["split_instances"] == 1, info
     y = sim.run(1500).double().cpu().numpy()[0]
     assert rel_l2(y, OS.run(o, 1500, 44100.0)) < TOL
-    _say("case: latency plan, 20 plates of 12/12")
-    wls = [W.plate_vk(seed=40 + i, n_t=12, family="sine", grid=None, n_steps=800) for i in range(20)]
+    _say("case: latency plan, 20 plates of 66/12")
+    wls = [W.plate_vk(seed=40 + i, n_t=66, n_in=12, family="sine", grid=None, n_steps=800) for i in range(20)]
     sim = modal.Sim([physics.plate_instance(w) for w in wls], 44100.0)
     info = sim.info()
-    assert info["workgroups"] == 20 and info["split_instances"] == 0, info
+    assert info["path"] == 0 and info["workgroups"] == 20 and info["split_instances"] == 0, info
     y = sim.run(800).double().cpu().numpy()
     for i in (0, 7, 19):
         assert rel_l2(y[i], OS.run(OI.plate_instance(wls[i]), 800, 44100.0)) < TOL
