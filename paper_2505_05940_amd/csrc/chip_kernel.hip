@@ -7,14 +7,20 @@
 // that exchange partial forces through global memory each step; a small
 // plate's step is then bound by the latency of those round trips, not by its
 // arithmetic.  Here the tensor of an instance with at most 64 transverse
-// modes is loaded once: wave w keeps the in-plane rows n = w + kChipWaves r
-// (r < R), lane k the column k of each, h[r][j] = Ht[n][j][k] (j < NT).  Per
-// sample (paper: Sec. 3.1 modal forces, Sec. 3.2 modal update)
-//   1. wave 0 publishes q^n (fp32 high part) to LDS and writes the output
-//      y^n = sum_k c_k q_k^n;
-//   2. every wave forms, for its rows, V[n, k] = sum_j Ht[n][j][k] q_j
-//      (q broadcast from LDS), eta_n = sum_k V[n, k] q_k (a DPP sum over the
-//      wave) and its partial force F_k = sum_n eta_n V[n, k];
+// modes is loaded once, laid out by the instance's ChipMap: lane p stands
+// for mode perm[p], wave w keeps the in-plane rows row[w][r] (r < R), and
+// for each of them lane p holds the W entries h[r][t] = Ht[n][perm[jb + t]][perm[p]]
+// (t < jl, zero past it) of the one run of columns that can be nonzero
+// against it: all modes for a tensor without classes; for a sine-family
+// tensor, whose entries vanish unless the parity classes of the two columns
+// and the row match (Sec. 5, sparsity), only the partner class, a quarter of
+// them.  Per sample (paper: Sec. 3.1 modal forces, Sec. 3.2 modal update)
+//   1. wave 0 publishes q^n (fp32 high part, lane order) to LDS and writes
+//      the output y^n = sum_k c_k q_k^n;
+//   2. every wave forms, for its rows, V[n, p] = sum_t h[r][t] q[jb + t]
+//      (a wave's rows share jb, so each q read serves all of them),
+//      eta_n = sum_p V[n, p] q_p (a DPP sum over the wave) and its partial
+//      force F_p = sum_n eta_n V[n, p];
 //   3. wave 0 adds the waves' partial forces (LDS) and advances its lane's
 //      mode in float-float arithmetic, d+ = m X - p d + r (b e - F),
 //      X+ = X + d+, exactly as the streaming kernel does.
@@ -52,36 +58,45 @@ __device__ __forceinline__ void wave_sums(float (&v)[R]) {
 
 }  // namespace
 
-// NT: tensor columns held per row (>= nt of every instance, multiple of 8);
-// R: rows per wave (>= ceil(nin / kChipWaves)).
-template <int NT, int R>
+// W: tensor columns held per row and lane (>= every jl, multiple of 4);
+// R: rows per wave (>= every wave's row count).
+template <int W, int R>
 __global__ void __launch_bounds__(kWave * kChipWaves) chip_kernel(StepParams P) {
-  __shared__ float4 xs4[kWave / 4];               // q^n (high parts), zero past nt
-  __shared__ float red[kChipWaves][kWave];       // per-wave partial forces
-  float* Xs = reinterpret_cast<float*>(xs4);
+  // q^n (high parts) in lane order, zero past the last lane so that a run of
+  // W columns from any jb reads zeros beyond the modes
+  __shared__ float4 xc4[(kWave + 64) / 4];
+  __shared__ float red[kChipWaves][kWave];  // per-wave partial forces
+  float* Xc = reinterpret_cast<float*>(xc4);
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const UnitDev U = P.unit[P.wg_begin[blockIdx.x]];
   const InstDev I = P.inst[U.inst];
+  const ChipMap& M = P.chip[U.inst];
   const int nt = I.nt;
   const bool vk = I.kind == KIND_VK;
-  const bool mine = lane < nt;  // this lane's mode exists
+  const int k = M.perm[lane];  // this lane's mode (-1: none)
+  const int jb = M.jb[wave][lane];
+  const int jl = M.jl[wave][lane];
 
-  float h[R][NT];
+  float h[R][W];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int n = wave + kChipWaves * r;
-    const float* row = P.H + I.h_off + (long long)n * nt * I.ntp + lane;
+  for (int t = 0; t < W; ++t) {
+    const int j = (vk && k >= 0 && t < jl) ? M.perm[jb + t] : -1;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) h[r][j] = (vk && mine && n < I.nin && j < nt) ? row[(long long)j * I.ntp] : 0.f;
+    for (int r = 0; r < R; ++r) {
+      const int n = M.row[wave][r];
+      h[r][t] = (j >= 0 && n >= 0) ? P.H[I.h_off + ((long long)n * nt + j) * I.ntp + k] : 0.f;
+    }
   }
+  for (int i = threadIdx.x; i < kWave + 64; i += kWave * kChipWaves) Xc[i] = 0.f;
+  __syncthreads();
 
   // wave 0: its lane's mode, state and coefficients
   float xh = 0.f, xl = 0.f, dh = 0.f, dl = 0.f;
   float mh = 0.f, ml = 0.f, ph = 0.f, pl = 0.f, rh = 0.f, rl = 0.f, bx = 0.f, cw = 0.f, lam = 0.f;
   if (wave == 0) {
-    if (mine) {
-      const int so = U.state_off + lane, mo = I.mode_off + lane;
+    if (k >= 0) {
+      const int so = U.state_off + k, mo = I.mode_off + k;
       xh = P.x_hi[so];
       xl = P.x_lo[so];
       dh = P.d_hi[so];
@@ -96,8 +111,9 @@ __global__ void __launch_bounds__(kWave * kChipWaves) chip_kernel(StepParams P) 
       cw = P.c_out[mo];
       lam = P.lam[mo];
     }
-    Xs[lane] = xh;
+    Xc[lane] = xh;
   }
+  const float4* xq = reinterpret_cast<const float4*>(Xc + jb);
   const long long base = *P.step_base;
   bool bad = false;
   for (int s = 0; s < P.n_steps; ++s) {
@@ -115,17 +131,17 @@ __global__ void __launch_bounds__(kWave * kChipWaves) chip_kernel(StepParams P) 
 #pragma unroll
       for (int r = 0; r < R; ++r) V[r] = 0.f;
 #pragma unroll
-      for (int j4 = 0; j4 < NT / 4; ++j4) {
-        const float4 q = xs4[j4];
+      for (int t4 = 0; t4 < W / 4; ++t4) {
+        const float4 q = xq[t4];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          V[r] = fmaf(h[r][4 * j4], q.x, V[r]);
-          V[r] = fmaf(h[r][4 * j4 + 1], q.y, V[r]);
-          V[r] = fmaf(h[r][4 * j4 + 2], q.z, V[r]);
-          V[r] = fmaf(h[r][4 * j4 + 3], q.w, V[r]);
+          V[r] = fmaf(h[r][4 * t4], q.x, V[r]);
+          V[r] = fmaf(h[r][4 * t4 + 1], q.y, V[r]);
+          V[r] = fmaf(h[r][4 * t4 + 2], q.z, V[r]);
+          V[r] = fmaf(h[r][4 * t4 + 3], q.w, V[r]);
         }
       }
-      const float qk = Xs[lane];
+      const float qk = Xc[lane];
       float eta[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) eta[r] = V[r] * qk;
@@ -146,12 +162,12 @@ __global__ void __launch_bounds__(kWave * kChipWaves) chip_kernel(StepParams P) 
     if (wave == 0) {
       ff_step(xh, xl, dh, dl, mh, ml, ph, pl, rh, rl, fmaf(bx, e, -F));
       bad |= !isfinite(xh);
-      if (mine) Xs[lane] = xh;
+      if (k >= 0) Xc[lane] = xh;
     }
   }
   if (wave == 0) {
-    if (mine) {
-      const int so = U.state_off + lane;
+    if (k >= 0) {
+      const int so = U.state_off + k;
       P.x_hi[so] = xh;
       P.x_lo[so] = xl;
       P.d_hi[so] = dh;
@@ -161,28 +177,39 @@ __global__ void __launch_bounds__(kWave * kChipWaves) chip_kernel(StepParams P) 
   }
 }
 
-// Column widths and rows per wave with a kernel: R NT <= 200 floats of
-// tensor per lane (with the rest of the kernel's registers, at most two
-// waves per SIMD).
-bool chip_shape(int max_nt, int max_rows, int& nt_tile, int& rows) {
-  static const int widths[] = {16, 32, 40, 48, 64};
-  rows = std::max(1, max_rows);
-  for (int w : widths)
-    if (w >= max_nt) {
-      nt_tile = w;
-      return rows * w <= 200 && rows <= 8;
+// Widths and rows per wave with a kernel: W R <= 200 tensor floats per lane
+// (with the rest of the kernel's registers, at most two waves per SIMD).
+bool chip_shape(int max_w, int max_rows, int& w_tile, int& rows) {
+  static const int widths[] = {8, 16, 20, 24, 32, 40, 48, 64};
+  static const int counts[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12};
+  int w = 0, r = 0;
+  for (int x : widths)
+    if (x >= max_w) {
+      w = x;
+      break;
     }
-  return false;
+  for (int x : counts)
+    if (x >= std::max(1, max_rows)) {
+      r = x;
+      break;
+    }
+  if (!w || !r || w * r > 200) return false;
+  w_tile = w;
+  rows = r;
+  return true;
 }
 
-hipError_t launch_chip(const StepParams& P, int nt_tile, int rows, int n_wg, hipStream_t s) {
-  if (P.ckpt || P.rec_x) return hipErrorInvalidValue;  // forward-only contexts
-#define CL(W, RR)                                                                                \
-  if (nt_tile == W && rows == RR) {                                                              \
-    hipLaunchKernelGGL((chip_kernel<W, RR>), dim3(n_wg), dim3(kWave * kChipWaves), 0, s, P);     \
+hipError_t launch_chip(const StepParams& P, int w_tile, int rows, int n_wg, hipStream_t s) {
+  if (P.ckpt || P.rec_x || !P.chip) return hipErrorInvalidValue;  // forward-only contexts
+#define CL(WW, RR)                                                                               \
+  if (w_tile == WW && rows == RR) {                                                              \
+    hipLaunchKernelGGL((chip_kernel<WW, RR>), dim3(n_wg), dim3(kWave * kChipWaves), 0, s, P);    \
     return hipGetLastError();                                                                    \
   }
-  CL(16, 1) CL(16, 2) CL(16, 3) CL(16, 4) CL(16, 5) CL(16, 6) CL(16, 7) CL(16, 8)
+  CL(8, 1) CL(8, 2) CL(8, 3) CL(8, 4) CL(8, 5) CL(8, 6) CL(8, 7) CL(8, 8) CL(8, 10) CL(8, 12)
+  CL(16, 1) CL(16, 2) CL(16, 3) CL(16, 4) CL(16, 5) CL(16, 6) CL(16, 7) CL(16, 8) CL(16, 10) CL(16, 12)
+  CL(20, 1) CL(20, 2) CL(20, 3) CL(20, 4) CL(20, 5) CL(20, 6) CL(20, 7) CL(20, 8) CL(20, 10)
+  CL(24, 1) CL(24, 2) CL(24, 3) CL(24, 4) CL(24, 5) CL(24, 6) CL(24, 7) CL(24, 8)
   CL(32, 1) CL(32, 2) CL(32, 3) CL(32, 4) CL(32, 5) CL(32, 6)
   CL(40, 1) CL(40, 2) CL(40, 3) CL(40, 4) CL(40, 5)
   CL(48, 1) CL(48, 2) CL(48, 3) CL(48, 4)

@@ -11,6 +11,7 @@ constexpr int kMaxModes = 1024;  // per instance
 constexpr int kMaxGroups = kMaxModes / 4 / kWave;  // float4 groups per lane
 constexpr int kSweepLoads = 4;  // float4 loads per lane per sweep of Ht rows
 constexpr int kChipWaves = 8;   // waves of an on-chip (register-resident) workgroup
+constexpr int kChipMaxRows = 12;  // in-plane rows per wave on the on-chip path
 
 enum : int { KIND_LINEAR = 0, KIND_TENSION = 1, KIND_VK = 2 };
 
@@ -109,6 +110,20 @@ __host__ __device__ inline GradLds grad_lds(float* base) {
   return L;
 }
 
+// Register layout of one instance on the on-chip path.  Lane p of every
+// wave stands for mode perm[p] (-1: none); modes may be grouped by parity
+// class (each class's lanes contiguous from a multiple of 4).  Wave w holds
+// the in-plane rows row[w][r] (-1: none), all with the same column pattern:
+// lane p multiplies, in each of them, the jl[w][p] consecutive lanes' modes
+// from lane jb[w][p] (the one column class whose entries can be nonzero
+// against p's class; for a tensor without classes, all nt modes from 0).
+struct ChipMap {
+  short perm[kWave];
+  short row[kChipWaves][kChipMaxRows];
+  unsigned char jb[kChipWaves][kWave];
+  unsigned char jl[kChipWaves][kWave];
+};
+
 struct StepParams {
   const InstDev* inst;
   const int4* jmap;     // block maps of parity-blocked instances
@@ -142,6 +157,7 @@ struct StepParams {
   // per-step record of q^n and d^n (fp32) for steps rec_base.. : [step][mode_floats]
   float *rec_x, *rec_d;
   long long rec_base;
+  const ChipMap* chip;  // on-chip path: one map per instance
 };
 
 // Reverse (adjoint) sweep over a recorded segment of steps.

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -210,8 +211,10 @@ struct modal_ctx {
   int n_wg = 0, n_units = 0, n_split = 0, occ = 0, gm = 1, nw = 4;
   int res_stride = 0;  // > 0: LDS-resident state (one unit per workgroup)
   // > 0: the on-chip kernel (one workgroup per instance, tensor in
-  // registers), with chip_nt tensor columns and chip_rows rows per wave
+  // registers), with chip_nt tensor columns per lane and chip_rows rows per
+  // wave, and its register layouts (one ChipMap per instance)
   int chip_nt = 0, chip_rows = 0;
+  ChipMap* dChip = nullptr;
   // waves of the reverse kernel without and with a tangent tensor (its
   // reduction space per wave holds two or three reduced vectors per row)
   int nw_grad[2] = {4, 4};
@@ -321,7 +324,7 @@ void free_ctx(modal_ctx* c) {
                   c->dStep, c->dE,   c->dHd,   c->dCkpt,  c->dRec,  c->dAdj, c->dAcc,
                   c->dGPart, c->dGCtr, c->dShA, c->dShS2, c->dJmap, c->dRrec, c->dRacc,
                   c->dLinModes, c->dLinInit, c->dLinAmp, c->dLinSeg, c->dLinForced, c->dLinH,
-                  c->dLinTab, c->dUrec, c->dTrec, c->dTJobs, c->dRecAll};
+                  c->dLinTab, c->dUrec, c->dTrec, c->dTJobs, c->dRecAll, c->dChip};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -575,6 +578,110 @@ void plan_blocks(const modal_desc* d, std::vector<BlockPlan>& plans) {
   for (unsigned t = 1; t < nth; ++t) th.emplace_back(work);
   work();
   for (auto& t : th) t.join();
+}
+
+// On-chip register layout of one instance (see ChipMap), with the columns
+// per lane (w_need) and rows per wave (r_need) it takes; false if it does
+// not fit one workgroup (more than kWave lanes, or more than kChipMaxRows
+// rows on a wave).  A VK tensor with mode classes, on the host, with the
+// exact block structure of the classes gets its modes grouped by class, and
+// each wave the rows of one column pattern, so a lane holds only the one
+// class of columns that can be nonzero against it; any other tensor is
+// held whole (all nt columns), its rows dealt to the waves in turn.
+bool chip_map(const modal_instance& I, ChipMap& m, int& w_need, int& r_need) {
+  const int nt = I.n_t;
+  w_need = r_need = 0;
+  if (nt > kWave) return false;
+  for (int p = 0; p < kWave; ++p) m.perm[p] = (short)(p < nt ? p : -1);
+  for (int w = 0; w < kChipWaves; ++w) {
+    for (int r = 0; r < kChipMaxRows; ++r) m.row[w][r] = -1;
+    for (int p = 0; p < kWave; ++p) {
+      m.jb[w][p] = 0;
+      m.jl[w][p] = 0;
+    }
+  }
+  if (I.kind != MODAL_KIND_VK) return true;
+  BlockPlan bp;
+  if (I.mode_class) {
+    hipPointerAttribute_t attr;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&attr, I.H) == hipSuccess)
+      on_device = attr.type == hipMemoryTypeDevice;
+    else
+      (void)hipGetLastError();
+    if (!on_device) analyze_blocks(I, bp);
+  }
+  const int nin = I.n_in;
+  if (!bp.ok || bp.cls[4] > kWave) {  // whole tensor, rows dealt in turn
+    r_need = (nin + kChipWaves - 1) / kChipWaves;
+    if (r_need > kChipMaxRows) return false;
+    for (int n = 0; n < nin; ++n) m.row[n % kChipWaves][n / kChipWaves] = (short)n;
+    for (int w = 0; w < kChipWaves; ++w)
+      for (int p = 0; p < nt; ++p) m.jl[w][p] = (unsigned char)nt;
+    w_need = nt;
+    return true;
+  }
+  // modes grouped by class; the column class partnering each class of a
+  // row, with a stored transposed pair counted for both of its blocks
+  for (int p = 0; p < kWave; ++p) m.perm[p] = (short)(p < bp.cls[4] ? bp.slot_mode[p] : -1);
+  int real[4] = {0, 0, 0, 0};
+  for (int c = 0; c < 4; ++c)
+    for (int p = bp.cls[c]; p < bp.cls[c + 1]; ++p) real[c] += bp.slot_mode[p] >= 0;
+  std::map<std::array<int, 4>, std::vector<int>> by_pattern;
+  for (int n = 0; n < nin; ++n) {
+    std::array<int, 4> part = {-1, -1, -1, -1};
+    for (int i = 0; i < 4; ++i) {
+      const int je = bp.jmap[(size_t)n * 4 + i];
+      if (je < 0) continue;
+      part[i] = je & 7;
+      if (je & 8) part[je & 7] = i;
+    }
+    if (part[0] < 0 && part[1] < 0 && part[2] < 0 && part[3] < 0) continue;  // a zero row
+    by_pattern[part].push_back(n);
+  }
+  const int npat = (int)by_pattern.size();
+  if (npat > kChipWaves) return false;
+  std::vector<const std::array<int, 4>*> pats;
+  std::vector<const std::vector<int>*> rows;
+  for (auto& kv : by_pattern) {
+    pats.push_back(&kv.first);
+    rows.push_back(&kv.second);
+  }
+  // one wave per pattern, the rest where the most rows per wave remain
+  std::vector<int> waves(npat, 1);
+  for (int left = kChipWaves - npat; left > 0; --left) {
+    int best = -1;
+    double most = -1;
+    for (int i = 0; i < npat; ++i) {
+      const double per = (double)rows[i]->size() / waves[i];
+      if (per > most) {
+        most = per;
+        best = i;
+      }
+    }
+    if (best < 0) break;
+    waves[best]++;
+  }
+  int w0 = 0;
+  for (int i = 0; i < npat; ++i) {
+    const std::vector<int>& rs = *rows[i];
+    const int per = ((int)rs.size() + waves[i] - 1) / waves[i];
+    if (per > kChipMaxRows) return false;
+    r_need = std::max(r_need, per);
+    for (size_t t = 0; t < rs.size(); ++t) m.row[w0 + (int)(t % waves[i])][t / waves[i]] = (short)rs[t];
+    for (int w = w0; w < w0 + waves[i]; ++w)
+      for (int c = 0; c < 4; ++c) {
+        const int cj = (*pats[i])[c];
+        if (cj < 0) continue;
+        for (int p = bp.cls[c]; p < bp.cls[c + 1]; ++p) {
+          m.jb[w][p] = (unsigned char)bp.cls[cj];
+          m.jl[w][p] = (unsigned char)real[cj];
+        }
+        w_need = std::max(w_need, real[cj]);
+      }
+    w0 += waves[i];
+  }
+  return true;
 }
 
 // Planning cost of an instance in streamed-byte units: per in-plane row the
@@ -1391,16 +1498,22 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
   // workgroup that holds its tensor for the launch, with no exchange
   // between workgroups.
   int chip_nt = 0, chip_rows = 0;
+  std::vector<ChipMap> chip_maps;
   if (latency && !(d->flags & MODAL_FLAG_GRAD)) {
-    int max_nt = 0, max_rows = 0;
+    int max_w = 0, max_rows = 0;
     bool ok = true;
+    chip_maps.resize(d->batch);
     for (int b = 0; b < d->batch && ok; ++b) {
-      const modal_instance& I = d->inst[b];
-      max_nt = std::max(max_nt, I.n_t);
-      if (I.kind == MODAL_KIND_VK) max_rows = std::max(max_rows, (I.n_in + kChipWaves - 1) / kChipWaves);
+      int w = 0, r = 0;
+      ok = chip_map(d->inst[b], chip_maps[b], w, r);
+      max_w = std::max(max_w, w);
+      max_rows = std::max(max_rows, r);
     }
-    ok = max_nt <= kWave && chip_shape(max_nt, max_rows, chip_nt, chip_rows);
-    if (!ok) chip_nt = chip_rows = 0;
+    ok = ok && chip_shape(max_w, max_rows, chip_nt, chip_rows);
+    if (!ok) {
+      chip_nt = chip_rows = 0;
+      chip_maps.clear();
+    }
   }
   std::vector<BlockPlan> plans;
   if (!latency) plan_blocks(d, plans);
@@ -1728,6 +1841,7 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
   ALLOC(c->dStep, sizeof(long long));
   ALLOC(c->dE, sizeof(float) * (size_t)(e_floats + 1));
   ALLOC(c->dJmap, sizeof(int) * (jmap_pool.size() + 4));
+  if (c->chip_nt) ALLOC(c->dChip, sizeof(ChipMap) * chip_maps.size());
 #undef ALLOC
   auto bail = [&](int r) {
     free_ctx(c);
@@ -1745,6 +1859,9 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
     if (r) return bail(r);
     if (!jmap_pool.empty())
       HIP_TRY_C(hipMemcpyAsync(c->dJmap, jmap_pool.data(), sizeof(int) * jmap_pool.size(),
+                               hipMemcpyHostToDevice, stream));
+    if (c->chip_nt)
+      HIP_TRY_C(hipMemcpyAsync(c->dChip, chip_maps.data(), sizeof(ChipMap) * chip_maps.size(),
                                hipMemcpyHostToDevice, stream));
   }
   char* meta = (char*)c->dMeta;
@@ -1807,6 +1924,7 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
   P.red_floats = red_floats;
   P.mode_floats = mode_floats;
   P.res_stride = c->res_stride;
+  P.chip = c->dChip;
 #undef HIP_TRY_C
   int r = modal_reset(c, stream_);
   if (r) return bail(r);

@@ -56,15 +56,37 @@ def test_c2_plate_full_second_on_chip(gpu):
     assert rel_l2(xm, states[-2]) < TOL
 
 
+@pytest.mark.parametrize("n", [40, 50, 60])
+def test_sine_plates_full_second_on_chip(gpu, n):
+    """Sine-family plates up to the paper's 50-mode benchmark shape and
+    beyond (Sec. 4.2): modes grouped by parity class so that a lane holds
+    only the quarter of each row that can be nonzero against its mode."""
+    modal, physics = gpu
+    wl = W.plate_sweep(n)
+    _say(f"case: on-chip {n}/{n} sine plate, 44100 steps")
+    sim = modal.Sim([physics.plate_instance(wl)], wl["fs"])
+    assert sim.info()["path"] == PATH_CHIP
+    y = sim.run(wl["n_steps"])[0].double().cpu().numpy()
+    ref = OS.run(OI.plate_instance(wl), wl["n_steps"], wl["fs"])
+    e = rel_l2(y, ref)
+    _say(f"  rel L2 {e:.2e}")
+    assert e < TOL, e
+
+
 def _mixed():
-    """Ragged small instances of every kind: vK plates whose mode counts are
-    and are not multiples of 4 and whose in-plane rows fill one to five rows
-    per wave, a tension-modulated string, and a forced linear system."""
+    """Ragged small instances of every kind: sine-family vK plates (modes
+    grouped by class) whose mode counts are and are not multiples of 4 and
+    whose in-plane rows fill one to five rows per wave, a clamped-family
+    plate (held whole), a tension-modulated string, and a forced linear
+    system."""
     out = []
     for i, (nt, nin) in enumerate([(3, 2), (10, 10), (17, 9), (33, 33), (40, 40), (24, 31)]):
         wl = W.plate_vk(seed=300 + i, n_t=nt, n_in=nin, family="sine", grid=None, n_steps=6000)
         wl["strike"]["amplitude"] = 2e-3
         out.append(("plate", wl))
+    wl = W.plate_vk(seed=299, n_t=16, n_steps=6000)  # clamped family: no classes, held whole
+    wl["strike"]["amplitude"] = 2e-3
+    out.append(("plate", wl))
     out.append(("string", W.string_kc(n_steps=6000)))
     rng = np.random.default_rng(12)
     n = 13
@@ -138,7 +160,7 @@ def test_streaming_plan_is_still_chosen_when_it_must_be(gpu):
     gradient contexts keep the streaming kernel."""
     modal, physics = gpu
     small = physics.plate_instance(W.plate_vk(n_t=20, family="sine", grid=None))
-    big = physics.plate_instance(W.plate_sweep(50))
+    big = physics.plate_instance(W.plate_sweep(100))
     assert modal.Sim([small], 44100.0).info()["path"] == PATH_CHIP
     assert modal.Sim([big], 44100.0).info()["path"] == 0
     assert modal.Sim([small, big], 44100.0).info()["path"] == 0
