@@ -202,6 +202,28 @@ def gradient(workers, log_term=True):
           flush=True)
 
 
+def ybar():
+    """The config-4 adjoint inputs in FP64: the oracle's output at theta0 and
+    the target's, and dL/dy of the MR-STFT loss (with and without its
+    log-magnitude term) at them, so that a test can drive the product's
+    reverse pass with exactly the oracle's dL/dy (the log-magnitude term's
+    dL/dy responds to FP32 rounding of the output in near-silent bins)."""
+    import workloads as W
+    from oracle import adjoint as OA
+    from oracle import losses as OL
+    from oracle import params as OP
+    fit = W.plate_fit()
+    th0 = np.asarray(fit["theta0"], float)
+    tht = np.asarray(fit["theta_target"], float)
+    t0 = time.time()
+    target = OA.forward(OP.plate_from_theta(fit, tht), FULL_STEPS, FS)[0]
+    y0 = OA.forward(OP.plate_from_theta(fit, th0), FULL_STEPS, FS)[0]
+    print(f"  forward passes in {time.time() - t0:.0f} s", flush=True)
+    np.savez(os.path.join(HERE, "gradient_200_ybar.npz"), y0=y0, target=target,
+             ybar=OL.mrstft_loss_grad(y0, target, log_term=True),
+             ybar_sc=OL.mrstft_loss_grad(y0, target, log_term=False))
+
+
 def main():
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
     workers = int(os.environ.get("GOLDEN_WORKERS", "4"))
@@ -211,6 +233,8 @@ def main():
         gradient(workers)
     if what in ("gradient_sc", "all"):
         gradient(workers, log_term=False)
+    if what in ("ybar", "all"):
+        ybar()
     if what in ("batch", "all"):
         batch(workers)
 

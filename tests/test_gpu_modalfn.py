@@ -76,11 +76,18 @@ def test_config4_mrstft_gradient_against_oracle_and_differences(torch_gpu):
     FP64 oracle's reverse recursion + chain rule (tests/golden/
     gradient_200.json) to 1e-3 per component.  The same for the loss's
     spectral-convergence terms alone (gradient_200_sc.json), also against
-    the oracle's central differences at the configured relative step 1e-4,
-    to 1e-3 per component.  (The log-magnitude term is an absolute value per
-    STFT bin; at a step of 1e-4 the differences of the full loss cross its
-    kinks and miss the derivative by up to tens of per cent for D^ and a, so
-    that check is made on the smooth part of the loss.)"""
+    the oracle's central differences at a relative step of 1e-6, to 1e-3 per
+    component.  Central differences at the configured relative step 1e-4 are
+    not a derivative estimate here: a relative change of 1e-4 in D^ moves a
+    5 kHz mode's phase by about 1.6 rad over the second, so the loss is far
+    from linear over the step (the stored 1e-4 differences miss the reverse
+    gradient by 30 % for D^ and a, for both losses).  The full loss is
+    checked against the reverse pass only: its log-magnitude term has a kink
+    per STFT bin, and even at 1e-6 its differences miss by up to 0.7 %.  Its
+    dL/dy also follows the FP32 rounding of the output in near-silent bins,
+    so the product's reverse pass is checked to 1e-3 when driven by the
+    oracle's own dL/dy (tests/golden/gradient_200_ybar.npz), and the
+    gradient through the loss to 1e-2."""
     torch = torch_gpu
     from paper_2505_05940_amd import fit
     from paper_2505_05940_amd.losses import mrstft_loss
@@ -91,6 +98,7 @@ def test_config4_mrstft_gradient_against_oracle_and_differences(torch_gpu):
             pytest.fail(f"{path} missing: run tests/golden/make_golden.py")
         recs[name] = json.load(open(path))
     arr = np.load(os.path.join(GOLDEN, "gradient_200.npz"))
+    yb = np.load(os.path.join(GOLDEN, "gradient_200_ybar.npz"))
     fw = W.plate_fit()
     st = _setup(fw)
     th0 = np.asarray(recs["gradient_200"]["theta0"])
@@ -106,17 +114,38 @@ def test_config4_mrstft_gradient_against_oracle_and_differences(torch_gpu):
                   / np.linalg.norm(arr["y0"].astype(float)))
         _say(f"  forward rel L2 against the oracle: {e:.2e}")
         assert e < 1e-5, e
-        L = mrstft_loss(y, target, log_term=log_term)
+        # The loss in FP64, as the oracle's.  Its log-magnitude term responds
+        # to the FP32 rounding of the output in near-silent STFT bins:
+        # rounding the oracle's own output and target to FP32 moves the full
+        # loss by 1.2e-5 relative, and an output within 1e-7 rel L2 of the
+        # oracle's by about 5e-5; the spectral-convergence terms move by
+        # 1e-9.  Bars: 2e-4 and 1e-6.
+        L = mrstft_loss(y.double(), target.double(), log_term=log_term)
         _say(f"  loss {L.item():.8f} (oracle {rec['loss']:.8f})")
-        assert abs(L.item() - rec["loss"]) < 1e-5 * abs(rec["loss"])
+        assert abs(L.item() - rec["loss"]) < (2e-4 if log_term else 1e-6) * abs(rec["loss"])
         L.backward()
         got = theta.grad.numpy()[0]
-        refs = [("oracle reverse", "grad_reverse")] + ([] if log_term else [("differences 1e-4", "grad_fd")])
-        for what, key in refs:
+        # the reverse pass driven by the oracle's own dL/dy (FP64 output and
+        # target): the adjoint and chain rule alone, to 1e-3
+        theta2 = torch.tensor(th0[None], dtype=torch.float64, requires_grad=True)
+        y2 = fit.ModalFn.apply(theta2, st, steps, 512)
+        y2.backward(torch.tensor(yb["ybar" if log_term else "ybar_sc"], dtype=torch.float32,
+                                 device="cuda").reshape(1, -1))
+        driven = theta2.grad.numpy()[0]
+        checks = [("oracle dL/dy vs oracle reverse", driven, "grad_reverse", 1e-3)]
+        if log_term:
+            # through the loss: its dL/dy in near-silent bins follows the
+            # FP32 rounding of y (above); measured 3.5e-3 on T0^, the
+            # smallest component
+            checks.append(("loss gradient vs oracle reverse", got, "grad_reverse", 1e-2))
+        else:
+            checks += [("loss gradient vs oracle reverse", got, "grad_reverse", 1e-3),
+                       ("loss gradient vs differences 1e-6", got, "grad_fd_1e6", 1e-3)]
+        for what, g, key, bar in checks:
             ref = np.asarray(rec[key])
-            err = np.abs(got - ref) / np.abs(ref)
-            _say(f"  vs {what}: {got} / {ref}, rel err {err}")
-            assert err.max() < 1e-3, (name, what, got, ref, err)
+            err = np.abs(g - ref) / np.abs(ref)
+            _say(f"  {what}: {g} / {ref}, rel err {err}")
+            assert err.max() < bar, (name, what, g, ref, err)
 
 
 @pytest.mark.timeout(600)
