@@ -51,6 +51,18 @@ int mlp_backward(mlp_ctx *c, const float *dy, void *stream);
  * stored gradients. */
 int mlp_adam_step(mlp_ctx *c, float lr, float beta1, float beta2, float eps, int32_t t, void *stream);
 
+/* One training step of the mean squared error on a batch drawn by index:
+ * x_b = X[idx[b]] (rows of dims[0] floats), z_b = Z[idx[b]] (rows of
+ * dims[L] floats), b < B <= max_batch; forward, gradient of
+ * L = sum_b |y_b - z_b|^2 / (B dims[L]), backward and one Adam step (as
+ * mlp_adam_step with step number t), all on `stream` without host
+ * synchronisation; adds L to *loss_acc (device float) unless loss_acc is
+ * NULL.  X, Z, idx (int64, each in range; not checked) and loss_acc are
+ * device memory.  Leaves the batch's activations and gradients as
+ * mlp_forward and mlp_backward would.  Errors: EINVAL, EHIP. */
+int mlp_train_step(mlp_ctx *c, const float *X, const float *Z, const int64_t *idx, int32_t B, float lr,
+                   float beta1, float beta2, float eps, int32_t t, float *loss_acc, void *stream);
+
 void mlp_destroy(mlp_ctx *c);
 const char *mlp_last_error(void);
 

@@ -14,6 +14,9 @@ namespace modal {
 hipError_t launch_gemm(const float* A, long long lda, int a_kc, const float* B, long long ldb, int b_kc, float* C,
                        long long ldc, int M, int N, int K, int epi, const float* bias, const float* mask,
                        float* part, hipStream_t s);
+hipError_t launch_gather_rows(const float* src, const long long* idx, int B, int d, float* dst, hipStream_t s);
+hipError_t launch_mse_grad(const float* y, const float* z, const long long* idx, int B, int d, float* g,
+                           float* acc, hipStream_t s);
 constexpr int kMaxSplit = 8;
 hipError_t launch_colsum(const float* G, int M, int N, float* part, float* db, hipStream_t s);
 constexpr int kColSlices = 16;
@@ -130,10 +133,12 @@ int mlp_get(mlp_ctx* c, int32_t which, float* host, void* stream) {
   return MODAL_OK;
 }
 
-int mlp_forward(mlp_ctx* c, const float* x, int32_t B, float* y, void* stream) {
-  if (!c || !x || !y || B < 1 || B > c->max_batch) return mfail(MODAL_EINVAL, "bad arguments");
-  hipStream_t s = (hipStream_t)stream;
-  MHIP(hipMemcpyAsync(c->act, x, sizeof(float) * (size_t)B * c->dims[0], hipMemcpyDeviceToDevice, s));
+}  // extern "C"
+
+namespace {
+
+// the layers on the input already in act (layer 0)
+int forward_layers(mlp_ctx* c, int B, hipStream_t s) {
   for (int l = 0; l < c->L; ++l) {
     const int in = c->dims[l], out = c->dims[l + 1];
     const float* a = c->act + c->act_off[l];
@@ -142,19 +147,15 @@ int mlp_forward(mlp_ctx* c, const float* x, int32_t B, float* y, void* stream) {
     MHIP(launch_gemm(a, in, 1, c->p + c->w_off[l], in, 1, z, out, B, out, in,
                      l + 1 < c->L ? EPI_BIAS_RELU : EPI_BIAS, c->p + c->b_off[l], nullptr, c->kpart, s));
   }
-  MHIP(hipMemcpyAsync(y, c->act + c->act_off[c->L], sizeof(float) * (size_t)B * c->dims[c->L],
-                      hipMemcpyDeviceToDevice, s));
   c->last_batch = B;
   return MODAL_OK;
 }
 
-int mlp_backward(mlp_ctx* c, const float* dy, void* stream) {
-  if (!c || !dy || c->last_batch < 1) return mfail(MODAL_ESTATE, "backward needs a forward first");
-  hipStream_t s = (hipStream_t)stream;
+// the gradients for the output gradient already in d0
+int backward_layers(mlp_ctx* c, hipStream_t s) {
   const int B = c->last_batch;
   float* gcur = c->d0;
   float* gnext = c->d1;
-  MHIP(hipMemcpyAsync(gcur, dy, sizeof(float) * (size_t)B * c->dims[c->L], hipMemcpyDeviceToDevice, s));
   for (int l = c->L - 1; l >= 0; --l) {
     const int in = c->dims[l], out = c->dims[l + 1];
     const float* a = c->act + c->act_off[l];
@@ -171,6 +172,44 @@ int mlp_backward(mlp_ctx* c, const float* dy, void* stream) {
       std::swap(gcur, gnext);
     }
   }
+  return MODAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlp_forward(mlp_ctx* c, const float* x, int32_t B, float* y, void* stream) {
+  if (!c || !x || !y || B < 1 || B > c->max_batch) return mfail(MODAL_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  MHIP(hipMemcpyAsync(c->act, x, sizeof(float) * (size_t)B * c->dims[0], hipMemcpyDeviceToDevice, s));
+  int r = forward_layers(c, B, s);
+  if (r) return r;
+  MHIP(hipMemcpyAsync(y, c->act + c->act_off[c->L], sizeof(float) * (size_t)B * c->dims[c->L],
+                      hipMemcpyDeviceToDevice, s));
+  return MODAL_OK;
+}
+
+int mlp_backward(mlp_ctx* c, const float* dy, void* stream) {
+  if (!c || !dy || c->last_batch < 1) return mfail(MODAL_ESTATE, "backward needs a forward first");
+  hipStream_t s = (hipStream_t)stream;
+  MHIP(hipMemcpyAsync(c->d0, dy, sizeof(float) * (size_t)c->last_batch * c->dims[c->L],
+                      hipMemcpyDeviceToDevice, s));
+  return backward_layers(c, s);
+}
+
+int mlp_train_step(mlp_ctx* c, const float* X, const float* Z, const int64_t* idx, int32_t B, float lr,
+                   float beta1, float beta2, float eps, int32_t t, float* loss_acc, void* stream) {
+  if (!c || !X || !Z || !idx || B < 1 || B > c->max_batch || t < 1) return mfail(MODAL_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const long long* ix = reinterpret_cast<const long long*>(idx);
+  MHIP(launch_gather_rows(X, ix, B, c->dims[0], c->act, s));
+  int r = forward_layers(c, B, s);
+  if (r) return r;
+  MHIP(launch_mse_grad(c->act + c->act_off[c->L], Z, ix, B, c->dims[c->L], c->d0, loss_acc, s));
+  r = backward_layers(c, s);
+  if (r) return r;
+  MHIP(launch_adam(c->p, c->g, c->m, c->v, c->n_params, lr, beta1, beta2, eps, t, s));
   return MODAL_OK;
 }
 

@@ -211,6 +211,55 @@ __global__ void colsum_final(const float* __restrict__ part, int N, float* __res
   db[n] = s;
 }
 
+// dst[b][:] = src[idx[b]][:] (rows of d floats)
+__global__ void gather_rows(const float* __restrict__ src, const long long* __restrict__ idx, int d,
+                            float* __restrict__ dst) {
+  const long long r = idx[blockIdx.x];
+  const float* s = src + r * d;
+  float* o = dst + (long long)blockIdx.x * d;
+  if ((d & 3) == 0 && ((reinterpret_cast<unsigned long long>(src) & 15) == 0)) {
+    for (int i = threadIdx.x; i < d / 4; i += blockDim.x)
+      reinterpret_cast<float4*>(o)[i] = reinterpret_cast<const float4*>(s)[i];
+  } else {
+    for (int i = threadIdx.x; i < d; i += blockDim.x) o[i] = s[i];
+  }
+}
+
+// Mean squared error of y [B][d] against z[idx[b]][:] and its gradient:
+// g = 2 (y - z) / (B d); *acc += sum (y - z)^2 / (B d).  One workgroup, a
+// fixed summation order (deterministic).
+__global__ void __launch_bounds__(1024) mse_grad(const float* __restrict__ y, const float* __restrict__ z,
+                                                const long long* __restrict__ idx, int B, int d,
+                                                float* __restrict__ g, float* __restrict__ acc) {
+  __shared__ float red[1024];
+  const float inv = 1.f / ((float)B * (float)d);
+  float s = 0.f;
+#pragma unroll 4
+  for (int i = threadIdx.x; i < B * d; i += 1024) {
+    const int b = i / d, j = i - b * d;
+    const float e = y[i] - z[idx[b] * d + j];
+    g[i] = 2.f * e * inv;
+    s = fmaf(e, e, s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && acc) *acc += red[0] * inv;
+}
+
+hipError_t launch_gather_rows(const float* src, const long long* idx, int B, int d, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(gather_rows, dim3(B), dim3(256), 0, s, src, idx, d, dst);
+  return hipGetLastError();
+}
+hipError_t launch_mse_grad(const float* y, const float* z, const long long* idx, int B, int d, float* g,
+                           float* acc, hipStream_t s) {
+  hipLaunchKernelGGL(mse_grad, dim3(1), dim3(1024), 0, s, y, z, idx, B, d, g, acc);
+  return hipGetLastError();
+}
+
 // Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
 // p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
 __global__ void adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,

@@ -18,11 +18,13 @@ _lib.mlp_get.argtypes = [vp, C.c_int32, _fp, vp]
 _lib.mlp_forward.argtypes = [vp, _fp, C.c_int32, _fp, vp]
 _lib.mlp_backward.argtypes = [vp, _fp, vp]
 _lib.mlp_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32, vp]
+_lib.mlp_train_step.argtypes = [vp, _fp, _fp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float,
+                                C.c_int32, _fp, vp]
 _lib.mlp_destroy.argtypes = [vp]
 _lib.mlp_destroy.restype = None
 _lib.mlp_last_error.restype = C.c_char_p
 for _f in ("mlp_init", "mlp_n_params", "mlp_set_params", "mlp_get", "mlp_forward",
-           "mlp_backward", "mlp_adam_step"):
+           "mlp_backward", "mlp_adam_step", "mlp_train_step"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -87,6 +89,19 @@ class MLP:
     def adam_step(self, lr, b1=0.9, b2=0.999, eps=1e-8):
         self.t += 1
         _check(_lib.mlp_adam_step(self._ctx, lr, b1, b2, eps, self.t, _stream_handle(self._stream)))
+
+    def train_step(self, X, Z, idx, lr, loss_acc=None, b1=0.9, b2=0.999, eps=1e-8):
+        """``mlp_train_step``: MSE step on rows idx (int64 CUDA tensor) of
+        X and Z (float32 CUDA, contiguous); adds the loss to loss_acc (a
+        float32 CUDA scalar) if given."""
+        import torch
+        assert X.is_contiguous() and Z.is_contiguous() and idx.is_contiguous()
+        assert X.dtype == torch.float32 and Z.dtype == torch.float32 and idx.dtype == torch.int64
+        assert X.shape[1] == self.dims[0] and Z.shape[1] == self.dims[-1]
+        self.t += 1
+        acc = _ptr(loss_acc) if loss_acc is not None else None
+        _check(_lib.mlp_train_step(self._ctx, _ptr(X), _ptr(Z), C.c_void_p(idx.data_ptr()), idx.shape[0], lr,
+                                   b1, b2, eps, self.t, acc, _stream_handle(self._stream)))
 
     def close(self):
         if self._ctx:

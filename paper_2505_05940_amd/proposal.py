@@ -110,14 +110,10 @@ def train(net, X, Z, epochs=60, batch=1024, lr=1e-3, seed=0, log=None):
     last = None
     for ep in range(epochs):
         order = torch.tensor(rng.permutation(n), device=X.device)
-        tot = torch.zeros((), device=X.device)  # summed on the device: no sync per step
+        tot = torch.zeros((), device=X.device, dtype=torch.float32)  # summed on the device
+        lr_ep = lr * 0.5 * (1 + np.cos(np.pi * ep / epochs))
         for s in range(0, n - batch + 1, batch):
-            idx = order[s:s + batch]
-            y = net.forward(X[idx])
-            d = y - Z[idx]
-            tot += (d * d).mean()
-            net.backward(2.0 * d / d.numel())
-            net.adam_step(lr * 0.5 * (1 + np.cos(np.pi * ep / epochs)))
+            net.train_step(X, Z, order[s:s + batch], lr_ep, loss_acc=tot)
         if log or ep == epochs - 1:
             last = float(tot) / max(1, n // batch)
         if log:

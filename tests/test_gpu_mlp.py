@@ -12,35 +12,9 @@ from oracle import mlp as OM
 pytestmark = pytest.mark.gpu
 
 
-def _bf16(a):
-    a = np.asarray(a, np.float32)
-    u = a.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32)
-
-
-def _bf16_forward(theta, dims, x):
-    """The kernel's arithmetic in FP64: GEMM operands rounded to BF16,
-    products accumulated exactly, bias and ReLU in full precision."""
-    acts = [x]
-    layers = OM.unflatten(theta, dims)
-    for l, (W, b) in enumerate(layers):
-        z = _bf16(acts[-1]).astype(float) @ _bf16(W).astype(float).T + b
-        acts.append(np.maximum(z, 0.0) if l + 1 < len(layers) else z)
-    return acts
-
-
-def _bf16_backward(theta, dims, acts, dy):
-    layers = OM.unflatten(theta, dims)
-    g = dy
-    out = [None] * len(layers)
-    for l in range(len(layers) - 1, -1, -1):
-        W, _ = layers[l]
-        gb = _bf16(g).astype(float)
-        out[l] = np.concatenate([(gb.T @ _bf16(acts[l]).astype(float)).ravel(), g.sum(axis=0)])
-        if l > 0:
-            g = (gb @ _bf16(W).astype(float)) * (acts[l] > 0)
-    return np.concatenate(out)
+_bf16 = OM.bf16
+_bf16_forward = OM.forward_bf16_operands
+_bf16_backward = OM.backward_bf16_operands
 
 
 def test_matches_bf16_operand_reference_at_full_size():
@@ -106,3 +80,37 @@ def test_gemm_layout_on_identity():
     y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy()
     assert np.array_equal(y, x)
     net.close()
+
+
+def test_train_step_matches_separate_calls():
+    """mlp_train_step (rows gathered by index, forward, MSE gradient,
+    backward, Adam, loss accumulated on the device) against the same step
+    from mlp_forward / mlp_backward / mlp_adam_step with the batch gathered
+    and the MSE gradient formed by torch: parameters after two steps to 1e-6
+    relative (only the rounding of 2 (y - z) / (B d) differs), losses to
+    1e-6."""
+    import torch
+    from paper_2505_05940_amd.mlp import MLP
+    dims, n, B = [1024, 512, 512, 512, 512, 5], 3000, 1024
+    g = torch.Generator(device="cpu").manual_seed(7)
+    X = torch.randn(n, dims[0], generator=g).cuda()
+    Z = torch.randn(n, dims[-1], generator=g).cuda()
+    fused, split = MLP(dims, max_batch=B), MLP(dims, max_batch=B)
+    fused.init_params(seed=3)
+    split.init_params(seed=3)
+    acc = torch.zeros((), device="cuda")
+    losses = []
+    for step in range(2):
+        idx = torch.randperm(n, generator=g)[:B].cuda()
+        fused.train_step(X, Z, idx, 1e-3, loss_acc=acc)
+        y = split.forward(X[idx])
+        d = y - Z[idx]
+        losses.append(float((d.double() ** 2).mean()))
+        split.backward(2.0 * d / d.numel())
+        split.adam_step(1e-3)
+    torch.cuda.synchronize()
+    pf, ps = fused.params(), split.params()
+    assert np.linalg.norm(pf - ps) / np.linalg.norm(ps) < 1e-6
+    assert abs(float(acc) - sum(losses)) < 1e-6 * sum(losses)
+    fused.close()
+    split.close()
