@@ -63,6 +63,18 @@ int mlp_adam_step(mlp_ctx *c, float lr, float beta1, float beta2, float eps, int
 int mlp_train_step(mlp_ctx *c, const float *X, const float *Z, const int64_t *idx, int32_t B, float lr,
                    float beta1, float beta2, float eps, int32_t t, float *loss_acc, void *stream);
 
+/* n_steps training steps as mlp_train_step, step st on the rows
+ * order[st B .. st B + B) (int64, device, in range; not checked), with the
+ * learning rate lr and Adam step numbers continuing the context's own count
+ * (0 after mlp_init or mlp_set_params; the first step of the first epoch is
+ * step 1).  The first call with a given (X, Z, order, n_steps, B, beta1,
+ * beta2, eps, loss_acc) records the epoch as a HIP graph; later calls with
+ * the same pointers replay it, reading lr and the step count from device
+ * memory, so the caller refills order in place between epochs.  No host
+ * synchronisation.  Errors: EINVAL, EHIP. */
+int mlp_train_epoch(mlp_ctx *c, const float *X, const float *Z, const int64_t *order, int32_t n_steps,
+                    int32_t B, float lr, float beta1, float beta2, float eps, float *loss_acc, void *stream);
+
 void mlp_destroy(mlp_ctx *c);
 const char *mlp_last_error(void);
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -14,6 +15,8 @@ namespace modal {
 hipError_t launch_gemm(const float* A, long long lda, int a_kc, const float* B, long long ldb, int b_kc, float* C,
                        long long ldc, int M, int N, int K, int epi, const float* bias, const float* mask,
                        float* part, hipStream_t s);
+hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, long long n, const float* sched, int k,
+                           float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_gather_rows(const float* src, const long long* idx, int B, int d, float* dst, hipStream_t s);
 hipError_t launch_mse_grad(const float* y, const float* z, const long long* idx, int B, int d, float* g,
                            float* acc, hipStream_t s);
@@ -49,6 +52,24 @@ struct mlp_ctx {
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *act = nullptr, *d0 = nullptr,
         *d1 = nullptr, *part = nullptr,  // part: column-sum partials
         *kpart = nullptr;                 // split-K partial tiles
+  // mlp_train_epoch: Adam's step count so far and the recorded epochs, each
+  // with the device table its Adam steps read (learning rate, then the bias
+  // corrections 1 - beta1^t, 1 - beta2^t of each step) and the host copy it
+  // was last filled from
+  int t = 0;
+  hipStream_t cap = nullptr;
+  struct Epoch {
+    const float *X, *Z;
+    const int64_t* order;
+    int n_steps, B;
+    float b1, b2, eps;
+    float* loss;
+    hipGraphExec_t exec;
+    float* sched;
+    std::vector<float> host;
+    hipEvent_t copied;  // the last copy from `host` has been made
+  };
+  std::vector<Epoch> epochs;
 };
 
 extern "C" {
@@ -59,6 +80,12 @@ void mlp_destroy(mlp_ctx* c) {
   if (!c) return;
   for (float* q : {c->p, c->g, c->m, c->v, c->act, c->d0, c->d1, c->part, c->kpart})
     if (q) (void)hipFree(q);
+  for (auto& e : c->epochs) {
+    (void)hipGraphExecDestroy(e.exec);
+    (void)hipFree(e.sched);
+    if (e.copied) (void)hipEventDestroy(e.copied);
+  }
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
 }
 
@@ -121,6 +148,7 @@ int mlp_set_params(mlp_ctx* c, const float* host, void* stream) {
   MHIP(hipMemsetAsync(c->m, 0, sizeof(float) * (size_t)c->n_params, s));
   MHIP(hipMemsetAsync(c->v, 0, sizeof(float) * (size_t)c->n_params, s));
   MHIP(hipStreamSynchronize(s));
+  c->t = 0;
   return MODAL_OK;
 }
 
@@ -210,6 +238,78 @@ int mlp_train_step(mlp_ctx* c, const float* X, const float* Z, const int64_t* id
   r = backward_layers(c, s);
   if (r) return r;
   MHIP(launch_adam(c->p, c->g, c->m, c->v, c->n_params, lr, beta1, beta2, eps, t, s));
+  return MODAL_OK;
+}
+
+int mlp_train_epoch(mlp_ctx* c, const float* X, const float* Z, const int64_t* order, int32_t n_steps,
+                    int32_t B, float lr, float beta1, float beta2, float eps, float* loss_acc, void* stream) {
+  if (!c || !X || !Z || !order || n_steps < 1 || B < 1 || B > c->max_batch)
+    return mfail(MODAL_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  mlp_ctx::Epoch* ep = nullptr;
+  for (auto& e : c->epochs)
+    if (e.X == X && e.Z == Z && e.order == order && e.n_steps == n_steps && e.B == B && e.b1 == beta1 &&
+        e.b2 == beta2 && e.eps == eps && e.loss == loss_acc)
+      ep = &e;
+  if (!ep) {
+    float* sched = nullptr;
+    MHIP(hipMalloc((void**)&sched, sizeof(float) * (1 + 2 * (size_t)n_steps)));
+    hipGraphExec_t exec = nullptr;
+    // record the epoch once on a private stream (the caller's may be the
+    // legacy default stream, which cannot be captured)
+    if (!c->cap) MHIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipGraph_t graph;
+    MHIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    int r = MODAL_OK;
+    for (int st = 0; st < n_steps && !r; ++st) {
+      const long long* ix = reinterpret_cast<const long long*>(order) + (long long)st * B;
+      hipError_t e = launch_gather_rows(X, ix, B, c->dims[0], c->act, c->cap);
+      if (e == hipSuccess) r = forward_layers(c, B, c->cap);
+      if (e == hipSuccess && !r)
+        e = launch_mse_grad(c->act + c->act_off[c->L], Z, ix, B, c->dims[c->L], c->d0, loss_acc, c->cap);
+      if (e == hipSuccess && !r) r = backward_layers(c, c->cap);
+      if (e == hipSuccess && !r)
+        e = launch_adam_dev(c->p, c->g, c->m, c->v, c->n_params, sched, st, beta1, beta2, eps, c->cap);
+      if (e != hipSuccess) r = mfail(MODAL_EHIP, std::string("recording an epoch: ") + hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (!r && e != hipSuccess) r = mfail(MODAL_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    if (!r) {
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) r = mfail(MODAL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    if (r) {
+      (void)hipFree(sched);
+      return r;
+    }
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipGraphExecDestroy(exec);
+      (void)hipFree(sched);
+      return mfail(MODAL_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
+    c->epochs.push_back({X, Z, order, n_steps, B, beta1, beta2, eps, loss_acc, exec, sched, {}, ev});
+    ep = &c->epochs.back();
+  } else {
+    MHIP(hipEventSynchronize(ep->copied));  // before its host table is rewritten
+  }
+  // this epoch's schedule, the corrections formed on the host as
+  // mlp_adam_step forms them
+  std::vector<float>& h = ep->host;
+  h.assign(1 + 2 * (size_t)n_steps, 0.f);
+  h[0] = lr;
+  for (int k = 0; k < n_steps; ++k) {
+    const float t = (float)(c->t + k + 1);
+    h[1 + 2 * k] = 1.f - powf(beta1, t);
+    h[2 + 2 * k] = 1.f - powf(beta2, t);
+  }
+  MHIP(hipMemcpyAsync(ep->sched, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, s));
+  MHIP(hipEventRecord(ep->copied, s));
+  MHIP(hipGraphLaunch(ep->exec, s));
+  c->t += n_steps;
+  c->last_batch = B;
   return MODAL_OK;
 }
 

@@ -307,6 +307,31 @@ hipError_t launch_colsum(const float* G, int M, int N, float* part, float* db, h
   return hipGetLastError();
 }
 
+// Adam with the learning rate and the bias corrections read from device
+// memory: lr = sched[0], c1 = sched[2 k + 1], c2 = sched[2 k + 2] for the
+// k-th step of a recorded epoch, so that the recorded graph can be replayed
+// with a new schedule (the host writes the table before each replay).
+__global__ void adam_dev(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                         float* __restrict__ v, long long n, const float* __restrict__ sched, int k, float b1,
+                         float b2, float eps) {
+  const float lr = sched[0], c1 = sched[2 * k + 1], c2 = sched[2 * k + 2];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, long long n, const float* sched, int k,
+                           float b1, float b2, float eps, hipStream_t s) {
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(adam_dev, dim3(blocks), dim3(256), 0, s, p, g, m, v, n, sched, k, b1, b2, eps);
+  return hipGetLastError();
+}
+
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
                        float b2, float eps, int t, hipStream_t s) {
   const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);

@@ -20,11 +20,13 @@ _lib.mlp_backward.argtypes = [vp, _fp, vp]
 _lib.mlp_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32, vp]
 _lib.mlp_train_step.argtypes = [vp, _fp, _fp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float,
                                 C.c_int32, _fp, vp]
+_lib.mlp_train_epoch.argtypes = [vp, _fp, _fp, vp, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                 C.c_float, _fp, vp]
 _lib.mlp_destroy.argtypes = [vp]
 _lib.mlp_destroy.restype = None
 _lib.mlp_last_error.restype = C.c_char_p
 for _f in ("mlp_init", "mlp_n_params", "mlp_set_params", "mlp_get", "mlp_forward",
-           "mlp_backward", "mlp_adam_step", "mlp_train_step"):
+           "mlp_backward", "mlp_adam_step", "mlp_train_step", "mlp_train_epoch"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -102,6 +104,20 @@ class MLP:
         acc = _ptr(loss_acc) if loss_acc is not None else None
         _check(_lib.mlp_train_step(self._ctx, _ptr(X), _ptr(Z), C.c_void_p(idx.data_ptr()), idx.shape[0], lr,
                                    b1, b2, eps, self.t, acc, _stream_handle(self._stream)))
+
+    def train_epoch(self, X, Z, order, batch, lr, loss_acc=None, b1=0.9, b2=0.999, eps=1e-8):
+        """``mlp_train_epoch``: len(order) // batch MSE steps on consecutive
+        slices of order (int64 CUDA tensor, refilled in place between
+        epochs so that the recorded epoch is replayed)."""
+        import torch
+        assert X.is_contiguous() and Z.is_contiguous() and order.is_contiguous()
+        assert X.dtype == torch.float32 and Z.dtype == torch.float32 and order.dtype == torch.int64
+        assert X.shape[1] == self.dims[0] and Z.shape[1] == self.dims[-1]
+        steps = order.shape[0] // batch
+        acc = _ptr(loss_acc) if loss_acc is not None else None
+        _check(_lib.mlp_train_epoch(self._ctx, _ptr(X), _ptr(Z), C.c_void_p(order.data_ptr()), steps, batch, lr,
+                                    b1, b2, eps, acc, _stream_handle(self._stream)))
+        self.t += steps
 
     def close(self):
         if self._ctx:

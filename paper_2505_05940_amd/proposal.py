@@ -108,12 +108,15 @@ def train(net, X, Z, epochs=60, batch=1024, lr=1e-3, seed=0, log=None):
     rng = np.random.default_rng(seed)
     n = X.shape[0]
     last = None
+    # one device buffer each for the shuffled order and the loss sum, refilled
+    # every epoch, so that the epoch recorded by the first call is replayed
+    order = torch.empty(n, dtype=torch.int64, device=X.device)
+    tot = torch.zeros((), device=X.device, dtype=torch.float32)
     for ep in range(epochs):
-        order = torch.tensor(rng.permutation(n), device=X.device)
-        tot = torch.zeros((), device=X.device, dtype=torch.float32)  # summed on the device
+        order.copy_(torch.from_numpy(rng.permutation(n)))
+        tot.zero_()
         lr_ep = lr * 0.5 * (1 + np.cos(np.pi * ep / epochs))
-        for s in range(0, n - batch + 1, batch):
-            net.train_step(X, Z, order[s:s + batch], lr_ep, loss_acc=tot)
+        net.train_epoch(X, Z, order[:(n // batch) * batch], batch, lr_ep, loss_acc=tot)
         if log or ep == epochs - 1:
             last = float(tot) / max(1, n // batch)
         if log:

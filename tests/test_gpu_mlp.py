@@ -114,3 +114,43 @@ def test_train_step_matches_separate_calls():
     assert abs(float(acc) - sum(losses)) < 1e-6 * sum(losses)
     fused.close()
     split.close()
+
+
+def test_recorded_epochs_match_single_steps():
+    """mlp_train_epoch (the epoch recorded as a HIP graph on its first call,
+    replayed with a refilled order buffer and a new learning rate on the
+    next) against the same steps from mlp_train_step: parameters after each
+    of two epochs and each epoch's loss sum to 1e-6 relative (both form
+    Adam's bias corrections on the host; a wrong learning rate or step
+    number moves the parameters by 1e-3 relative and more).  The order
+    buffer is refilled in place, so the second epoch replays the first
+    one's graph."""
+    import torch
+    from paper_2505_05940_amd.mlp import MLP
+    dims, B, steps = [1024, 512, 512, 512, 512, 5], 1024, 3
+    n = B * steps
+    g = torch.Generator(device="cpu").manual_seed(11)
+    X = torch.randn(n + 100, dims[0], generator=g).cuda()
+    Z = torch.randn(n + 100, dims[-1], generator=g).cuda()
+    ep, st = MLP(dims, max_batch=B), MLP(dims, max_batch=B)
+    ep.init_params(seed=4)
+    st.init_params(seed=4)
+    order = torch.empty(n, dtype=torch.int64, device="cuda")
+    acc_e = torch.zeros((), device="cuda")
+    for e, lr in enumerate((1e-3, 5e-4)):
+        perm = torch.randperm(n + 100, generator=g)[:n]
+        order.copy_(perm)
+        acc_e.zero_()
+        ep.train_epoch(X, Z, order, B, lr, loss_acc=acc_e)
+        acc_s = torch.zeros((), device="cuda")
+        o = perm.cuda()
+        for s in range(steps):
+            st.train_step(X, Z, o[s * B:(s + 1) * B].contiguous(), lr, loss_acc=acc_s)
+        torch.cuda.synchronize()
+        pe, ps = ep.params(), st.params()
+        dp = np.linalg.norm(pe - ps) / np.linalg.norm(ps)
+        dl = abs(float(acc_e) - float(acc_s)) / abs(float(acc_s))
+        print(f"epoch {e}: params {dp:.2e}, loss {dl:.2e}", flush=True)
+        assert dp < 1e-6 and dl < 1e-6, (e, dp, dl)
+    ep.close()
+    st.close()
