@@ -228,15 +228,18 @@ def tensor_fit_rate(iters=4, starts=16):
 def single_instance_rates():
     """One instance at a time, as in the paper's benchmark (Sec. 4.2, Fig. 2):
     wall time of one modal_run over 1 s of audio at 44.1 kHz (the KC string:
-    0.5 s) after a 441-step warm-up, HIP events on the launch stream, and the
-    real-time factor (audio seconds per wall second); then the gradient of a
+    0.5 s) after a 441-step warm-up, HIP events on the launch stream, the
+    real-time factor (audio seconds per wall second) and the plan the library
+    chose (on-chip: one workgroup, tensor in registers; streaming: row slabs
+    on several workgroups); then the gradient of a
     200/200-mode plate over 1 s (forward with checkpoints, recompute and
     reverse sweep)."""
     import torch
     import workloads as W
     from paper_2505_05940_amd import modal, physics
-    cases = [("KC string, 30 modes", physics.string_instance(W.string_kc(n_modes=30)), 22050)]
-    for n in (10, 50, 100):
+    cases = [("KC string, 30 modes", physics.string_instance(W.string_kc(n_modes=30)), 22050),
+             ("vK plate, 40/40 modes, clamped family", physics.plate_instance(W.plate_vk()), 44100)]
+    for n in (10, 50, 60, 100):
         cases.append((f"vK plate, {n}/{n} modes", physics.plate_instance(W.plate_sweep(n)), 44100))
     for n in (10, 50, 100):
         cases.append((f"Berger plate, {n} modes", physics.plate_berger_instance(W.plate_berger(n_t=n)), 44100))
@@ -254,7 +257,9 @@ def single_instance_rates():
         torch.cuda.synchronize()
         t = a.elapsed_time(b) * 1e-3
         out.append({"case": name, "audio_s": steps / 44100.0, "wall_s": t,
-                    "realtime_factor": steps / 44100.0 / t, "us_per_step": 1e6 * t / steps})
+                    "realtime_factor": steps / 44100.0 / t, "us_per_step": 1e6 * t / steps,
+                    "plan": {0: "streaming", 3: "on-chip"}.get(sim.info()["path"], "other"),
+                    "workgroups": sim.info()["workgroups"]})
         sim.close()
     p200 = physics.plate_instance(W.plate_vk(n_t=200, family="sine", grid=None))
     sim = modal.Sim([p200], 44100.0, flags=modal.FLAG_GRAD)

@@ -2395,15 +2395,34 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   // recorded them)
   int r = modal_reset(c, stream_);
   if (r) return r;
+  // the forward pass also records the whole trajectory while it fits, so
+  // that the reverse sweep needs no segment recomputes
+  bool rec_now = false;
   if (!reuse) {
     StepParams P = c->P;
     P.y = nullptr;
     P.ckpt = c->dCkpt;
     P.ckpt_every = K;
     P.n_steps = (int)n_steps;
+    if ((double)n_steps * 2.0 * mf * sizeof(float) <= kRecAllBytes) {
+      if (c->recall_cap < n_steps) {
+        if (c->dRecAll) HIP_TRY(hipFree(c->dRecAll));
+        c->dRecAll = nullptr;
+        c->recall_cap = 0;
+        c->rec_upto = 0;
+        int r2 = dalloc(&c->dRecAll, sizeof(float) * 2 * (size_t)n_steps * mf);
+        if (r2) return r2;
+        c->recall_cap = n_steps;
+      }
+      P.rec_x = c->dRecAll;
+      P.rec_d = c->dRecAll + (size_t)c->recall_cap * mf;
+      P.rec_base = 0;
+      rec_now = true;
+    }
     HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
-    // slots now hold this spacing's checkpoints
+    // slots now hold this spacing's checkpoints, and the record this run
     c->ckpt_upto = K == kRunCkpt ? std::max<long long>(c->ckpt_upto, n_steps) : 0;
+    c->rec_upto = rec_now ? n_steps : 0;
   }
   HIP_TRY(hipMemsetAsync(c->dAdj, 0, sizeof(float) * 4 * (size_t)sf, s));
   HIP_TRY(hipMemsetAsync(c->dAcc, 0, sizeof(float) * 12 * (size_t)sf, s));
@@ -2422,7 +2441,7 @@ int modal_grad(modal_ctx* c, int64_t n_steps, const float* ybar, int64_t y_strid
   G.c_out = F.c_out; G.lam = F.lam; G.b_ext = F.b_ext; G.e_ext = F.e_ext;
   // the whole trajectory recorded by the last runs, if it covers the steps,
   // replaces the segment recomputes
-  const bool reuse_rec = reuse && c->dRecAll && c->rec_upto >= n_steps;
+  const bool reuse_rec = rec_now || (reuse && c->dRecAll && c->rec_upto >= n_steps);
   G.mode_floats = mf;
   G.ybar = ybar;
   G.ybar_stride = y_stride;

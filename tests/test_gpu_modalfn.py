@@ -150,10 +150,13 @@ def test_config4_mrstft_gradient_against_oracle_and_differences(torch_gpu):
 
 @pytest.mark.timeout(600)
 def test_fit_bending_stiffness_only(torch_gpu):
-    """fit.fit with only D^ free, from 1.05 times the target on a 16/16
+    """fit.fit with only D^ free, from 1.02 times the target on a 16/16
     plate over 0.25 s, MR-STFT loss: recovers the target's D^ to 1e-4.  (The
-    start lies in the loss's monotone basin around the target, about
-    [0.95, 1.085] times it; further out the spectral loss has local minima.)"""
+    start lies in the loss's monotone basin around the target: scanned in
+    steps of 0.002, the loss rises monotonically from the target to 1.032
+    and falls monotonically to it from 0.974; at 1.044-1.050 it has a
+    shallow local minimum in which Adam settles or not depending on FP32
+    rounding, and further out more of them.)"""
     torch = torch_gpu
     from paper_2505_05940_amd import fit, modal
     fw = W.plate_fit(n_t=16)
@@ -164,8 +167,8 @@ def test_fit_bending_stiffness_only(torch_gpu):
     target = sim.run(steps).clone()
     sim.close()
     th0 = tgt.copy()
-    th0[1] *= 1.05
-    _say("case: fit.fit, D^ only, 16/16 plate, 11025 steps, start 1.05 x target")
+    th0[1] *= 1.02
+    _say("case: fit.fit, D^ only, 16/16 plate, 11025 steps, start 1.02 x target")
     best, L, its, hist = fit.fit(target, th0, st, steps, iters=400, lr=0.01, tol=0.0, free=[1])
     rel = abs(best[0][1] / tgt[1] - 1.0)
     _say(f"  best D^ {best[0][1]:.8g} target {tgt[1]:.8g} rel {rel:.1e} loss {L[0]:.2e} after {its} iterations")
