@@ -261,6 +261,16 @@ def single_instance_rates():
                     "plan": {0: "streaming", 3: "on-chip"}.get(sim.info()["path"], "other"),
                     "workgroups": sim.info()["workgroups"]})
         sim.close()
+    return {"runs": out, "gradient_200_modes_1s_wall_s": gradient_200_wall()}
+
+
+def gradient_200_wall():
+    """Wall time of the gradient of a 200/200-mode sine plate over 1 s
+    (forward with checkpoints and the trajectory record, reverse sweep), a
+    constant dL/dy, after a 441-step warm-up gradient."""
+    import torch
+    import workloads as W
+    from paper_2505_05940_amd import modal, physics
     p200 = physics.plate_instance(W.plate_vk(n_t=200, family="sine", grid=None))
     sim = modal.Sim([p200], 44100.0, flags=modal.FLAG_GRAD)
     g = torch.full((1, 44100), 1e3, device="cuda")
@@ -271,7 +281,32 @@ def single_instance_rates():
     torch.cuda.synchronize()
     grad_s = time.perf_counter() - t0
     sim.close()
-    return {"runs": out, "gradient_200_modes_1s_wall_s": grad_s}
+    return grad_s
+
+
+def mlp_training_rate(epochs, n=200000, batch=1024):
+    """The proposal network's training on synthetic features and targets of
+    the experiment's shapes (n rows of 1024 features, 5 targets): one
+    untimed epoch, then `epochs` timed ones; seconds per step and the
+    projection to 60 epochs of n rows."""
+    import torch
+    from paper_2505_05940_amd import proposal
+    from paper_2505_05940_amd.mlp import MLP
+    g = torch.Generator(device="cpu").manual_seed(1)
+    X = torch.randn(n, proposal.DIMS[0], generator=g).cuda()
+    Z = torch.randn(n, proposal.DIMS[-1], generator=g).cuda()
+    net = MLP(proposal.DIMS, max_batch=batch)
+    net.init_params(seed=1)
+    proposal.train(net, X, Z, epochs=1, batch=batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    proposal.train(net, X, Z, epochs=epochs, batch=batch)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    steps = epochs * (n // batch)
+    net.close()
+    return {"epochs": epochs, "rows": n, "batch": batch, "ms_per_step": 1e3 * dt / steps,
+            "projected_60_epochs_s": dt / steps * 60 * (n // batch)}
 
 
 def fit_wall_time():
@@ -368,10 +403,22 @@ def main():
                     help="steps of every batch plate in the CPU oracle baseline")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
+    ap.add_argument("--only", choices=("gradient", "mlp"),
+                    help="run only the 200/200 gradient timing or the proposal network's training "
+                         "timing, print it as one JSON line and exit (for profiling)")
+    ap.add_argument("--mlp-epochs", type=int, default=8, help="timed epochs of --only mlp")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the measured-traffic record from two rocprofv3 --pmc "
                          "counter_collection.csv files of this command, then exit")
     args = ap.parse_args()
+    if args.only:  # one measurement alone (for profiling), printed as its own JSON line
+        import torch
+        torch.cuda.set_device(0)
+        if args.only == "gradient":
+            print(json.dumps({"gradient_200_modes_1s_wall_s": gradient_200_wall()}))
+        else:
+            print(json.dumps({"mlp_training": mlp_training_rate(args.mlp_epochs)}))
+        return
     if args.traffic_from:
         write_traffic(*args.traffic_from, args.calibrate_copy_mib, args.samples_per_step,
                       {"max_workgroups": args.max_workgroups, "waves": args.waves})

@@ -21,8 +21,7 @@ hipError_t launch_gather_rows(const float* src, const long long* idx, int B, int
 hipError_t launch_mse_grad(const float* y, const float* z, const long long* idx, int B, int d, float* g,
                            float* acc, hipStream_t s);
 constexpr int kMaxSplit = 8;
-hipError_t launch_colsum(const float* G, int M, int N, float* part, float* db, hipStream_t s);
-constexpr int kColSlices = 16;
+hipError_t launch_colsum(const float* G, int M, int N, float* db, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n, float lr, float b1,
                        float b2, float eps, int t, hipStream_t s);
 }  // namespace modal
@@ -50,8 +49,7 @@ struct mlp_ctx {
   std::vector<long long> w_off, b_off, act_off;
   long long n_params = 0, act_floats = 0;
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *act = nullptr, *d0 = nullptr,
-        *d1 = nullptr, *part = nullptr,  // part: column-sum partials
-        *kpart = nullptr;                 // split-K partial tiles
+        *d1 = nullptr, *kpart = nullptr;  // kpart: split-K partial tiles
   // mlp_train_epoch: Adam's step count so far and the recorded epochs, each
   // with the device table its Adam steps read (learning rate, then the bias
   // corrections 1 - beta1^t, 1 - beta2^t of each step) and the host copy it
@@ -78,7 +76,7 @@ const char* mlp_last_error(void) { return g_mlp_err.c_str(); }
 
 void mlp_destroy(mlp_ctx* c) {
   if (!c) return;
-  for (float* q : {c->p, c->g, c->m, c->v, c->act, c->d0, c->d1, c->part, c->kpart})
+  for (float* q : {c->p, c->g, c->m, c->v, c->act, c->d0, c->d1, c->kpart})
     if (q) (void)hipFree(q);
   for (auto& e : c->epochs) {
     (void)hipGraphExecDestroy(e.exec);
@@ -125,7 +123,6 @@ int mlp_init(mlp_ctx** out, int32_t n_layers, const int32_t* dims, int32_t max_b
   if (hipMalloc((void**)&c->act, sizeof(float) * (size_t)c->act_floats) != hipSuccess ||
       hipMalloc((void**)&c->d0, sizeof(float) * (size_t)max_batch * c->max_d) != hipSuccess ||
       hipMalloc((void**)&c->d1, sizeof(float) * (size_t)max_batch * c->max_d) != hipSuccess ||
-      hipMalloc((void**)&c->part, sizeof(float) * (size_t)kColSlices * c->max_d) != hipSuccess ||
       hipMalloc((void**)&c->kpart, sizeof(float) * (size_t)kMaxSplit * std::max(max_batch, c->max_d) *
                                        c->max_d) != hipSuccess) {
     mlp_destroy(c);
@@ -191,7 +188,7 @@ int backward_layers(mlp_ctx* c, hipStream_t s) {
     // B(b, i) = a[b in + i] (i contiguous)
     MHIP(launch_gemm(gcur, out, 0, a, in, 0, c->g + c->w_off[l], in, out, in, B, EPI_STORE, nullptr,
                      nullptr, c->kpart, s));
-    MHIP(launch_colsum(gcur, B, out, c->part, c->g + c->b_off[l], s));
+    MHIP(launch_colsum(gcur, B, out, c->g + c->b_off[l], s));
     if (l > 0) {
       // g_prev[b, i] = (sum_o g[b, o] W[o, i]) * [a[b, i] > 0]: A(b, o) =
       // g[b out + o] (o contiguous), B(o, i) = W[o in + i] (i contiguous)

@@ -20,6 +20,8 @@
 
 #include <algorithm>
 
+#include "device_common.h"
+
 namespace modal {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -52,34 +54,50 @@ __device__ __forceinline__ float4 ld_group(const float* __restrict__ X, long lon
   return make_float4(v[0], v[1], v[2], v[3]);
 }
 
+// 16-byte load through a buffer resource (cached); an offset past the
+// resource's size reads zeros without touching memory.
+__device__ __forceinline__ float4 ld4_rsrc(v4i r, int voff) {
+  const v4f v = llvm_raw_buffer_load_v4f32(r, voff, 0, 0);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+constexpr int kOutside = 0x7ffffff0;  // a byte offset past every operand resource
+
 // Stages one operand tile of R rows (m or n) by TK k into registers: R * TK
-// / 4 float4 groups over the 128 threads.  kc: the operand's k index is
+// / 4 float4 groups over the 128 threads.  KC: the operand's k index is
 // contiguous in memory (groups run along k), else its m / n index is.
-template <int R>
+// VEC: the contiguous extent and the row stride are multiples of 4 and the
+// base 16-byte aligned, so every group is whole and is one 16-byte buffer
+// load, with no branch (groups outside the matrix read zeros); otherwise
+// element by element.
+template <int R, bool KC, bool VEC>
 struct Stage {
   static constexpr int G = R * TK / 4 / kGemmThreads;  // groups per thread
   float4 v[G];
-  __device__ __forceinline__ void load(const float* __restrict__ X, long long ld, bool kc, int r0, int k0,
-                                       int rows, int K, bool vec, int tid) {
+  __device__ __forceinline__ void load(const float* __restrict__ X, v4i rs, long long ld, int r0, int k0,
+                                       int rows, int K, int tid) {
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const int q = tid + kGemmThreads * j;
-      if (kc) {  // group q: row q / (TK/4), k = 4 (q % (TK/4))
-        const int r = q / (TK / 4), k = 4 * (q % (TK / 4));
-        v[j] = ld_group(X, ld, r0 + r, k0 + k, rows, K, vec);
-      } else {  // group q: k row q / (R/4), rows 4 (q % (R/4)) .. +3
-        const int k = q / (R / 4), r = 4 * (q % (R / 4));
-        v[j] = ld_group(X, ld, k0 + k, r0 + r, K, rows, vec);
+      // group q: along k, row q / (TK/4) and k = 4 (q % (TK/4)); along the
+      // rows, k row q / (R/4) and rows 4 (q % (R/4)) .. +3
+      const int a = KC ? r0 + q / (TK / 4) : k0 + q / (R / 4);      // memory row
+      const int c = KC ? k0 + 4 * (q % (TK / 4)) : r0 + 4 * (q % (R / 4));  // first column
+      const int na = KC ? rows : K, nc = KC ? K : rows;
+      if (VEC) {
+        const bool in = a < na && c < nc;
+        v[j] = ld4_rsrc(rs, in ? (int)(((long long)a * ld + c) * 4) : kOutside);
+      } else {
+        v[j] = ld_group(X, ld, a, c, na, nc, false);
       }
     }
   }
-  __device__ __forceinline__ void store(unsigned short (*T)[TKP], bool kc, int tid) const {
+  __device__ __forceinline__ void store(unsigned short (*T)[TKP], int tid) const {
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       const int q = tid + kGemmThreads * j;
       const unsigned short b0 = to_bf16(v[j].x), b1 = to_bf16(v[j].y), b2 = to_bf16(v[j].z),
                            b3 = to_bf16(v[j].w);
-      if (kc) {
+      if (KC) {
         const int r = q / (TK / 4), k = 4 * (q % (TK / 4));
         uint2 w;
         w.x = (unsigned int)b0 | ((unsigned int)b1 << 16);
@@ -99,8 +117,9 @@ struct Stage {
 // blockIdx.z selects a slice [k0, k0 + kc) of K (split K); with several
 // slices (gridDim.z > 1) each writes its raw partial tile to
 // part[z][M][N] and gemm_reduce adds the slices and applies the epilogue.
-__global__ void __launch_bounds__(kGemmThreads) gemm_bf16(const float* __restrict__ A, long long lda, int a_kc,
-                                                          const float* __restrict__ B, long long ldb, int b_kc,
+template <bool AKC, bool BKC, bool VEC>
+__global__ void __launch_bounds__(kGemmThreads) gemm_bf16(const float* __restrict__ A, long long lda,
+                                                          const float* __restrict__ B, long long ldb,
                                                           float* __restrict__ C, long long ldc, int M, int N,
                                                           int K, int kc, int epi, const float* __restrict__ bias,
                                                           const float* __restrict__ mask, float* __restrict__ part) {
@@ -110,11 +129,11 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_bf16(const float* __restric
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  // 16-byte loads need rows that start on 16-byte boundaries
-  const bool va = (lda & 3) == 0 && ((reinterpret_cast<unsigned long long>(A) & 15) == 0);
-  const bool vb = (ldb & 3) == 0 && ((reinterpret_cast<unsigned long long>(B) & 15) == 0);
-  Stage<TM> sa;
-  Stage<TN> sb;
+  // operand resources sized to the matrices (the host keeps them below 2 GB)
+  const v4i ra = buf_rsrc(A, VEC ? (int)(4 * (AKC ? (long long)M : (long long)K) * lda) : 0);
+  const v4i rb = buf_rsrc(B, VEC ? (int)(4 * (BKC ? (long long)N : (long long)K) * ldb) : 0);
+  Stage<TM, AKC, VEC> sa;
+  Stage<TN, BKC, VEC> sb;
   v16f acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
@@ -123,16 +142,16 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_bf16(const float* __restric
   const int kend = min(K, kb0 + kc);
   const int nk = (kend - kb0 + TK - 1) / TK;
   // operands are read as if K ended at kend (zeros past it)
-  sa.load(A, lda, a_kc, m0, kb0, M, kend, va, tid);
-  sb.load(B, ldb, b_kc, n0, kb0, N, kend, vb, tid);
-  sa.store(As[0], a_kc, tid);
-  sb.store(Bs[0], b_kc, tid);
+  sa.load(A, ra, lda, m0, kb0, M, kend, tid);
+  sb.load(B, rb, ldb, n0, kb0, N, kend, tid);
+  sa.store(As[0], tid);
+  sb.store(Bs[0], tid);
   __syncthreads();
   for (int t = 0; t < nk; ++t) {
     const int cur = t & 1;
     if (t + 1 < nk) {  // next tile's loads in flight during this tile's MFMAs
-      sa.load(A, lda, a_kc, m0, kb0 + (t + 1) * TK, M, kend, va, tid);
-      sb.load(B, ldb, b_kc, n0, kb0 + (t + 1) * TK, N, kend, vb, tid);
+      sa.load(A, ra, lda, m0, kb0 + (t + 1) * TK, M, kend, tid);
+      sb.load(B, rb, ldb, n0, kb0 + (t + 1) * TK, N, kend, tid);
     }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 16) {
@@ -142,8 +161,8 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_bf16(const float* __restric
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     if (t + 1 < nk) {
-      sa.store(As[cur ^ 1], a_kc, tid);
-      sb.store(Bs[cur ^ 1], b_kc, tid);
+      sa.store(As[cur ^ 1], tid);
+      sb.store(Bs[cur ^ 1], tid);
     }
     __syncthreads();
   }
@@ -185,30 +204,27 @@ __global__ void gemm_reduce(const float* __restrict__ part, int S, float* __rest
   C[row * ldc + col] = v;
 }
 
-// db[n] = sum_m G[m, n]  (G row-major [M, N]) in two deterministic stages:
-// partial sums over kColSlices row slices (64 columns x 4 row phases per
-// workgroup, phases added through LDS), then the slices added in order.
-constexpr int kColSlices = 16;
-__global__ void __launch_bounds__(256) colsum_part(const float* __restrict__ G, int M, int N,
-                                                  float* __restrict__ part) {
-  __shared__ float red[4][64];
+// db[n] = sum_m G[m, n]  (G row-major [M, N]) in one pass: a workgroup of
+// 1024 threads owns 64 columns, its 16 row phases each sum every 16th row
+// (loads unrolled so that several are in flight), and the phases are added
+// through LDS in a fixed order (deterministic).
+__global__ void __launch_bounds__(1024) colsum(const float* __restrict__ G, int M, int N, float* __restrict__ db) {
+  __shared__ float red[16][64];
   const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + c;
-  const int rows = (M + kColSlices - 1) / kColSlices;
-  const int r0 = blockIdx.y * rows, r1 = min(M, r0 + rows);
   float s = 0.f;
-  if (n < N)
-    for (int m = r0 + ph; m < r1; m += 4) s += G[(long long)m * N + n];
+  if (n < N) {
+#pragma unroll 8
+    for (int m = ph; m < M; m += 16) s += G[(long long)m * N + n];
+  }
   red[ph][c] = s;
   __syncthreads();
-  if (ph == 0 && n < N) part[(long long)blockIdx.y * N + n] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
-}
-__global__ void colsum_final(const float* __restrict__ part, int N, float* __restrict__ db) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int t = 0; t < kColSlices; ++t) s += part[(long long)t * N + n];
-  db[n] = s;
+  if (ph == 0 && n < N) {
+    float t = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t += red[i][c];
+    db[n] = t;
+  }
 }
 
 // dst[b][:] = src[idx[b]][:] (rows of d floats)
@@ -290,8 +306,25 @@ hipError_t launch_gemm(const float* A, long long lda, int a_kc, const float* B, 
   const int kc = ((ktiles + S - 1) / S) * TK;
   S = (K + kc - 1) / kc;
   dim3 grid((N + TN - 1) / TN, (M + TM - 1) / TM, S);
-  hipLaunchKernelGGL(gemm_bf16, grid, dim3(kGemmThreads), 0, s, A, lda, a_kc, B, ldb, b_kc, C, ldc, M, N, K, kc,
-                     epi, bias, mask, part);
+  // whole 16-byte groups along each operand's contiguous index, aligned,
+  // and operands addressable by 32-bit byte offsets
+  auto aligned = [](const float* p) { return (reinterpret_cast<unsigned long long>(p) & 15) == 0; };
+  const long long a_bytes = 4 * (a_kc ? (long long)M : (long long)K) * lda;
+  const long long b_bytes = 4 * (b_kc ? (long long)N : (long long)K) * ldb;
+  const bool vec = (lda & 3) == 0 && (ldb & 3) == 0 && aligned(A) && aligned(B) &&
+                   ((a_kc ? K : M) & 3) == 0 && ((b_kc ? K : N) & 3) == 0 && a_bytes < kOutside &&
+                   b_bytes < kOutside;
+#define GL(AK, BK, V)                                                                                      \
+  hipLaunchKernelGGL((gemm_bf16<AK, BK, V>), grid, dim3(kGemmThreads), 0, s, A, lda, B, ldb, C, ldc, M, N, K, \
+                     kc, epi, bias, mask, part)
+  if (vec) {
+    if (a_kc && b_kc) GL(true, true, true); else if (a_kc) GL(true, false, true);
+    else if (b_kc) GL(false, true, true); else GL(false, false, true);
+  } else {
+    if (a_kc && b_kc) GL(true, true, false); else if (a_kc) GL(true, false, false);
+    else if (b_kc) GL(false, true, false); else GL(false, false, false);
+  }
+#undef GL
   if (S > 1) {
     const long long n = (long long)M * N;
     hipLaunchKernelGGL(gemm_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, S, C, ldc, M, N, epi,
@@ -300,10 +333,8 @@ hipError_t launch_gemm(const float* A, long long lda, int a_kc, const float* B, 
   return hipGetLastError();
 }
 
-// part: scratch of kColSlices * N floats
-hipError_t launch_colsum(const float* G, int M, int N, float* part, float* db, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_part, dim3((N + 63) / 64, kColSlices), dim3(256), 0, s, G, M, N, part);
-  hipLaunchKernelGGL(colsum_final, dim3((N + 255) / 256), dim3(256), 0, s, part, N, db);
+hipError_t launch_colsum(const float* G, int M, int N, float* db, hipStream_t s) {
+  hipLaunchKernelGGL(colsum, dim3((N + 63) / 64), dim3(1024), 0, s, G, M, N, db);
   return hipGetLastError();
 }
 
