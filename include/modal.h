@@ -144,7 +144,9 @@ typedef struct {
 } modal_desc;
 
 /* Validates the description (before any device work), computes the per-mode
- * recursion coefficients in FP64 and stores them as float-float pairs,
+ * recursion coefficients in FP64 (paper: Sec. 3.2, the Stormer-Verlet and
+ * transfer-function updates of each modal oscillator) and stores them as
+ * float-float pairs,
  * partitions the batch into per-workgroup work, allocates device memory and
  * uploads the coupling tensors and initial states on `stream`.
  * Shared-tensor path: when every instance is VK with n_t <= 64 and
@@ -180,12 +182,15 @@ typedef struct {
  * sine-family tensors stored parity-blocked (mode_class given, forward
  * only).
  * Errors: EINVAL (NULL/size/kind/finite/symmetry), EUNSTABLE (a mode's
- * characteristic roots outside the unit circle; also gamma < 0 or, for TF,
+ * characteristic roots outside the unit circle; also gamma <= 0 or, for TF,
  * omega <= gamma), ENOMEM, EHIP.  On error *out is NULL. */
 int modal_init(modal_ctx **out, const modal_desc *d, void *stream);
 
-/* Advances every instance by n_steps samples from its current state and
- * writes y[b * y_stride + i] = output of instance b at step (current + i),
+/* Advances every instance by n_steps samples from its current state (paper:
+ * Sec. 3.2, one update per sample with the nonlinear modal force of Sec. 3.1
+ * evaluated at q^n) and writes y[b * y_stride + i] = output of instance b at
+ * step (current + i), the modal-to-physical transform at the pickup
+ * (Sec. 4.1),
  * i < n_steps.  y is device memory of at least batch * y_stride floats,
  * y_stride >= n_steps.  Launches on `stream`.  Unless MODAL_FLAG_ASYNC, waits
  * for completion and returns ENONFINITE / EHANG if raised.  Steps already
@@ -217,11 +222,14 @@ int modal_run_noalloc(modal_ctx *c, int64_t n_steps, float *y, int64_t y_stride,
 /* Waits for `stream` and reports ENONFINITE / EHANG raised since init/reset. */
 int modal_check(modal_ctx *c, void *stream);
 
-/* Restores q^0, q^-1 and the step counter to their values at init. */
+/* Restores q^0, q^-1 (the initial conditions of Sec. 3.2's two-step
+ * recursion) and the step counter to their values at init. */
 int modal_reset(modal_ctx *c, void *stream);
 
-/* Copies the current state of every instance to host FP64 arrays laid out as
- * the concatenation of the instances' modes: x = q^n, xm1 = q^{n-1}
+/* Copies the current state of every instance (the modal displacements of
+ * Sec. 3.2's recursion, recombined from their float-float pairs) to host
+ * FP64 arrays laid out as the concatenation of the instances' modes:
+ * x = q^n, xm1 = q^{n-1}
  * (each [sum n_t]).  Waits for `stream`. */
 int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
 

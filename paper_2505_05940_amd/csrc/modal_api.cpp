@@ -387,7 +387,10 @@ int validate(const modal_desc* d) {
     for (int64_t i = 0; i < I.n_exc; ++i)
       if (!std::isfinite(I.e_ext[i])) return fail(MODAL_EINVAL, "non-finite e_ext" + at);
     for (int k = 0; k < I.n_t; ++k) {
-      if (I.gamma[k] < 0) return fail(MODAL_EUNSTABLE, "gamma < 0" + at);
+      // a mode without loss (gamma = 0) is rejected too: every scheme's
+      // damping factors then sit on the unit circle, where rounding decides
+      // growth or decay
+      if (!(I.gamma[k] > 0)) return fail(MODAL_EUNSTABLE, "gamma <= 0" + at);
       if (I.omega[k] < 0) return fail(MODAL_EINVAL, "omega < 0" + at);
       if (d->scheme == MODAL_SCHEME_TF && !(I.omega[k] > I.gamma[k]))
         return fail(MODAL_EUNSTABLE, "TF needs omega > gamma" + at);

@@ -33,6 +33,7 @@ def _inst(kind="linear", n=4, **kw):
 
 @pytest.mark.parametrize("bad,code", [
     (dict(gamma=np.full(4, -1.0)), "EUNSTABLE"),
+    (dict(gamma=np.zeros(4)), "EUNSTABLE"),
     (dict(omega=np.full(4, 2.01 * 44100.0)), "EUNSTABLE"),
     (dict(x0=np.array([1.0, np.nan, 0, 0])), "EINVAL"),
 ])
