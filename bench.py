@@ -311,30 +311,34 @@ def mlp_training_rate(epochs, n=200000, batch=1024):
 
 def fit_wall_time():
     """Wall time to the target spectral loss, proposal-initialised against
-    plain fitting: a proposal network is trained on 200 000 plates simulated
-    by the dense path (60 epochs); then 64 held-out seeded targets (40/40
-    modes, 0.25 s) are fitted by gradients through the time loop with Adam
+    plain fitting, for each family: a proposal network is trained on 200 000
+    plates (40/40 modes, dense path) or Kirchhoff-Carrier strings (12 modes)
+    simulated from the priors (60 epochs); then 64 held-out seeded targets
+    (0.25 s) are fitted by gradients through the time loop with Adam
     (one-cycle cosine, 60 iterations at most), once from the network's
     guesses (inference included in the wall time) and once from the prior
     centre, on the same targets and budget.  The headline figure is the
-    proposal arm's wall time, from the start of its fit, until half of the
-    targets have an MR-STFT loss below 0.1 (None if fewer than half get
+    plate proposal arm's wall time, from the start of its fit, until half of
+    the targets have an MR-STFT loss below 0.1 (None if fewer than half get
     there)."""
     from paper_2505_05940_amd import proposal
-    args = proposal.bench_args()
-    res = proposal.run(args, stream=sys.stderr)
     keys = ("time_to_half_s", "success_rate", "time_to_target_median_s", "final_loss_median",
             "iterations", "wall_s", "param_error_start", "param_error_end")
-    arms = {name: {k: arm[k] for k in keys} for name, arm in res["arms"].items()}
-    return res["arms"]["proposal"]["time_to_half_s"], {
-        "workload": f"{args.test} held-out plates ({args.modes}/{args.modes} modes, {args.steps} steps), "
-                    f"fits from the proposal and from the prior centre, target MR-STFT < {args.tol}",
-        "arms": arms,
-        "reduced_from_config": {"audio_s": [args.steps / 44100.0, 1.0], "targets": [args.test, 512],
-                                "max_iterations": [args.iters, 1000], "families": [["plate"], ["string", "plate"]]},
-        "dataset_s": res["gen_s"], "train_s": res["train_s"], "proposal_z_err": res["proposal_z_err"],
-        "training_sims": args.train, "epochs": args.epochs,
-    }
+    out = {}
+    for family in ("plate", "string"):
+        args = proposal.bench_args(family)
+        res = proposal.run(args, stream=sys.stderr)
+        arms = {name: {k: arm[k] for k in keys} for name, arm in res["arms"].items()}
+        out[family] = {
+            "workload": f"{args.test} held-out {family}s ({args.modes} modes, {args.steps} steps), fits from the "
+                        f"proposal and from the prior centre, target MR-STFT < {args.tol}",
+            "arms": arms,
+            "reduced_from_config": {"audio_s": [args.steps / 44100.0, 1.0], "targets": [args.test, 512],
+                                    "max_iterations": [args.iters, 1000]},
+            "dataset_s": res["gen_s"], "train_s": res["train_s"], "proposal_z_err": res["proposal_z_err"],
+            "training_sims": args.train, "epochs": args.epochs,
+        }
+    return out["plate"]["arms"]["proposal"]["time_to_half_s"], out
 
 
 def _cpu_info():

@@ -79,3 +79,55 @@ def theta_gradient(fit, theta, n_steps, fs, ybar, h_rel=1e-6):
         np.sum(g_omega * d["omega"]) + np.sum(g_gamma * d["gamma"])
         + np.sum((g["x0"] + g["xm1"]) * d["x0"]) + np.sum(g["c"] * d["c"]) + g["theta"][j]
         for j, d in enumerate(dpiece)])
+
+
+# ----------------------------------------------------------------------------
+# Strings.  theta = (T0/rhoA, EI/rhoA, L, d1^, d3^) of a Kirchhoff-Carrier
+# string (paper: Sec. 3, the tension-modulated string and tau = EA/(2L);
+# Sec. 4.3, density-normalised parameters), gamma_k = d1^ + d3^ lambda_k, with
+# EA/rhoA, the pluck and the pickup (relative positions) fixed.  Built through
+# the oracle's own physical string with rho A = 1, so that the parameters
+# are the physical quantities per unit mass.
+
+def string_from_theta(sfit, theta):
+    from . import instances
+    T0h, EIh, L, d1, d3 = (float(v) for v in theta)
+    xp, amp, w = sfit["pluck"]
+    wl = dict(L=L, T0=T0h, EI=EIh, EA=sfit["EAhat"], rhoA=1.0, n_modes=sfit["n_modes"],
+              damping=("d1d3", 2.0 * d1, 2.0 * d3),
+              pluck=dict(x0=xp * L, amplitude=amp, width=w * L),
+              x_out=sfit["out"] * L, proj_cells=sfit["proj_cells"])
+    return instances.string_instance(wl)
+
+
+def _force_scale(inst):
+    """The string's nonlinear force kappa lambda_k q_k sum_j lambda_j q_j^2 is
+    a fixed shape times kappa lambda_1^2 when every lambda scales alike."""
+    return inst["kappa"] * inst["lam"][0] ** 2
+
+
+def string_theta_gradient(sfit, theta, n_steps, fs, ybar, h_rel=1e-6):
+    """dL/dtheta of a string for dL/dy^n = ybar[n]: the reverse recursion
+    gives the gradients with respect to omega, gamma, q^0, q^-1, c and the
+    force scale; the derivatives of those pieces with respect to theta are
+    central differences of ``string_from_theta`` (for the force, of the log of
+    its scale, after checking that the lambdas move by one common factor)."""
+    from . import adjoint
+    theta = np.asarray(theta, dtype=float)
+    inst = string_from_theta(sfit, theta)
+    g = adjoint.reverse(inst, n_steps, fs, np.asarray(ybar, dtype=float))
+    g_omega, g_gamma = adjoint.sv_omega_gamma_grads(g, inst["omega"], inst["gamma"], 1.0 / fs)
+    out = np.empty(len(theta))
+    for j in range(len(theta)):
+        e = h_rel * theta[j]
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += e
+        tm[j] -= e
+        a, b = string_from_theta(sfit, tp), string_from_theta(sfit, tm)
+        ra = a["lam"] / inst["lam"]
+        assert np.allclose(ra, ra[0], rtol=1e-12), "the lambdas do not move together"
+        d = {k: (a[k] - b[k]) / (2.0 * e) for k in ("omega", "gamma", "x0", "c")}
+        dlog_s = (np.log(_force_scale(a)) - np.log(_force_scale(b))) / (2.0 * e)
+        out[j] = (np.sum(g_omega * d["omega"]) + np.sum(g_gamma * d["gamma"])
+                  + np.sum((g["x0"] + g["xm1"]) * d["x0"]) + np.sum(g["c"] * d["c"]) + g["scale"] * dlog_s)
+    return out

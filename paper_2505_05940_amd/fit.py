@@ -18,6 +18,16 @@ a per-row rescaling through zeta_n^2 = lambda_n(a).
 
 ``ModalFn`` is a torch.autograd.Function whose forward runs modal_run and
 whose backward runs modal_grad, followed by the FP64 chain rule to theta.
+
+A tension-modulated (Kirchhoff-Carrier) string has five parameters too,
+theta = (T0^, EI^, L, d1^, d3^) with T0^ = T0/(rho A), EI^ = EI/(rho A):
+    omega_k^2 = EI^ lambda_k^2 + T0^ lambda_k,   gamma_k = d1^ + d3^ lambda_k,
+    lambda_k  = (k pi / L)^2,   kappa = EA^/(2 L)   (Sec. 3: tau = EA/(2L)),
+with EA^ = EA/(rho A), the pluck and the pickup (relative positions) fixed.
+Its nonlinear force kappa lambda_k q_k sum_j lambda_j q_j^2 scales as L^-5
+when L changes (kappa as 1/L, every lambda as 1/L^2), so the length enters the
+force through the force-scale gradient.  ``StringFn`` is its autograd
+function.
 """
 from __future__ import annotations
 
@@ -217,42 +227,138 @@ def one_cycle_cosine(step, total, peak, warm_frac=0.3, div=25.0, final_div=1e4):
     return lo + (peak - lo) * 0.5 * (1 + math.cos(math.pi * t))
 
 
-def to_unconstrained(theta):
-    """theta -> z: logs of the positive parameters, logit of a in (0.3, 1.5)
-    (keeps gamma > 0 and the plate non-degenerate)."""
+def to_unconstrained(theta, bounds=(0.3, 1.5)):
+    """theta -> z: logs of the positive parameters, logit of the geometry
+    parameter (a plate's aspect ratio, a string's length) in `bounds`
+    (keeps gamma > 0 and the instance non-degenerate)."""
+    lo, hi = bounds
     t = np.asarray(theta, float)
     z = np.log(t.copy())
-    z[2] = math.log((t[2] - 0.3) / (1.5 - t[2]))
+    z[2] = math.log((t[2] - lo) / (hi - t[2]))
     return z
 
 
-def from_unconstrained(z):
+def from_unconstrained(z, bounds=(0.3, 1.5)):
+    lo, hi = bounds
     z = torch.as_tensor(z)
     t = torch.exp(z)
-    a = 0.3 + 1.2 * torch.sigmoid(z[..., 2])
+    a = lo + (hi - lo) * torch.sigmoid(z[..., 2])
     return torch.cat([t[..., :2], a[..., None], t[..., 3:]], dim=-1)
 
 
-def fit(target: torch.Tensor, theta0, setup: PlateSetup, n_steps: int, iters: int = 100,
+# ------------------------------------------------------------------ strings
+STRING_PARAM_NAMES = ("T0hat", "EIhat", "length", "d1hat", "d3hat")
+
+
+@dataclass
+class StringSetup:
+    """Fixed part of a fitted Kirchhoff-Carrier string."""
+    n_modes: int = 20
+    EAhat: float = 5e8                  # EA / (rho A): the 3e5 N, 6e-4 kg/m string
+    pluck: tuple = (0.27, 1e-3, 0.1)    # x / L, amplitude, total width / L
+    out: float = 0.71                   # pickup x / L
+    proj_cells: int = 4096
+    fs: float = 44100.0
+    bounds: tuple = (0.3, 1.2)          # length range of the unconstrained fit
+
+
+_STRING_EXC = {}
+
+
+def _string_excitation(setup, L):
+    """Pluck projection and pickup weights at length L (cached per length)."""
+    key = (id(setup), float(L))
+    if key not in _STRING_EXC:
+        if len(_STRING_EXC) > 4096:
+            _STRING_EXC.clear()
+        k = np.arange(1, setup.n_modes + 1, dtype=np.float64)
+        xp, amp, w = setup.pluck
+        x0 = physics.string_initial(k, L, dict(x0=xp * L, amplitude=amp, width=w * L), setup.proj_cells)
+        c = math.sqrt(2.0 / L) * np.sin(k * np.pi * setup.out)
+        _STRING_EXC[key] = (setup, (x0, c))
+    x0, c = _STRING_EXC[key][1]
+    return x0.copy(), c.copy()
+
+
+def string_instance(setup: StringSetup, theta):
+    """Instance dict (kind tension) for theta = (T0^, EI^, L, d1^, d3^)."""
+    T0h, EIh, L, d1, d3 = (float(v) for v in theta)
+    _, lam = physics.string_eigs(L, setup.n_modes)
+    omega = np.sqrt(EIh * lam ** 2 + T0h * lam)
+    gamma = d1 + d3 * lam
+    x0, c = _string_excitation(setup, L)
+    return dict(kind="tension", omega=omega, gamma=gamma, lam=lam, kappa=setup.EAhat / (2.0 * L),
+                x0=x0, xm1=x0.copy(), c=c)
+
+
+def string_chain_rule(setup, theta, inst, g, h_rel=1e-6):
+    """dL/dtheta of a string from the per-mode gradients of modal_grad."""
+    T0h, EIh, L, d1, d3 = (float(v) for v in theta)
+    lam, om = inst["lam"], inst["omega"]
+    gw, gg = g["omega"], g["gamma"]
+    dT0 = np.sum(gw * lam / (2 * om))
+    dEI = np.sum(gw * lam ** 2 / (2 * om))
+    dd1 = np.sum(gg)
+    dd3 = np.sum(gg * lam)
+    # length: lambda_k = (k pi / L)^2, d lambda_k / dL = -2 lambda_k / L, in
+    # omega, gamma and (with kappa ~ 1/L) the force's scale L^-5
+    dlam = -2.0 * lam / L
+    dL = (np.sum(gw * (2 * EIh * lam + T0h) * dlam / (2 * om)) + np.sum(gg * d3 * dlam)
+          - 5.0 * g["scale"] / L)
+    eps = h_rel * L
+    xp, cp = _string_excitation(setup, L + eps)
+    xm, cm = _string_excitation(setup, L - eps)
+    dL += np.sum((g["x0"] + g["xm1"]) * (xp - xm) / (2 * eps)) + np.sum(g["c"] * (cp - cm) / (2 * eps))
+    return np.array([dT0, dEI, dL, dd1, dd3])
+
+
+class StringFn(torch.autograd.Function):
+    """y = simulate(theta) for a batch of string parameter vectors; backward
+    through modal_grad and string_chain_rule."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, setup: StringSetup, n_steps: int, ckpt: int = 512):
+        th = theta.detach().double().cpu().numpy().reshape(-1, 5)
+        insts = [string_instance(setup, t) for t in th]
+        sim = modal.Sim(insts, setup.fs, flags=modal.FLAG_GRAD)
+        y = sim.run(n_steps).clone()
+        ctx.save = (sim, insts, th, setup, n_steps, ckpt)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        sim, insts, th, setup, n_steps, ckpt = ctx.save
+        g = sim.grad(n_steps, gy.contiguous().float(), ckpt_every=ckpt)
+        out = np.stack([string_chain_rule(setup, th[b], insts[b], {k: v[b] for k, v in g.items()})
+                        for b in range(len(insts))])
+        sim.close()
+        return torch.tensor(out, dtype=torch.float64).reshape(-1, 5), None, None, None
+
+
+def fit(target: torch.Tensor, theta0, setup, n_steps: int, iters: int = 100,
         lr: float = 0.05, tol: float = 0.1, loss_fn=mrstft_loss, callback=None, free=None):
     """Adam with a one-cycle cosine schedule on unconstrained parameters,
     batched over rows of theta0.  A row that reaches tol is frozen there;
     the loop stops when every row has.  ``free``: the indices of the
     parameters that are fitted (default all five); the others keep their
     values from theta0 (their gradients are dropped before each step).
+    ``setup``: a PlateSetup (ModalFn) or a StringSetup (StringFn).
     Returns (theta [B,5] and losses [B] of each row's best iterate,
     iterations, loss history)."""
     fixed = np.ones(5, bool)
     fixed[list(range(5)) if free is None else list(free)] = False
     fixed_t = torch.from_numpy(fixed)
-    z = torch.tensor(np.stack([to_unconstrained(t) for t in np.atleast_2d(theta0)]),
+    string = isinstance(setup, StringSetup)
+    Fn = StringFn if string else ModalFn
+    bounds = setup.bounds if string else (0.3, 1.5)
+    z = torch.tensor(np.stack([to_unconstrained(t, bounds) for t in np.atleast_2d(theta0)]),
                      dtype=torch.float64, requires_grad=True)
     B = z.shape[0]
     opt = torch.optim.Adam([z], lr=lr)
     hist = []
     tgt = target.reshape(-1, target.shape[-1])
     best_L = np.full(B, np.inf)
-    best_th = from_unconstrained(z).detach().numpy().copy()
+    best_th = from_unconstrained(z, bounds).detach().numpy().copy()
     frozen = np.zeros(B, bool)
     z_frozen = z.detach().clone()
     it = 0
@@ -260,8 +366,8 @@ def fit(target: torch.Tensor, theta0, setup: PlateSetup, n_steps: int, iters: in
         for gparam in opt.param_groups:
             gparam["lr"] = one_cycle_cosine(it, iters, lr)
         opt.zero_grad()
-        theta = from_unconstrained(z)
-        y = ModalFn.apply(theta, setup, n_steps)
+        theta = from_unconstrained(z, bounds)
+        y = Fn.apply(theta, setup, n_steps)
         L = loss_fn(y, tgt.expand_as(y), reduce=False)
         Ln = L.detach().cpu().numpy()
         hist.append(Ln)

@@ -9,9 +9,11 @@ seeded priors, maps a target sound's features to a starting point; gradient
 fitting then refines it, and the plain fit from the prior centre is both the
 fallback and the yardstick.
 
-Parameters theta = (T0^, D^, a, d1^, d3^) of a von Karman plate (fit.py).
-Priors: log-uniform over one decade centred on the base point for T0^, D^,
-d1^ and d3^; the aspect ratio a from a 64-point grid on [0.5, 1].
+Parameters theta = (T0^, D^, a, d1^, d3^) of a von Karman plate, or
+(T0^, EI^, L, d1^, d3^) of a Kirchhoff-Carrier string (fit.py); one network
+per family.  Priors: log-uniform over one decade centred on the base point
+for the four positive parameters; the geometry parameter (a plate's aspect
+ratio, a string's length) from a 64-point grid on [0.5, 1] or [0.5, 0.8] m.
 Network: 1024 log-mel features (8 time slices x 128 mel bands) -> 4 hidden
 layers of 512 (ReLU) -> 5 normalised log-parameters; MSE loss; Adam.
 
@@ -32,50 +34,58 @@ from .mlp import MLP
 
 DIMS = [1024, 512, 512, 512, 512, 5]
 ASPECTS = np.linspace(0.5, 1.0, 64)
+LENGTHS = np.linspace(0.5, 0.8, 64)
+# geometry grid, its centre and half-width per family
+_GEOM = {"plate": (ASPECTS, 0.75, 0.25), "string": (LENGTHS, 0.65, 0.15)}
 
 
-def prior_center(base):
+def prior_center(base, family="plate"):
     c = np.array(base, float).copy()
-    c[2] = 0.75
+    c[2] = _GEOM[family][1]
     return c
 
 
-def sample_prior(rng, n, base):
+def sample_prior(rng, n, base, family="plate"):
     """n x 5 seeded draws."""
     base = np.asarray(base, float)
     th = np.empty((n, 5))
     for i in (0, 1, 3, 4):
         th[:, i] = base[i] * 10.0 ** rng.uniform(-0.5, 0.5, n)
-    th[:, 2] = rng.choice(ASPECTS, n)
+    th[:, 2] = rng.choice(_GEOM[family][0], n)
     return th
 
 
-def normalize(th, base):
+def normalize(th, base, family="plate"):
     """theta -> z in about [-1, 1]^5 (log-decades for the positive ones)."""
+    _, mid, half = _GEOM[family]
     th = np.atleast_2d(th)
     z = np.empty_like(th)
     for i in (0, 1, 3, 4):
         z[:, i] = 2.0 * np.log10(th[:, i] / base[i])
-    z[:, 2] = 4.0 * (th[:, 2] - 0.75)
+    z[:, 2] = (th[:, 2] - mid) / half
     return z
 
 
-def denormalize(z, base):
+def denormalize(z, base, family="plate"):
+    _, mid, half = _GEOM[family]
     z = np.clip(np.atleast_2d(z), -1.0, 1.0)
     th = np.empty_like(z)
     for i in (0, 1, 3, 4):
         th[:, i] = base[i] * 10.0 ** (0.5 * z[:, i])
-    th[:, 2] = 0.75 + 0.25 * z[:, 2]
+    th[:, 2] = mid + half * z[:, 2]
     return th
 
 
 def simulate(setup, thetas, n_steps, batch=65536):
-    """Outputs [n, n_steps] (CUDA float32) of the plates theta, by batches of
-    one launch each.  The plates share the setup's base tensor up to per-row
-    scales, so a batch runs on the library's dense (MFMA) path."""
+    """Outputs [n, n_steps] (CUDA float32) of the instances theta, by batches
+    of one launch each.  Plates share the setup's base tensor up to per-row
+    scales, so a batch of them runs on the library's dense (MFMA) path;
+    strings have no tensor and run on the step kernel."""
+    string = isinstance(setup, fit.StringSetup)
     out = []
     for s in range(0, len(thetas), batch):
-        insts = [fit.plate_instance_shared(setup, t) for t in thetas[s:s + batch]]
+        insts = [fit.string_instance(setup, t) if string else fit.plate_instance_shared(setup, t)
+                 for t in thetas[s:s + batch]]
         sim = modal.Sim(insts, setup.fs)
         out.append(sim.run(n_steps).clone())
         sim.close()
@@ -92,9 +102,9 @@ def features(y, chunk=16384):
     return torch.cat(out)
 
 
-def param_error(th, th_ref, base):
+def param_error(th, th_ref, base, family="plate"):
     """Mean |difference| of normalised parameters per row (prior spread ~ 0.5)."""
-    return np.mean(np.abs(normalize(th, base) - normalize(th_ref, base)), axis=1)
+    return np.mean(np.abs(normalize(th, base, family) - normalize(th_ref, base, family)), axis=1)
 
 
 def predict(net, X, batch=1024):
@@ -130,21 +140,26 @@ def run(args, stream=None):
     import sys
     stream = stream or sys.stdout
     torch.manual_seed(0)
-    fw = dict(n_t=args.modes, n_in=args.modes)
-    setup = fit.PlateSetup(n_t=args.modes, n_in=args.modes)
     import workloads as W
-    wl = W.plate_fit(n_t=args.modes)
-    base = wl["theta0"]
+    family = getattr(args, "family", "plate")
+    if family == "string":
+        sw = W.string_fit(n_modes=args.modes)
+        setup = fit.StringSetup(n_modes=args.modes, EAhat=sw["EAhat"], pluck=sw["pluck"], out=sw["out"],
+                                proj_cells=sw["proj_cells"], fs=sw["fs"])
+        base = sw["theta0"]
+    else:
+        setup = fit.PlateSetup(n_t=args.modes, n_in=args.modes)
+        base = W.plate_fit(n_t=args.modes)["theta0"]
     rng = np.random.default_rng(5)
-    log = lambda m: print(f"[proposal] {m}", file=stream, flush=True)
+    log = lambda m: print(f"[proposal] {family}: {m}", file=stream, flush=True)
     t0 = time.time()
-    th_train = sample_prior(rng, args.train, base)
+    th_train = sample_prior(rng, args.train, base, family)
     X = []
     for s in range(0, args.train, args.gen_batch):
         y = simulate(setup, th_train[s:s + args.gen_batch], args.steps)
         X.append(features(y))
     X = torch.cat(X)
-    Z = torch.tensor(normalize(th_train, base), dtype=torch.float32, device="cuda")
+    Z = torch.tensor(normalize(th_train, base, family), dtype=torch.float32, device="cuda")
     t_gen = time.time() - t0
     log(f"generated {args.train} sims x {args.steps} steps in {t_gen:.1f} s")
     net = MLP(DIMS, max_batch=1024)
@@ -155,14 +170,14 @@ def run(args, stream=None):
     log(f"trained {args.epochs} epochs in {t_train:.1f} s, mse {mse:.4f}")
     # held-out targets
     rng_t = np.random.default_rng(50)
-    th_test = sample_prior(rng_t, args.test, base)
+    th_test = sample_prior(rng_t, args.test, base, family)
     y_tgt = simulate(setup, th_test, args.steps)
     z_hat = predict(net, features(y_tgt))
-    th_prop = denormalize(z_hat, base)
-    prop_err = float(np.mean(np.abs(normalize(th_prop, base) - normalize(th_test, base))))
+    th_prop = denormalize(z_hat, base, family)
+    prop_err = float(np.mean(np.abs(normalize(th_prop, base, family) - normalize(th_test, base, family))))
     log(f"proposal mean |z error| {prop_err:.3f} (prior spread about 0.5)")
     results = {}
-    starts = {"default": np.tile(prior_center(base), (args.test, 1)), "proposal": th_prop}
+    starts = {"default": np.tile(prior_center(base, family), (args.test, 1)), "proposal": th_prop}
     arms = [(a, starts[a]) for a in args.arms.split(",")]
     # untimed warm-up of the fit path (the loss's FFT plans, first kernel
     # launches), as the step benchmark's warm-up steps
@@ -188,22 +203,25 @@ def run(args, stream=None):
                             time_to_target_median_s=float(np.median(t_first[done])) if done.any() else None,
                             time_to_half_s=float(np.sort(np.where(done, t_first, np.inf))[args.test // 2])
                             if np.mean(done) >= 0.5 else None,
-                            param_error_start=float(np.mean(param_error(th0, th_test, base))),
-                            param_error_end=float(np.mean(param_error(th, th_test, base))))
+                            param_error_start=float(np.mean(param_error(th0, th_test, base, family))),
+                            param_error_end=float(np.mean(param_error(th, th_test, base, family))))
         log(f"{arm}: {results[arm]}")
-    out = dict(train=args.train, steps=args.steps, modes=args.modes, epochs=args.epochs,
+    out = dict(family=family, train=args.train, steps=args.steps, modes=args.modes, epochs=args.epochs,
                test=args.test, gen_s=t_gen, train_s=t_train, mlp_mse=mse, proposal_z_err=prop_err,
                arms=results)
     print(json.dumps(out), file=stream, flush=True)
     return out
 
 
-def bench_args(**kw):
-    """The experiment as the benchmark runs it: 200 000 simulated plates, 60
-    epochs, 64 held-out targets fitted from the network's guesses and from
-    the prior centre (plain fitting), 60 iterations each."""
-    a = dict(modes=40, steps=11025, train=200000, gen_batch=65536, epochs=60, test=64, iters=60,
-             lr=0.01, tol=0.1, verbose=False, arms="proposal,default")
+def bench_args(family="plate", **kw):
+    """The experiment as the benchmark runs it: 200 000 simulated plates (40
+    modes) or strings (12 modes), 60 epochs, 64 held-out targets fitted from
+    the network's guesses and from the prior centre (plain fitting), 60
+    iterations each.  (With 20 string modes about 0.2 % of the prior's draws,
+    short strings at high tension, drive the explicit scheme unstable through
+    the tension term; the FP64 oracle diverges on them too.)"""
+    a = dict(family=family, modes=40 if family == "plate" else 12, steps=11025, train=200000, gen_batch=65536,
+             epochs=60, test=64, iters=60, lr=0.01, tol=0.1, verbose=False, arms="proposal,default")
     a.update(kw)
     return argparse.Namespace(**a)
 
@@ -220,6 +238,7 @@ def main():
     ap.add_argument("--lr", type=float, default=0.01)
     ap.add_argument("--tol", type=float, default=0.1)
     ap.add_argument("--arms", default="default,proposal", help="fit arms to run")
+    ap.add_argument("--family", default="plate", choices=("plate", "string"))
     ap.add_argument("--verbose", action="store_true")
     run(ap.parse_args())
 

@@ -85,6 +85,13 @@ def test_proposal_normalisation_roundtrip_and_prior_range():
     assert np.abs(z).max() <= 1.0 + 1e-12
     assert np.allclose(proposal.denormalize(z, base), th, rtol=1e-12)
     assert set(np.unique(th[:, 2])) <= set(proposal.ASPECTS)
+    sbase = W.string_fit()["theta0"]
+    th = proposal.sample_prior(np.random.default_rng(1), 200, sbase, "string")
+    z = proposal.normalize(th, sbase, "string")
+    assert np.abs(z).max() <= 1.0 + 1e-12
+    assert np.allclose(proposal.denormalize(z, sbase, "string"), th, rtol=1e-12)
+    assert set(np.unique(th[:, 2])) <= set(proposal.LENGTHS)
+    assert np.allclose(proposal.prior_center(sbase, "string"), sbase)
 
 
 def test_unconstrained_map_roundtrip():
@@ -95,3 +102,50 @@ def test_unconstrained_map_roundtrip():
     assert np.allclose(fit.from_unconstrained(torch.tensor(z)).numpy(), th, rtol=1e-12)
     assert abs(fit.one_cycle_cosine(0, 100, 1.0) - 1.0 / 25) < 1e-12
     assert abs(fit.one_cycle_cosine(30, 100, 1.0) - 1.0) < 1e-12
+
+
+def _string_setup(sf):
+    from paper_2505_05940_amd import fit
+    return fit.StringSetup(n_modes=sf["n_modes"], EAhat=sf["EAhat"], pluck=sf["pluck"], out=sf["out"],
+                           proj_cells=sf["proj_cells"], fs=sf["fs"])
+
+
+def test_parameterised_string_matches_oracle():
+    """The product's parameterised Kirchhoff-Carrier string equals the
+    oracle's (built through its physical string with rho A = 1)."""
+    from paper_2505_05940_amd import fit
+    sf = W.string_fit()
+    st = _string_setup(sf)
+    for th in (sf["theta0"], sf["theta_target"]):
+        p = fit.string_instance(st, th)
+        o = OP.string_from_theta(sf, th)
+        for k in ("omega", "gamma", "lam", "x0", "c"):
+            assert np.allclose(p[k], o[k], rtol=1e-12, atol=1e-14 * np.abs(o[k]).max()), k
+        assert abs(p["kappa"] - o["kappa"]) <= 1e-14 * o["kappa"]
+
+
+def test_string_chain_rule_against_oracle_differences():
+    """The product's string chain rule fed with the oracle's per-mode and
+    force-scale gradients equals central differences of the oracle loop (the
+    length through omega, gamma, the force scale L^-5, the pluck and the
+    pickup)."""
+    from paper_2505_05940_amd import fit
+    sf = W.string_fit(n_modes=10)
+    st = _string_setup(sf)
+    th = sf["theta0"] * np.array([1.0, 50.0, 1.0, 3.0, 1.0])
+    steps = 2000
+    rng = np.random.default_rng(4)
+    oi = OP.string_from_theta(sf, th)
+    gy = rng.normal(size=steps) / np.abs(oi["x0"]).max()
+    L = lambda t: float(gy @ OA.forward(OP.string_from_theta(sf, t), steps, 44100.0)[0])
+    r = OA.reverse(oi, steps, 44100.0, gy)
+    om, ga = OA.sv_omega_gamma_grads(r, oi["omega"], oi["gamma"], 1 / 44100.0)
+    g = dict(omega=om, gamma=ga, c=r["c"], x0=r["x0"], xm1=r["xm1"], scale=r["scale"])
+    grad = fit.string_chain_rule(st, th, fit.string_instance(st, th), g)
+    for i in range(5):
+        h = 1e-5 * th[i]
+        tp, tm = th.copy(), th.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (L(tp) - L(tm)) / (2 * h)
+        assert abs(fd - grad[i]) < 2e-4 * abs(fd), (fit.STRING_PARAM_NAMES[i], fd, grad[i])

@@ -332,3 +332,35 @@ def test_theta_gradient_matches_differences_of_the_loop():
         fd = (gy @ OA.forward(OP.plate_from_theta(fw, tp), steps, 44100.0)[0]
               - gy @ OA.forward(OP.plate_from_theta(fw, tm), steps, 44100.0)[0]) / (2 * h)
         assert abs(fd - g[i]) < 1e-5 * abs(fd), (i, fd, g[i])
+
+
+def test_string_theta_gradient_matches_differences_of_the_loop():
+    """The oracle's string theta-gradient (reverse recursion + chain rule
+    through the parameterised Kirchhoff-Carrier string) against central
+    differences of the oracle time loop, on a 10-mode string over 2000
+    steps; and the parameterised string equals the physical one built from
+    the same tension, stiffness, length and damping."""
+    from oracle import adjoint as OA
+    sf = W.string_fit(n_modes=10)
+    th = sf["theta0"] * np.array([1.0, 50.0, 1.0, 3.0, 1.0])  # a stiffer string
+    steps = 2000
+    rng = np.random.default_rng(6)
+    gy = rng.normal(size=steps) / np.abs(OP.string_from_theta(sf, th)["x0"]).max()
+    g = OP.string_theta_gradient(sf, th, steps, 44100.0, gy)
+    for i in range(5):
+        h = 1e-5 * th[i]
+        tp, tm = th.copy(), th.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (gy @ OA.forward(OP.string_from_theta(sf, tp), steps, 44100.0)[0]
+              - gy @ OA.forward(OP.string_from_theta(sf, tm), steps, 44100.0)[0]) / (2 * h)
+        assert abs(fd - g[i]) < 1e-5 * abs(fd), (i, fd, g[i])
+    # the textbook stiff string: f_k = k f1 sqrt(1 + B k^2), f1 = sqrt(T0^)/(2L),
+    # B = pi^2 EI^ / (T0^ L^2)
+    inst = OP.string_from_theta(sf, th)
+    T0h, EIh, L = th[0], th[1], th[2]
+    k = np.arange(1, 11)
+    f = k * np.sqrt(T0h) / (2 * L) * np.sqrt(1 + np.pi ** 2 * EIh / (T0h * L ** 2) * k ** 2)
+    assert np.allclose(inst["omega"] / (2 * np.pi), f, rtol=1e-12)
+    assert np.isclose(inst["kappa"], sf["EAhat"] / (2 * L), rtol=1e-14)
+    assert np.allclose(inst["gamma"], th[3] + th[4] * (k * np.pi / L) ** 2, rtol=1e-13)

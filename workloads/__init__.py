@@ -139,6 +139,24 @@ def plate_fit(seed: int = 4, n_t: int = 200, n_in: int | None = None, n_steps: i
                 proj_grid=(200, 150), fs=FS, n_steps=n_steps, theta0=base, theta_target=target)
 
 
+def string_fit(seed: int = 7, n_modes: int = 20, n_steps: int = 11025, perturb: float = 0.1) -> dict:
+    """Parameter fitting of one Kirchhoff-Carrier string by gradients through
+    the time loop.
+
+    theta = (T0/rhoA, EI/rhoA, L, d1^, d3^) with gamma_k = d1^ + d3^ lambda_k.
+    The base point is the 0.65 m, 60 N, 6e-4 kg/m string (T0^ = 1e5) with a
+    light bending stiffness (EI^ = 0.2, inharmonicity about 1e-5), d1^ = 1 /s
+    and d3^ such that the 20th mode (about 4.9 kHz) decays at about 57 /s;
+    EA/rhoA = 5e8 fixed.  Pluck at 0.27 L, 1 mm, width 0.1 L; pickup at
+    0.71 L.  The target is the base times exp(U[-perturb, perturb]) each
+    (seeded)."""
+    rng = np.random.default_rng(seed)
+    base = np.array([1e5, 0.2, 0.65, 1.0, 6e-3])
+    target = base * np.exp(rng.uniform(-perturb, perturb, size=5))
+    return dict(n_modes=n_modes, EAhat=5e8, pluck=(0.27, 1e-3, 0.1), out=0.71, proj_cells=4096,
+                fs=FS, n_steps=n_steps, theta0=base, theta_target=target)
+
+
 def plate_group(seed: int = 6, batch: int = 48, n_t: int = 40, n_in: int | None = None,
                 n_steps: int = 44100, forced: int = 0) -> dict:
     """A group of plates that share one coupling tensor up to per-row scales.
