@@ -100,6 +100,51 @@ __device__ __forceinline__ float dot4(float4 a, float4 b) {
 }
 __device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 
+// The partial forces that the slabs of a split instance exchange in global
+// memory are written and read as agent-scope relaxed atomics, which gfx950
+// carries out coherently across the XCDs' separate L2 caches (the sc1 cache
+// policy).  Publishing a partial then needs only a wait for its stores to
+// complete before the arrival word is stored, and reading one needs no L2
+// invalidation: an agent-scope release or acquire fence would write back or
+// invalidate the whole L2 of the XCD on every step.
+__device__ __forceinline__ void st4_agent(float* p, float4 v) {
+  __hip_atomic_store(p, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 2, v.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 3, v.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float4 ld4_agent(const float* q) {
+  float* p = const_cast<float*>(q);
+  return make_float4(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                     __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                     __hip_atomic_load(p + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                     __hip_atomic_load(p + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+// After a wave's partial-force stores (st4_agent): waits until they are
+// complete, so that an arrival word stored afterwards cannot be seen before
+// them.  Before reading partials (ld4_agent) once the words have been seen:
+// keeps the reads after the words' loads.  Both at workgroup scope, which
+// costs a wait on the wave's memory counters and no cache maintenance.
+__device__ __forceinline__ void publish_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup"); }
+__device__ __forceinline__ void consume_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup"); }
+
+// sum over t = t0, t0 + dt, ... (t < n) of the float4 at p + t * stride
+// (partial forces of other workgroups, read as agent-scope atomics), eight
+// reads issued before the first add
+__device__ __forceinline__ float4 sum_slabs4_agent(const float* p, int t0, int dt, int n, long long stride) {
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  int t = t0;
+  for (; t + 7 * dt < n; t += 8 * dt) {
+    float4 a[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = ld4_agent(p + (long long)(t + i * dt) * stride);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s = add4(s, a[i]);
+  }
+  for (; t < n; t += dt) s = add4(s, ld4_agent(p + (long long)t * stride));
+  return s;
+}
+
 // sum over t < n of the float4 at p + t * stride (LDS), with four partial
 // sums so that four reads are in flight before the first add waits
 __device__ __forceinline__ float4 sum_strided4(const float* p, int n, int stride) {

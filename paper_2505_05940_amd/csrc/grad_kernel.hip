@@ -604,14 +604,14 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
           for (int g = 0; g < GM; ++g) {
             const int k4 = lane + kWave * g;
             if (g < G && k4 < nc) {
-              st4(dst + 4 * k4, Ju[g]);
-              st4(dst + I.ntp + 4 * k4, Fa[g]);
+              st4_agent(dst + 4 * k4, Ju[g]);
+              st4_agent(dst + I.ntp + 4 * k4, Fa[g]);
             }
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          publish_fence();
           __builtin_amdgcn_wave_barrier();
           if (lane == 0)
-            __hip_atomic_store(&P.ctr[I.ctr_off + U.slab], (unsigned int)(rstep + 1), __ATOMIC_RELEASE,
+            __hip_atomic_store(&P.ctr[I.ctr_off + U.slab], (unsigned int)(rstep + 1), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
       }
@@ -633,15 +633,15 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
       if (SPLIT && NW > 1 && I.nslab >= 2 * NW) {
         // many slabs: every wave sums every NW-th partial, wave 0 adds the
         // waves' sums
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        consume_fence();
         float4 Ju[GM], F[GM];
 #pragma unroll
         for (int g = 0; g < GM; ++g) {
           Ju[g] = F[g] = f4(0.f);
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc) {
-            Ju[g] = sum_slabs4(src + 4 * k4, wave, NW, I.nslab, 2LL * I.ntp);
-            F[g] = sum_slabs4(src + I.ntp + 4 * k4, wave, NW, I.nslab, 2LL * I.ntp);
+            Ju[g] = sum_slabs4_agent(src + 4 * k4, wave, NW, I.nslab, 2LL * I.ntp);
+            F[g] = sum_slabs4_agent(src + I.ntp + 4 * k4, wave, NW, I.nslab, 2LL * I.ntp);
             st4(red + 4 * k4, Ju[g]);
             st4(red + I.ntp + 4 * k4, F[g]);
           }
@@ -661,7 +661,7 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
           adj_post<GM>(P, I, U, n, Ju, F, G, lane);
         }
       } else if (wave == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        consume_fence();
         float4 Ju[GM], F[GM];
 #pragma unroll
         for (int g = 0; g < GM; ++g) {
@@ -669,8 +669,8 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc)
             for (int t = 0; t < I.nslab; ++t) {
-              Ju[g] = add4(Ju[g], ld4(src + (long long)t * 2 * I.ntp + 4 * k4));
-              F[g] = add4(F[g], ld4(src + (long long)t * 2 * I.ntp + I.ntp + 4 * k4));
+              Ju[g] = add4(Ju[g], ld4_agent(src + (long long)t * 2 * I.ntp + 4 * k4));
+              F[g] = add4(F[g], ld4_agent(src + (long long)t * 2 * I.ntp + I.ntp + 4 * k4));
             }
         }
         adj_post<GM>(P, I, U, n, Ju, F, G, lane);

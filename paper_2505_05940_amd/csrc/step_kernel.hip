@@ -715,12 +715,12 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
             const int k4 = lane + kWave * g;
-            if (g < G && k4 < nc) st4(dst + 4 * k4, Fa[g]);
+            if (g < G && k4 < nc) st4_agent(dst + 4 * k4, Fa[g]);
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          publish_fence();
           __builtin_amdgcn_wave_barrier();
           if (lane == 0)
-            __hip_atomic_store(&P.ctr[I.ctr_off + U.slab], (unsigned int)(n + 1), __ATOMIC_RELEASE,
+            __hip_atomic_store(&P.ctr[I.ctr_off + U.slab], (unsigned int)(n + 1), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
       }
@@ -746,14 +746,14 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
       if (RES && NW > 1 && I.nslab >= 2 * NW) {
         // one unit per workgroup and many slabs: every wave sums every NW-th
         // partial force, and wave 0 adds the waves' sums
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        consume_fence();
         float4 F[GM];
 #pragma unroll
         for (int g = 0; g < GM; ++g) {
           F[g] = f4(0.f);
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc) {
-            F[g] = sum_slabs4(src + 4 * k4, wave, NW, I.nslab, I.ntp);
+            F[g] = sum_slabs4_agent(src + 4 * k4, wave, NW, I.nslab, I.ntp);
             st4(red + 4 * k4, F[g]);
           }
         }
@@ -771,7 +771,7 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
           update_groups<GM>(M, nc, e, F, G, lane, P.flags);
         }
       } else if (wave == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        consume_fence();
         const ModeRefs M = refs(U, I);
         float e = 0.f;
         if (n < I.n_exc) e = P.e_ext[I.e_off + n];
@@ -782,7 +782,7 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc)
             for (int t = 0; t < I.nslab; ++t)
-              F[g] = add4(F[g], ld4(src + (long long)t * I.ntp + 4 * k4));
+              F[g] = add4(F[g], ld4_agent(src + (long long)t * I.ntp + 4 * k4));
         }
         update_groups<GM>(M, nc, e, F, G, lane, P.flags);
       }
