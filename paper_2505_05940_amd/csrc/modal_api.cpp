@@ -427,13 +427,12 @@ constexpr int kLatencyMaxSplitBatch = 16;  // larger latency-bound batches keep 
 // A large instance of such a batch is also cut so that no slab streams more
 // than about this many tensor bytes per step (the waves of a one-unit
 // workgroup share its row blocks, so slabs of fewer rows than waves keep
-// every wave busy).  Measured on lone sine plates: forward, 256 KB slabs
-// step a 100/100 plate in 10.1 us (16 slabs) against 12.1 us at 512 KB
-// (13, the row rule) and 13.4 us at 128 KB (31); the 200/200 gradient over
-// 1 s takes 2.34 s at 512 KB (62 slabs), 2.46 s at 256 KB and 2.65 s at
-// 1 MB, so gradient contexts take the larger slabs.
+// every wave busy).  Measured on lone sine plates with the partial forces
+// exchanged as agent-scope atomics: forward, 256 KB slabs step a 100/100
+// plate in 9.0 us (16 slabs) against 11.4 us at 128 KB (31) and 10.2 us at
+// 512 KB before that exchange; the 200/200 gradient over 1 s takes 2.17 s at
+// 256 KB (123 slabs), 2.30 s at 512 KB and 2.42 s at 128 KB.
 constexpr double kLatencySlabBytes = 256.0 * 1024.0;
-constexpr double kLatencySlabBytesGrad = 512.0 * 1024.0;
 
 // Per-step cost of the exchange and barrier of one slab of a split instance,
 // in streamed-byte units (release fence, arrival, wait, acquire and reading
@@ -1677,8 +1676,7 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
       const int rows = inst[b].kind == KIND_VK ? inst[b].nin : 1;
       const double bytes = inst[b].kind == KIND_VK ? 4.0 * inst[b].nin * (double)inst[b].nt * inst[b].nt : 0.0;
       const int by_rows = (rows + kLatencyRows / 2) / kLatencyRows;
-      const int by_bytes =
-          (int)std::ceil(bytes / ((d->flags & MODAL_FLAG_GRAD) ? kLatencySlabBytesGrad : kLatencySlabBytes));
+      const int by_bytes = (int)std::ceil(bytes / kLatencySlabBytes);
       const int S = inst[b].kind == KIND_VK && !chip_nt
                         ? std::max(1, std::min({cap_slabs, rows, std::max(by_rows, by_bytes)}))
                         : 1;
