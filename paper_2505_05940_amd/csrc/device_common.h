@@ -100,48 +100,78 @@ __device__ __forceinline__ float dot4(float4 a, float4 b) {
 }
 __device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+// Raw buffer resource over `bytes` bytes at p (stride 0).  Loads at byte
+// offsets >= bytes are out of range and return zeros without a memory
+// access; the last word is the standard gfx9 raw-buffer format word.  The
+// callers' values are wave-uniform; readfirstlane states it so that the
+// resource lives in scalar registers.
+typedef int v4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4i buf_rsrc(const float* p, int bytes) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+  v4i r;
+  r.x = __builtin_amdgcn_readfirstlane((int)(unsigned)a);
+  r.y = __builtin_amdgcn_readfirstlane((int)((a >> 32) & 0xffffu));
+  r.z = __builtin_amdgcn_readfirstlane(bytes);
+  r.w = 0x00020000;
+  return r;
+}
+// The LLVM raw buffer load intrinsic, declared directly.
+__device__ v4f llvm_raw_buffer_load_v4f32(v4i rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v4f32");
 // The partial forces that the slabs of a split instance exchange in global
-// memory are written and read as agent-scope relaxed atomics, which gfx950
-// carries out coherently across the XCDs' separate L2 caches (the sc1 cache
-// policy).  Publishing a partial then needs only a wait for its stores to
-// complete before the arrival word is stored, and reading one needs no L2
-// invalidation: an agent-scope release or acquire fence would write back or
-// invalidate the whole L2 of the XCD on every step.
-__device__ __forceinline__ void st4_agent(float* p, float4 v) {
-  __hip_atomic_store(p, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(p + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(p + 2, v.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(p + 3, v.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// memory are written and read with the sc1 cache policy, which gfx950 keeps
+// coherent across the XCDs' separate L2 caches: the policy of an agent-scope
+// relaxed atomic access, here on 16-byte buffer accesses instead of four
+// separate 4-byte atomics.  Publishing a partial then needs only a wait for
+// its stores to complete before the arrival word (an agent-scope atomic) is
+// stored, and reading one needs no L2 invalidation: an agent-scope release or
+// acquire fence would write back or invalidate the whole L2 of the XCD on
+// every step.  The resource spans one instance's exchange region (offsets
+// past it read zeros and drop stores); byte offsets per lane.
+constexpr int kCoherentPolicy = 16;  // sc1 bit of the buffer instructions' cache-policy operand
+__device__ void llvm_raw_buffer_store_v4f32(v4f v, v4i rsrc, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.raw.buffer.store.v4f32");
+__device__ __forceinline__ void st4_coherent(v4i r, int byte_off, float4 v) {
+  v4f w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  llvm_raw_buffer_store_v4f32(w, r, byte_off, 0, kCoherentPolicy);
 }
-__device__ __forceinline__ float4 ld4_agent(const float* q) {
-  float* p = const_cast<float*>(q);
-  return make_float4(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                     __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                     __hip_atomic_load(p + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                     __hip_atomic_load(p + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+__device__ __forceinline__ float4 ld4_coherent(v4i r, int byte_off) {
+  const v4f v = llvm_raw_buffer_load_v4f32(r, byte_off, 0, kCoherentPolicy);
+  return make_float4(v.x, v.y, v.z, v.w);
 }
-// After a wave's partial-force stores (st4_agent): waits until they are
-// complete, so that an arrival word stored afterwards cannot be seen before
-// them.  Before reading partials (ld4_agent) once the words have been seen:
-// keeps the reads after the words' loads.  Both at workgroup scope, which
-// costs a wait on the wave's memory counters and no cache maintenance.
-__device__ __forceinline__ void publish_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup"); }
+// After a wave's partial-force stores (st4_coherent): waits until the memory
+// system has acknowledged them, so that an arrival word stored afterwards
+// cannot be seen before them.  A workgroup-scope release fence emits no such
+// wait when a workgroup's waves share one CU, and an agent-scope one would
+// also write back the XCD's whole L2; the wait on the vector-memory counter
+// alone is what the exchange needs.  It is also a compiler barrier.
+__device__ __forceinline__ void publish_fence() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Before reading partials (ld4_coherent) once the words have been seen:
+// keeps the compiler from moving the reads above the words' loads (the
+// hardware issues them after the polling loop, whose exit depends on the
+// words' values).
 __device__ __forceinline__ void consume_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup"); }
 
-// sum over t = t0, t0 + dt, ... (t < n) of the float4 at p + t * stride
-// (partial forces of other workgroups, read as agent-scope atomics), eight
-// reads issued before the first add
-__device__ __forceinline__ float4 sum_slabs4_agent(const float* p, int t0, int dt, int n, long long stride) {
+// sum over t = t0, t0 + dt, ... (t < n) of the float4 at byte offset
+// off + t * stride of resource r (partial forces of other workgroups, read
+// coherently), eight reads issued before the first add (sixteen measured
+// slower); a fixed order, so every caller gets the same bits
+__device__ __forceinline__ float4 sum_slabs4_coherent(v4i r, int off, int t0, int dt, int n, int stride) {
   float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
   int t = t0;
   for (; t + 7 * dt < n; t += 8 * dt) {
     float4 a[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) a[i] = ld4_agent(p + (long long)(t + i * dt) * stride);
+    for (int i = 0; i < 8; ++i) a[i] = ld4_coherent(r, off + (t + i * dt) * stride);
 #pragma unroll
     for (int i = 0; i < 8; ++i) s = add4(s, a[i]);
   }
-  for (; t < n; t += dt) s = add4(s, ld4_agent(p + (long long)t * stride));
+  for (; t < n; t += dt) s = add4(s, ld4_coherent(r, off + t * stride));
   return s;
 }
 
@@ -191,7 +221,6 @@ __device__ __forceinline__ float sum_run(const float* p, int n) {
   for (; c < n; ++c) s0 += p[c];
   return (s0 + s1) + (s2 + s3);
 }
-typedef float v4f __attribute__((ext_vector_type(4)));
 // streaming 16-byte load with the non-temporal hint (read once per step)
 __device__ __forceinline__ float4 ldnt4(const float* p) {
   const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
@@ -199,24 +228,6 @@ __device__ __forceinline__ float4 ldnt4(const float* p) {
 }
 __device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
 
-// Raw buffer resource over `bytes` bytes at p (stride 0).  Loads at byte
-// offsets >= bytes are out of range and return zeros without a memory
-// access; the last word is the standard gfx9 raw-buffer format word.  The
-// callers' values are wave-uniform; readfirstlane states it so that the
-// resource lives in scalar registers.
-typedef int v4i __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ v4i buf_rsrc(const float* p, int bytes) {
-  const unsigned long long a = reinterpret_cast<unsigned long long>(p);
-  v4i r;
-  r.x = __builtin_amdgcn_readfirstlane((int)(unsigned)a);
-  r.y = __builtin_amdgcn_readfirstlane((int)((a >> 32) & 0xffffu));
-  r.z = __builtin_amdgcn_readfirstlane(bytes);
-  r.w = 0x00020000;
-  return r;
-}
-// The LLVM raw buffer load intrinsic, declared directly.
-__device__ v4f llvm_raw_buffer_load_v4f32(v4i rsrc, int voffset, int soffset, int aux)
-    __asm("llvm.amdgcn.raw.buffer.load.v4f32");
 // 16-byte streaming load through a buffer resource, non-temporal hint.
 __device__ __forceinline__ float4 buf_ld4(v4i r, int voff) {
   const v4f v = llvm_raw_buffer_load_v4f32(r, voff, 0, 2);

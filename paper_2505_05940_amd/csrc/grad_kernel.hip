@@ -599,13 +599,15 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
         if (I.nslab == 1) {
           adj_post<GM>(P, I, U, n, Ju, Fa, G, lane);
         } else {
-          float* dst = P.part + 2 * I.part_off + ((long long)(rstep & 1) * I.nslab + U.slab) * 2 * I.ntp;
+          // this instance's exchange region: [2][nslab][2 ntp] floats
+          const v4i pr = buf_rsrc(P.part + 2 * I.part_off, 16 * I.nslab * I.ntp);
+          const int dst = 8 * ((int)(rstep & 1) * I.nslab + U.slab) * I.ntp;
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
             const int k4 = lane + kWave * g;
             if (g < G && k4 < nc) {
-              st4_agent(dst + 4 * k4, Ju[g]);
-              st4_agent(dst + I.ntp + 4 * k4, Fa[g]);
+              st4_coherent(pr, dst + 16 * k4, Ju[g]);
+              st4_coherent(pr, dst + 4 * I.ntp + 16 * k4, Fa[g]);
             }
           }
           publish_fence();
@@ -629,7 +631,8 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
       if (L.flag[0] == 0) return;  // every wave leaves together
       const int nc = I.ntp >> 2;
       const int G = (nc + kWave - 1) / kWave;
-      const float* src = P.part + 2 * I.part_off + (long long)(rstep & 1) * I.nslab * 2 * I.ntp;
+      const v4i pr = buf_rsrc(P.part + 2 * I.part_off, 16 * I.nslab * I.ntp);
+      const int src = 8 * (int)(rstep & 1) * I.nslab * I.ntp;  // byte offset of this step's partials
       if (SPLIT && NW > 1 && I.nslab >= 2 * NW) {
         // many slabs: every wave sums every NW-th partial, wave 0 adds the
         // waves' sums
@@ -640,8 +643,8 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
           Ju[g] = F[g] = f4(0.f);
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc) {
-            Ju[g] = sum_slabs4_agent(src + 4 * k4, wave, NW, I.nslab, 2LL * I.ntp);
-            F[g] = sum_slabs4_agent(src + I.ntp + 4 * k4, wave, NW, I.nslab, 2LL * I.ntp);
+            Ju[g] = sum_slabs4_coherent(pr, src + 16 * k4, wave, NW, I.nslab, 8 * I.ntp);
+            F[g] = sum_slabs4_coherent(pr, src + 4 * I.ntp + 16 * k4, wave, NW, I.nslab, 8 * I.ntp);
             st4(red + 4 * k4, Ju[g]);
             st4(red + I.ntp + 4 * k4, F[g]);
           }
@@ -669,8 +672,8 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc)
             for (int t = 0; t < I.nslab; ++t) {
-              Ju[g] = add4(Ju[g], ld4_agent(src + (long long)t * 2 * I.ntp + 4 * k4));
-              F[g] = add4(F[g], ld4_agent(src + (long long)t * 2 * I.ntp + I.ntp + 4 * k4));
+              Ju[g] = add4(Ju[g], ld4_coherent(pr, src + 8 * t * I.ntp + 16 * k4));
+              F[g] = add4(F[g], ld4_coherent(pr, src + 8 * t * I.ntp + 4 * I.ntp + 16 * k4));
             }
         }
         adj_post<GM>(P, I, U, n, Ju, F, G, lane);

@@ -711,11 +711,13 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
         if (I.nslab == 1) {
           update_groups<GM>(M, nc, e, Fa, G, lane, P.flags);
         } else {
-          float* dst = P.part + I.part_off + ((long long)(n & 1) * I.nslab + U.slab) * I.ntp;
+          // this instance's exchange region: [2][nslab][ntp] floats
+          const v4i pr = buf_rsrc(P.part + I.part_off, 8 * I.nslab * I.ntp);
+          const int dst = 4 * ((int)(n & 1) * I.nslab + U.slab) * I.ntp;
 #pragma unroll
           for (int g = 0; g < GM; ++g) {
             const int k4 = lane + kWave * g;
-            if (g < G && k4 < nc) st4_agent(dst + 4 * k4, Fa[g]);
+            if (g < G && k4 < nc) st4_coherent(pr, dst + 16 * k4, Fa[g]);
           }
           publish_fence();
           __builtin_amdgcn_wave_barrier();
@@ -742,7 +744,8 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
       }
       const int nc = I.ntp >> 2;
       const int G = (nc + kWave - 1) / kWave;
-      const float* src = P.part + I.part_off + (long long)(n & 1) * I.nslab * I.ntp;
+      const v4i pr = buf_rsrc(P.part + I.part_off, 8 * I.nslab * I.ntp);
+      const int src = 4 * (int)(n & 1) * I.nslab * I.ntp;  // byte offset of this step's partials
       if (RES && NW > 1 && I.nslab >= 2 * NW) {
         // one unit per workgroup and many slabs: every wave sums every NW-th
         // partial force, and wave 0 adds the waves' sums
@@ -753,7 +756,7 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
           F[g] = f4(0.f);
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc) {
-            F[g] = sum_slabs4_agent(src + 4 * k4, wave, NW, I.nslab, I.ntp);
+            F[g] = sum_slabs4_coherent(pr, src + 16 * k4, wave, NW, I.nslab, 4 * I.ntp);
             st4(red + 4 * k4, F[g]);
           }
         }
@@ -782,7 +785,7 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
           const int k4 = lane + kWave * g;
           if (g < G && k4 < nc)
             for (int t = 0; t < I.nslab; ++t)
-              F[g] = add4(F[g], ld4_agent(src + (long long)t * I.ntp + 4 * k4));
+              F[g] = add4(F[g], ld4_coherent(pr, src + 4 * t * I.ntp + 16 * k4));
         }
         update_groups<GM>(M, nc, e, F, G, lane, P.flags);
       }
