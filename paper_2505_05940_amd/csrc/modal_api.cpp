@@ -427,12 +427,17 @@ constexpr int kLatencyMaxSplitBatch = 16;  // larger latency-bound batches keep 
 // A large instance of such a batch is also cut so that no slab streams more
 // than about this many tensor bytes per step (the waves of a one-unit
 // workgroup share its row blocks, so slabs of fewer rows than waves keep
-// every wave busy).  Measured on lone sine plates with the partial forces
-// exchanged as agent-scope atomics: forward, 256 KB slabs step a 100/100
-// plate in 9.0 us (16 slabs) against 11.4 us at 128 KB (31) and 10.2 us at
-// 512 KB before that exchange; the 200/200 gradient over 1 s takes 2.17 s at
-// 256 KB (123 slabs), 2.30 s at 512 KB and 2.42 s at 128 KB.
+// every wave busy); half as many for a tensor larger than kLatencyBigTensor,
+// which no longer stays in the XCDs' L2 caches, so that more CUs stream it
+// from the last-level cache.  Measured on lone sine plates with the partial
+// forces exchanged as 16-byte coherent accesses: a 100/100 plate (4 MB)
+// steps in 9.0 us with 256 KB slabs (16) against 11.5 us at 128 KB (31) and
+// 11.7 us at 384 KB (13); a 200/200 plate (32 MB) steps forward in 14.1 us
+// with 128 KB slabs (one in-plane row each, 200) against 16.9 us at 256 KB
+// (123) and 21.2 us at 512 KB (62), its forward and reverse step together in
+// 32.8 us against 38.4 and 47.0 us.
 constexpr double kLatencySlabBytes = 256.0 * 1024.0;
+constexpr double kLatencyBigTensor = 16.0 * 1048576.0;
 
 // Per-step cost of the exchange and barrier of one slab of a split instance,
 // in streamed-byte units (release fence, arrival, wait, acquire and reading
@@ -1676,7 +1681,8 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
       const int rows = inst[b].kind == KIND_VK ? inst[b].nin : 1;
       const double bytes = inst[b].kind == KIND_VK ? 4.0 * inst[b].nin * (double)inst[b].nt * inst[b].nt : 0.0;
       const int by_rows = (rows + kLatencyRows / 2) / kLatencyRows;
-      const int by_bytes = (int)std::ceil(bytes / kLatencySlabBytes);
+      const double slab_bytes = bytes > kLatencyBigTensor ? 0.5 * kLatencySlabBytes : kLatencySlabBytes;
+      const int by_bytes = (int)std::ceil(bytes / slab_bytes);
       const int S = inst[b].kind == KIND_VK && !chip_nt
                         ? std::max(1, std::min({cap_slabs, rows, std::max(by_rows, by_bytes)}))
                         : 1;
