@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(kWave * kChipWaves) chip_kernel(StepParams P) 
   __shared__ float red[kChipWaves][kWave];  // per-wave partial forces
   float* Xc = reinterpret_cast<float*>(xc4);
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const UnitDev U = P.unit[P.wg_begin[blockIdx.x]];
   const InstDev I = P.inst[U.inst];
   const ChipMap& M = P.chip[U.inst];

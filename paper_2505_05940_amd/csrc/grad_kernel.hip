@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
   float* Xs = L.xs;
   float* Us = L.us;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   float* red = L.red + wave * P.red_floats;
   const int u0 = P.wg_begin[blockIdx.x];
   const int u1 = P.wg_begin[blockIdx.x + 1];

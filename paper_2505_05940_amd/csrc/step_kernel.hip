@@ -518,7 +518,9 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
   StepLds L = step_lds(reinterpret_cast<float*>(lds4), NW, P.red_floats);
   float* Xs = L.xs;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  // wave-uniform by construction; readfirstlane tells the compiler, so that
+  // the row ranges and the block walks derived from it stay in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   float* red = L.red + wave * P.red_floats;
   const int u0 = P.wg_begin[blockIdx.x];
   const int u1 = P.wg_begin[blockIdx.x + 1];
