@@ -1579,9 +1579,9 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
         c->padded_bytes += 4 * f;
         c->n_blocked++;
         choose_sweep(plans[b].rmax, D.w / 4, qs_of[b], J_of[b]);
-        // reduction double buffer (two pieces' slot layouts), per-slot row dot
+        // reduction buffer (one piece's slot layout), per-slot row dot
         // partials, row-dot vector
-        red_floats = std::max(red_floats, 2 * 4 * kSweepLoads * kWave + kSweepLoads * kWave + D.ntp);
+        red_floats = std::max(red_floats, 4 * kSweepLoads * kWave + kSweepLoads * kWave + D.ntp);
       } else {
         const long long f = (long long)D.nin * D.nt * D.ntp;
         h_floats += (f + 63) & ~63LL;  // 256-byte aligned instances

@@ -322,7 +322,9 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
 #pragma unroll
   for (int i = 0; i < 5; ++i) cb[i] = I.cls[i];
   auto co = [&](int i) { return cb[i]; };
-  float* rd = red + 2 * kSlotFloats;  // [kSweepLoads * 64] per-slot row dot partials
+  // one piece's slot layout for the class-end reductions (a wave's LDS
+  // operations complete in order, so one buffer serves them all)
+  float* rd = red + kSlotFloats;  // [kSweepLoads * 64] per-slot row dot partials
   float* vrow = rd + J * kWave;       // [ntp] row-dot part of V for the current row
   for (int k = lane; k < ntp; k += kWave) vrow[k] = 0.f;
   // loader position: row ln, class li, piece lb; jv, jo = map entries and
@@ -389,7 +391,6 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
   for (int j = 0; j < J; ++j) acc[j] = f4(0.f);
 #pragma unroll
   for (int g = 0; g < GM; ++g) V[g] = f4(0.f);
-  int par = 0;
   // consumes block `hc` after issuing the loads of the next block into `hn`
   auto step = [&](float4 (&hc)[J], const BlkMeta& mc, float4 (&hn)[J], BlkMeta& mn) -> bool {
     load(hn, mn);
@@ -414,8 +415,7 @@ __device__ void vk_rows_blk(const float* __restrict__ Hb, const int4* __restrict
     }
     if (mc.flags & 1) {
       // block row of class i done: reduce over sub-rows onto the target modes
-      float* rb = red + (par & 1) * kSlotFloats;
-      ++par;
+      float* rb = red;
       const int wj = 4 * mc.tlen;
 #pragma unroll
       for (int j = 0; j < J; ++j) {
