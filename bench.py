@@ -458,17 +458,18 @@ def main():
         from paper_2505_05940_amd import tune
         t0 = time.time()
         tune_cache = tune.CACHE
-        waves_t, mw_t = tune.autotune(insts, 44100.0, cache=tune_cache,
-                                      log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
-        print(f"[bench] autotuned waves={waves_t} max_workgroups={mw_t} in {time.time() - t0:.1f} s "
-              f"(cache {tune_cache})", file=sys.stderr, flush=True)
+        waves_t, mw_t, sk_t = tune.autotune(insts, 44100.0, cache=tune_cache,
+                                            log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        print(f"[bench] autotuned waves={waves_t} max_workgroups={mw_t} split_cost_kb={sk_t} in "
+              f"{time.time() - t0:.1f} s (cache {tune_cache})", file=sys.stderr, flush=True)
     t0 = time.time()
     sim = modal.Sim(insts, 44100.0, flags=modal.FLAG_GRAPH | modal.FLAG_ASYNC,
                     chunk_steps=S, max_workgroups=mw, waves=waves, tune_cache=tune_cache)
     info = sim.info()
     del insts
-    if args.autotune:  # the shape modal_init took from the cache
-        waves, mw = waves_t, mw_t
+    split_kb = 0
+    if args.autotune:  # the shape and exchange cost modal_init took from the cache
+        waves, mw, split_kb = waves_t, mw_t, sk_t
     print(f"[bench] modal_init {time.time() - t0:.1f} s, plan {info}", file=sys.stderr, flush=True)
     modes = int(sum(w["n_t"] for w in wls))
     y = torch.empty((args.batch, S), device="cuda")
@@ -516,7 +517,7 @@ def main():
             "batch": args.batch, "modes_total": modes, "samples_per_step": S,
             "coupling_bytes_per_sample": info["coupling_bytes_per_step"],
             "workgroups": info["workgroups"], "split_instances": info["split_instances"],
-            "max_workgroups": mw, "waves_per_workgroup": waves or 4,
+            "max_workgroups": mw, "waves_per_workgroup": waves or 4, "split_cost_kb": split_kb or 32,
             "fit_wall_time_s": None,
         },
         "roofline": {

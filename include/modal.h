@@ -140,7 +140,15 @@ typedef struct {
                                    waves and max_workgroups 0, a batch whose
                                    key (modal_tune_key) is listed takes that
                                    launch shape; a missing file or key
-                                   leaves the defaults.  NULL = none.       */
+                                   leaves the defaults.  NULL = none.  An
+                                   entry's optional "split_cost_kb" applies
+                                   when split_cost_kb below is 0.           */
+  int32_t split_cost_kb;        /* the per-step cost the planner charges each
+                                   slab of a split instance for its exchange,
+                                   in KiB of streamed tensor (0 = default, 32;
+                                   at most 2^20).  It shifts which instances
+                                   are cut and how units are packed; the
+                                   autotuner searches it.                    */
 } modal_desc;
 
 /* Validates the description (before any device work), computes the per-mode

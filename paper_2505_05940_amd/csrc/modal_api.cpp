@@ -353,8 +353,8 @@ int validate(const modal_desc* d) {
   if (d->scheme != MODAL_SCHEME_SV && d->scheme != MODAL_SCHEME_TF)
     return fail(MODAL_EINVAL, "unknown scheme");
   if ((d->waves != 0 && d->waves != 1 && d->waves != 4 && d->waves != 8) || d->max_workgroups < 0 ||
-      d->chunk_steps < 0 || d->barrier_us < 0)
-    return fail(MODAL_EINVAL, "waves (0, 1, 4 or 8), max_workgroups, chunk_steps or barrier_us");
+      d->chunk_steps < 0 || d->barrier_us < 0 || d->split_cost_kb < 0 || d->split_cost_kb > (1 << 20))
+    return fail(MODAL_EINVAL, "waves (0, 1, 4 or 8), max_workgroups, chunk_steps, barrier_us or split_cost_kb");
   const double T = 1.0 / d->fs;
   for (int b = 0; b < d->batch; ++b) {
     const modal_instance& I = d->inst[b];
@@ -440,9 +440,17 @@ constexpr double kLatencySlabBytes = 256.0 * 1024.0;
 constexpr double kLatencyBigTensor = 16.0 * 1048576.0;
 
 // Per-step cost of the exchange and barrier of one slab of a split instance,
-// in streamed-byte units (release fence, arrival, wait, acquire and reading
-// every slab's partial force: microseconds of one wave's streaming time).
-constexpr double kSplitSyncCost = 65536.0;
+// in streamed-byte units (publishing its partial force, arrival, wait and
+// reading every slab's partial).  It steers the packing rather than
+// predicting time: on the 256-plate batch, with the exchange as 16-byte
+// coherent accesses, 0, 8, 16, 24, 32, 48, 64, 128 and 256 KB gave 231.8,
+// 234.7, 235.8, 232.6, 232.9, 240.2, 241.9, 236.7 and 238.1 ms per
+// 441-sample launch (runs of one setting differ by about 1 %).
+constexpr double kSplitSyncCost = 32768.0;
+// the cost a description asks for (its autotuned value), else the default
+double split_cost(const modal_desc* d) {
+  return d->split_cost_kb > 0 ? 1024.0 * d->split_cost_kb : kSplitSyncCost;
+}
 // Instances below this cost are never split: their tensors stay L2-resident
 // from step to step and a whole-instance workgroup outruns any slab barrier.
 constexpr double kMinSplitCost = 4.0 * 1048576.0;
@@ -728,7 +736,7 @@ int pack(const modal_desc* d, const std::vector<double>& row_cost,
     const double whole = fixed_cost[b] + rows * row_cost[b];
     const bool may_split = (d->flags & MODAL_FLAG_SPLIT_ANY) || whole >= kMinSplitCost;
     if (I.kind == MODAL_KIND_VK && whole > cap && may_split) {
-      const double sync = (d->flags & MODAL_FLAG_SPLIT_ANY) ? 0.0 : kSplitSyncCost;
+      const double sync = (d->flags & MODAL_FLAG_SPLIT_ANY) ? 0.0 : split_cost(d);
       const int per = (int)std::floor((cap - sync - fixed_cost[b]) / row_cost[b]);
       if (per < 1) return n_bins + 1;
       S = (rows + per - 1) / per;
@@ -736,7 +744,7 @@ int pack(const modal_desc* d, const std::vector<double>& row_cost,
     if (S > n_bins) return n_bins + 1;
     for (int s = 0; s < S; ++s) {
       const int r0 = (int)((long long)rows * s / S), r1 = (int)((long long)rows * (s + 1) / S);
-      const double sync = S > 1 && !(d->flags & MODAL_FLAG_SPLIT_ANY) ? kSplitSyncCost : 0.0;
+      const double sync = S > 1 && !(d->flags & MODAL_FLAG_SPLIT_ANY) ? split_cost(d) : 0.0;
       units.push_back({b, r0, r1, s, sync + fixed_cost[b] + (r1 - r0) * row_cost[b]});
     }
   }
@@ -777,7 +785,7 @@ bool plan_batch(const modal_desc* d, const std::vector<double>& row_cost,
   double max_item = 0;
   for (int b = 0; b < d->batch; ++b) {
     const double whole = fixed_cost[b] + (d->inst[b].kind == MODAL_KIND_VK ? d->inst[b].n_in : 1) * row_cost[b];
-    const double one_row = ((d->flags & MODAL_FLAG_SPLIT_ANY) ? 0.0 : kSplitSyncCost) + fixed_cost[b] +
+    const double one_row = ((d->flags & MODAL_FLAG_SPLIT_ANY) ? 0.0 : split_cost(d)) + fixed_cost[b] +
                            (d->inst[b].kind == MODAL_KIND_VK ? row_cost[b] : 0.0);
     const bool may_split = (d->flags & MODAL_FLAG_SPLIT_ANY) || whole >= kMinSplitCost;
     max_item = std::max(max_item, may_split ? std::min(whole, one_row) : whole);
@@ -1392,7 +1400,7 @@ bool json_int(const std::string& text, size_t from, size_t to, const char* name,
 }
 
 // Launch shape for `d` from the autotuner's cache, if listed.
-bool tuned_shape(const modal_desc* d, int& waves, int& max_wg) {
+bool tuned_shape(const modal_desc* d, int& waves, int& max_wg, int& split_kb) {
   FILE* fp = std::fopen(d->tune_cache, "rb");
   if (!fp) return false;
   std::string text;
@@ -1410,6 +1418,8 @@ bool tuned_shape(const modal_desc* d, int& waves, int& max_wg) {
   if ((w != 1 && w != 4 && w != 8) || m < 1) return false;
   waves = w;
   max_wg = m;
+  int sk = 0;  // optional: the planner's per-slab exchange cost
+  if (json_int(text, k, end, "split_cost_kb", sk) && sk > 0 && sk <= (1 << 20) && split_kb == 0) split_kb = sk;
   return true;
 }
 
@@ -1435,7 +1445,7 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
   // the autotuner's launch shape for this batch, if cached
   modal_desc tuned = *d_in;
   if (d_in->tune_cache && d_in->waves == 0 && d_in->max_workgroups == 0)
-    (void)tuned_shape(d_in, tuned.waves, tuned.max_workgroups);
+    (void)tuned_shape(d_in, tuned.waves, tuned.max_workgroups, tuned.split_cost_kb);
   const modal_desc* d = &tuned;
   hipStream_t stream = (hipStream_t)stream_;
   const double T = 1.0 / d->fs;
@@ -1688,7 +1698,7 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
                         : 1;
       for (int sl = 0; sl < S; ++sl) {
         const int r0 = (int)((long long)rows * sl / S), r1 = (int)((long long)rows * (sl + 1) / S);
-        const double cost = (S > 1 ? kSplitSyncCost : 0.0) + fixed_cost[b] + (r1 - r0) * row_cost[b];
+        const double cost = (S > 1 ? split_cost(d) : 0.0) + fixed_cost[b] + (r1 - r0) * row_cost[b];
         units.push_back({b, r0, r1, sl, cost});
         bin_of.push_back((int)load.size());
         load.push_back(cost);

@@ -46,7 +46,7 @@ class modal_desc(C.Structure):
                 ("inst", C.POINTER(modal_instance)), ("fs", C.c_double),
                 ("flags", C.c_int32), ("max_workgroups", C.c_int32),
                 ("chunk_steps", C.c_int32), ("waves", C.c_int32), ("barrier_us", C.c_int32),
-                ("tune_cache", C.c_char_p)]
+                ("tune_cache", C.c_char_p), ("split_cost_kb", C.c_int32)]
 
 
 class ModalError(RuntimeError):
@@ -133,7 +133,7 @@ def vk_coupling_sine(Lx, Ly, m, q, a, b, scale_n, grid=None, threads=0):
 
 
 def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_steps=0,
-                shapes_only=False, waves=0, barrier_us=0, tune_cache=None):
+                shapes_only=False, waves=0, barrier_us=0, tune_cache=None, split_cost_kb=0):
     """modal_desc for a list of instance dicts; returns (desc, keep-alive list, n_t list).
     With shapes_only (planning previews, which never read tensors) a vk
     instance may give "n_in" instead of "Ht"."""
@@ -198,7 +198,7 @@ def _build_desc(instances, fs, scheme="sv", flags=0, max_workgroups=0, chunk_ste
     keep.append(tc)
     desc = modal_desc(batch=batch, scheme=SCHEME[scheme], inst=arr, fs=float(fs), flags=flags,
                       max_workgroups=max_workgroups, chunk_steps=chunk_steps, waves=waves,
-                      barrier_us=barrier_us, tune_cache=tc)
+                      barrier_us=barrier_us, tune_cache=tc, split_cost_kb=split_cost_kb)
     return desc, keep, n_t
 
 
@@ -210,9 +210,10 @@ def tune_key(instances, fs=44100.0, scheme="sv", flags=0):
     return out.value.decode()
 
 
-def plan(instances, n_workgroups, fs=44100.0, scheme="sv", flags=0):
+def plan(instances, n_workgroups, fs=44100.0, scheme="sv", flags=0, split_cost_kb=0):
     """Host-only preview of the work partition (``modal_plan``)."""
-    desc, keep, _ = _build_desc(instances, fs, scheme, flags=flags, shapes_only=True)
+    desc, keep, _ = _build_desc(instances, fs, scheme, flags=flags, shapes_only=True,
+                                split_cost_kb=split_cost_kb)
     out = (C.c_int64 * 4)()
     _check(lib.modal_plan(C.byref(desc), n_workgroups, out))
     return dict(units=out[0], workgroups=out[1], makespan=out[2], mean=out[3])
@@ -231,11 +232,12 @@ class Sim:
     """
 
     def __init__(self, instances, fs, scheme="sv", flags=0, max_workgroups=0,
-                 chunk_steps=0, stream=None, waves=0, barrier_us=0, tune_cache=None):
+                 chunk_steps=0, stream=None, waves=0, barrier_us=0, tune_cache=None, split_cost_kb=0):
         self._ctx = C.c_void_p()
         self.batch = len(instances)
         desc, keep, self.n_t = _build_desc(instances, fs, scheme, flags, max_workgroups, chunk_steps,
-                                           waves=waves, barrier_us=barrier_us, tune_cache=tune_cache)
+                                           waves=waves, barrier_us=barrier_us, tune_cache=tune_cache,
+                                           split_cost_kb=split_cost_kb)
         self._stream = stream
         _check(lib.modal_init(C.byref(self._ctx), C.byref(desc), _stream_handle(stream)))
         self.modes_total = sum(self.n_t)

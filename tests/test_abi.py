@@ -103,3 +103,23 @@ def test_plan_splits_only_when_needed():
     assert modal.plan([inst(120)], 1)["units"] == 1
     p = modal.plan([inst(120)], 8)
     assert p["units"] == 8 and p["workgroups"] == 8
+
+
+def test_split_cost_steers_the_plan():
+    """The per-slab exchange cost the planner charges (modal_desc.split_cost_kb,
+    the autotuner's knob): 0 is the default (32 KiB); another cost gives
+    another partition, and a dearer one a costlier heaviest workgroup (its
+    slabs carry the cost); a negative one is rejected."""
+    import workloads as W
+    from paper_2505_05940_amd import modal
+    wls = W.plate_batch()
+    insts = [dict(kind="vk", omega=np.full(w["n_t"], 1e3), gamma=np.ones(w["n_t"]),
+                  x0=np.zeros(w["n_t"]), xm1=np.zeros(w["n_t"]), c=np.ones(w["n_t"]),
+                  n_in=w["n_in"]) for w in wls]
+    assert modal.plan(insts, 768) == modal.plan(insts, 768, split_cost_kb=32)
+    cheap = modal.plan(insts, 768, split_cost_kb=1)
+    dear = modal.plan(insts, 768, split_cost_kb=4096)
+    assert dear != cheap and dear["makespan"] > cheap["makespan"], (cheap, dear)
+    with pytest.raises(modal.ModalError) as e:
+        modal.plan(insts, 768, split_cost_kb=-1)
+    assert e.value.status == "EINVAL"

@@ -1,8 +1,8 @@
-"""The autotuner: it times candidate launch shapes on the actual batch and
-records the best under the batch's key; modal_init then reads that shape
-from the cache file.  The tuned context must equal a context given the same
-shape explicitly, bit for bit, and the FP64 oracle to 1e-5 relative L2 per
-output signal."""
+"""The autotuner: it times candidate launch shapes and the planner's
+per-slab exchange cost on the actual batch and records the best under the
+batch's key; modal_init then reads that plan from the cache file.  The
+tuned context must equal a context given the same plan explicitly, bit for
+bit, and the FP64 oracle to 1e-5 relative L2 per output signal."""
 import json
 import sys
 
@@ -32,17 +32,18 @@ def test_tuned_shape_from_the_cache_is_parity_green(tmp_path):
         wls.append(wl)
     insts = [physics.plate_instance(w) for w in wls]
     cache = str(tmp_path / "tune.json")
-    _say("case: autotune of 6 plates over 3 shapes, then a context from the cache")
-    w, mw = tune.autotune(insts, 44100.0, shapes=((4, 1), (1, 2), (4, 2)), samples=60, cache=cache,
-                          log=_say)
+    _say("case: autotune of 6 plates over 3 shapes and 3 exchange costs, then a context from the cache")
+    w, mw, sk = tune.autotune(insts, 44100.0, shapes=((4, 1), (1, 2), (4, 2)), samples=60, cache=cache,
+                              log=_say, split_costs=(1, 32, 1024))
     key = modal.tune_key(insts, 44100.0)
     entry = json.load(open(cache))[key]
-    assert (entry["waves"], entry["max_workgroups"]) == (w, mw)
-    assert tune.autotune(insts, 44100.0, cache=cache) == (w, mw)  # served from the cache
+    assert (entry["waves"], entry["max_workgroups"], entry["split_cost_kb"]) == (w, mw, sk)
+    assert tune.autotune(insts, 44100.0, cache=cache) == (w, mw, sk)  # served from the cache
     tuned = modal.Sim(insts, 44100.0, tune_cache=cache)
-    explicit = modal.Sim(insts, 44100.0, waves=w, max_workgroups=mw)
+    explicit = modal.Sim(insts, 44100.0, waves=w, max_workgroups=mw, split_cost_kb=sk)
     default = modal.Sim(insts, 44100.0, tune_cache=str(tmp_path / "absent.json"))
-    assert tuned.info()["workgroups"] == explicit.info()["workgroups"]
+    for k in ("workgroups", "units", "split_instances", "plan_makespan"):
+        assert tuned.info()[k] == explicit.info()[k], k
     yt = tuned.run(1500).double().cpu().numpy()
     ye = explicit.run(1500).double().cpu().numpy()
     yd = default.run(1500).double().cpu().numpy()
