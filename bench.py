@@ -231,9 +231,7 @@ def single_instance_rates():
     0.5 s) after a 441-step warm-up, HIP events on the launch stream, the
     real-time factor (audio seconds per wall second) and the plan the library
     chose (on-chip: one workgroup, tensor in registers; streaming: row slabs
-    on several workgroups); then the gradient of a
-    200/200-mode plate over 1 s (forward with checkpoints, recompute and
-    reverse sweep)."""
+    on several workgroups)."""
     import torch
     import workloads as W
     from paper_2505_05940_amd import modal, physics
@@ -261,27 +259,57 @@ def single_instance_rates():
                     "plan": {0: "streaming", 3: "on-chip"}.get(sim.info()["path"], "other"),
                     "workgroups": sim.info()["workgroups"]})
         sim.close()
-    return {"runs": out, "gradient_200_modes_1s_wall_s": gradient_200_wall()}
+    return {"runs": out}
 
 
-def gradient_200_wall():
-    """Wall time of the gradient of a 200/200-mode sine plate over 1 s
-    (forward with checkpoints and the trajectory record, reverse sweep), a
-    constant dL/dy, after a 441-step warm-up gradient."""
+def adjoint_200():
+    """The gradient of a 200/200-mode sine plate over 1 s (the fitting
+    configuration's shape), a constant dL/dy, after a 441-step warm-up
+    gradient: the wall time of one modal_grad from the initial state
+    (forward with checkpoints and the trajectory record, then the reverse
+    sweep), and apart, the forward pass (a recording modal_run) and the
+    reverse sweep that reuses its record, each bracketed by HIP events on
+    the stream the context launches on.  Roofline of the reverse sweep: its
+    algorithmic bytes are the dense tensor, 4 n_in n_t^2, streamed once per
+    step (two right-hand sides per row), against the HBM peak; the plate is
+    bound by each step's latency across 200 slab workgroups, not by bytes."""
     import torch
     import workloads as W
     from paper_2505_05940_amd import modal, physics
-    p200 = physics.plate_instance(W.plate_vk(n_t=200, family="sine", grid=None))
-    sim = modal.Sim([p200], 44100.0, flags=modal.FLAG_GRAD)
-    g = torch.full((1, 44100), 1e3, device="cuda")
+    n, steps = 200, 44100
+    p200 = physics.plate_instance(W.plate_vk(n_t=n, family="sine", grid=None))
+    stream = torch.cuda.current_stream()
+    sim = modal.Sim([p200], 44100.0, flags=modal.FLAG_GRAD, stream=stream)
+    g = torch.full((1, steps), 1e3, device="cuda")
+    y = torch.empty((1, steps), device="cuda")
     sim.grad(441, g[:, :441].contiguous())
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.grad(44100, g)
-    torch.cuda.synchronize()
-    grad_s = time.perf_counter() - t0
+
+    def timed(f):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        f()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+    sim.reset()
+    wall = timed(lambda: sim.grad(steps, g))
+    sim.reset()
+    fwd = timed(lambda: sim.run(steps, out=y))
+    rev = timed(lambda: sim.grad(steps, g))  # reuses the run's checkpoints and record
+    workgroups = sim.info()["workgroups"]
     sim.close()
-    return grad_s
+    tensor_bytes = 4.0 * n * n * n
+    achieved = tensor_bytes * steps / rev / 1e9
+    return {"workload": f"gradient of a {n}/{n}-mode sine von Karman plate over 1 s ({steps} steps) "
+                        "from the initial state, constant dL/dy",
+            "wall_s": wall, "forward_s": fwd, "reverse_s": rev, "workgroups": workgroups,
+            "forward_us_per_step": 1e6 * fwd / steps, "reverse_us_per_step": 1e6 * rev / steps,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "modal::grad_kernel (reverse sweep)",
+                         "algorithmic_bytes_per_step": tensor_bytes}}
 
 
 def mlp_training_rate(epochs, n=200000, batch=1024):
@@ -419,7 +447,8 @@ def main():
         import torch
         torch.cuda.set_device(0)
         if args.only == "gradient":
-            print(json.dumps({"gradient_200_modes_1s_wall_s": gradient_200_wall()}))
+            adj = adjoint_200()
+            print(json.dumps({"gradient_200_modes_1s_wall_s": adj["wall_s"], "adjoint": adj}))
         else:
             print(json.dumps({"mlp_training": mlp_training_rate(args.mlp_epochs)}))
         return
@@ -542,6 +571,11 @@ def main():
         print("[bench] single instances: " + ", ".join(
             f"{r['case']} {r['realtime_factor']:.1f}x" for r in out["single_instance"]["runs"]),
             file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_200()
+        out["single_instance"]["gradient_200_modes_1s_wall_s"] = out["adjoint"]["wall_s"]
+        print(f"[bench] adjoint: 200/200 gradient over 1 s in {out['adjoint']['wall_s']:.3f} s "
+              f"(forward {out['adjoint']['forward_s']:.3f} s, reverse {out['adjoint']['reverse_s']:.3f} s)",
+              file=sys.stderr, flush=True)
     if not args.no_tensor_fit:
         out["tensor_fit"] = tensor_fit_rate()
         print(f"[bench] tensor fit: {out['tensor_fit']['one_start']['seconds_per_iteration']:.3f} s per "

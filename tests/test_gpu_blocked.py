@@ -1,6 +1,6 @@
-"""Parity-blocked coupling tensors (sine in-plane plates stored one block
-per in-plane row and mode class) against the FP64 oracle, which always uses
-the dense tensor.  Bar: relative L2 error of each output signal <= 1e-5."""
+"""Parity-blocked coupling tensors (plates stored one block per in-plane row
+and mode class) against the FP64 oracle, which always uses the dense
+tensor.  Bar: relative L2 error of each output signal <= 1e-5."""
 import sys
 
 import numpy as np
@@ -70,6 +70,30 @@ def test_blocked_ragged_batch(gpu, ragged_refs, max_wg, waves):
                    flags=modal.FLAG_SPLIT_ANY | modal.FLAG_NO_BLOCK).run(3000).double().cpu().numpy()
     for b in range(len(insts)):
         assert rel_l2(yd[b], y[b]) < 2 * TOL
+
+
+def test_blocked_clamped_batch(gpu):
+    """Clamped in-plane plates, whose quadrature rounding the builder zeroes
+    by parity class, stream parity-blocked too; the oracle keeps its own
+    FP64 clamped tensors with that rounding in place."""
+    modal, physics = gpu
+    wls = []
+    for i, (nt, nin) in enumerate([(40, 40), (33, 20), (61, 45), (24, 24)]):
+        wl = W.plate_vk(seed=220 + i, n_t=nt, n_in=nin, family="clamped", n_steps=3000)
+        wl["strike"]["amplitude"] = 2e-3
+        wls.append(wl)
+    insts = [physics.plate_instance(w) for w in wls]
+    _say(f"case: blocked clamped batch of {len(insts)}, 3000 steps")
+    sim = modal.Sim(insts, 44100.0, max_workgroups=6, waves=4, flags=modal.FLAG_SPLIT_ANY)
+    info = sim.info()
+    assert info["blocked_instances"] == len(insts), info
+    assert info["split_instances"] >= 1
+    y = sim.run(3000).double().cpu().numpy()
+    for b, wl in enumerate(wls):
+        ref = OS.run(OI.plate_instance(wl), 3000, wl["fs"])
+        e = rel_l2(y[b], ref)
+        _say(f"  {wl['n_t']}/{wl['n_in']}: rel L2 {e:.2e}")
+        assert e < TOL, (b, e)
 
 
 def test_blocked_state_and_resume(gpu):

@@ -38,7 +38,8 @@ def gpu():
 
 
 def test_c2_plate_full_second_on_chip(gpu):
-    """The 40/40 clamped-family plate (the latency configuration) over 1 s."""
+    """The 40/40 clamped-family plate (the latency configuration) over 1 s,
+    its modes grouped by parity class like a sine-family plate's."""
     modal, physics = gpu
     wl = W.plate_vk()
     _say("case: on-chip 40/40 clamped plate, 44100 steps")
@@ -77,16 +78,16 @@ def _mixed():
     """Ragged small instances of every kind: sine-family vK plates (modes
     grouped by class) whose mode counts are and are not multiples of 4 and
     whose in-plane rows fill one to five rows per wave, a clamped-family
-    plate (held whole), a tension-modulated string, and a forced linear
-    system."""
+    plate given without its classes (held whole), a tension-modulated string,
+    and a forced linear system."""
     out = []
     for i, (nt, nin) in enumerate([(3, 2), (10, 10), (17, 9), (33, 33), (40, 40), (24, 31)]):
         wl = W.plate_vk(seed=300 + i, n_t=nt, n_in=nin, family="sine", grid=None, n_steps=6000)
         wl["strike"]["amplitude"] = 2e-3
         out.append(("plate", wl))
-    wl = W.plate_vk(seed=299, n_t=16, n_steps=6000)  # clamped family: no classes, held whole
+    wl = W.plate_vk(seed=299, n_t=16, n_steps=6000)  # clamped family, its classes withheld: held whole
     wl["strike"]["amplitude"] = 2e-3
-    out.append(("plate", wl))
+    out.append(("plate_whole", wl))
     out.append(("string", W.string_kc(n_steps=6000)))
     rng = np.random.default_rng(12)
     n = 13
@@ -100,13 +101,17 @@ def _mixed():
 def _product(physics, kind, wl):
     if kind == "plate":
         return physics.plate_instance(wl)
+    if kind == "plate_whole":
+        inst = physics.plate_instance(wl)
+        inst.pop("mode_class", None)
+        return inst
     if kind == "string":
         return physics.string_instance(wl)
     return wl
 
 
 def _oracle(kind, wl, steps):
-    if kind == "plate":
+    if kind in ("plate", "plate_whole"):
         return OS.run(OI.plate_instance(wl), steps, wl["fs"])
     if kind == "string":
         return OS.run(OI.string_instance(wl), steps, wl["fs"])
@@ -124,7 +129,7 @@ def test_mixed_batch_on_chip(gpu, scheme):
     y = sim.run(steps).double().cpu().numpy()
     for b, (kind, wl) in enumerate(cases):
         ref = (_oracle(kind, wl, steps) if scheme == "sv" else
-               OS.run(OI.plate_instance(wl) if kind == "plate" else
+               OS.run(OI.plate_instance(wl) if kind in ("plate", "plate_whole") else
                       OI.string_instance(wl) if kind == "string" else
                       dict(wl, e_ext=wl["e_ext"].astype(np.float64)), steps, 44100.0, scheme="tf"))
         e = rel_l2(y[b], ref)
