@@ -177,6 +177,100 @@ __global__ void __launch_bounds__(kWave * kChipWaves) chip_kernel(StepParams P) 
   }
 }
 
+// Instances without a coupling tensor (tension-modulated and linear ones)
+// of up to 64 M modes (M <= kChipWaveModes / 64), one wave each: lane p
+// steps modes p, p + 64, ..., p + 64 (M - 1).  Per sample: the output and, for the tension
+// force F_k = kappa lam_k q_k sum_j lam_j q_j^2, one more sum over the wave
+// (DPP), then every mode's float-float update; no barrier and no memory
+// traffic but the output and the excitation, read 64 samples ahead.
+template <int M>
+__global__ void __launch_bounds__(kWave) chip_wave_kernel(StepParams P) {
+  const int lane = threadIdx.x;
+  const UnitDev U = P.unit[P.wg_begin[blockIdx.x]];
+  const InstDev I = P.inst[U.inst];
+  const int nt = I.nt;
+  const bool tension = I.kind == KIND_TENSION;
+  float xh[M], xl[M], dh[M], dl[M], mh[M], ml[M], ph[M], pl[M], rh[M], rl[M], bx[M], cw[M], lam[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const int k = lane + kWave * i;
+    const bool live = k < nt;
+    const int so = U.state_off + k, mo = I.mode_off + k;
+    xh[i] = live ? P.x_hi[so] : 0.f;
+    xl[i] = live ? P.x_lo[so] : 0.f;
+    dh[i] = live ? P.d_hi[so] : 0.f;
+    dl[i] = live ? P.d_lo[so] : 0.f;
+    mh[i] = live ? P.m_hi[mo] : 0.f;
+    ml[i] = live ? P.m_lo[mo] : 0.f;
+    ph[i] = live ? P.p_hi[mo] : 0.f;
+    pl[i] = live ? P.p_lo[mo] : 0.f;
+    rh[i] = live ? P.r_hi[mo] : 0.f;
+    rl[i] = live ? P.r_lo[mo] : 0.f;
+    bx[i] = live ? P.b_ext[mo] : 0.f;
+    cw[i] = live ? P.c_out[mo] : 0.f;
+    lam[i] = live ? P.lam[mo] : 0.f;
+  }
+  const long long base = *P.step_base;
+  // excitation samples 64 at a time, lane j holding step 64 c + j of chunk
+  // c; each chunk's loads are issued a chunk ahead, and the steps of a chunk
+  // read no memory, so no step waits on the vector-memory counter
+  auto chunk = [&](long long n0) {
+    const long long m = n0 + lane;
+    return m < I.n_exc ? P.e_ext[I.e_off + m] : 0.f;
+  };
+  float en = chunk(base);
+  bool bad = false;
+  for (int s0 = 0; s0 < P.n_steps; s0 += kWave) {
+    const float ec = en;
+    en = chunk(base + s0 + kWave);
+    const int js = min(kWave, P.n_steps - s0);
+    for (int j = 0; j < js; ++j) {
+      const float e = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ec), j));
+      float yp = 0.f, sp = 0.f;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        yp = fmaf(cw[i], xh[i], yp);
+        sp = fmaf(lam[i] * xh[i], xh[i], sp);
+      }
+      const float yv = wave_sum(yp);
+      if (lane == 0 && P.y) P.y[(long long)I.out_row * P.y_stride + s0 + j] = yv;
+      const float S = tension ? wave_sum(sp) * I.kappa : 0.f;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const float F = lam[i] * xh[i] * S;
+        ff_step(xh[i], xl[i], dh[i], dl[i], mh[i], ml[i], ph[i], pl[i], rh[i], rl[i], fmaf(bx[i], e, -F));
+        bad |= !isfinite(xh[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const int k = lane + kWave * i;
+    if (k < nt) {
+      const int so = U.state_off + k;
+      P.x_hi[so] = xh[i];
+      P.x_lo[so] = xl[i];
+      P.d_hi[so] = dh[i];
+      P.d_lo[so] = dl[i];
+    }
+  }
+  if (__any(bad) && lane == 0) atomicOr(&P.flags[1], 1);
+}
+
+// m: modes per lane, at least the batch's largest n_t / 64
+hipError_t launch_chip_wave(const StepParams& P, int m, int n_wg, hipStream_t s) {
+  if (P.ckpt || P.rec_x) return hipErrorInvalidValue;  // forward-only contexts
+  static_assert(kChipWaveModes == 4 * kWave, "one kernel per modes-per-lane count");
+  switch (m) {
+    case 1: hipLaunchKernelGGL(chip_wave_kernel<1>, dim3(n_wg), dim3(kWave), 0, s, P); break;
+    case 2: hipLaunchKernelGGL(chip_wave_kernel<2>, dim3(n_wg), dim3(kWave), 0, s, P); break;
+    case 3: hipLaunchKernelGGL(chip_wave_kernel<3>, dim3(n_wg), dim3(kWave), 0, s, P); break;
+    case 4: hipLaunchKernelGGL(chip_wave_kernel<4>, dim3(n_wg), dim3(kWave), 0, s, P); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // Widths and rows per wave with a kernel: W R <= 200 tensor floats per lane
 // (with the rest of the kernel's registers, at most two waves per SIMD).
 bool chip_shape(int max_w, int max_rows, int& w_tile, int& rows) {

@@ -12,6 +12,7 @@ constexpr int kMaxGroups = kMaxModes / 4 / kWave;  // float4 groups per lane
 constexpr int kSweepLoads = 4;  // float4 loads per lane per sweep of Ht rows
 constexpr int kChipWaves = 8;   // waves of an on-chip (register-resident) workgroup
 constexpr int kChipMaxRows = 12;  // in-plane rows per wave on the on-chip path
+constexpr int kChipWaveModes = 4 * 64;  // modes of an instance stepped by one wave (no tensor)
 
 enum : int { KIND_LINEAR = 0, KIND_TENSION = 1, KIND_VK = 2 };
 

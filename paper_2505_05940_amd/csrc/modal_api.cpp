@@ -29,6 +29,7 @@ hipError_t launch_ctr_fill(const InstDev* inst, int batch, const long long* step
 hipError_t launch_check(const float* H, const InstDev* inst, int batch, int* out, hipStream_t s);
 hipError_t step_occupancy(int* blocks_per_cu, int gm, int nw, size_t lds_bytes, bool res = false);
 hipError_t launch_chip(const StepParams& P, int nt_tile, int rows, int n_wg, hipStream_t s);
+hipError_t launch_chip_wave(const StepParams& P, int m, int n_wg, hipStream_t s);
 bool chip_shape(int max_nt, int max_rows, int& nt_tile, int& rows);
 hipError_t launch_grad(const GradParams& P, int gm, bool tangent, int nw, bool split, int n_wg, size_t lds,
                        hipStream_t s);
@@ -215,6 +216,9 @@ struct modal_ctx {
   // wave, and its register layouts (one ChipMap per instance)
   int chip_nt = 0, chip_rows = 0;
   ChipMap* dChip = nullptr;
+  // > 0: the on-chip kernel for instances without a tensor, one wave each,
+  // with this many modes per lane
+  int chip_wave = 0;
   // waves of the reverse kernel without and with a tangent tensor (its
   // reduction space per wave holds two or three reduced vectors per row)
   int nw_grad[2] = {4, 4};
@@ -1518,7 +1522,12 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
   // between workgroups.
   int chip_nt = 0, chip_rows = 0;
   std::vector<ChipMap> chip_maps;
-  if (latency && !(d->flags & MODAL_FLAG_GRAD)) {
+  // A batch with no tensor at all (tension-modulated and linear instances,
+  // each of at most kChipWaveModes modes) takes the one-wave variant.
+  bool chip_wave = latency && !(d->flags & MODAL_FLAG_GRAD);
+  for (int b = 0; b < d->batch && chip_wave; ++b)
+    chip_wave = d->inst[b].kind != MODAL_KIND_VK && d->inst[b].n_t <= kChipWaveModes;
+  if (latency && !(d->flags & MODAL_FLAG_GRAD) && !chip_wave) {
     int max_w = 0, max_rows = 0;
     bool ok = true;
     chip_maps.resize(d->batch);
@@ -1781,6 +1790,12 @@ int modal_init(modal_ctx** out, const modal_desc* d_in, void* stream_) {
     c->chip_rows = chip_rows;
     c->nw = kChipWaves;
     c->lds_bytes = 0;
+  } else if (latency && chip_wave && n_wg == d->batch) {
+    int nt_max = 1;
+    for (int b = 0; b < d->batch; ++b) nt_max = std::max(nt_max, d->inst[b].n_t);
+    c->chip_wave = (nt_max + kWave - 1) / kWave;
+    c->nw = 1;
+    c->lds_bytes = 0;
   } else if (latency && n_wg == (int)udev.size() && (c->nw == 4 || c->nw == 8)) {
     int S = 0;
     for (int b = 0; b < d->batch; ++b) S = std::max(S, inst[b].ntp);
@@ -1996,7 +2011,9 @@ static int enqueue_run(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride
         P.rec_d = c->dRecAll + (size_t)c->recall_cap * c->mode_floats;
         P.rec_base = 0;
       }
-      if (c->chip_nt)
+      if (c->chip_wave)
+        HIP_TRY(launch_chip_wave(P, c->chip_wave, c->n_wg, s));
+      else if (c->chip_nt)
         HIP_TRY(launch_chip(P, c->chip_nt, c->chip_rows, c->n_wg, s));
       else
         HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
@@ -2145,7 +2162,9 @@ int modal_run_noalloc(modal_ctx* c, int64_t n_steps, float* y, int64_t y_stride,
     P.y = y + done;
     P.y_stride = y_stride;
     P.n_steps = (int)k;
-    if (c->chip_nt)
+    if (c->chip_wave)
+      HIP_TRY(launch_chip_wave(P, c->chip_wave, c->n_wg, s));
+    else if (c->chip_nt)
       HIP_TRY(launch_chip(P, c->chip_nt, c->chip_rows, c->n_wg, s));
     else
       HIP_TRY(launch_step(P, c->gm, c->nw, c->n_wg, c->lds_bytes, s));
@@ -2609,7 +2628,7 @@ int modal_info(const modal_ctx* c, int64_t info[15]) {
   info[7] = c->occ;
   info[8] = (int64_t)c->makespan;
   info[9] = (int64_t)c->mean_load;
-  info[10] = c->shared ? 1 : (c->linear ? 2 : (c->chip_nt ? 3 : 0));
+  info[10] = c->shared ? 1 : (c->linear ? 2 : (c->chip_nt || c->chip_wave ? 3 : 0));
   info[11] = c->flops;
   info[12] = c->n_blocked;
   info[13] = c->shared ? c->coupling_bytes : c->dense_bytes;

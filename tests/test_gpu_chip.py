@@ -182,3 +182,50 @@ def test_nonfinite_is_reported_on_chip(gpu):
     assert sim.info()["path"] == PATH_CHIP
     with pytest.raises(modal.ModalError, match="non-finite"):
         sim.run(2000)
+
+
+def _plain():
+    """Instances without a tensor, beyond 64 modes too: the 100-mode Berger
+    plate of the paper's Fig. 2, a Kirchhoff-Carrier string and a forced
+    linear system of 130 modes whose 1500-sample forcing ends inside a
+    64-sample chunk."""
+    rng = np.random.default_rng(31)
+    n = 130
+    om = np.sort(rng.uniform(2 * np.pi * 50, 2 * np.pi * 8000, n))
+    lin = dict(kind="linear", omega=om, gamma=1 + 0.002 * om, x0=np.zeros(n), xm1=np.zeros(n),
+               c=rng.normal(size=n), b_ext=rng.normal(size=n), e_ext=rng.normal(size=1500).astype(np.float32))
+    return [("berger", W.plate_berger(n_t=100, n_steps=4000)), ("string", W.string_kc(n_steps=4000)),
+            ("linear", lin)]
+
+
+def test_wave_path_for_instances_without_tensor(gpu):
+    """A batch with no tensor (tension-modulated and linear instances of up
+    to 256 modes) steps one wave per instance (modal_info path 3); parity
+    with the oracle, and eager, chunked-graph and modal_run_noalloc runs
+    bit-identical over launches that start inside a 64-sample chunk."""
+    import torch
+    modal, physics = gpu
+    cases = _plain()
+    prod = {"berger": physics.plate_berger_instance, "string": physics.string_instance, "linear": lambda w: w}
+    orac = {"berger": OI.plate_berger_instance, "string": OI.string_instance,
+            "linear": lambda w: dict(w, e_ext=w["e_ext"].astype(np.float64))}
+    insts = [prod[k](w) for k, w in cases]
+    steps = 4000
+    _say(f"case: one-wave on-chip path, {len(insts)} instances, {steps} steps")
+    sim = modal.Sim(insts, 44100.0, flags=modal.FLAG_RECURSE)
+    assert sim.info()["path"] == PATH_CHIP and sim.info()["workgroups"] == len(insts)
+    y = sim.run(steps).double().cpu().numpy()
+    for b, (kind, wl) in enumerate(cases):
+        ref = OS.run(orac[kind](wl), steps, 44100.0)
+        e = rel_l2(y[b], ref)
+        _say(f"  {kind}: rel L2 {e:.2e}")
+        assert e < TOL, (kind, e)
+    graph = modal.Sim(insts, 44100.0, flags=modal.FLAG_RECURSE | modal.FLAG_GRAPH, chunk_steps=441)
+    noal = modal.Sim(insts, 44100.0, flags=modal.FLAG_RECURSE)
+    out = torch.empty((len(insts), steps), device="cuda")
+    out2 = torch.empty((len(insts), steps), device="cuda")
+    graph.run(steps, out=out)
+    noal.run_noalloc(steps, out2)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), y.astype(np.float32))
+    assert np.array_equal(out2.cpu().numpy(), y.astype(np.float32))

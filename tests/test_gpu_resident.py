@@ -67,7 +67,9 @@ def test_resident_state_across_launches(gpu):
     insts = [physics.string_instance(ws), physics.plate_berger_instance(wb)]
     oinsts = [OI.string_instance(ws), OI.plate_berger_instance(wb)]
     _say("case: resident state, a KC string and a Berger plate")
-    sim = modal.Sim(insts, 44100.0)
+    # a gradient context keeps the streaming kernel (a forward-only batch
+    # without tensors would step on chip, one wave per instance)
+    sim = modal.Sim(insts, 44100.0, flags=modal.FLAG_GRAD)
     assert sim.info()["resident_floats"] > 0
     y = np.concatenate([sim.run(k).cpu().numpy() for k in (300, 700)], axis=1)
     for b, o in enumerate(oinsts):
