@@ -180,14 +180,17 @@ typedef struct {
  * rounded up to 16, 32, 40, 48 or 64, at most 200: 40/40 and 64/24 fit)
  * steps each instance in one workgroup of 8 waves that loads its tensor
  * into registers at the start of each launch; no memory traffic between
- * workgroups, two workgroup barriers per step.
+ * workgroups, two workgroup barriers per step.  A batch with no tensor at
+ * all (MODAL_KIND_TENSION and MODAL_KIND_LINEAR instances of n_t <= 256)
+ * steps each instance in one wave instead, ceil(n_t / 64) modes per lane,
+ * with no barrier.
  * Streaming path plans: a latency-bound batch (at most one instance per CU,
  * dense tensors under 64 MB per step, waves and max_workgroups 0, no
  * MODAL_FLAG_SPLIT_ANY) keeps its tensors dense, takes 8 waves per
  * workgroup and, in batches of at most 16 instances, cuts each instance
  * into slabs of about 8 in-plane rows, one per workgroup.  Any other batch
  * is packed onto the co-resident workgroups by streamed bytes, with
- * sine-family tensors stored parity-blocked (mode_class given, forward
+ * tensors whose mode_class hint holds stored parity-blocked (forward
  * only).
  * Errors: EINVAL (NULL/size/kind/finite/symmetry), EUNSTABLE (a mode's
  * characteristic roots outside the unit circle; also gamma <= 0 or, for TF,
@@ -251,7 +254,8 @@ int modal_get_state(modal_ctx *c, double *x, double *xm1, void *stream);
  * workgroup (both in streamed-byte units), [10] the path: 0 persistent
  * recursion, 1 shared tensor (then [1] is the number of instance columns
  * and [2], [8], [9] are 0), 2 linear closed form, 3 on-chip recursion
- * (one workgroup per instance, [6] 0),
+ * (one workgroup of 8 waves, or of one wave without tensors, per instance,
+ * [6] 0),
  * [11] FP32 operations of the force per step (sum over VK instances of
  * 2 n_in n_t^2 + 4 n_in n_t), [12] instances stored parity-blocked,
  * [13] dense-equivalent tensor bytes per step (sum of 4 n_in n_t^2),
