@@ -408,7 +408,8 @@ def cpu_baseline(wls, n_steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100,
+                    help="timed launches of --samples-per-step samples (100 x 441: one second of audio)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--samples-per-step", type=int, default=441)
     ap.add_argument("--batch", type=int, default=256)
@@ -544,6 +545,7 @@ def main():
                         "modes, sine in-plane family (exact integrals), 44.1 kHz, "
                         f"{S} samples per step",
             "batch": args.batch, "modes_total": modes, "samples_per_step": S,
+            "audio_s_timed": S * args.steps / 44100.0,
             "coupling_bytes_per_sample": info["coupling_bytes_per_step"],
             "workgroups": info["workgroups"], "split_instances": info["split_instances"],
             "max_workgroups": mw, "waves_per_workgroup": waves or 4, "split_cost_kb": split_kb or 32,
