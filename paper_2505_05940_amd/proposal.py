@@ -194,6 +194,9 @@ def run(args, stream=None):
         def cb(it, theta, L):
             ok = (L.cpu().numpy() < args.tol) & np.isnan(t_first)
             t_first[ok] = time.time() - t0
+            if (it + 1) % 10 == 0:  # progress of long runs
+                log(f"{arm}: iteration {it + 1}, {int(np.sum(~np.isnan(t_first)))} of {args.test} at the "
+                    f"target, {time.time() - t0:.1f} s")
         th, L, iters, _ = fit.fit(y_tgt, th0, setup, args.steps, iters=args.iters, lr=args.lr,
                                   tol=args.tol, callback=cb)
         wall = time.time() - t0
