@@ -228,9 +228,16 @@ __device__ __forceinline__ float4 ldnt4(const float* p) {
 }
 __device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
 
-// 16-byte streaming load through a buffer resource, non-temporal hint.
+// 16-byte load through a buffer resource with cache policy POL: kStream,
+// the non-temporal hint, for tensors streamed from HBM once per step (the
+// batch), or kKeep, the default policy, for a latency-bound instance whose
+// tensor stays in the caches from step to step (measured on a lone 200/200
+// plate: forward 14.0 -> 12.1 us and reverse 18.2 -> 16.8 us per step; the
+// 256-plate batch 233 -> 247 ms per launch with kKeep).
+constexpr int kStream = 2, kKeep = 0;
+template <int POL = kStream>
 __device__ __forceinline__ float4 buf_ld4(v4i r, int voff) {
-  const v4f v = llvm_raw_buffer_load_v4f32(r, voff, 0, 2);
+  const v4f v = llvm_raw_buffer_load_v4f32(r, voff, 0, POL);
   return make_float4(v.x, v.y, v.z, v.w);
 }
 

@@ -18,7 +18,7 @@
 
 namespace modal {
 
-template <int GM, bool TAN, int DEPTH>
+template <int GM, bool TAN, int DEPTH, int POL>
 __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__ Hdb, int nt,
                          int ntp, int qs, int row0, int row1, const float* Xs, const float* Us,
                          float* red, float4 (&Ju)[GM], float4 (&Fa)[GM], float& tsum, int G,
@@ -51,11 +51,11 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
     const int bytes = live ? (lb == nblk - 1 ? last_bytes : blk_bytes) : 0;
     const v4i r = buf_rsrc(Hb + o, bytes);
 #pragma unroll
-    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4<POL>(r, voff[j]);
     if (TAN) {
       const v4i rd = buf_rsrc(Hdb + o, bytes);
 #pragma unroll
-      for (int j = 0; j < J; ++j) hd[j] = buf_ld4(rd, voff[j]);
+      for (int j = 0; j < J; ++j) hd[j] = buf_ld4<POL>(rd, voff[j]);
     }
     if (++lb == nblk) {
       lb = 0;
@@ -153,7 +153,7 @@ __device__ void vk_rows2(const float* __restrict__ Hb, const float* __restrict__
 // Vd) are parked in `defer` (slot s at s NR ntp) and the partial eta, V.u,
 // Vd.q and Vd.u with the row index in the wave's exchange words (slot 0: a
 // row entered mid-row, slot 1: a row left mid-row), for vk_rows2_finish.
-template <int GM, bool TAN, int DEPTH>
+template <int GM, bool TAN, int DEPTH, int POL>
 __device__ void vk_rows2_range(const float* __restrict__ Hb, const float* __restrict__ Hdb, int nt,
                                int ntp, int qs, int row0, int t0, int t1, const float* Xs,
                                const float* Us, float* red, float4 (&Ju)[GM], float4 (&Fa)[GM],
@@ -188,11 +188,11 @@ __device__ void vk_rows2_range(const float* __restrict__ Hb, const float* __rest
     const int bytes = live ? (lb == nblk - 1 ? last_bytes : blk_bytes) : 0;
     const v4i r = buf_rsrc(Hb + o, bytes);
 #pragma unroll
-    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4<POL>(r, voff[j]);
     if (TAN) {
       const v4i rd = buf_rsrc(Hdb + o, bytes);
 #pragma unroll
-      for (int j = 0; j < J; ++j) hd[j] = buf_ld4(rd, voff[j]);
+      for (int j = 0; j < J; ++j) hd[j] = buf_ld4<POL>(rd, voff[j]);
     }
     ++lt;
     if (++lb == nblk) {
@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
           float* xv = L.xch;
           int* xr = reinterpret_cast<int*>(L.xch + 2 * NW * kXchVals);
           float* defer = red + 2 * NR * U.qs * I.ntp;
-          vk_rows2_range<GM, TAN, (NW == 8 && GM <= 2) ? 3 : 2>(
+          vk_rows2_range<GM, TAN, (NW == 8 && GM <= 2) ? 3 : 2, kKeep>(
               P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs, U.row0, (T * wave) / NW,
               (T * (wave + 1)) / NW, Xs, Us, red, Ju, Fa, tsum, G, lane, rrow, teta, tw, defer,
               xv + 2 * wave * kXchVals, xr + 2 * wave);
@@ -543,9 +543,9 @@ __global__ void __launch_bounds__(kWave * NW) grad_kernel(GradParams P) {
             vk_rows2_finish<GM, TAN>(xv, xr, NW, wave, I.ntp, defer, Ju, Fa, tsum, G, lane, rrow, teta, tw);
           }
         } else {
-          vk_rows2<GM, TAN, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt,
-                                                          I.ntp, U.qs, r0, r1, Xs, Us, red, Ju, Fa, tsum, G,
-                                                          lane, rrow, teta, tw);
+          vk_rows2<GM, TAN, (NW == 8 && GM <= 2) ? 3 : 2, SPLIT ? kKeep : kStream>(
+              P.H + I.h_off, TAN ? P.Hd + I.h_off : nullptr, I.nt, I.ntp, U.qs, r0, r1, Xs, Us, red, Ju, Fa, tsum,
+              G, lane, rrow, teta, tw);
         }
         if (NW > 1) {
 #pragma unroll

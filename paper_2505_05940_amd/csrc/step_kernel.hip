@@ -44,7 +44,7 @@ namespace modal {
 // the force follow: F += eta_n V[n, :].  DEPTH buffers (2 or 3) keep
 // DEPTH - 1 blocks' loads in flight; three serve small latency-bound units
 // whose rows are only a block or two long.
-template <int GM, int DEPTH>
+template <int GM, int DEPTH, int POL>
 __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, int row0,
                         int row1, const float* Xs, float* red, float4 (&Fa)[GM], int G,
                         int lane) {
@@ -74,7 +74,7 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
     const int bytes = live ? (lb == nblk - 1 ? last_bytes : blk_bytes) : 0;
     const v4i r = buf_rsrc(bp, bytes);
 #pragma unroll
-    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4<POL>(r, voff[j]);
     if (++lb == nblk) {
       lb = 0;
       ++ln;
@@ -143,7 +143,7 @@ __device__ void vk_rows(const float* __restrict__ Hb, int nt, int ntp, int qs, i
 // slots of ntp floats) and the partial eta_n and the row index in the
 // wave's exchange words (slot 0: a row the range enters mid-row, slot 1: a
 // row it leaves mid-row; row -1 = unused), for vk_rows_finish.
-template <int GM, int DEPTH>
+template <int GM, int DEPTH, int POL>
 __device__ void vk_rows_range(const float* __restrict__ Hb, int nt, int ntp, int qs, int row0, int t0,
                               int t1, const float* Xs, float* red, float4 (&Fa)[GM], int G, int lane,
                               float* defer, float* xv, int* xr) {
@@ -175,7 +175,7 @@ __device__ void vk_rows_range(const float* __restrict__ Hb, int nt, int ntp, int
     const int bytes = live ? (lb == nblk - 1 ? last_bytes : blk_bytes) : 0;
     const v4i r = buf_rsrc(bp, bytes);
 #pragma unroll
-    for (int j = 0; j < J; ++j) h[j] = buf_ld4(r, voff[j]);
+    for (int j = 0; j < J; ++j) h[j] = buf_ld4<POL>(r, voff[j]);
     ++lt;
     if (++lb == nblk) {
       lb = 0;
@@ -664,9 +664,9 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
           float* xv = L.xch;
           int* xr = reinterpret_cast<int*>(L.xch + 2 * NW);
           float* defer = red + 2 * U.qs * I.ntp;
-          vk_rows_range<GM, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, I.nt, I.ntp, U.qs, U.row0,
-                                                          (T * wave) / NW, (T * (wave + 1)) / NW, Xs, red,
-                                                          Fa, G, lane, defer, xv + 2 * wave, xr + 2 * wave);
+          vk_rows_range<GM, (NW == 8 && GM <= 2) ? 3 : 2, kKeep>(
+              P.H + I.h_off, I.nt, I.ntp, U.qs, U.row0, (T * wave) / NW, (T * (wave + 1)) / NW, Xs, red, Fa, G,
+              lane, defer, xv + 2 * wave, xr + 2 * wave);
           bool cut = false;  // a wave boundary inside a row
           for (int w = 1; w < NW; ++w) cut |= ((T * w) / NW) % nblk != 0;
           if (cut) {
@@ -678,8 +678,8 @@ __global__ void __launch_bounds__(kWave * NW) step_kernel(StepParams P) {
           if (I.blk)
             vk_rows_blk<GM>(P.H + I.h_off, P.jmap + I.jmap_off, I, r0, r1, Xs, red, Fa, G, lane);
           else
-            vk_rows<GM, (NW == 8 && GM <= 2) ? 3 : 2>(P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa,
-                                                      G, lane);
+            vk_rows<GM, (NW == 8 && GM <= 2) ? 3 : 2, RES ? kKeep : kStream>(
+                P.H + I.h_off, I.nt, I.ntp, U.qs, r0, r1, Xs, red, Fa, G, lane);
         }
         if (NW > 1) {
 #pragma unroll
