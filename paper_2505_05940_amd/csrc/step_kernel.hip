@@ -18,9 +18,11 @@
 //      over several workgroups first exchange their partial forces through
 //      global memory and wait until every slab of the instance has stored
 //      its arrival word for the step.
-// The coupling tensor is streamed from HBM once per step with 16-byte
-// non-temporal loads; each element is used once, so it goes straight to
-// registers.  LDS holds q^n and the cross-lane reduction of V.
+// The coupling tensor is streamed from HBM once per step with 16-byte loads
+// into registers, with the non-temporal hint for a batch (each element is
+// used once per step) and the default policy for a latency plan, whose
+// tensors stay in the caches from step to step.  LDS holds q^n and the
+// cross-lane reduction of V.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
